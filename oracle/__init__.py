@@ -1,0 +1,193 @@
+"""CPU oracle for the Memory-Model data-race check.
+
+TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH: only the tests, the smoke
+check and the benchmark's CPU-baseline leg use it.  It shares no code with
+the GPU path and never imports it.
+
+Two native tiers live in ``oracle.c`` (built into ``liboracle.so``):
+  * ``brute_force`` -- Tier A, the pairwise race definition of Theorem 1
+    (Sec. 4.2.3) applied to every pair, O(n^2);
+  * ``closed_form`` -- Tier B, group counts by location / block / epoch /
+    thread and inclusion-exclusion over them.
+``tier_a_py`` is a third, pure-Python rendering of the pairwise definition
+for tiny inputs, written separately so that the C tiers can be checked
+against it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+RACE_DTYPE = np.dtype(
+    [
+        ("trace", "<u4"),
+        ("space", "u1"),
+        ("kinds", "u1"),
+        ("reserved16", "<u2"),
+        ("block", "<u4"),
+        ("reserved32", "<u4"),
+        ("unit", "<u8"),
+        ("pairs_ww", "<u8"),
+        ("pairs_rw", "<u8"),
+        ("pairs_aw", "<u8"),
+        ("pairs_ar", "<u8"),
+        ("pairs_xblock", "<u8"),
+    ]
+)
+assert RACE_DTYPE.itemsize == 64
+
+SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pairs", "<u8")])
+
+KIND_BITS = {"ww": 1, "rw": 2, "aw": 4, "ar": 8, "xblock": 16}
+
+
+class OracleError(Exception):
+    def __init__(self, code, bad_index=None):
+        super().__init__(f"oracle rejected input (code {code}, bad index {bad_index})")
+        self.code = code
+        self.bad_index = bad_index
+
+
+def build() -> str:
+    """Compile liboracle.so with gcc (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        for name in ("orc_brute_force", "orc_closed_form"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int64
+            f.argtypes = [
+                ctypes.c_void_p,
+                ctypes.c_void_p,
+                ctypes.c_uint32,
+                ctypes.c_void_p,
+                ctypes.POINTER(ctypes.c_void_p),
+                ctypes.c_void_p,
+                ctypes.POINTER(ctypes.c_uint64),
+            ]
+        lib.orc_free.restype = None
+        lib.orc_free.argtypes = [ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _as_batch(records, offsets=None, tpb=None):
+    records = np.ascontiguousarray(records)
+    if offsets is None:
+        offsets = np.array([0, len(records)], dtype=np.uint64)
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    n_traces = len(offsets) - 1
+    if tpb is None:
+        raise ValueError("threads-per-block is required")
+    tpb = np.asarray(tpb, dtype=np.uint32)
+    if tpb.ndim == 0:
+        tpb = np.full(n_traces, int(tpb), dtype=np.uint32)
+    tpb = np.ascontiguousarray(tpb)
+    return records, offsets, n_traces, tpb
+
+
+def _run(fname, records, offsets, tpb):
+    records, offsets, n_traces, tpb = _as_batch(records, offsets, tpb)
+    lib = _load()
+    out = ctypes.c_void_p()
+    summ = np.zeros(max(n_traces, 1), dtype=SUMMARY_DTYPE)
+    bad = ctypes.c_uint64(0)
+    n = getattr(lib, fname)(
+        records.ctypes.data if len(records) else None,
+        offsets.ctypes.data,
+        n_traces,
+        tpb.ctypes.data,
+        ctypes.byref(out),
+        summ.ctypes.data,
+        ctypes.byref(bad),
+    )
+    if n < 0:
+        raise OracleError(int(n), int(bad.value) if n == -2 else None)
+    races = np.zeros(n, dtype=RACE_DTYPE)
+    if n:
+        ctypes.memmove(races.ctypes.data, out.value, n * RACE_DTYPE.itemsize)
+    if out.value:
+        lib.orc_free(out)
+    return races, summ[:n_traces]
+
+
+def brute_force(records, offsets=None, tpb=None):
+    """Tier A: every pair tested against the race definition."""
+    return _run("orc_brute_force", records, offsets, tpb)
+
+
+def closed_form(records, offsets=None, tpb=None):
+    """Tier B: inclusion-exclusion over location/block/epoch/thread groups."""
+    return _run("orc_closed_form", records, offsets, tpb)
+
+
+# ---------------------------------------------------------------------------
+# Pure-Python Tier A for tiny traces (independent rendering of Theorem 1).
+# ---------------------------------------------------------------------------
+
+def tier_a_py(records, tpb, trace=0):
+    """Return {(space, block_or_None, unit): {'ww','rw','aw','ar','xblock'}}
+    for one trace, by testing every unordered pair of record positions."""
+    recs = [tuple(int(v) for v in r) for r in records]  # unit, tid, epoch, action, space
+    out = {}
+    names = {frozenset(["W"]): "ww", frozenset(["R", "W"]): "rw",
+             frozenset(["A", "W"]): "aw", frozenset(["A", "R"]): "ar"}
+    letter = {0: "R", 1: "W", 2: "A"}
+    for i in range(len(recs)):
+        for j in range(i + 1, len(recs)):
+            u1, t1, e1, a1, s1 = recs[i]
+            u2, t2, e2, a2, s2 = recs[j]
+            b1, b2 = t1 // tpb, t2 // tpb
+            if s1 != s2 or u1 != u2:
+                continue
+            if s1 == 1 and b1 != b2:  # shared memory belongs to one block
+                continue
+            if t1 == t2:
+                continue
+            acts = frozenset([letter[a1], letter[a2]])
+            if acts in (frozenset(["R"]), frozenset(["A"])):
+                continue
+            if b1 == b2 and e1 != e2:  # a barrier of the block separates them
+                continue
+            key = (s1, b1 if s1 == 1 else None, u1)
+            d = out.setdefault(key, {"ww": 0, "rw": 0, "aw": 0, "ar": 0, "xblock": 0})
+            d[names[acts]] += 1
+            if b1 != b2:
+                d["xblock"] += 1
+    return out
+
+
+def races_to_dict(races, trace=0):
+    """Convert a RACE_DTYPE array (one trace) to the tier_a_py form."""
+    out = {}
+    for r in races:
+        if int(r["trace"]) != trace:
+            continue
+        key = (int(r["space"]), int(r["block"]) if int(r["space"]) == 1 else None, int(r["unit"]))
+        out[key] = {
+            "ww": int(r["pairs_ww"]),
+            "rw": int(r["pairs_rw"]),
+            "aw": int(r["pairs_aw"]),
+            "ar": int(r["pairs_ar"]),
+            "xblock": int(r["pairs_xblock"]),
+        }
+    return out

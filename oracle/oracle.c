@@ -1,0 +1,345 @@
+/*
+ * oracle.c -- CPU oracle for the Memory-Model data-race check.
+ *
+ * TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load this file's
+ * library.  It shares no code, header, table or helper with the GPU path.
+ *
+ * What is computed (paper Sec. 4.2.3, Theorem 1; Alg. 5, data-race part):
+ * two accesses (Unit Tuples) of one trace race when
+ *   - they touch the same memory unit (same location: global memory is one
+ *     array for all blocks, shared memory is private to a block, Alg. 3),
+ *   - they come from different threads (Theorem 1, second condition),
+ *   - they are concurrent: the same visit order, i.e. the same barrier
+ *     interval (Theorem 1, first condition), or different blocks, since a
+ *     barrier only orders the threads of one block (Sec. 2),
+ *   - at least one writes (Theorem 1, third condition), where an atomic
+ *     races with a plain read or write but not with another atomic.
+ * The warp clauses (1)-(3) of Theorem 1 are not applied: records carry no
+ * statement or divergence information, so every pair of distinct threads is
+ * treated as potentially concurrent.
+ *
+ * For every location with at least one racing pair, one entry gives the
+ * number of racing unordered record pairs by kind (write/write, read/write,
+ * atomic/write, atomic/read) and how many of them span two blocks.
+ *
+ * Tier A (orc_brute_force) applies the pairwise definition literally to all
+ * O(n^2) pairs.  Tier B (orc_closed_form) groups records by location, block,
+ * epoch and thread with the C library's qsort and counts pairs from group
+ * sizes by inclusion-exclusion:
+ *   pairs_k(L) = K_k(L) - sum_b K_k(L_b) + sum_{b,e} K_k(L_be) - sum_{b,e,t} K_k(L_bet)
+ * with K_WW = w(w-1)/2, K_RW = r w, K_AW = a w, K_AR = a r for a group with
+ * r reads, w writes and a atomics.  A pair with the same thread is counted
+ * +1-1+1-1 = 0 times, one in the same block and epoch from different threads
+ * +1-1+1 = 1 time, one in the same block and different epochs +1-1 = 0
+ * times, and one in different blocks +1 time.  The cross-block count is
+ * sum_k [K_k(L) - sum_b K_k(L_b)].  Tier B is checked against Tier A by the
+ * tests; it is not assumed.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  uint64_t unit;
+  uint32_t tid;
+  uint16_t epoch;
+  uint8_t action; /* 0 read, 1 write, 2 atomic */
+  uint8_t space;  /* 0 global, 1 shared */
+} orc_record;
+
+typedef struct {
+  uint32_t trace;
+  uint8_t space;
+  uint8_t kinds; /* bit0 WW, bit1 RW, bit2 AW, bit3 AR, bit4 cross-block */
+  uint16_t reserved16;
+  uint32_t block; /* owning block for shared, 0xFFFFFFFF for global */
+  uint32_t reserved32;
+  uint64_t unit;
+  uint64_t pairs_ww, pairs_rw, pairs_aw, pairs_ar, pairs_xblock;
+} orc_race;
+
+typedef struct {
+  uint64_t n_records, n_race_locs, n_pairs;
+} orc_summary;
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ERECORD = -2, ORC_ENOMEM = -3 };
+enum { KIND_WW = 0, KIND_RW = 1, KIND_AW = 2, KIND_AR = 3 };
+
+/* Kind of an unordered action pair, or -1 when the pair does not conflict
+ * (read/read, atomic/atomic). */
+static int kind_of(int a, int b) {
+  if (a > b) { int t = a; a = b; b = t; }
+  if (a == 0 && b == 0) return -1; /* R R */
+  if (a == 0 && b == 1) return KIND_RW;
+  if (a == 0 && b == 2) return KIND_AR;
+  if (a == 1 && b == 1) return KIND_WW;
+  if (a == 1 && b == 2) return KIND_AW;
+  return -1; /* A A */
+}
+
+/* ---------- growable entry list ---------- */
+typedef struct {
+  orc_race* v;
+  uint64_t n, cap;
+} race_list;
+
+static int push(race_list* L, const orc_race* e) {
+  if (L->n == L->cap) {
+    uint64_t nc = L->cap ? 2 * L->cap : 256;
+    orc_race* nv = (orc_race*)realloc(L->v, nc * sizeof(orc_race));
+    if (!nv) return ORC_ENOMEM;
+    L->v = nv;
+    L->cap = nc;
+  }
+  L->v[L->n++] = *e;
+  return ORC_OK;
+}
+
+static int validate(const orc_record* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                    uint64_t* bad_index) {
+  if (n_traces && (!off || !tpb)) return ORC_EINVAL;
+  if (n_traces && off[0] != 0) return ORC_EINVAL;
+  for (uint32_t t = 0; t < n_traces; t++) {
+    if (off[t + 1] < off[t]) return ORC_EINVAL;
+    if (tpb[t] == 0) return ORC_EINVAL;
+  }
+  uint64_t n = n_traces ? off[n_traces] : 0;
+  if (n && !recs) return ORC_EINVAL;
+  for (uint64_t i = 0; i < n; i++) {
+    if (recs[i].action > 2 || recs[i].space > 1) {
+      if (bad_index) *bad_index = i;
+      return ORC_ERECORD;
+    }
+  }
+  return ORC_OK;
+}
+
+static void finish_entry(orc_race* e) {
+  e->kinds = (uint8_t)((e->pairs_ww ? 1 : 0) | (e->pairs_rw ? 2 : 0) | (e->pairs_aw ? 4 : 0) |
+                       (e->pairs_ar ? 8 : 0) | (e->pairs_xblock ? 16 : 0));
+}
+
+/* ---------- location ordering shared by both tiers' outputs ---------- */
+static int cmp_entry(const void* pa, const void* pb) {
+  const orc_race* a = (const orc_race*)pa;
+  const orc_race* b = (const orc_race*)pb;
+  if (a->trace != b->trace) return a->trace < b->trace ? -1 : 1;
+  if (a->space != b->space) return a->space < b->space ? -1 : 1;
+  if (a->block != b->block) return a->block < b->block ? -1 : 1;
+  if (a->unit != b->unit) return a->unit < b->unit ? -1 : 1;
+  return 0;
+}
+
+static void summarise(const race_list* L, const uint64_t* off, uint32_t n_traces, orc_summary* S) {
+  if (!S) return;
+  for (uint32_t t = 0; t < n_traces; t++) {
+    S[t].n_records = off[t + 1] - off[t];
+    S[t].n_race_locs = 0;
+    S[t].n_pairs = 0;
+  }
+  for (uint64_t i = 0; i < L->n; i++) {
+    orc_summary* s = &S[L->v[i].trace];
+    s->n_race_locs++;
+    s->n_pairs += L->v[i].pairs_ww + L->v[i].pairs_rw + L->v[i].pairs_aw + L->v[i].pairs_ar;
+  }
+}
+
+/* ======================= Tier A: brute force ======================= */
+
+/* One racing pair becomes one "hit" on its location; hits are then sorted by
+ * location and summed. */
+int64_t orc_brute_force(const orc_record* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                        orc_race** out, orc_summary* summary, uint64_t* bad_index) {
+  int rc = validate(recs, off, n_traces, tpb, bad_index);
+  if (rc) return rc;
+  race_list hits = {0, 0, 0};
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t lo = off[tr], hi = off[tr + 1];
+    const uint32_t T = tpb[tr];
+    for (uint64_t i = lo; i < hi; i++) {
+      const orc_record* x = &recs[i];
+      const uint32_t bx = x->tid / T;
+      for (uint64_t j = i + 1; j < hi; j++) {
+        const orc_record* y = &recs[j];
+        const uint32_t by = y->tid / T;
+        /* same memory unit: same space and unit; shared memory is per block */
+        if (x->space != y->space || x->unit != y->unit) continue;
+        if (x->space == 1 && bx != by) continue;
+        /* different threads */
+        if (x->tid == y->tid) continue;
+        /* at least one write (atomics conflict with plain accesses only) */
+        const int kind = kind_of(x->action, y->action);
+        if (kind < 0) continue;
+        /* concurrent: same barrier interval, or different blocks */
+        if (!(bx != by || x->epoch == y->epoch)) continue;
+        orc_race h;
+        memset(&h, 0, sizeof h);
+        h.trace = tr;
+        h.space = x->space;
+        h.block = x->space == 1 ? bx : 0xFFFFFFFFu;
+        h.unit = x->unit;
+        if (kind == KIND_WW) h.pairs_ww = 1;
+        if (kind == KIND_RW) h.pairs_rw = 1;
+        if (kind == KIND_AW) h.pairs_aw = 1;
+        if (kind == KIND_AR) h.pairs_ar = 1;
+        h.pairs_xblock = (bx != by) ? 1 : 0;
+        if (push(&hits, &h)) { free(hits.v); return ORC_ENOMEM; }
+      }
+    }
+  }
+  if (hits.n) qsort(hits.v, hits.n, sizeof(orc_race), cmp_entry);
+  race_list res = {0, 0, 0};
+  for (uint64_t i = 0; i < hits.n;) {
+    orc_race e = hits.v[i];
+    uint64_t j = i + 1;
+    while (j < hits.n && cmp_entry(&hits.v[j], &hits.v[i]) == 0) {
+      e.pairs_ww += hits.v[j].pairs_ww;
+      e.pairs_rw += hits.v[j].pairs_rw;
+      e.pairs_aw += hits.v[j].pairs_aw;
+      e.pairs_ar += hits.v[j].pairs_ar;
+      e.pairs_xblock += hits.v[j].pairs_xblock;
+      j++;
+    }
+    finish_entry(&e);
+    if (push(&res, &e)) { free(hits.v); free(res.v); return ORC_ENOMEM; }
+    i = j;
+  }
+  free(hits.v);
+  summarise(&res, off, n_traces, summary);
+  *out = res.v;
+  return (int64_t)res.n;
+}
+
+/* ===================== Tier B: group counts ===================== */
+
+typedef struct {
+  uint64_t unit;
+  uint32_t lblock; /* block if shared, 0xFFFFFFFF if global: part of the location */
+  uint32_t block;
+  uint32_t tid;
+  uint16_t epoch;
+  uint8_t space;
+  uint8_t action;
+} item;
+
+static int cmp_item(const void* pa, const void* pb) {
+  const item* a = (const item*)pa;
+  const item* b = (const item*)pb;
+  if (a->space != b->space) return a->space < b->space ? -1 : 1;
+  if (a->lblock != b->lblock) return a->lblock < b->lblock ? -1 : 1;
+  if (a->unit != b->unit) return a->unit < b->unit ? -1 : 1;
+  if (a->block != b->block) return a->block < b->block ? -1 : 1;
+  if (a->epoch != b->epoch) return a->epoch < b->epoch ? -1 : 1;
+  if (a->tid != b->tid) return a->tid < b->tid ? -1 : 1;
+  return 0;
+}
+
+typedef struct {
+  uint64_t r, w, a;
+} counts;
+
+/* K_k of one group, k = WW, RW, AW, AR */
+static void K(const counts* c, uint64_t k[4]) {
+  k[KIND_WW] = c->w ? c->w * (c->w - 1) / 2 : 0;
+  k[KIND_RW] = c->r * c->w;
+  k[KIND_AW] = c->a * c->w;
+  k[KIND_AR] = c->a * c->r;
+}
+
+static void add(counts* c, uint8_t action) {
+  if (action == 0) c->r++;
+  else if (action == 1) c->w++;
+  else c->a++;
+}
+
+static int same_loc(const item* x, const item* y) {
+  return x->space == y->space && x->lblock == y->lblock && x->unit == y->unit;
+}
+
+int64_t orc_closed_form(const orc_record* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                        orc_race** out, orc_summary* summary, uint64_t* bad_index) {
+  int rc = validate(recs, off, n_traces, tpb, bad_index);
+  if (rc) return rc;
+  race_list res = {0, 0, 0};
+  uint64_t maxn = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++)
+    if (off[tr + 1] - off[tr] > maxn) maxn = off[tr + 1] - off[tr];
+  item* it = maxn ? (item*)malloc(maxn * sizeof(item)) : NULL;
+  if (maxn && !it) return ORC_ENOMEM;
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t lo = off[tr], n = off[tr + 1] - off[tr];
+    const uint32_t T = tpb[tr];
+    for (uint64_t i = 0; i < n; i++) {
+      const orc_record* r = &recs[lo + i];
+      it[i].unit = r->unit;
+      it[i].block = r->tid / T;
+      it[i].lblock = r->space == 1 ? it[i].block : 0xFFFFFFFFu;
+      it[i].tid = r->tid;
+      it[i].epoch = r->epoch;
+      it[i].space = r->space;
+      it[i].action = r->action;
+    }
+    if (n) qsort(it, n, sizeof(item), cmp_item);
+    uint64_t i = 0;
+    while (i < n) {
+      /* one location [i, iL) */
+      uint64_t iL = i;
+      counts cL = {0, 0, 0};
+      while (iL < n && same_loc(&it[iL], &it[i])) add(&cL, it[iL++].action);
+      uint64_t KL[4], SB[4] = {0, 0, 0, 0}, SE[4] = {0, 0, 0, 0}, ST[4] = {0, 0, 0, 0}, tmp[4];
+      K(&cL, KL);
+      for (uint64_t ib = i; ib < iL;) { /* block groups */
+        uint64_t jb = ib;
+        counts cB = {0, 0, 0};
+        while (jb < iL && it[jb].block == it[ib].block) add(&cB, it[jb++].action);
+        K(&cB, tmp);
+        for (int k = 0; k < 4; k++) SB[k] += tmp[k];
+        for (uint64_t ie = ib; ie < jb;) { /* epoch groups */
+          uint64_t je = ie;
+          counts cE = {0, 0, 0};
+          while (je < jb && it[je].epoch == it[ie].epoch) add(&cE, it[je++].action);
+          K(&cE, tmp);
+          for (int k = 0; k < 4; k++) SE[k] += tmp[k];
+          for (uint64_t itd = ie; itd < je;) { /* thread groups */
+            uint64_t jt = itd;
+            counts cT = {0, 0, 0};
+            while (jt < je && it[jt].tid == it[itd].tid) add(&cT, it[jt++].action);
+            K(&cT, tmp);
+            for (int k = 0; k < 4; k++) ST[k] += tmp[k];
+            itd = jt;
+          }
+          ie = je;
+        }
+        ib = jb;
+      }
+      uint64_t p[4], xb = 0;
+      for (int k = 0; k < 4; k++) {
+        p[k] = KL[k] - SB[k] + SE[k] - ST[k];
+        xb += KL[k] - SB[k];
+      }
+      if (p[0] + p[1] + p[2] + p[3] > 0) {
+        orc_race e;
+        memset(&e, 0, sizeof e);
+        e.trace = tr;
+        e.space = it[i].space;
+        e.block = it[i].lblock;
+        e.unit = it[i].unit;
+        e.pairs_ww = p[KIND_WW];
+        e.pairs_rw = p[KIND_RW];
+        e.pairs_aw = p[KIND_AW];
+        e.pairs_ar = p[KIND_AR];
+        e.pairs_xblock = xb;
+        finish_entry(&e);
+        if (push(&res, &e)) { free(it); free(res.v); return ORC_ENOMEM; }
+      }
+      i = iL;
+    }
+  }
+  free(it);
+  summarise(&res, off, n_traces, summary);
+  *out = res.v;
+  return (int64_t)res.n;
+}
+
+void orc_free(void* p) { free(p); }
