@@ -1,0 +1,182 @@
+/*
+ * simcheck.h -- C ABI of the MI355X data-race check over Memory-Model traces.
+ *
+ * The operation (paper Sec. 4.2.3, Theorem 1, and the data-race loop of
+ * Alg. 5): a trace is a multiset of accesses, each one Unit Tuple of the
+ * paper's Memory Model (Sec. 4.2.1) -- memory unit, thread, visit order,
+ * action -- plus its memory space.  Two records of one trace race when
+ *   - they touch the same location: the same unit of global memory (one
+ *     array for all blocks), or the same unit of one block's shared memory
+ *     (shared memory is private to a block, Alg. 3);
+ *   - their thread ids differ;
+ *   - they are concurrent: the same epoch (visit order, i.e. the number of
+ *     barriers the thread has passed; Sec. 4.2.2, Alg. 4) within one block,
+ *     or different blocks (a barrier synchronises one block only, Sec. 2);
+ *   - at least one writes, and they are not both atomic (an atomic races
+ *     with a plain read or write).
+ * The warp clauses (1)-(3) of Theorem 1 are not applied (records carry no
+ * statement or divergence data): every pair of distinct threads counts as
+ * potentially concurrent.
+ *
+ * For every racing location the library returns one entry with the exact
+ * number of racing unordered record pairs by kind and the cross-block
+ * subset; entries are ordered by (trace, space, block, unit), global before
+ * shared.  The result depends only on the multiset of records of each trace.
+ *
+ * Conventions
+ *   - Little-endian, C99, no C++ or HIP types across the ABI.
+ *   - Return value 0 on success, a negative SIM_E* code on error.  On error
+ *     *out is set to NULL, nothing partial is returned and the context stays
+ *     usable; sim_last_error() describes the failure.
+ *   - A context is used by one host thread at a time; several contexts may
+ *     coexist.  All work runs on the GPU given to sim_create(); there is no
+ *     CPU fallback -- creation fails when no usable gfx950 device exists.
+ */
+#ifndef SIMCHECK_H
+#define SIMCHECK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ types */
+
+/* One access record (16 bytes, 8-byte aligned).
+ *   unit   : memory unit index within its space (4-byte word address)
+ *   tid    : grid-wide linear thread id; block = tid / threads_per_block
+ *   epoch  : barriers the thread had passed at the access (visit order)
+ *   action : SIM_READ, SIM_WRITE or SIM_ATOMIC
+ *   space  : SIM_GLOBAL or SIM_SHARED                                      */
+typedef struct sim_record {
+  uint64_t unit;
+  uint32_t tid;
+  uint16_t epoch;
+  uint8_t action;
+  uint8_t space;
+} sim_record;
+
+enum { SIM_READ = 0, SIM_WRITE = 1, SIM_ATOMIC = 2 };
+enum { SIM_GLOBAL = 0, SIM_SHARED = 1 };
+
+/* kinds bits of a sim_race */
+enum {
+  SIM_KIND_WW = 1,     /* write / write   */
+  SIM_KIND_RW = 2,     /* read / write    */
+  SIM_KIND_AW = 4,     /* atomic / write  */
+  SIM_KIND_AR = 8,     /* atomic / read   */
+  SIM_KIND_XBLOCK = 16 /* some racing pair spans two blocks */
+};
+
+/* One racing location (64 bytes). */
+typedef struct sim_race {
+  uint32_t trace;      /* index of the trace in the call */
+  uint8_t space;       /* SIM_GLOBAL or SIM_SHARED */
+  uint8_t kinds;       /* SIM_KIND_* bits: pairs_k > 0, pairs_xblock > 0 */
+  uint16_t reserved16; /* 0 */
+  uint32_t block;      /* owning block if SIM_SHARED, 0xFFFFFFFF if SIM_GLOBAL */
+  uint32_t reserved32; /* 0 */
+  uint64_t unit;
+  uint64_t pairs_ww, pairs_rw, pairs_aw, pairs_ar; /* racing unordered record pairs by kind */
+  uint64_t pairs_xblock; /* subset of the above whose two records are in different blocks */
+} sim_race;
+
+typedef struct sim_trace_summary {
+  uint64_t n_records;   /* records of the trace */
+  uint64_t n_race_locs; /* entries of the trace */
+  uint64_t n_pairs;     /* sum of pairs_ww + pairs_rw + pairs_aw + pairs_ar */
+} sim_trace_summary;
+
+/* Result of one call; allocated by the library, freed by sim_result_free(). */
+typedef struct sim_result {
+  sim_race* races;            /* n_races entries, host memory */
+  uint64_t n_races;
+  sim_trace_summary* traces;  /* n_traces summaries, host memory */
+  uint32_t n_traces;
+} sim_result;
+
+typedef struct sim_config {
+  uint64_t reserve_records; /* pre-size device buffers for this many records (0: grow on demand) */
+  uint32_t flags;           /* SIM_CFG_* */
+  uint32_t reserved;
+} sim_config;
+
+enum { SIM_CFG_PROFILE = 1 }; /* record per-stage HIP events (see sim_stage_times) */
+
+typedef struct sim_ctx sim_ctx;
+
+/* error codes */
+enum {
+  SIM_OK = 0,
+  SIM_EINVAL = -1,  /* null pointer, offsets not CSR, threads_per_block = 0, too many records */
+  SIM_ERECORD = -2, /* action > 2 or space > 1; sim_last_error() names the first bad index */
+  SIM_ENOMEM = -3,  /* device or host allocation failed */
+  SIM_EDEVICE = -4, /* HIP runtime error (text in sim_last_error()) */
+  SIM_ERANGE = -6   /* a trace's sort key would need more than 64 bits */
+};
+
+/* --------------------------------------------------------------- context */
+
+/* Create a context on HIP device `hip_device` (must be gfx950).
+ * cfg may be NULL.  Returns SIM_EDEVICE when the device is missing or not
+ * gfx950.                                                                  */
+int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg);
+
+/* Release a context and its device buffers.  NULL is ignored. */
+void sim_destroy(sim_ctx* ctx);
+
+/* Text of the last error on this context ("" if none).  Valid until the
+ * next call on the context.                                                */
+const char* sim_last_error(const sim_ctx* ctx);
+
+/* ----------------------------------------------------------------- checks */
+
+/* Check n_traces traces whose records sit in host memory.
+ *   records           : offsets[n_traces] records, host memory, caller-owned
+ *   offsets           : n_traces + 1 CSR offsets, host memory; offsets[0] = 0,
+ *                       non-decreasing; trace i is records[offsets[i] ..
+ *                       offsets[i+1])
+ *   threads_per_block : n_traces values >= 1, host memory
+ *   out               : receives the result (caller frees it)
+ * n_traces = 0 and empty traces are valid.  Inputs are read only and must
+ * stay valid until the call returns.  The records are copied to the device
+ * on the context's stream.                                                 */
+int sim_check_traces(sim_ctx* ctx, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
+                     const uint32_t* threads_per_block, sim_result** out);
+
+/* Same check for records already in device memory of the context's GPU
+ * (e.g. a torch tensor's storage).  offsets and threads_per_block are host
+ * arrays as above (they size the launch grids).  stream is a hipStream_t
+ * (NULL: the default stream); the library orders all of its work on it and
+ * returns after the stream has finished the call's work.  The stream is not
+ * owned by the library.                                                    */
+int sim_check_traces_device(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offsets,
+                            uint32_t n_traces, const uint32_t* threads_per_block, void* stream,
+                            sim_result** out);
+
+/* Free a result.  NULL is ignored. */
+void sim_result_free(sim_result* r);
+
+/* -------------------------------------------------------------- profiling */
+
+/* Per-stage device time of the last call on a context created with
+ * SIM_CFG_PROFILE, measured with HIP events on the stream the kernels ran
+ * on.  Stages are listed by sim_stage_name(); launches counts the kernel
+ * launches that did work in each stage.  Returns the number of stages
+ * written (at most cap).                                                   */
+typedef struct sim_stage_time {
+  double ms;
+  uint32_t launches;
+  uint32_t reserved;
+} sim_stage_time;
+
+int sim_stage_times(const sim_ctx* ctx, sim_stage_time* out, int cap);
+const char* sim_stage_name(int stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIMCHECK_H */

@@ -1,0 +1,225 @@
+"""Python binding of the MI355X data-race check (libsimcheck.so).
+
+Argument marshalling only: every step of the check runs in the HIP kernels
+behind the C ABI of include/simcheck.h.  The binding keeps the C names
+(sim_create, sim_check_traces, sim_check_traces_device, ...) and adds a small
+Context wrapper.  Loading fails loudly when the library is not built; there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from ._build import LIB, build_library
+
+RECORD_DTYPE = np.dtype(
+    [("unit", "<u8"), ("tid", "<u4"), ("epoch", "<u2"), ("action", "u1"), ("space", "u1")]
+)
+RACE_DTYPE = np.dtype(
+    [
+        ("trace", "<u4"), ("space", "u1"), ("kinds", "u1"), ("reserved16", "<u2"), ("block", "<u4"),
+        ("reserved32", "<u4"), ("unit", "<u8"), ("pairs_ww", "<u8"), ("pairs_rw", "<u8"),
+        ("pairs_aw", "<u8"), ("pairs_ar", "<u8"), ("pairs_xblock", "<u8"),
+    ]
+)
+SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pairs", "<u8")])
+
+SIM_OK, SIM_EINVAL, SIM_ERECORD, SIM_ENOMEM, SIM_EDEVICE, SIM_ERANGE = 0, -1, -2, -3, -4, -6
+SIM_CFG_PROFILE = 1
+STAGES = ["init", "stats", "layout", "keygen", "digits", "sort_pass", "scan"]
+
+# Symbols declared in include/simcheck.h.
+EXPORTS = [
+    "sim_create", "sim_destroy", "sim_last_error", "sim_check_traces", "sim_check_traces_device",
+    "sim_result_free", "sim_stage_times", "sim_stage_name",
+]
+
+
+class SimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"simcheck error {code}: {msg}")
+        self.code = code
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [
+        ("races", ctypes.c_void_p),
+        ("n_races", ctypes.c_uint64),
+        ("traces", ctypes.c_void_p),
+        ("n_traces", ctypes.c_uint32),
+    ]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("reserve_records", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _StageTime(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return LIB
+
+
+def load() -> ctypes.CDLL:
+    """Load libsimcheck.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        raise ImportError(f"{LIB} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    lib.sim_create.restype = ctypes.c_int
+    lib.sim_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+    lib.sim_destroy.restype = None
+    lib.sim_destroy.argtypes = [P]
+    lib.sim_last_error.restype = ctypes.c_char_p
+    lib.sim_last_error.argtypes = [P]
+    lib.sim_check_traces.restype = ctypes.c_int
+    lib.sim_check_traces.argtypes = [P, P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.POINTER(_Result))]
+    lib.sim_check_traces_device.restype = ctypes.c_int
+    lib.sim_check_traces_device.argtypes = [P, P, P, ctypes.c_uint32, P, P, ctypes.POINTER(ctypes.POINTER(_Result))]
+    lib.sim_result_free.restype = None
+    lib.sim_result_free.argtypes = [ctypes.POINTER(_Result)]
+    lib.sim_stage_times.restype = ctypes.c_int
+    lib.sim_stage_times.argtypes = [P, ctypes.POINTER(_StageTime), ctypes.c_int]
+    lib.sim_stage_name.restype = ctypes.c_char_p
+    lib.sim_stage_name.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+# ------------------------------------------------------------ C-named API
+
+def sim_create(hip_device: int = 0, profile: bool = False, reserve_records: int = 0) -> ctypes.c_void_p:
+    lib = load()
+    ctx = ctypes.c_void_p()
+    cfg = _Config(reserve_records, SIM_CFG_PROFILE if profile else 0, 0)
+    rc = lib.sim_create(ctypes.byref(ctx), hip_device, ctypes.byref(cfg))
+    if rc != SIM_OK:
+        raise SimError(rc, f"sim_create failed on device {hip_device} (needs a gfx950 GPU)")
+    return ctx
+
+
+def sim_destroy(ctx) -> None:
+    load().sim_destroy(ctx)
+
+
+def sim_last_error(ctx) -> str:
+    return (load().sim_last_error(ctx) or b"").decode()
+
+
+def _tables(offsets, tpb, n_records):
+    if offsets is None:
+        offsets = np.array([0, n_records], dtype=np.uint64)
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    n_traces = len(offsets) - 1
+    tpb = np.asarray(tpb, dtype=np.uint32)
+    if tpb.ndim == 0:
+        tpb = np.full(n_traces, int(tpb), dtype=np.uint32)
+    tpb = np.ascontiguousarray(tpb)
+    if len(tpb) != n_traces:
+        raise ValueError("threads_per_block needs one value per trace")
+    return offsets, n_traces, tpb
+
+
+def _take_result(res_p):
+    lib = load()
+    r = res_p.contents
+    races = np.zeros(r.n_races, dtype=RACE_DTYPE)
+    if r.n_races:
+        ctypes.memmove(races.ctypes.data, r.races, r.n_races * RACE_DTYPE.itemsize)
+    summ = np.zeros(r.n_traces, dtype=SUMMARY_DTYPE)
+    if r.n_traces:
+        ctypes.memmove(summ.ctypes.data, r.traces, r.n_traces * SUMMARY_DTYPE.itemsize)
+    lib.sim_result_free(res_p)
+    return races, summ
+
+
+def sim_check_traces(ctx, records: np.ndarray, offsets=None, threads_per_block=1):
+    """Check traces whose records are in host memory (numpy RECORD_DTYPE)."""
+    lib = load()
+    records = np.ascontiguousarray(records)
+    if records.dtype.itemsize != 16:
+        raise TypeError("records must be 16-byte sim_record entries")
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, len(records))
+    out = ctypes.POINTER(_Result)()
+    rc = lib.sim_check_traces(ctx, records.ctypes.data if len(records) else None, offsets.ctypes.data, n_traces,
+                              tpb.ctypes.data, ctypes.byref(out))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return _take_result(out)
+
+
+def sim_check_traces_device(ctx, d_records_ptr: int, n_records: int, offsets=None, threads_per_block=1, stream=None):
+    """Check traces whose records are in device memory at d_records_ptr
+    (e.g. tensor.data_ptr()); stream is a hipStream_t handle (int) or None."""
+    lib = load()
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, n_records)
+    if int(offsets[-1]) != n_records:
+        raise ValueError("offsets[-1] must equal the number of device records")
+    out = ctypes.POINTER(_Result)()
+    rc = lib.sim_check_traces_device(ctx, ctypes.c_void_p(d_records_ptr) if n_records else None, offsets.ctypes.data,
+                                     n_traces, tpb.ctypes.data, ctypes.c_void_p(stream or 0), ctypes.byref(out))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return _take_result(out)
+
+
+def sim_stage_times(ctx):
+    lib = load()
+    arr = (_StageTime * 16)()
+    n = lib.sim_stage_times(ctx, arr, 16)
+    return {lib.sim_stage_name(i).decode(): (arr[i].ms, arr[i].launches) for i in range(n)}
+
+
+# ----------------------------------------------------------- convenience
+
+class Context:
+    """One library context on one GPU."""
+
+    def __init__(self, device: int = 0, profile: bool = False, reserve_records: int = 0):
+        self._ctx = sim_create(device, profile=profile, reserve_records=reserve_records)
+
+    def close(self):
+        if self._ctx:
+            sim_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check_traces(self, records, offsets=None, threads_per_block=1):
+        return sim_check_traces(self._ctx, records, offsets, threads_per_block)
+
+    def check_traces_device(self, tensor, offsets=None, threads_per_block=1, stream=None):
+        """tensor: a device tensor whose storage holds sim_record entries
+        (16 bytes each, e.g. uint8 [n, 16] or int64 [n, 2])."""
+        nbytes = tensor.numel() * tensor.element_size()
+        if nbytes % 16:
+            raise ValueError("tensor size is not a multiple of 16 bytes")
+        if not tensor.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream(tensor.device).cuda_stream
+        return sim_check_traces_device(self._ctx, tensor.data_ptr(), nbytes // 16, offsets, threads_per_block,
+                                       stream)
+
+    def stage_times(self):
+        return sim_stage_times(self._ctx)
+
+    def last_error(self) -> str:
+        return sim_last_error(self._ctx)

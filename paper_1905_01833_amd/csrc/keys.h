@@ -1,0 +1,136 @@
+// keys.h -- per-trace sort-key layout for the race check.
+//
+// Every record of a trace is packed into one 64-bit key whose order groups
+// the records first by location (the paper's Memory Unit, Sec. 4.2.1: one
+// unit of global memory, or one unit of one block's shared memory, Alg. 3),
+// then by block, by epoch (visit order) and by thread, with the action in
+// the two lowest bits:
+//
+//   global : [0 | unit - gmin : ug | block : bb | epoch : eb | local tid : tb | action : 2]
+//   shared : [1 | block : bb | unit - smin : us | epoch : eb | local tid : tb | action : 2]
+//
+// The fields between the space bit and the epoch field span wl = max(ug + bb,
+// bb + us) bits in both layouts.  Field widths come from per-trace minima
+// and maxima, so a key is lossless and the record can be read back from it.
+// Within a location the key orders records by (block, epoch, thread), which
+// makes every group used by the race count contiguous after sorting.
+//
+// Functions are usable from host and device code.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define SC_HD __host__ __device__ __forceinline__
+#else
+#define SC_HD static inline
+#endif
+
+namespace sc {
+
+// Per-trace statistics, reduced over all records of a trace.
+struct TraceStats {
+  uint64_t gmin, gmax;  // unit range of global records (gmin > gmax: none)
+  uint64_t smin, smax;  // unit range of shared records
+  uint64_t bad_index;   // smallest trace-relative index of an invalid record (~0: none)
+  uint32_t max_tid;
+  uint32_t max_epoch;
+};
+
+// Key layout of one trace.
+struct TraceLayout {
+  uint64_t gmin, smin;
+  uint32_t tb, eb, bb, ug, us, wl;
+  uint32_t key_bits;   // total bits including the action bits
+  uint32_t npasses;    // 8-bit radix passes over bits [2, key_bits)
+  uint32_t shift_e;    // epoch field
+  uint32_t shift_b;    // block field of global keys; unit field of shared keys
+  uint32_t shift_ug;   // unit field of global keys
+  uint32_t shift_bs;   // block field of shared keys
+  uint32_t shift_space;
+  uint32_t error;      // LAYOUT_ERR_* bits
+};
+
+// LAYOUT_ERR_* are per-trace layout errors; ERR_INTERNAL_* are raised by the
+// kernels' own checks (a scatter outside its trace, a look-back wait that
+// did not end) and reported as device errors.
+enum : uint32_t { LAYOUT_ERR_WIDE = 1, LAYOUT_ERR_RECORD = 2, ERR_INTERNAL_BOUNDS = 4, ERR_INTERNAL_SPIN = 8 };
+
+constexpr uint32_t RADIX_BITS = 8;
+constexpr uint32_t RADIX = 1u << RADIX_BITS;
+constexpr uint32_t MAX_PASSES = 8;  // ceil(62 / 8)
+
+SC_HD uint32_t bits32(uint32_t x) { return x ? 32u - (uint32_t)__builtin_clz(x) : 0u; }
+SC_HD uint32_t bits64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 0u; }
+SC_HD uint64_t lowmask(uint32_t b) { return b >= 64 ? ~0ull : ((1ull << b) - 1); }
+
+SC_HD void stats_init(TraceStats& s) {
+  s.gmin = ~0ull; s.gmax = 0; s.smin = ~0ull; s.smax = 0;
+  s.bad_index = ~0ull; s.max_tid = 0; s.max_epoch = 0;
+}
+
+SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
+  TraceLayout L;
+  const bool has_g = s.gmin <= s.gmax;
+  const bool has_s = s.smin <= s.smax;
+  L.gmin = has_g ? s.gmin : 0;
+  L.smin = has_s ? s.smin : 0;
+  L.tb = bits32(tpb - 1);
+  L.eb = bits32(s.max_epoch);
+  L.bb = bits32(s.max_tid / tpb);
+  L.ug = has_g ? bits64(s.gmax - s.gmin) : 0;
+  L.us = has_s ? bits64(s.smax - s.smin) : 0;
+  const uint32_t wg = L.ug + L.bb, ws = L.bb + L.us;
+  L.wl = wg > ws ? wg : ws;
+  L.key_bits = 3 + L.tb + L.eb + L.wl;
+  L.shift_e = 2 + L.tb;
+  L.shift_b = L.shift_e + L.eb;
+  L.shift_ug = L.shift_b + L.bb;
+  L.shift_bs = L.shift_b + L.us;
+  L.shift_space = 2 + L.tb + L.eb + L.wl;
+  L.error = 0;
+  if (L.key_bits > 64) L.error |= LAYOUT_ERR_WIDE;
+  if (s.bad_index != ~0ull) L.error |= LAYOUT_ERR_RECORD;
+  L.npasses = L.error ? 0 : (L.key_bits - 2 + RADIX_BITS - 1) / RADIX_BITS;
+  return L;
+}
+
+// Key of one record (fields must be valid and within the trace's ranges).
+SC_HD uint64_t make_key(const TraceLayout& L, uint64_t unit, uint32_t tid, uint32_t epoch, uint32_t action,
+                        uint32_t space, uint32_t tpb) {
+  const uint32_t blk = tid / tpb;
+  const uint32_t loc = tid - blk * tpb;
+  const uint64_t low = ((uint64_t)epoch << L.shift_e) | ((uint64_t)loc << 2) | (uint64_t)(action & 3u);
+  if (space == 0) return ((unit - L.gmin) << L.shift_ug) | ((uint64_t)blk << L.shift_b) | low;
+  return (1ull << L.shift_space) | ((uint64_t)blk << L.shift_bs) | ((unit - L.smin) << L.shift_b) | low;
+}
+
+// Nesting level at which key x starts a new group relative to the previous
+// key p of the same trace: 0 new location, 1 new block (global only),
+// 2 new epoch, 3 new thread, 4 same (location, block, epoch, thread).
+SC_HD uint32_t head_level(const TraceLayout& L, uint64_t p, uint64_t x) {
+  const uint64_t d = (x ^ p) & ~3ull;
+  if (d == 0) return 4;
+  const uint32_t hb = 63u - (uint32_t)__builtin_clzll(d);  // highest differing bit
+  const bool shared = ((x >> L.shift_space) & 1ull) != 0;
+  if (shared) {
+    if (hb >= L.shift_b) return 0;
+    return hb >= L.shift_e ? 2 : 3;
+  }
+  if (hb >= L.shift_ug) return 0;
+  if (hb >= L.shift_b) return 1;
+  return hb >= L.shift_e ? 2 : 3;
+}
+
+// Location of a key: space, owning block (shared) or 0xFFFFFFFF, unit.
+SC_HD void key_location(const TraceLayout& L, uint64_t k, uint32_t& space, uint32_t& block, uint64_t& unit) {
+  space = (uint32_t)((k >> L.shift_space) & 1ull);
+  if (space == 0) {
+    block = 0xFFFFFFFFu;
+    unit = ((k >> L.shift_ug) & lowmask(L.ug)) + L.gmin;
+  } else {
+    block = (uint32_t)((k >> L.shift_bs) & lowmask(L.bb));
+    unit = ((k >> L.shift_b) & lowmask(L.us)) + L.smin;
+  }
+}
+
+}  // namespace sc

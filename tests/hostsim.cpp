@@ -1,0 +1,142 @@
+// hostsim.cpp -- CPU model of the GPU path's tiled race count (test only).
+//
+// Compiles the product's key-layout and monoid headers for the host and runs
+// the same tile decomposition as the GPU kernels: keys are built and sorted
+// per trace, cut into tiles, each tile is summarised from its own elements
+// (carry-free), tiles are chained with combine() as the look-back does, and a
+// location is reported by the tile that holds its last element.  Tiles are
+// additionally split into "thread" chunks whose summaries are combined, to
+// exercise associativity at a second level.  The tests compare the output
+// with the oracle; nothing here is used by the product path.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../paper_1905_01833_amd/csrc/segstate.h"
+
+struct rec {
+  uint64_t unit;
+  uint32_t tid;
+  uint16_t epoch;
+  uint8_t action;
+  uint8_t space;
+};
+struct race {
+  uint32_t trace;
+  uint8_t space, kinds;
+  uint16_t r16;
+  uint32_t block, r32;
+  uint64_t unit, ww, rw, aw, ar, xb;
+};
+
+using namespace sc;
+
+static void emit(std::vector<race>& out, uint32_t tr, const TraceLayout& L, uint64_t key, const uint64_t s[5]) {
+  if (s[K_WW] + s[K_RW] + s[K_AW] + s[K_AR] == 0) return;
+  race e;
+  std::memset(&e, 0, sizeof e);
+  e.trace = tr;
+  uint32_t sp, blk;
+  uint64_t unit;
+  key_location(L, key, sp, blk, unit);
+  e.space = (uint8_t)sp;
+  e.block = blk;
+  e.unit = unit;
+  e.ww = s[K_WW]; e.rw = s[K_RW]; e.aw = s[K_AW]; e.ar = s[K_AR]; e.xb = s[K_XB];
+  e.kinds = (uint8_t)((e.ww ? 1 : 0) | (e.rw ? 2 : 0) | (e.aw ? 4 : 0) | (e.ar ? 8 : 0) | (e.xb ? 16 : 0));
+  out.push_back(e);
+}
+
+extern "C" int64_t hs_check(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                            uint32_t tile, uint32_t chunk, race* out, uint64_t cap, uint32_t* max_passes) {
+  std::vector<race> res;
+  uint32_t mp = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t lo = off[tr], n = off[tr + 1] - off[tr];
+    if (n == 0) continue;
+    TraceStats S;
+    stats_init(S);
+    for (uint64_t i = 0; i < n; i++) {
+      const rec& r = recs[lo + i];
+      if (r.action > 2 || r.space > 1) { S.bad_index = std::min<uint64_t>(S.bad_index, i); continue; }
+      if (r.space == 0) { S.gmin = std::min(S.gmin, r.unit); S.gmax = std::max(S.gmax, r.unit); }
+      else { S.smin = std::min(S.smin, r.unit); S.smax = std::max(S.smax, r.unit); }
+      S.max_tid = std::max(S.max_tid, r.tid);
+      S.max_epoch = std::max<uint32_t>(S.max_epoch, r.epoch);
+    }
+    const TraceLayout L = make_layout(S, tpb[tr]);
+    if (L.error) return -(int64_t)L.error;
+    mp = std::max(mp, L.npasses);
+    std::vector<uint64_t> k(n);
+    for (uint64_t i = 0; i < n; i++) {
+      const rec& r = recs[lo + i];
+      k[i] = make_key(L, r.unit, r.tid, r.epoch, r.action, r.space, tpb[tr]);
+    }
+    std::sort(k.begin(), k.end());
+    State carry = identity();  // inclusive summary of all earlier tiles
+    for (uint64_t t0 = 0; t0 < n; t0 += tile) {
+      const uint64_t t1 = std::min<uint64_t>(n, t0 + tile);
+      std::vector<uint32_t> lv(t1 - t0);
+      for (uint64_t i = t0; i < t1; i++) lv[i - t0] = (i == 0) ? 0 : head_level(L, k[i - 1], k[i]);
+      // tile summary from chunk summaries (carry-free)
+      State agg = identity();
+      for (uint64_t c0 = t0; c0 < t1; c0 += chunk) {
+        State cs = identity();
+        for (uint64_t i = c0; i < std::min<uint64_t>(t1, c0 + chunk); i++) push(cs, lv[i - t0], action_class(k[i]));
+        agg = combine(agg, cs);
+      }
+      uint64_t open[5];
+      open_sums(carry, agg, open);
+      // in-tile walk, carry-free, reporting each location at its last element
+      State run = identity();
+      bool seen_head = false;
+      for (uint64_t i = t0; i < t1; i++) {
+        const uint32_t l = lv[i - t0];
+        push(run, l, action_class(k[i]));
+        if (l == 0) seen_head = true;
+        const bool last = (i + 1 == n) || head_level(L, k[i], k[i + 1]) == 0;
+        if (!last) continue;
+        if (!seen_head) emit(res, tr, L, k[i], open);
+        else emit(res, tr, L, k[i], run.trailsum);
+      }
+      carry = combine(carry, agg);
+    }
+  }
+  if (max_passes) *max_passes = mp;
+  if (res.size() > cap) return (int64_t)res.size();
+  std::memcpy(out, res.data(), res.size() * sizeof(race));
+  return (int64_t)res.size();
+}
+
+// Associativity check on random element sequences: fold(push) equals the
+// combine() of arbitrary splits.  Returns 0 when all trials agree.
+extern "C" int hs_assoc(uint64_t seed, int trials) {
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+  auto rnd = [&]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
+  for (int t = 0; t < trials; t++) {
+    const int n = 1 + (int)(rnd() % 40);
+    std::vector<uint32_t> lv(n), cl(n);
+    for (int i = 0; i < n; i++) { lv[i] = (uint32_t)(rnd() % 5); cl[i] = (uint32_t)(rnd() % 3); }
+    State whole = identity();
+    for (int i = 0; i < n; i++) push(whole, lv[i], cl[i]);
+    // three-way split combined as (A B) C and A (B C)
+    const int s1 = (int)(rnd() % (n + 1)), s2 = s1 + (int)(rnd() % (n - s1 + 1));
+    State A = identity(), B = identity(), C = identity();
+    for (int i = 0; i < s1; i++) push(A, lv[i], cl[i]);
+    for (int i = s1; i < s2; i++) push(B, lv[i], cl[i]);
+    for (int i = s2; i < n; i++) push(C, lv[i], cl[i]);
+    const State l = combine(combine(A, B), C), r = combine(A, combine(B, C));
+    for (const State* s : {&l, &r}) {
+      if (s->m != whole.m) return 1;
+      for (int k = 0; k < 5; k++) {
+        if (s->trailsum[k] != whole.trailsum[k] && whole.m == 0) return 2;
+        if (s->leadsum[k] != whole.leadsum[k]) return 3;
+      }
+      for (int l2 = 0; l2 < 4; l2++)
+        for (int q = 0; q < 3; q++)
+          if (s->trail[l2][q] != whole.trail[l2][q] || s->lead[l2][q] != whole.lead[l2][q]) return 4;
+    }
+  }
+  return 0;
+}

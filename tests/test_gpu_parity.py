@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit-exact.
+
+Every case prints its name before it touches the GPU.  Inputs are seeded
+and synthetic; expected values come from oracle/ only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tracegen
+from golden_io import trace_fixture, truth_table
+from tracegen import RECORD_DTYPE
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1905_01833_amd as pkg
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def run_device(ctx, recs, offsets, tpb):
+    dev = torch.from_numpy(np.ascontiguousarray(recs).view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    races, summ = ctx.check_traces_device(dev, offsets, tpb)
+    torch.cuda.synchronize()
+    return races, summ
+
+
+def assert_parity(ctx, recs, offsets=None, tpb=256, host=False, name=""):
+    if offsets is None:
+        offsets = np.array([0, len(recs)], dtype=np.uint64)
+    offsets = np.asarray(offsets, dtype=np.uint64)
+    tpb = np.asarray(tpb, dtype=np.uint32)
+    if tpb.ndim == 0:
+        tpb = np.full(len(offsets) - 1, int(tpb), dtype=np.uint32)
+    say(f"{name}: {len(recs)} records, {len(offsets) - 1} traces")
+    want, wsum = oracle.closed_form(recs, offsets, tpb)
+    if host:
+        got, gsum = ctx.check_traces(recs, offsets, tpb)
+    else:
+        got, gsum = run_device(ctx, recs, offsets, tpb)
+    assert len(got) == len(want), (name, len(got), len(want))
+    assert got.tobytes() == want.tobytes(), name
+    assert gsum.tobytes() == wsum.tobytes(), name
+    return got
+
+
+def batch_of(traces):
+    recs = np.concatenate(traces) if traces else np.zeros(0, dtype=RECORD_DTYPE)
+    off = np.zeros(len(traces) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(t) for t in traces])
+    return recs, off
+
+
+# ------------------------------------------------------------- hand cases
+
+def test_c0_tree_reduction(ctx):
+    got = assert_parity(ctx, tracegen.c0(), tpb=256, name="c0")
+    assert len(got) == 32 and list(got["unit"]) == list(range(32, 64))
+
+
+def test_tree_family_batched(ctx):
+    traces = [tracegen.tree_reduction(k) for k in range(-1, 9)]
+    recs, off = batch_of(traces)
+    got = assert_parity(ctx, recs, off, 256, name="tree family")
+    per_trace = np.bincount(got["trace"], minlength=10)
+    assert list(per_trace) == [0] + [128 >> k for k in range(8)] + [0]
+
+
+def test_truth_table_batched(ctx):
+    rows = truth_table()
+    recs, off = batch_of([r for _, r, _ in rows])
+    got = assert_parity(ctx, recs, off, 2, name="truth table")
+    for i, (line, _, exp) in enumerate(rows):
+        assert oracle.races_to_dict(got[got["trace"] == i], trace=i) == exp, line
+
+
+@pytest.mark.parametrize("name", ["fig6_unit.txt", "fig6_unit_write.txt", "kaldi_copy.txt"])
+def test_fixtures(ctx, name):
+    recs, tpb, exp = trace_fixture(name)
+    got = assert_parity(ctx, recs, tpb=tpb, name=name)
+    assert oracle.races_to_dict(got) == exp
+
+
+# ------------------------------------------------------------ random cases
+
+def test_random_tiny_batch(ctx):
+    rng = np.random.default_rng(1)
+    traces, tpbs = [], []
+    for _ in range(400):
+        tpb = int(rng.integers(1, 5))
+        traces.append(tracegen.random_small(rng, int(rng.integers(0, 65)), units=int(rng.integers(1, 5)),
+                                            blocks=int(rng.integers(1, 4)), tpb=tpb, epochs=int(rng.integers(1, 4))))
+        tpbs.append(tpb)
+    recs, off = batch_of(traces)
+    assert_parity(ctx, recs, off, tpbs, name="400 tiny traces")
+    # the pairwise definition itself on a sample of them
+    got, _ = ctx.check_traces(recs, off, tpbs)
+    for i in range(0, 400, 37):
+        bf, _ = oracle.brute_force(traces[i], tpb=tpbs[i])
+        sub = got[got["trace"] == i].copy()
+        sub["trace"] = 0
+        assert sub.tobytes() == bf.tobytes()
+
+
+@pytest.mark.parametrize("n", [4096 - 1, 4096, 4096 + 1, 3 * 4096 + 123, 10 * 4096 + 4095])
+def test_tile_boundaries(ctx, n):
+    rng = np.random.default_rng(n)
+    r = tracegen.random_small(rng, n, units=50, blocks=5, tpb=7, epochs=4)
+    assert_parity(ctx, r, tpb=7, name=f"ragged n={n}")
+
+
+def test_host_entry_point(ctx):
+    rng = np.random.default_rng(2)
+    r = tracegen.random_small(rng, 20000, units=300, blocks=4, tpb=16, epochs=3)
+    assert_parity(ctx, r, tpb=16, host=True, name="host records")
+
+
+def test_mega_location(ctx):
+    rng = np.random.default_rng(3)
+    m = tracegen.random_small(rng, 60000, units=1, blocks=9, tpb=128, epochs=5)
+    m["space"] = 0
+    assert_parity(ctx, m, tpb=128, name="one global unit, 60k records")
+    m["space"] = 1
+    assert_parity(ctx, m, tpb=128, name="one shared unit per block, 60k records")
+
+
+def test_uniform_groups(ctx):
+    r = np.zeros(50000, dtype=RECORD_DTYPE)
+    r["unit"] = 77
+    r["tid"] = 5
+    r["action"] = np.arange(50000) % 3
+    got = assert_parity(ctx, r, tpb=32, name="one thread, one unit")
+    assert len(got) == 0
+    r["tid"][::2] = 6
+    assert_parity(ctx, r, tpb=32, name="two threads, one unit")
+
+
+def test_many_racing_locations_grow_output(ctx):
+    # 150k locations with one write/write pair each: more than the initial
+    # output buffer, exercising the rescan path
+    n = 150000
+    r = np.zeros(2 * n, dtype=RECORD_DTYPE)
+    r["unit"] = np.repeat(np.arange(n, dtype=np.uint64) * 3, 2)
+    r["tid"] = np.tile([0, 1], n)
+    r["action"] = 1
+    got = assert_parity(ctx, r, tpb=2, name="150k racing locations")
+    assert len(got) == n
+
+
+def test_batched_mixed_sizes(ctx):
+    shapes = tracegen.c3_shapes(48, log2_max=16)
+    recs, off, tpb, inj = tracegen.batch(shapes, inject_rate=5e-4)
+    got = assert_parity(ctx, recs, off, tpb, name="48 generated traces")
+    for i, log in inj:
+        for e in log:
+            blk = int(e["block"])
+            hit = (got["trace"] == i) & (got["space"] == e["space"]) & (got["unit"] == e["unit"])
+            if int(e["space"]) == 1:
+                hit &= got["block"] == blk
+            assert hit.any()
+
+
+def test_empty_and_mixed_empty(ctx):
+    r = np.zeros(0, dtype=RECORD_DTYPE)
+    races, summ = ctx.check_traces(r, np.array([0], dtype=np.uint64), np.zeros(0, dtype=np.uint32))
+    assert len(races) == 0 and len(summ) == 0
+    traces = [np.zeros(0, dtype=RECORD_DTYPE), tracegen.c0(), np.zeros(0, dtype=RECORD_DTYPE), tracegen.c0()[:5]]
+    recs, off = batch_of(traces)
+    assert_parity(ctx, recs, off, [3, 256, 9, 256], name="empty traces mixed in")
+
+
+# ------------------------------------------------------------ invariants
+
+def test_permutation_invariance(ctx):
+    r, _ = tracegen.c1(n_blocks=32, inject_rate=5e-4)
+    a = assert_parity(ctx, r, tpb=256, name="c1 x32 blocks")
+    perm = np.random.default_rng(4).permutation(len(r))
+    b, _ = run_device(ctx, r[perm], None, 256)
+    assert a.tobytes() == b.tobytes()
+
+
+def test_results_identical_across_repeats_and_contexts(ctx):
+    import paper_1905_01833_amd as pkg
+
+    r, _ = tracegen.c1(n_blocks=16, inject_rate=1e-3, seed=77)
+    first, _ = run_device(ctx, r, None, 256)
+    for _ in range(3):
+        again, _ = run_device(ctx, r, None, 256)
+        assert again.tobytes() == first.tobytes()
+    other = pkg.Context(0)
+    try:
+        got, _ = other.check_traces(r, None, 256)
+        assert got.tobytes() == first.tobytes()
+    finally:
+        other.close()
+
+
+# ------------------------------------------------------------ error paths
+
+def test_error_paths_leave_context_usable(ctx):
+    import paper_1905_01833_amd as pkg
+
+    r = tracegen.c0().copy()
+    r["action"][500] = 7
+    say("invalid action")
+    with pytest.raises(pkg.SimError) as ei:
+        ctx.check_traces(r, None, 256)
+    assert ei.value.code == pkg.SIM_ERECORD and "500" in str(ei.value)
+    r["action"][500] = 0
+    r["space"][12] = 3
+    with pytest.raises(pkg.SimError) as ei:
+        run_device(ctx, r, None, 256)
+    assert ei.value.code == pkg.SIM_ERECORD and "12" in str(ei.value)
+    say("bad offsets / tpb")
+    good = tracegen.c0()
+    with pytest.raises(pkg.SimError) as ei:
+        ctx.check_traces(good, np.array([0, 700, 600, 1279], dtype=np.uint64), [256, 256, 256])
+    assert ei.value.code == pkg.SIM_EINVAL
+    with pytest.raises(pkg.SimError) as ei:
+        ctx.check_traces(good, None, 0)
+    assert ei.value.code == pkg.SIM_EINVAL
+    say("key wider than 64 bits")
+    w = np.zeros(4, dtype=RECORD_DTYPE)
+    w["unit"] = [0, 1 << 62, 5, 5]
+    w["tid"] = [0, 1 << 20, 3, 1 << 21]
+    w["action"] = 1
+    with pytest.raises(pkg.SimError) as ei:
+        ctx.check_traces(w, None, 1024)
+    assert ei.value.code == pkg.SIM_ERANGE
+    assert_parity(ctx, good, tpb=256, name="after errors")
+
+
+# ---------------------------------------------------------- full sizes
+
+def test_c1_full_size(ctx):
+    """The benchmark workload at full size: 1024 blocks x 256 threads,
+    2^24 records, injection rate 1e-4; complete comparison."""
+    r, inj = tracegen.c1()
+    assert len(r) == 1 << 24
+    got = assert_parity(ctx, r, tpb=256, name="c1 full")
+    keys = set(zip(got["space"].tolist(), got["block"].tolist(), got["unit"].tolist()))
+    for e in inj:
+        blk = int(e["block"]) if int(e["space"]) == 1 else 0xFFFFFFFF
+        assert (int(e["space"]), blk, int(e["unit"])) in keys

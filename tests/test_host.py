@@ -1,0 +1,104 @@
+"""CPU tests of the product's host-side logic and library boundary (no GPU).
+
+* The host model (tests/hostsim.cpp) compiles the product's key-layout and
+  pair-count monoid headers for the CPU and runs the GPU path's tile
+  decomposition; it must reproduce the oracle exactly.
+* libsimcheck.so must load and export every function declared in
+  include/simcheck.h; without a GPU, sim_create must fail cleanly.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import tracegen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HOSTSIM = os.path.join(ROOT, "tests", "libhostsim.so")
+
+
+def _hostsim():
+    if not os.path.exists(HOSTSIM):
+        import subprocess
+        subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
+                        os.path.join(ROOT, "tests", "hostsim.cpp"), "-o", HOSTSIM], check=True)
+    lib = ctypes.CDLL(HOSTSIM)
+    lib.hs_check.restype = ctypes.c_int64
+    lib.hs_check.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                                     ctypes.c_uint64, ctypes.c_void_p]
+    lib.hs_assoc.restype = ctypes.c_int
+    lib.hs_assoc.argtypes = [ctypes.c_uint64, ctypes.c_int]
+    return lib
+
+
+def hs_check(recs, off, tpb, tile, chunk):
+    lib = _hostsim()
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.uint64))
+    tpb = np.ascontiguousarray(np.asarray(tpb, dtype=np.uint32))
+    out = np.zeros(len(recs) + 1, dtype=oracle.RACE_DTYPE)
+    mp = ctypes.c_uint32(0)
+    n = lib.hs_check(recs.ctypes.data, off.ctypes.data, len(off) - 1, tpb.ctypes.data, tile, chunk,
+                     out.ctypes.data, len(out), ctypes.byref(mp))
+    assert n >= 0, n
+    return out[:n], int(mp.value)
+
+
+def test_monoid_associative():
+    assert _hostsim().hs_assoc(12345, 50000) == 0
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_host_model_matches_oracle_small(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(0, 300))
+    tpb = int(rng.integers(1, 6))
+    r = tracegen.random_small(rng, n, units=int(rng.integers(1, 8)), blocks=int(rng.integers(1, 4)), tpb=tpb,
+                              epochs=int(rng.integers(1, 4)))
+    want, _ = oracle.closed_form(r, tpb=tpb)
+    for tile, chunk in [(1, 1), (2, 1), (5, 2), (17, 4), (4096, 16)]:
+        got, _ = hs_check(r, [0, n], [tpb], tile, chunk)
+        assert got.tobytes() == want.tobytes(), (tile, chunk)
+
+
+def test_host_model_generated_and_mega_location():
+    r, _ = tracegen.c1(n_blocks=8, inject_rate=2e-3)
+    want, _ = oracle.closed_form(r, tpb=256)
+    got, mp = hs_check(r, [0, len(r)], [256], 4096, 16)
+    assert got.tobytes() == want.tobytes() and len(want) > 0
+    assert mp >= 1
+    # one global unit hit by every record: a location spanning many tiles
+    rng = np.random.default_rng(9)
+    m = tracegen.random_small(rng, 30000, units=1, blocks=6, tpb=64, epochs=3)
+    m["space"] = 0
+    want, _ = oracle.closed_form(m, tpb=64)
+    for tile in (4096, 1000, 64):
+        got, _ = hs_check(m, [0, len(m)], [64], tile, 16)
+        assert got.tobytes() == want.tobytes()
+
+
+def test_header_exports_match_library():
+    import paper_1905_01833_amd as pkg
+
+    hdr = open(os.path.join(ROOT, "include", "simcheck.h")).read()
+    declared = set(re.findall(r"^(?:int|void|const char\*)\s+(sim_\w+)\(", hdr, re.M))
+    assert declared == set(pkg.EXPORTS)
+    lib = pkg.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_create_fails_cleanly_without_gpu():
+    import paper_1905_01833_amd as pkg
+
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(pkg.SimError) as ei:
+        pkg.Context(0)
+    assert ei.value.code == pkg.SIM_EDEVICE
