@@ -1,0 +1,202 @@
+"""Benchmark of the MI355X data-race check.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1]
+
+One step is one complete check of one batch of synthetic traces through the
+C ABI (sim_check_traces_device): key statistics, key generation, the radix
+passes, the pair count and the download of the racing-location list.  The
+records are generated on the host, copied to HBM once, and stay resident
+while K steps are timed between two device synchronisations.
+
+The library's profiling mode records HIP events around every kernel on the
+stream the kernels run on; the dominant kernel's average launch time over
+the timed steps gives the roofline figure.  The oracle (CPU, one thread) is
+timed on a bounded sample of the same workload and its output is compared
+with the GPU's, bit for bit.
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+METRIC = "access records checked/sec and achieved HBM GB/s (batched vs plain, bit-exact)"
+
+# Algorithmic bytes per record moved by each kernel (one launch):
+#   stats  reads the 16-byte record
+#   keygen reads the record and writes its 8-byte key
+#   sort   one radix pass reads and writes every 8-byte key
+#   scan   reads every 8-byte key once (tile scan; the crossing-location
+#          and output kernels touch per-tile data only)
+BYTES_PER_RECORD = {"stats": 16, "keygen": 24, "sort_pass": 16, "scan_tiles": 8}
+KERNEL_SYMBOL = {"stats": "k_stats", "keygen": "k_keygen", "sort_pass": "k_sort_pass", "scan_tiles": "k_scan_tiles"}
+
+
+def workload(name):
+    import tracegen
+
+    if name == "c1":
+        recs, inj = tracegen.c1()
+        desc = {"workload": "c1: plain single trace, 1024 blocks x 256 threads, 2^24 records, 75% reads, "
+                            "shared window 48 KiB/block, global reads Zipf(1.1) over 64 MiB, barrier every 16 "
+                            "accesses, injected races 1e-4",
+                "traces": 1, "records": int(len(recs)), "threads_per_block": 256}
+        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([256], dtype=np.uint32), desc
+    if name == "c0":
+        recs = tracegen.c0()
+        desc = {"workload": "c0: shared-memory tree reduction, 1 block x 256 threads, barrier before level 3 "
+                            "removed", "traces": 1, "records": int(len(recs)), "threads_per_block": 256}
+        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([256], dtype=np.uint32), desc
+    if name == "c2":
+        recs, inj = tracegen.c2()
+        desc = {"workload": "c2: plain large trace, 8192 blocks x 512 threads, 2^28 records, 5% atomics, global "
+                            "reads Zipf(1.1) over 1 GiB, injected races 1e-5",
+                "traces": 1, "records": int(len(recs)), "threads_per_block": 512}
+        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([512], dtype=np.uint32), desc
+    if name == "c3":
+        shapes = tracegen.c3_shapes(4096)
+        recs, off, tpb, _ = tracegen.batch(shapes, inject_rate=1e-4)
+        desc = {"workload": "c3: 4096 traces, sizes log-uniform 2^8..2^20 records, 1..256 blocks x 256 threads, "
+                            "c1 distributions", "traces": 4096, "records": int(len(recs)), "threads_per_block": 256}
+        return recs, off, tpb, desc
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(recs, offsets, tpb, budget_records):
+    """Oracle (group counts, one thread) on the first traces of the workload
+    up to budget_records records (whole traces only, at least one)."""
+    import oracle
+
+    n_tr = len(offsets) - 1
+    k = 1
+    while k < n_tr and int(offsets[k + 1]) <= budget_records:
+        k += 1
+    n = int(offsets[k])
+    t0 = time.perf_counter()
+    races, summ = oracle.closed_form(recs[:n], offsets[: k + 1], tpb[:k])
+    dt = time.perf_counter() - t0
+    return races, summ, n, k, dt
+
+
+def pmc_traffic(stage, n_records):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_SYMBOL[stage]}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    src = open(os.path.join(ROOT, "paper_1905_01833_amd", "csrc", "kernels.hip"), "rb").read()
+    if d.get("kernels_sha256") != hashlib.sha256(src).hexdigest() or d.get("records") != n_records:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3"])
+    ap.add_argument("--cpu-budget", type=int, default=1 << 24, help="records in the oracle's timed sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this check runs on one GPU; --gpus {args.gpus} is not supported "
+              "(traces shard across GPUs without exchange, but only the one-GPU path is built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1905_01833_amd as pkg
+
+    recs, offsets, tpb, desc = workload(args.workload)
+    n = int(len(recs))
+    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    torch.cuda.synchronize()
+    ctx = pkg.Context(0, profile=True)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    for _ in range(args.warmup):
+        ctx.check_traces_device(dev, offsets, tpb, stream=stream)
+    torch.cuda.synchronize()
+
+    stage_ms = {}
+    stage_launches = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        races, summ = ctx.check_traces_device(dev, offsets, tpb, stream=stream)
+        for name, (ms, launches) in ctx.stage_times().items():
+            stage_ms[name] = stage_ms.get(name, 0.0) + ms
+            stage_launches[name] = stage_launches.get(name, 0) + launches
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = n * args.steps / elapsed
+
+    # dominant kernel and its roofline
+    dom = max(BYTES_PER_RECORD, key=lambda s: stage_ms.get(s, 0.0))
+    avg_ms = stage_ms[dom] / max(1, stage_launches[dom])
+    alg_bytes = BYTES_PER_RECORD[dom] * n
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = pmc_traffic(dom, n)
+    roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic, "avg_launch_ms": round(avg_ms, 5),
+                "launches_per_step": stage_launches[dom] / args.steps,
+                "alg_bytes_per_launch": alg_bytes}
+    passes = stage_launches.get("sort_pass", 0) / args.steps
+    pipe_bytes = n * (16 + 24 + 16 * passes + 8)
+    stages = {k: round(v / args.steps, 4) for k, v in stage_ms.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "records/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded generator, shapes of the workload named in config)",
+        "config": desc,
+        "hbm_gbps_pipeline": round(pipe_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "radix_passes": passes,
+        "stage_ms_per_step": stages,
+        "racing_locations": int(len(races)),
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu:
+        want, wsum, n_cpu, k_cpu, dt = cpu_baseline(recs, offsets, tpb, args.cpu_budget)
+        if k_cpu == len(offsets) - 1:
+            parity = races.tobytes() == want.tobytes() and summ.tobytes() == wsum.tobytes()
+        else:
+            got, gsum = ctx.check_traces_device(dev[:n_cpu], offsets[: k_cpu + 1], tpb[:k_cpu], stream=stream)
+            parity = got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes()
+        out["cpu_baseline"] = {"value": n_cpu / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {k_cpu} trace(s) of the workload, {n_cpu} records, oracle group-count "
+                                         f"tier, {dt:.2f} s"}
+        out["parity"] = "bit-exact" if parity else "MISMATCH"
+        if not parity:
+            print(json.dumps(out))
+            sys.exit(1)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -2,19 +2,21 @@
 //
 // A context owns grow-only device buffers sized by the largest call seen so
 // far, a default-priority stream for the host-record entry point, pinned
-// host staging for the small per-call tables and the results, and the
-// launch-tag counter that keeps look-back status words of different
-// launches apart.  Every check runs as one ordered sequence of kernel
-// launches on one stream followed by a single synchronisation; there is no
-// CPU fallback.
+// host staging for the small per-call tables and results, and the launch
+// tag counter that keeps look-back status words of different launches
+// apart.  A check is one ordered sequence of kernel launches on one stream
+// and one synchronisation; there is no CPU fallback.  Rare conditions cost
+// a second round on the device: a trace needing more radix passes than the
+// previous call did, a tile with more racing locations than its staging
+// slice holds, or more racing locations than the output buffer holds.
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <string>
-#include <vector>
 
 #include "../../include/simcheck.h"
 #include "launch.h"
@@ -24,12 +26,13 @@ using namespace sc;
 static_assert(sizeof(sim_record) == 16, "sim_record is 16 bytes");
 static_assert(sizeof(sim_race) == 64, "sim_race is 64 bytes");
 static_assert(sizeof(RaceOut) == sizeof(sim_race), "device entry mirrors sim_race");
-static_assert(sizeof(Summary) == sizeof(sim_trace_summary), "device summary mirrors sim_trace_summary");
 
 namespace {
 
 constexpr int N_STAGE = ST_COUNT;
-const char* const kStageNames[N_STAGE] = {"init", "stats", "layout", "keygen", "digits", "sort_pass", "scan"};
+const char* const kStageNames[N_STAGE] = {"init",      "stats",      "layout",     "keygen",  "digits",
+                                          "sort_pass", "scan_tiles", "scan_cross", "scan_out"};
+constexpr int MAX_EV = 96;
 
 struct DevBuf {
   void* p = nullptr;
@@ -43,15 +46,17 @@ struct sim_ctx {
   hipStream_t stream = nullptr;  // used by sim_check_traces
   uint32_t flags = 0;
   uint32_t tag = 0;
+  uint32_t pass_guess = 0;  // radix passes the previous call needed
+  uint32_t sort_grid = 0;   // co-resident workgroups of the radix pass
   std::string err;
 
-  DevBuf records, keys0, keys1, desc, tiles, stats, layout, hist, sort_status, seg_status, cnt_status, ctrl, summary,
-      out;
+  DevBuf records, keys0, keys1, desc, tiles, stats_part, layout, hist, sort_status, agg, tout, cross, cross_flag,
+      group_sum, group_off, stage, ctrl, out;
   void* h_meta = nullptr;  // pinned: TraceDesc[] then TileRef[]
   size_t h_meta_cap = 0;
   Ctrl* h_ctrl = nullptr;  // pinned
 
-  hipEvent_t ev[2 * 16] = {};
+  hipEvent_t ev[MAX_EV] = {};
   sim_stage_time times[N_STAGE] = {};
 };
 
@@ -111,15 +116,13 @@ void release(DevBuf& b) {
   b.cap = 0;
 }
 
-// Next launch tag; when the 24-bit space is used up the status buffers are
+// Next launch tag; when the 24-bit space is used up the status buffer is
 // cleared and numbering restarts.
 hipError_t next_tag(sim_ctx* c, hipStream_t s, uint32_t* tag) {
   if (c->tag >= TAG_MAX) {
-    for (DevBuf* b : {&c->sort_status, &c->seg_status, &c->cnt_status}) {
-      if (b->p) {
-        hipError_t e = hipMemsetAsync(b->p, 0, b->cap, s);
-        if (e != hipSuccess) return e;
-      }
+    if (c->sort_status.p) {
+      hipError_t e = hipMemsetAsync(c->sort_status.p, 0, c->sort_status.cap, s);
+      if (e != hipSuccess) return e;
     }
     c->tag = 0;
   }
@@ -137,12 +140,10 @@ int validate(sim_ctx* c, const uint64_t* offsets, uint32_t n_traces, const uint3
   for (uint32_t i = 0; i < n_traces; i++) {
     if (offsets[i + 1] < offsets[i]) return fail(c, SIM_EINVAL, "offsets decrease at trace %u", i);
     if (tpb[i] == 0) return fail(c, SIM_EINVAL, "threads_per_block[%u] is 0", i);
-    const uint64_t n = offsets[i + 1] - offsets[i];
-    if (n >= (1ull << 32)) return fail(c, SIM_EINVAL, "trace %u has 2^32 or more records", i);
-    tiles += (n + TILE - 1) / TILE;
+    tiles += (offsets[i + 1] - offsets[i] + TILE - 1) / TILE;
   }
-  if (tiles >= (1ull << 31)) return fail(c, SIM_EINVAL, "too many records in one call");
   *total = n_traces ? offsets[n_traces] : 0;
+  if (*total >= (1ull << 32)) return fail(c, SIM_EINVAL, "a call holds at most 2^32 - 1 records");
   *n_tiles = (uint32_t)tiles;
   return SIM_OK;
 }
@@ -153,7 +154,7 @@ sim_result* alloc_result(uint64_t n_races, uint32_t n_traces) {
   r->n_races = n_races;
   r->n_traces = n_traces;
   r->races = (sim_race*)malloc(n_races ? n_races * sizeof(sim_race) : 1);
-  r->traces = (sim_trace_summary*)malloc(n_traces ? n_traces * sizeof(sim_trace_summary) : 1);
+  r->traces = (sim_trace_summary*)calloc(n_traces ? n_traces : 1, sizeof(sim_trace_summary));
   if (!r->races || !r->traces) {
     free(r->races);
     free(r->traces);
@@ -175,12 +176,11 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   if (total == 0) {  // nothing to check: summaries only
     sim_result* r = alloc_result(0, n_traces);
     if (!r) return fail(c, SIM_ENOMEM, "host allocation failed");
-    for (uint32_t i = 0; i < n_traces; i++) r->traces[i] = sim_trace_summary{0, 0, 0};
     *out = r;
     return SIM_OK;
   }
 
-  // ---- buffers
+  // ---- per-call tables (pinned), replica layout of the histograms
   hipError_t e;
   const size_t meta_bytes = (size_t)n_traces * sizeof(TraceDesc) + (size_t)n_tiles * sizeof(TileRef);
   if (c->h_meta_cap < meta_bytes) {
@@ -191,6 +191,22 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     if (e != hipSuccess) return hip_fail(c, e, "pinned allocation");
     c->h_meta_cap = meta_bytes + meta_bytes / 8;
   }
+  TraceDesc* hd = (TraceDesc*)c->h_meta;
+  TileRef* ht = (TileRef*)(hd + n_traces);
+  uint32_t t0 = 0, r0 = 0;
+  for (uint32_t i = 0; i < n_traces; i++) {
+    const uint64_t n = offsets[i + 1] - offsets[i];
+    const uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
+    const uint32_t nr = (nt + REP_TILES - 1) / REP_TILES;
+    hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, r0, nr, 0};
+    for (uint32_t k = 0; k < nt; k++) ht[t0 + k] = TileRef{i, k};
+    t0 += nt;
+    r0 += nr;
+  }
+  const uint32_t n_reps = r0;
+  const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
+
+  // ---- device buffers
   const uint64_t cap0 = total < 65536 ? total : 65536;
   struct {
     DevBuf* b;
@@ -201,31 +217,22 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       {&c->keys1, total * 8, false},
       {&c->desc, (size_t)n_traces * sizeof(TraceDesc), false},
       {&c->tiles, (size_t)n_tiles * sizeof(TileRef), false},
-      {&c->stats, (size_t)n_traces * sizeof(TraceStats), false},
+      {&c->stats_part, (size_t)n_tiles * sizeof(TraceStats), false},
       {&c->layout, (size_t)n_traces * sizeof(TraceLayout), false},
-      {&c->hist, (size_t)n_traces * MAX_PASSES * RADIX * 4, false},
+      {&c->hist, (size_t)n_reps * MAX_PASSES * RADIX * 4, false},
       {&c->sort_status, (size_t)n_tiles * RADIX * 8, true},
-      {&c->seg_status, (size_t)n_tiles * 2 * SW * 8, true},
-      {&c->cnt_status, (size_t)n_tiles * 8, true},
+      {&c->agg, (size_t)n_tiles * SW * 4, false},
+      {&c->tout, (size_t)n_tiles * sizeof(TileOut), false},
+      {&c->cross, (size_t)n_tiles * sizeof(RaceOut), false},
+      {&c->cross_flag, (size_t)n_tiles * 4, false},
+      {&c->group_sum, (size_t)n_groups * 4, false},
+      {&c->group_off, (size_t)n_groups * 8, false},
       {&c->ctrl, sizeof(Ctrl), false},
-      {&c->summary, (size_t)n_traces * sizeof(Summary), false},
       {&c->out, (size_t)(c->out.cap ? c->out.cap : cap0 * sizeof(RaceOut)), false},
   };
   for (auto& nb : need) {
     e = ensure(*nb.b, nb.bytes, nb.zero);
     if (e != hipSuccess) return hip_fail(c, e, "device allocation");
-  }
-
-  // ---- per-call tables
-  TraceDesc* hd = (TraceDesc*)c->h_meta;
-  TileRef* ht = (TileRef*)(hd + n_traces);
-  uint32_t t0 = 0;
-  for (uint32_t i = 0; i < n_traces; i++) {
-    const uint64_t n = offsets[i + 1] - offsets[i];
-    const uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
-    hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, 0};
-    for (uint32_t k = 0; k < nt; k++) ht[t0 + k] = TileRef{i, k};
-    t0 += nt;
   }
   if ((e = hipMemcpyAsync(c->desc.p, hd, (size_t)n_traces * sizeof(TraceDesc), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(c->tiles.p, ht, (size_t)n_tiles * sizeof(TileRef), hipMemcpyHostToDevice, s)))
@@ -235,92 +242,147 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.records = d_records;
   b.desc = (const TraceDesc*)c->desc.p;
   b.tiles = (const TileRef*)c->tiles.p;
-  b.stats = (TraceStats*)c->stats.p;
+  b.stats_part = (TraceStats*)c->stats_part.p;
   b.layout = (TraceLayout*)c->layout.p;
   b.hist = (uint32_t*)c->hist.p;
   b.keys[0] = (uint64_t*)c->keys0.p;
   b.keys[1] = (uint64_t*)c->keys1.p;
   b.sort_status = (uint64_t*)c->sort_status.p;
-  b.seg_status = (uint64_t*)c->seg_status.p;
-  b.cnt_status = (uint64_t*)c->cnt_status.p;
+  b.agg = (uint32_t*)c->agg.p;
+  b.tout = (TileOut*)c->tout.p;
+  b.cross = (RaceOut*)c->cross.p;
+  b.cross_flag = (uint32_t*)c->cross_flag.p;
+  b.group_sum = (uint32_t*)c->group_sum.p;
+  b.group_off = (uint64_t*)c->group_off.p;
+  b.stage = nullptr;
   b.ctrl = (Ctrl*)c->ctrl.p;
-  b.summary = (Summary*)c->summary.p;
   b.out = (RaceOut*)c->out.p;
   b.out_cap = c->out.cap / sizeof(RaceOut);
   b.n_traces = n_traces;
   b.n_tiles = n_tiles;
+  b.n_reps = n_reps;
+  b.sort_grid = c->sort_grid;
 
+  // ---- the pipeline.  Radix passes: the context remembers how many the
+  // previous call needed and launches that many; the scan kernels do
+  // nothing if some trace needs more, and the host then adds the missing
+  // passes and scans again.
   const bool prof = (c->flags & SIM_CFG_PROFILE) != 0;
-  int evn = 0;
-  auto mark = [&]() -> hipError_t { return prof ? hipEventRecord(c->ev[evn++], s) : hipSuccess; };
+  int nev = 0;
+  int ev_stage[MAX_EV / 2];
+  bool ev_counts[MAX_EV / 2];
+  auto timed = [&](int stage, bool counts, auto&& launch) -> hipError_t {
+    const bool rec = prof && nev + 2 <= MAX_EV;
+    if (rec) {
+      hipError_t e0 = hipEventRecord(c->ev[nev], s);
+      if (e0 != hipSuccess) return e0;
+    }
+    hipError_t e1 = launch();
+    if (e1 != hipSuccess) return e1;
+    if (rec) {
+      hipError_t e2 = hipEventRecord(c->ev[nev + 1], s);
+      if (e2 != hipSuccess) return e2;
+      ev_stage[nev / 2] = stage;
+      ev_counts[nev / 2] = counts;
+      nev += 2;
+    }
+    return hipSuccess;
+  };
+  auto sync_ctrl = [&]() -> hipError_t {
+    hipError_t e1 = hipMemcpyAsync(c->h_ctrl, c->ctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+    return e1 != hipSuccess ? e1 : hipStreamSynchronize(s);
+  };
+  auto sort_passes = [&](uint32_t from, uint32_t to) -> hipError_t {
+    for (uint32_t p = from; p < to; p++) {
+      uint32_t tag;
+      hipError_t e1 = next_tag(c, s, &tag);
+      if (e1 == hipSuccess) e1 = timed(ST_SORT, true, [&] { return launch_sort_pass(b, p, tag, s); });
+      if (e1 != hipSuccess) return e1;
+    }
+    return hipSuccess;
+  };
+  // counts: whether the launches are real work (a scan before missing
+  // passes, or a rescan after an overflow, is left out of the stage times)
+  auto scan = [&](uint32_t passes_done, bool counts) -> hipError_t {
+    hipError_t e1 = timed(ST_SCAN, counts, [&] { return launch_scan_tiles(b, passes_done, s); });
+    if (e1 == hipSuccess) e1 = timed(ST_CROSS, counts, [&] { return launch_scan_cross(b, passes_done, s); });
+    if (e1 == hipSuccess) e1 = timed(ST_OUT, counts, [&] { return launch_scan_out(b, passes_done, s); });
+    return e1;
+  };
 
-  // ---- the pipeline (stage events: init, stats, layout, keygen, digits, pass 0..7, scan)
-  uint32_t tags[MAX_PASSES + 1];
-  for (uint32_t p = 0; p <= MAX_PASSES; p++)
-    if ((e = next_tag(c, s, &tags[p]))) return hip_fail(c, e, "status reset");
-  if ((e = mark()) || (e = launch_init(b, s)) || (e = mark()) || (e = launch_stats(b, s)) || (e = mark()) ||
-      (e = launch_layout(b, s)) || (e = mark()) || (e = launch_keygen(b, s)) || (e = mark()) ||
-      (e = launch_digits(b, s)) || (e = mark()))
-    return hip_fail(c, e, "launch");
-  for (uint32_t p = 0; p < MAX_PASSES; p++)
-    if ((e = launch_sort_pass(b, p, tags[p], s)) || (e = mark())) return hip_fail(c, e, "launch");
-  if ((e = launch_scan(b, tags[MAX_PASSES], s)) || (e = mark())) return hip_fail(c, e, "launch");
-  if ((e = hipMemcpyAsync(c->h_ctrl, c->ctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s)) ||
-      (e = hipStreamSynchronize(s)))
+  const uint32_t guess = c->pass_guess < MAX_PASSES ? c->pass_guess : MAX_PASSES;
+  if ((e = timed(ST_INIT, true, [&] { return launch_init(b, s); })) ||
+      (e = timed(ST_STATS, true, [&] { return launch_stats(b, s); })) ||
+      (e = timed(ST_LAYOUT, true, [&] { return launch_layout(b, s); })) ||
+      (e = timed(ST_KEYGEN, true, [&] { return launch_keygen(b, s); })) ||
+      (e = timed(ST_DIGITS, true, [&] { return launch_digits(b, s); })) || (e = sort_passes(0, guess)))
     return hip_fail(c, e, "pipeline");
+  const int first_scan_ev = nev / 2;
+  if ((guess && (e = scan(guess, true))) || (e = sync_ctrl())) return hip_fail(c, e, "pipeline");
 
-  const Ctrl ctl = *c->h_ctrl;
+  Ctrl ctl = *c->h_ctrl;
   if (ctl.error_flags & LAYOUT_ERR_RECORD)
     return fail(c, SIM_ERECORD, "invalid record at index %llu (action > 2 or space > 1)",
                 (unsigned long long)ctl.first_bad);
   if (ctl.error_flags & LAYOUT_ERR_WIDE) return fail(c, SIM_ERANGE, "a trace's sort key needs more than 64 bits");
-  if (ctl.error_flags & (ERR_INTERNAL_BOUNDS | ERR_INTERNAL_SPIN))
+  const uint32_t needed = ctl.max_passes;
+  if (needed > guess) {
+    // too few passes ran: the scan kernels above returned at once
+    for (int k = first_scan_ev; k < nev / 2; k++) ev_counts[k] = false;
+    if ((e = sort_passes(guess, needed)) || (e = scan(needed, true)) || (e = sync_ctrl()))
+      return hip_fail(c, e, "pipeline");
+    ctl = *c->h_ctrl;
+  }
+  c->pass_guess = needed;
+  if (ctl.error_flags & ERR_STAGE_OVERFLOW) {
+    // a tile holds more racing locations than its slice of the idle key
+    // buffer: scan again with a dedicated staging buffer
+    if ((e = ensure(c->stage, (size_t)n_tiles * (TILE / 2 + 1) * sizeof(RaceOut))))
+      return hip_fail(c, e, "device allocation");
+    b.stage = (RaceOut*)c->stage.p;
+    if ((e = launch_reset_errors(b, ERR_STAGE_OVERFLOW, s)) || (e = scan(needed, false)) || (e = sync_ctrl()))
+      return hip_fail(c, e, "rescan");
+    ctl = *c->h_ctrl;
+  }
+  if (ctl.error_flags)
     return fail(c, SIM_EDEVICE, "internal kernel check failed (flags 0x%x)", ctl.error_flags);
 
-  if (prof) {
-    const int stage_of_event[] = {ST_INIT, ST_STATS, ST_LAYOUT, ST_KEYGEN, ST_DIGITS};
-    int k = 0;
-    for (; k < 5; k++) {
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]);
-      c->times[stage_of_event[k]].ms += ms;
-      c->times[stage_of_event[k]].launches += 1;
-    }
-    for (uint32_t p = 0; p < MAX_PASSES; p++, k++) {
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]);
-      c->times[ST_SORT].ms += ms;
-      if (p < ctl.max_passes) c->times[ST_SORT].launches += 1;
-    }
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]);
-    c->times[ST_SCAN].ms += ms;
-    c->times[ST_SCAN].launches += 1;
-  }
-
   uint64_t n_races = ctl.total_entries;
-  if (n_races > b.out_cap) {  // more racing locations than the output buffer holds: grow and rescan
+  if (n_races > b.out_cap) {  // more racing locations than the output buffer holds
     if ((e = ensure(c->out, n_races * sizeof(RaceOut)))) return hip_fail(c, e, "device allocation");
     b.out = (RaceOut*)c->out.p;
     b.out_cap = c->out.cap / sizeof(RaceOut);
-    uint32_t tag;
-    if ((e = next_tag(c, s, &tag)) || (e = launch_scan_reset(b, s)) || (e = launch_scan(b, tag, s)) ||
-        (e = hipMemcpyAsync(c->h_ctrl, c->ctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s)) ||
-        (e = hipStreamSynchronize(s)))
+    if ((e = timed(ST_OUT, false, [&] { return launch_scan_out(b, needed, s); })) || (e = sync_ctrl()))
       return hip_fail(c, e, "rescan");
-    n_races = c->h_ctrl->total_entries;
-    if (c->h_ctrl->error_flags) return fail(c, SIM_EDEVICE, "internal kernel check failed on rescan");
-    if (n_races > b.out_cap) return fail(c, SIM_EDEVICE, "entry count changed between scans");
+    if (c->h_ctrl->total_entries != n_races) return fail(c, SIM_EDEVICE, "entry count changed between scans");
+  }
+
+  if (prof) {
+    for (int k = 0; k < nev / 2; k++) {
+      if (!ev_counts[k]) continue;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
+      c->times[ev_stage[k]].ms += ms;
+      c->times[ev_stage[k]].launches += 1;
+    }
   }
 
   sim_result* r = alloc_result(n_races, n_traces);
   if (!r) return fail(c, SIM_ENOMEM, "host allocation failed");
-  if ((n_races && (e = hipMemcpyAsync(r->races, c->out.p, n_races * sizeof(sim_race), hipMemcpyDeviceToHost, s))) ||
-      (e = hipMemcpyAsync(r->traces, c->summary.p, (size_t)n_traces * sizeof(sim_trace_summary),
-                          hipMemcpyDeviceToHost, s)) ||
-      (e = hipStreamSynchronize(s))) {
+  if (n_races && ((e = hipMemcpyAsync(r->races, c->out.p, n_races * sizeof(sim_race), hipMemcpyDeviceToHost, s)) ||
+                  (e = hipStreamSynchronize(s)))) {
     sim_result_free(r);
     return hip_fail(c, e, "result download");
+  }
+  for (uint32_t i = 0; i < n_traces; i++) r->traces[i].n_records = offsets[i + 1] - offsets[i];
+  for (uint64_t k = 0; k < n_races; k++) {
+    const sim_race& x = r->races[k];
+    if (x.trace >= n_traces) {
+      sim_result_free(r);
+      return fail(c, SIM_EDEVICE, "entry %llu names trace %u", (unsigned long long)k, x.trace);
+    }
+    r->traces[x.trace].n_race_locs += 1;
+    r->traces[x.trace].n_pairs += x.pairs_ww + x.pairs_rw + x.pairs_aw + x.pairs_ar;
   }
   *out = r;
   return SIM_OK;
@@ -339,11 +401,18 @@ int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return SIM_EDEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SIM_EDEVICE;
+  if (!prop.cooperativeLaunch) return SIM_EDEVICE;
   sim_ctx* c = new (std::nothrow) sim_ctx();
   if (!c) return SIM_ENOMEM;
   c->device = hip_device;
   c->flags = cfg ? cfg->flags : 0;
   DeviceGuard g(hip_device);
+  const int per_cu = sort_pass_blocks_per_cu();
+  if (per_cu <= 0) {
+    delete c;
+    return SIM_EDEVICE;
+  }
+  c->sort_grid = (uint32_t)(per_cu * prop.multiProcessorCount);
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
     sim_destroy(c);
@@ -369,8 +438,9 @@ void sim_destroy(sim_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->stats, &c->layout, &c->hist,
-                    &c->sort_status, &c->seg_status, &c->cnt_status, &c->ctrl, &c->summary, &c->out})
+  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->stats_part, &c->layout, &c->hist,
+                    &c->sort_status, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->group_off,
+                    &c->stage, &c->ctrl, &c->out})
     release(*b);
   if (c->h_meta) (void)hipHostFree(c->h_meta);
   if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);

@@ -2,11 +2,12 @@
 //
 // Compiles the product's key-layout and monoid headers for the host and runs
 // the same tile decomposition as the GPU kernels: keys are built and sorted
-// per trace, cut into tiles, each tile is summarised from its own elements
-// (carry-free), tiles are chained with combine() as the look-back does, and a
-// location is reported by the tile that holds its last element.  Tiles are
-// additionally split into "thread" chunks whose summaries are combined, to
-// exercise associativity at a second level.  The tests compare the output
+// per trace and cut into tiles; each tile is summarised from its own
+// elements (carry-free) and reports the locations that start and end inside
+// it; a location that crosses tiles is finished by the tile where it starts,
+// by combining the summaries of the tiles it spans.  Tiles are additionally
+// split into "thread" chunks whose summaries are combined, to exercise
+// associativity at a second level.  The tests compare the output
 // with the oracle; nothing here is used by the product path.
 #include <algorithm>
 #include <cstdint>
@@ -74,33 +75,47 @@ extern "C" int64_t hs_check(const rec* recs, const uint64_t* off, uint32_t n_tra
       k[i] = make_key(L, r.unit, r.tid, r.epoch, r.action, r.space, tpb[tr]);
     }
     std::sort(k.begin(), k.end());
-    State carry = identity();  // inclusive summary of all earlier tiles
-    for (uint64_t t0 = 0; t0 < n; t0 += tile) {
-      const uint64_t t1 = std::min<uint64_t>(n, t0 + tile);
-      std::vector<uint32_t> lv(t1 - t0);
-      for (uint64_t i = t0; i < t1; i++) lv[i - t0] = (i == 0) ? 0 : head_level(L, k[i - 1], k[i]);
-      // tile summary from chunk summaries (carry-free)
-      State agg = identity();
-      for (uint64_t c0 = t0; c0 < t1; c0 += chunk) {
+    // tile summaries, carry-free (as the tile scan computes them)
+    const uint64_t nt = (n + tile - 1) / tile;
+    std::vector<State> agg(nt);
+    std::vector<uint32_t> lv(n);
+    for (uint64_t i = 0; i < n; i++) lv[i] = (i == 0) ? 0 : head_level(L, k[i - 1], k[i]);
+    for (uint64_t t = 0; t < nt; t++) {
+      const uint64_t t0 = t * tile, t1 = std::min<uint64_t>(n, t0 + tile);
+      State a = identity();
+      for (uint64_t c0 = t0; c0 < t1; c0 += chunk) {  // chunks combined: associativity at a second level
         State cs = identity();
-        for (uint64_t i = c0; i < std::min<uint64_t>(t1, c0 + chunk); i++) push(cs, lv[i - t0], action_class(k[i]));
-        agg = combine(agg, cs);
+        for (uint64_t i = c0; i < std::min<uint64_t>(t1, c0 + chunk); i++) push(cs, lv[i], action_class(k[i]));
+        a = combine(a, cs);
       }
-      uint64_t open[5];
-      open_sums(carry, agg, open);
-      // in-tile walk, carry-free, reporting each location at its last element
+      agg[t] = a;
+    }
+    for (uint64_t t = 0; t < nt; t++) {
+      const uint64_t t0 = t * tile, t1 = std::min<uint64_t>(n, t0 + tile);
+      // locations that start and end inside the tile
       State run = identity();
       bool seen_head = false;
       for (uint64_t i = t0; i < t1; i++) {
-        const uint32_t l = lv[i - t0];
-        push(run, l, action_class(k[i]));
-        if (l == 0) seen_head = true;
-        const bool last = (i + 1 == n) || head_level(L, k[i], k[i + 1]) == 0;
-        if (!last) continue;
-        if (!seen_head) emit(res, tr, L, k[i], open);
-        else emit(res, tr, L, k[i], run.trailsum);
+        push(run, lv[i], action_class(k[i]));
+        if (lv[i] == 0) seen_head = true;
+        if (!seen_head) continue;  // the location entering the tile is finished by its owner
+        const bool last = (i + 1 == n) || lv[i + 1] == 0;
+        if (last) emit(res, tr, L, k[i], run.trailsum);
       }
-      carry = combine(carry, agg);
+      // a location that starts in this tile and continues into later tiles
+      const bool owns = agg[t].m == 0 && t1 < n && lv[t1] != 0;
+      if (!owns) continue;
+      State S = agg[t];
+      uint64_t u = t + 1;
+      while (u < nt && agg[u].m != 0) S = combine(S, agg[u++]);
+      uint64_t fin[5];
+      if (u < nt) {
+        open_sums(S, agg[u], fin);
+      } else {
+        const uint64_t* ts = tail_sums(S);
+        for (int q = 0; q < 5; q++) fin[q] = ts[q];
+      }
+      emit(res, tr, L, k[t1 - 1], fin);
     }
   }
   if (max_passes) *max_passes = mp;
