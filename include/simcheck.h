@@ -103,7 +103,12 @@ typedef struct sim_config {
   uint32_t reserved;
 } sim_config;
 
-enum { SIM_CFG_PROFILE = 1 }; /* record per-stage HIP events (see sim_stage_times) */
+enum {
+  SIM_CFG_PROFILE = 1, /* record per-stage HIP events (see sim_stage_times); disables graphs */
+  SIM_CFG_GRAPHS = 2   /* capture each call's launch sequence as a HIP graph and replay it while
+                          calls keep the same shape (records pointer, offsets, threads per block,
+                          stream); needs a non-NULL stream */
+};
 
 typedef struct sim_ctx sim_ctx;
 

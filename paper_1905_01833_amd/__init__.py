@@ -29,7 +29,8 @@ SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pair
 
 SIM_OK, SIM_EINVAL, SIM_ERECORD, SIM_ENOMEM, SIM_EDEVICE, SIM_ERANGE = 0, -1, -2, -3, -4, -6
 SIM_CFG_PROFILE = 1
-STAGES = ["init", "stats", "layout", "keygen", "digits", "sort_pass", "scan"]
+SIM_CFG_GRAPHS = 2
+STAGES = ["init", "stats", "layout", "keygen", "upsweep", "sort_pass", "scan_tiles", "scan_cross", "scan_out"]
 
 # Symbols declared in include/simcheck.h.
 EXPORTS = [
@@ -99,10 +100,12 @@ def load() -> ctypes.CDLL:
 
 # ------------------------------------------------------------ C-named API
 
-def sim_create(hip_device: int = 0, profile: bool = False, reserve_records: int = 0) -> ctypes.c_void_p:
+def sim_create(hip_device: int = 0, profile: bool = False, reserve_records: int = 0,
+               graphs: bool = False) -> ctypes.c_void_p:
     lib = load()
     ctx = ctypes.c_void_p()
-    cfg = _Config(reserve_records, SIM_CFG_PROFILE if profile else 0, 0)
+    flags = (SIM_CFG_PROFILE if profile else 0) | (SIM_CFG_GRAPHS if graphs else 0)
+    cfg = _Config(reserve_records, flags, 0)
     rc = lib.sim_create(ctypes.byref(ctx), hip_device, ctypes.byref(cfg))
     if rc != SIM_OK:
         raise SimError(rc, f"sim_create failed on device {hip_device} (needs a gfx950 GPU)")
@@ -186,8 +189,8 @@ def sim_stage_times(ctx):
 class Context:
     """One library context on one GPU."""
 
-    def __init__(self, device: int = 0, profile: bool = False, reserve_records: int = 0):
-        self._ctx = sim_create(device, profile=profile, reserve_records=reserve_records)
+    def __init__(self, device: int = 0, profile: bool = False, reserve_records: int = 0, graphs: bool = False):
+        self._ctx = sim_create(device, profile=profile, reserve_records=reserve_records, graphs=graphs)
 
     def close(self):
         if self._ctx:

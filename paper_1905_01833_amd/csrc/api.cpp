@@ -2,9 +2,8 @@
 //
 // A context owns grow-only device buffers sized by the largest call seen so
 // far, a default-priority stream for the host-record entry point, pinned
-// host staging for the small per-call tables and results, and the launch
-// tag counter that keeps look-back status words of different launches
-// apart.  A check is one ordered sequence of kernel launches on one stream
+// host staging for the small per-call tables and results.  A check is one
+// ordered sequence of kernel launches on one stream
 // and one synchronisation; there is no CPU fallback.  Rare conditions cost
 // a second round on the device: a trace needing more radix passes than the
 // previous call did, a tile with more racing locations than its staging
@@ -30,7 +29,7 @@ static_assert(sizeof(RaceOut) == sizeof(sim_race), "device entry mirrors sim_rac
 namespace {
 
 constexpr int N_STAGE = ST_COUNT;
-const char* const kStageNames[N_STAGE] = {"init",      "stats",      "layout",     "keygen",  "digits",
+const char* const kStageNames[N_STAGE] = {"init",      "stats",      "layout",     "keygen",  "upsweep",
                                           "sort_pass", "scan_tiles", "scan_cross", "scan_out"};
 constexpr int MAX_EV = 96;
 
@@ -45,12 +44,20 @@ struct sim_ctx {
   int device = 0;
   hipStream_t stream = nullptr;  // used by sim_check_traces
   uint32_t flags = 0;
-  uint32_t tag = 0;
   uint32_t pass_guess = 0;  // radix passes the previous call needed
-  uint32_t sort_grid = 0;   // co-resident workgroups of the radix pass
+  uint64_t alloc_gen = 0;   // bumped whenever a device buffer is reallocated
+
+  // one captured launch sequence, replayed while calls keep the same shape
+  struct {
+    hipGraphExec_t exec = nullptr;
+    const void* records = nullptr;
+    hipStream_t stream = nullptr;
+    uint64_t total = 0, table_hash = 0, gen = 0;
+    uint32_t n_traces = 0, n_tiles = 0, guess = 0;
+  } graph;
   std::string err;
 
-  DevBuf records, keys0, keys1, desc, tiles, stats_part, layout, hist, sort_status, agg, tout, cross, cross_flag,
+  DevBuf records, keys0, keys1, desc, tiles, groups, stats_part, layout, thist, gtot, gbase, agg, tout, cross, cross_flag,
       group_sum, group_off, stage, ctrl, out;
   void* h_meta = nullptr;  // pinned: TraceDesc[] then TileRef[]
   size_t h_meta_cap = 0;
@@ -88,11 +95,12 @@ struct DeviceGuard {
   }
 };
 
-// Grow a device buffer to at least `bytes` (contents are not kept).  Status
-// buffers are zeroed so that no stale word carries a live tag.
-hipError_t ensure(DevBuf& b, size_t bytes, bool zero = false) {
+// Grow a device buffer to at least `bytes` (contents are not kept); *gen is
+// bumped on reallocation (captured launch sequences hold buffer addresses).
+hipError_t ensure(DevBuf& b, size_t bytes, bool zero = false, uint64_t* gen = nullptr) {
   if (bytes == 0) bytes = 64;
   if (b.cap >= bytes) return hipSuccess;
+  if (gen) ++*gen;
   if (b.p) {
     hipError_t e = hipFree(b.p);
     if (e != hipSuccess) return e;
@@ -114,20 +122,6 @@ void release(DevBuf& b) {
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.cap = 0;
-}
-
-// Next launch tag; when the 24-bit space is used up the status buffer is
-// cleared and numbering restarts.
-hipError_t next_tag(sim_ctx* c, hipStream_t s, uint32_t* tag) {
-  if (c->tag >= TAG_MAX) {
-    if (c->sort_status.p) {
-      hipError_t e = hipMemsetAsync(c->sort_status.p, 0, c->sort_status.cap, s);
-      if (e != hipSuccess) return e;
-    }
-    c->tag = 0;
-  }
-  *tag = ++c->tag;
-  return hipSuccess;
 }
 
 int validate(sim_ctx* c, const uint64_t* offsets, uint32_t n_traces, const uint32_t* tpb, sim_result** out,
@@ -180,9 +174,18 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     return SIM_OK;
   }
 
-  // ---- per-call tables (pinned), replica layout of the histograms
+  // ---- per-call tables (pinned); histogram groups of about sqrt(ntiles)
+  // tiles keep both serial offset loops of the radix kernels short
   hipError_t e;
-  const size_t meta_bytes = (size_t)n_traces * sizeof(TraceDesc) + (size_t)n_tiles * sizeof(TileRef);
+  uint64_t n_hgroups64 = 0;
+  for (uint32_t i = 0; i < n_traces; i++) {
+    const uint64_t nt = (offsets[i + 1] - offsets[i] + TILE - 1) / TILE;
+    uint32_t gs = 0;
+    while (gs < MAX_HGROUP_SHIFT && (1ull << (2 * gs)) < nt) gs++;
+    n_hgroups64 += (nt + (1ull << gs) - 1) >> gs;
+  }
+  const size_t meta_bytes = (size_t)n_traces * sizeof(TraceDesc) + (size_t)n_tiles * sizeof(TileRef) +
+                            (size_t)n_hgroups64 * sizeof(GroupRef);
   if (c->h_meta_cap < meta_bytes) {
     if (c->h_meta) (void)hipHostFree(c->h_meta);
     c->h_meta = nullptr;
@@ -193,17 +196,21 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   }
   TraceDesc* hd = (TraceDesc*)c->h_meta;
   TileRef* ht = (TileRef*)(hd + n_traces);
-  uint32_t t0 = 0, r0 = 0;
+  GroupRef* hg = (GroupRef*)(ht + n_tiles);
+  uint32_t t0 = 0, g0 = 0;
   for (uint32_t i = 0; i < n_traces; i++) {
     const uint64_t n = offsets[i + 1] - offsets[i];
     const uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
-    const uint32_t nr = (nt + REP_TILES - 1) / REP_TILES;
-    hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, r0, nr, 0};
+    uint32_t gs = 0;
+    while (gs < MAX_HGROUP_SHIFT && (1ull << (2 * gs)) < nt) gs++;
+    const uint32_t ng = (nt + (1u << gs) - 1) >> gs;
+    hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
     for (uint32_t k = 0; k < nt; k++) ht[t0 + k] = TileRef{i, k};
+    for (uint32_t k = 0; k < ng; k++) hg[g0 + k] = GroupRef{i, 0};
     t0 += nt;
-    r0 += nr;
+    g0 += ng;
   }
-  const uint32_t n_reps = r0;
+  const uint32_t n_hgroups = g0;
   const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
 
   // ---- device buffers
@@ -219,8 +226,10 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       {&c->tiles, (size_t)n_tiles * sizeof(TileRef), false},
       {&c->stats_part, (size_t)n_tiles * sizeof(TraceStats), false},
       {&c->layout, (size_t)n_traces * sizeof(TraceLayout), false},
-      {&c->hist, (size_t)n_reps * MAX_PASSES * RADIX * 4, false},
-      {&c->sort_status, (size_t)n_tiles * RADIX * 8, true},
+      {&c->groups, (size_t)n_hgroups * sizeof(GroupRef), false},
+      {&c->thist, (size_t)n_tiles * RADIX * 4, false},
+      {&c->gtot, (size_t)n_hgroups * RADIX * 4, false},
+      {&c->gbase, (size_t)n_hgroups * RADIX * 8, false},
       {&c->agg, (size_t)n_tiles * SW * 4, false},
       {&c->tout, (size_t)n_tiles * sizeof(TileOut), false},
       {&c->cross, (size_t)n_tiles * sizeof(RaceOut), false},
@@ -231,11 +240,12 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       {&c->out, (size_t)(c->out.cap ? c->out.cap : cap0 * sizeof(RaceOut)), false},
   };
   for (auto& nb : need) {
-    e = ensure(*nb.b, nb.bytes, nb.zero);
+    e = ensure(*nb.b, nb.bytes, nb.zero, &c->alloc_gen);
     if (e != hipSuccess) return hip_fail(c, e, "device allocation");
   }
   if ((e = hipMemcpyAsync(c->desc.p, hd, (size_t)n_traces * sizeof(TraceDesc), hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(c->tiles.p, ht, (size_t)n_tiles * sizeof(TileRef), hipMemcpyHostToDevice, s)))
+      (e = hipMemcpyAsync(c->tiles.p, ht, (size_t)n_tiles * sizeof(TileRef), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(c->groups.p, hg, (size_t)n_hgroups * sizeof(GroupRef), hipMemcpyHostToDevice, s)))
     return hip_fail(c, e, "table upload");
 
   Buffers b;
@@ -244,10 +254,12 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.tiles = (const TileRef*)c->tiles.p;
   b.stats_part = (TraceStats*)c->stats_part.p;
   b.layout = (TraceLayout*)c->layout.p;
-  b.hist = (uint32_t*)c->hist.p;
   b.keys[0] = (uint64_t*)c->keys0.p;
   b.keys[1] = (uint64_t*)c->keys1.p;
-  b.sort_status = (uint64_t*)c->sort_status.p;
+  b.groups = (const GroupRef*)c->groups.p;
+  b.thist = (uint32_t*)c->thist.p;
+  b.gtot = (uint32_t*)c->gtot.p;
+  b.gbase = (uint64_t*)c->gbase.p;
   b.agg = (uint32_t*)c->agg.p;
   b.tout = (TileOut*)c->tout.p;
   b.cross = (RaceOut*)c->cross.p;
@@ -260,8 +272,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.out_cap = c->out.cap / sizeof(RaceOut);
   b.n_traces = n_traces;
   b.n_tiles = n_tiles;
-  b.n_reps = n_reps;
-  b.sort_grid = c->sort_grid;
+  b.n_groups = n_hgroups;
 
   // ---- the pipeline.  Radix passes: the context remembers how many the
   // previous call needed and launches that many; the scan kernels do
@@ -294,9 +305,8 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   };
   auto sort_passes = [&](uint32_t from, uint32_t to) -> hipError_t {
     for (uint32_t p = from; p < to; p++) {
-      uint32_t tag;
-      hipError_t e1 = next_tag(c, s, &tag);
-      if (e1 == hipSuccess) e1 = timed(ST_SORT, true, [&] { return launch_sort_pass(b, p, tag, s); });
+      hipError_t e1 = timed(ST_UPSWEEP, true, [&] { return launch_upsweep(b, p, s); });
+      if (e1 == hipSuccess) e1 = timed(ST_SORT, true, [&] { return launch_scatter(b, p, s); });
       if (e1 != hipSuccess) return e1;
     }
     return hipSuccess;
@@ -311,14 +321,66 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   };
 
   const uint32_t guess = c->pass_guess < MAX_PASSES ? c->pass_guess : MAX_PASSES;
-  if ((e = timed(ST_INIT, true, [&] { return launch_init(b, s); })) ||
-      (e = timed(ST_STATS, true, [&] { return launch_stats(b, s); })) ||
-      (e = timed(ST_LAYOUT, true, [&] { return launch_layout(b, s); })) ||
-      (e = timed(ST_KEYGEN, true, [&] { return launch_keygen(b, s); })) ||
-      (e = timed(ST_DIGITS, true, [&] { return launch_digits(b, s); })) || (e = sort_passes(0, guess)))
-    return hip_fail(c, e, "pipeline");
-  const int first_scan_ev = nev / 2;
-  if ((guess && (e = scan(guess, true))) || (e = sync_ctrl())) return hip_fail(c, e, "pipeline");
+  auto first_round = [&]() -> hipError_t {
+    hipError_t e1;
+    if ((e1 = timed(ST_INIT, true, [&] { return launch_init(b, s); })) ||
+        (e1 = timed(ST_STATS, true, [&] { return launch_stats(b, s); })) ||
+        (e1 = timed(ST_LAYOUT, true, [&] { return launch_layout(b, s); })) ||
+        (e1 = timed(ST_KEYGEN, true, [&] { return launch_keygen(b, s); })) || (e1 = sort_passes(0, guess)))
+      return e1;
+    if (guess && (e1 = scan(guess, true))) return e1;
+    return hipMemcpyAsync(c->h_ctrl, c->ctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+  };
+  const int first_scan_ev = 5 + 2 * (int)guess - 1;  // events of the first round before its scan
+  // Graph mode: the first round (every launch up to the control download)
+  // is captured once per call shape and replayed while the shape, the
+  // buffers and the pass count stay the same.
+  const bool use_graph = (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0;
+  uint64_t th = 1469598103934665603ull;  // FNV-1a over the per-call tables
+  if (use_graph) {
+    const unsigned char* q = (const unsigned char*)offsets;
+    for (size_t k = 0; k < (size_t)(n_traces + 1) * sizeof(uint64_t); k++) th = (th ^ q[k]) * 1099511628211ull;
+    q = (const unsigned char*)tpb;
+    for (size_t k = 0; k < (size_t)n_traces * sizeof(uint32_t); k++) th = (th ^ q[k]) * 1099511628211ull;
+  }
+  auto& G = c->graph;
+  const bool replay = use_graph && G.exec && G.records == d_records && G.stream == s && G.total == total &&
+                      G.n_traces == n_traces && G.n_tiles == n_tiles && G.table_hash == th && G.gen == c->alloc_gen &&
+                      G.guess == guess;
+  if (replay) {
+    e = hipGraphLaunch(G.exec, s);
+  } else if (use_graph) {
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t e_cap = first_round();
+      e = hipStreamEndCapture(s, &graph);
+      if (e_cap != hipSuccess) e = e_cap;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) {
+      G.records = d_records;
+      G.stream = s;
+      G.total = total;
+      G.n_traces = n_traces;
+      G.n_tiles = n_tiles;
+      G.table_hash = th;
+      G.gen = c->alloc_gen;
+      G.guess = guess;
+      e = hipGraphLaunch(G.exec, s);
+    } else {  // capture not possible here: run the launches directly
+      (void)hipGetLastError();
+      if (G.exec) (void)hipGraphExecDestroy(G.exec);
+      G.exec = nullptr;
+      e = first_round();
+    }
+  } else {
+    e = first_round();
+  }
+  if (e != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "pipeline");
 
   Ctrl ctl = *c->h_ctrl;
   if (ctl.error_flags & LAYOUT_ERR_RECORD)
@@ -337,7 +399,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   if (ctl.error_flags & ERR_STAGE_OVERFLOW) {
     // a tile holds more racing locations than its slice of the idle key
     // buffer: scan again with a dedicated staging buffer
-    if ((e = ensure(c->stage, (size_t)n_tiles * (TILE / 2 + 1) * sizeof(RaceOut))))
+    if ((e = ensure(c->stage, (size_t)n_tiles * (TILE / 2 + 1) * sizeof(RaceOut), false, &c->alloc_gen)))
       return hip_fail(c, e, "device allocation");
     b.stage = (RaceOut*)c->stage.p;
     if ((e = launch_reset_errors(b, ERR_STAGE_OVERFLOW, s)) || (e = scan(needed, false)) || (e = sync_ctrl()))
@@ -349,7 +411,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
 
   uint64_t n_races = ctl.total_entries;
   if (n_races > b.out_cap) {  // more racing locations than the output buffer holds
-    if ((e = ensure(c->out, n_races * sizeof(RaceOut)))) return hip_fail(c, e, "device allocation");
+    if ((e = ensure(c->out, n_races * sizeof(RaceOut), false, &c->alloc_gen))) return hip_fail(c, e, "device allocation");
     b.out = (RaceOut*)c->out.p;
     b.out_cap = c->out.cap / sizeof(RaceOut);
     if ((e = timed(ST_OUT, false, [&] { return launch_scan_out(b, needed, s); })) || (e = sync_ctrl()))
@@ -401,18 +463,11 @@ int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return SIM_EDEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SIM_EDEVICE;
-  if (!prop.cooperativeLaunch) return SIM_EDEVICE;
   sim_ctx* c = new (std::nothrow) sim_ctx();
   if (!c) return SIM_ENOMEM;
   c->device = hip_device;
   c->flags = cfg ? cfg->flags : 0;
   DeviceGuard g(hip_device);
-  const int per_cu = sort_pass_blocks_per_cu();
-  if (per_cu <= 0) {
-    delete c;
-    return SIM_EDEVICE;
-  }
-  c->sort_grid = (uint32_t)(per_cu * prop.multiProcessorCount);
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
     sim_destroy(c);
@@ -438,10 +493,11 @@ void sim_destroy(sim_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->stats_part, &c->layout, &c->hist,
-                    &c->sort_status, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->group_off,
+  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->groups, &c->stats_part, &c->layout,
+                    &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->group_off,
                     &c->stage, &c->ctrl, &c->out})
     release(*b);
+  if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
   if (c->h_meta) (void)hipHostFree(c->h_meta);
   if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
   for (auto& ev : c->ev)

@@ -6,22 +6,23 @@
 //   k_init        reset per-call state
 //   k_stats       per-tile unit ranges, largest tid and epoch, record checks
 //   k_layout      per-trace reduction of the tile statistics, key layout
-//   k_keygen      records -> 64-bit keys, digit histograms of every pass
-//   k_digits      digit bases (exclusive scan of the histograms)
-//   k_sort_pass   one stable LSD radix pass, 8-bit digits (x passes)
+//   k_keygen      records -> 64-bit keys, tile histograms of radix digit 0
+//   k_upsweep     tile histograms of radix digit p (p >= 1)
+//   k_group_offsets / k_trace_offsets  histograms -> scatter offsets
+//   k_scatter     one stable LSD radix pass, 8-bit digits (x passes)
 //   k_scan_tiles  racing-pair counts of every location inside a tile, and
 //                 the tile's summary for locations that cross tiles
 //   k_scan_cross  pair counts of the locations that cross tiles
-//   k_group_*     ordered output: two-level prefix of per-tile entry counts
+//   k_group_* / k_scan_out  ordered output (two-level prefix over tiles)
 //
-// Device-scope atomics that many workgroups aim at one address serialise
-// (about 11 ns each on MI355X), so no kernel here funnels per-tile work
-// through one counter: statistics are per-tile partials, histograms are
-// spread over replicas, and the radix pass runs as a cooperative grid whose
-// workgroups are all resident, taking tiles in a fixed order instead of
-// from a ticket counter.  Only the radix pass chains tiles (decoupled
-// look-back); its status words carry a 24-bit tag unique to the launch and
-// are accessed with agent-scope atomics, coherent across the XCDs.
+// No kernel waits on another workgroup.  Radix offsets are computed
+// reduce-then-scan style: every tile stores its digit histogram, two small
+// kernels turn the histograms into offsets, and the scatter of a pass reads
+// finished offsets.  Device-scope atomics that many workgroups aim at one
+// address serialise (about 11 ns each on MI355X) and an agent-scope fence
+// writes back the whole L2, so neither appears on a hot path: statistics are
+// per-tile partials and hand-offs between workgroups go through kernel
+// boundaries.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -30,41 +31,12 @@
 namespace sc {
 
 constexpr int NWAVE = NT / 64;
-static_assert(NT == (int)RADIX, "one thread per digit in k_sort_pass");
+static_assert(NT == (int)RADIX, "one thread per digit in the radix kernels");
 static_assert(GROUP == NT, "one thread per tile in the output kernels");
 constexpr uint64_t SEGF = 1ull << 63;   // head flag of packed segmented values
 constexpr uint32_t CLS_NONE = 3;        // padding element past the end of a trace
-constexpr uint32_t LOOKBACK = 8;        // predecessors read per look-back round trip
 
 // ------------------------------------------------------------- utilities
-
-__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t status_word(uint32_t tag, uint32_t flag, uint32_t val) {
-  return ((uint64_t)tag << 40) | ((uint64_t)(flag & 0xFF) << 32) | (uint64_t)val;
-}
-__device__ __forceinline__ uint32_t status_tag(uint64_t w) { return (uint32_t)(w >> 40); }
-__device__ __forceinline__ uint32_t status_flag(uint64_t w) { return (uint32_t)(w >> 32) & 0xFF; }
-
-enum : uint32_t { FLAG_AGG = 1, FLAG_INCL = 2 };
-
-// A look-back wait polls at most this many times (each poll sleeps ~128
-// cycles, about 1 s in total) before it gives up and flags an error, so a
-// wait can never hang the device.
-constexpr uint32_t SPIN_LIMIT = 1u << 24;
-
-__device__ __forceinline__ bool spin_exhausted(uint32_t& spins, Ctrl* ctrl) {
-  if (++spins < SPIN_LIMIT) {
-    __builtin_amdgcn_s_sleep(2);
-    return false;
-  }
-  atomicOr(&ctrl->error_flags, ERR_INTERNAL_SPIN);
-  return true;
-}
 
 // record fields from its two 64-bit halves (little-endian sim_record)
 struct Rec {
@@ -100,8 +72,10 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// Exclusive sum over the workgroup; *total receives the sum of all values.
-__device__ uint32_t block_excl_sum(uint32_t v, uint32_t* lds /* NWAVE */, uint32_t* total) {
+// Exclusive sum over a workgroup of NW waves; *total receives the sum of all
+// values.  Every thread of the workgroup must call it (it holds barriers).
+template <int NW>
+__device__ uint32_t block_excl_sum_n(uint32_t v, uint32_t* lds /* NW */, uint32_t* total) {
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   uint32_t inc = v;
 #pragma unroll
@@ -113,7 +87,7 @@ __device__ uint32_t block_excl_sum(uint32_t v, uint32_t* lds /* NWAVE */, uint32
   __syncthreads();
   uint32_t pre = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < NWAVE; w++) {
+  for (int w = 0; w < NW; w++) {
     const uint32_t x = lds[w];
     if (w < (int)wave) pre += x;
     tot += x;
@@ -121,6 +95,10 @@ __device__ uint32_t block_excl_sum(uint32_t v, uint32_t* lds /* NWAVE */, uint32
   __syncthreads();
   *total = tot;
   return pre + inc - v;
+}
+
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* lds /* NWAVE */, uint32_t* total) {
+  return block_excl_sum_n<NWAVE>(v, lds, total);
 }
 
 // Segmented scan operator on packed values: a head flag in bit 63 restarts
@@ -171,15 +149,13 @@ __device__ void block_seg_scan(const uint64_t (&v)[K], uint64_t (&ex)[K], uint64
 
 // --------------------------------------------------------------- k_init
 
-__global__ void k_init(uint32_t* hist, uint64_t n_hist, Ctrl* ctrl) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
+__global__ void k_init(Ctrl* ctrl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->max_passes = 0;
     ctrl->error_flags = 0;
     ctrl->first_bad = ~0ull;
     ctrl->total_entries = 0;
   }
-  for (uint64_t j = i; j < n_hist; j += (uint64_t)gridDim.x * blockDim.x) hist[j] = 0;
 }
 
 // -------------------------------------------------------------- k_stats
@@ -290,197 +266,271 @@ __global__ __launch_bounds__(NT) void k_layout(const TraceDesc* __restrict__ des
     atomicMax(&ctrl->max_passes, L.npasses);
 }
 
-// ------------------------------------------------------------- k_keygen
-// Records -> keys, plus the digit histogram of every radix pass.  A trace's
-// tiles add their histograms into one of ceil(ntiles / 256) replicas, so no
-// histogram counter takes more than 256 atomic adds.
+// ----------------------------------------------------- radix offsets
+//
+// Each tile stores the digit histogram of the current pass in thist[tile].
+// k_group_offsets turns the rows of each histogram group (2^gshift
+// consecutive tiles of one trace, about sqrt(ntiles) of them) into
+// exclusive offsets within the group and stores the group totals;
+// k_trace_offsets turns a trace's group totals into absolute bases (trace
+// offset + digit base + earlier groups).  Separate launches make the
+// previous kernel's stores visible to plain, cached loads; no workgroup
+// waits on another.
 
-__global__ __launch_bounds__(NT) void k_keygen(const ulonglong2* __restrict__ recs, const TraceDesc* __restrict__ desc,
-                                               const TileRef* __restrict__ tiles, const TraceLayout* __restrict__ lay,
-                                               uint64_t* __restrict__ keys, uint32_t* hist) {
-  __shared__ uint32_t h[MAX_PASSES * RADIX];
-  const TileRef tr = tiles[blockIdx.x];
-  const TraceDesc T = desc[tr.trace];
-  const TraceLayout L = lay[tr.trace];
+constexpr uint32_t CHUNK = 16;   // rows loaded ahead in the serial offset loops
+constexpr int OT = 1024;         // threads of the offset kernels: 4 row ranges per digit
+constexpr int OPARTS = OT / (int)RADIX;
+
+// Exclusive prefix over `n` rows (stride RADIX) of one digit column, split
+// over OPARTS row ranges handled by the threads d, d + 256, d + 512, d + 768.
+// Returns the column total; rows are rewritten with `base` + prefix.
+template <typename In, typename Out>
+__device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t base, uint64_t (*s_part)[RADIX]) {
+  const uint32_t d = threadIdx.x % RADIX, part = threadIdx.x / RADIX;
+  const uint32_t per = (n + OPARTS - 1) / OPARTS;
+  const uint32_t r0 = min(n, part * per), r1 = min(n, r0 + per);
+  uint64_t sum = 0;
+  for (uint32_t k0 = r0; k0 < r1; k0 += CHUNK) {
+#pragma unroll
+    for (uint32_t k = 0; k < CHUNK; k++)
+      if (k0 + k < r1) sum += in[(uint64_t)(k0 + k) * RADIX + d];
+  }
+  s_part[part][d] = sum;
+  __syncthreads();
+  uint64_t run = base, total = 0;
+#pragma unroll
+  for (int q = 0; q < OPARTS; q++) {
+    const uint64_t x = s_part[q][d];
+    if (q < (int)part) run += x;
+    total += x;
+  }
+  for (uint32_t k0 = r0; k0 < r1; k0 += CHUNK) {
+    uint64_t c[CHUNK];
+#pragma unroll
+    for (uint32_t k = 0; k < CHUNK; k++) c[k] = (k0 + k < r1) ? (uint64_t)in[(uint64_t)(k0 + k) * RADIX + d] : 0ull;
+#pragma unroll
+    for (uint32_t k = 0; k < CHUNK; k++)
+      if (k0 + k < r1) {
+        out[(uint64_t)(k0 + k) * RADIX + d] = (Out)run;
+        run += c[k];
+      }
+  }
+  __syncthreads();
+  return total;
+}
+
+__global__ __launch_bounds__(OT) void k_group_offsets(Buffers b, uint32_t pass) {
+  __shared__ uint64_t s_part[OPARTS][RADIX];
+  const uint32_t g = blockIdx.x;
+  const GroupRef gr = b.groups[g];
+  const TraceDesc T = b.desc[gr.trace];
+  if (pass >= b.layout[gr.trace].npasses) return;
+  const uint32_t g_first = (g - T.group0) << T.gshift;
+  const uint32_t g_n = min(1u << T.gshift, T.ntiles - g_first);
+  uint32_t* rows = b.thist + (uint64_t)(T.tile0 + g_first) * RADIX;
+  const uint64_t total = column_prefix(rows, rows, g_n, 0, s_part);
+  if (threadIdx.x < RADIX) b.gtot[(uint64_t)g * RADIX + threadIdx.x] = (uint32_t)total;
+}
+
+__global__ __launch_bounds__(OT) void k_trace_offsets(Buffers b, uint32_t pass) {
+  __shared__ uint64_t s_part[OPARTS][RADIX];
+  __shared__ uint64_t s_base[RADIX];
+  __shared__ uint32_t s_sc[OT / 64];
+  const uint32_t t = blockIdx.x;
+  const TraceDesc T = b.desc[t];
+  if (pass >= b.layout[t].npasses) return;  // uniform over the workgroup
+  const uint32_t d = threadIdx.x % RADIX;
+  const uint32_t* gt = b.gtot + (uint64_t)T.group0 * RADIX;
+  // digit totals of the trace -> digit bases (first 256 threads)
+  const uint32_t part = threadIdx.x / RADIX, per = (T.ngroups + OPARTS - 1) / OPARTS;
+  const uint32_t r0 = min(T.ngroups, part * per), r1 = min(T.ngroups, r0 + per);
+  uint64_t sum = 0;
+  for (uint32_t k = r0; k < r1; k++) sum += gt[(uint64_t)k * RADIX + d];
+  s_part[part][d] = sum;
+  __syncthreads();
+  // every thread takes part in the scan (it holds barriers); threads past
+  // the first 256 contribute 0 and come after them
+  uint64_t tot = 0;
+  if (threadIdx.x < RADIX) {
+#pragma unroll
+    for (int q = 0; q < OPARTS; q++) tot += s_part[q][d];
+  }
+  uint32_t all;
+  const uint32_t ex = block_excl_sum_n<OT / 64>((uint32_t)tot, s_sc, &all);
+  if (threadIdx.x < RADIX) s_base[d] = T.off + ex;
+  __syncthreads();
+  // absolute base of every group: digit base + earlier groups
+  (void)column_prefix(gt, b.gbase + (uint64_t)T.group0 * RADIX, T.ngroups, s_base[d], s_part);
+}
+
+// Add one digit per lane of the wave to an LDS histogram.  Lanes holding the
+// same digit are matched with eight ballots and only the lowest of them adds
+// the group's size, so a skewed digit (the top key bits often take a handful
+// of values) costs one LDS atomic instead of 64 conflicting ones.
+__device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool valid) {
+  const uint64_t live = __ballot(valid);
+  if (!live) return;
+  uint64_t m = live;
+#pragma unroll
+  for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
+    const uint64_t bal = __ballot((dg >> bt) & 1u);
+    m &= ((dg >> bt) & 1u) ? bal : ~bal;
+  }
+  const uint64_t lt = (1ull << __lane_id()) - 1ull;
+  if (valid && (m & lt) == 0) atomicAdd(&h[dg], (uint32_t)__popcll(m));
+}
+
+// ------------------------------------------------------------- k_keygen
+// Records -> keys, and the tile histogram of radix digit 0.
+
+__global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
+  __shared__ uint32_t h[RADIX];
+  const TileRef tr = b.tiles[blockIdx.x];
+  const TraceDesc T = b.desc[tr.trace];
+  const TraceLayout L = b.layout[tr.trace];
   if (L.npasses == 0) return;
-  const uint32_t np = L.npasses;
-  for (uint32_t i = threadIdx.x; i < np * RADIX; i += NT) h[i] = 0;
+  h[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t start = (uint64_t)tr.local * TILE;
   const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-  const ulonglong2* p = recs + T.off + start;
-  uint64_t* kout = keys + T.off + start;
+  const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
+  uint64_t* kout = b.keys[0] + T.off + start;
 #pragma unroll 4
   for (int r = 0; r < ITEMS; r++) {
     const uint32_t j = threadIdx.x + r * NT;
-    if (j < n_in) {
+    const bool valid = j < n_in;
+    uint64_t k = 0;
+    if (valid) {
       const Rec x = unpack_rec(p[j]);
-      const uint64_t k = make_key(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
+      k = make_key(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
       kout[j] = k;
-      for (uint32_t q = 0; q < np; q++) atomicAdd(&h[q * RADIX + ((k >> (2 + RADIX_BITS * q)) & (RADIX - 1))], 1u);
     }
+    wave_hist_add(h, (uint32_t)(k >> 2) & (RADIX - 1), valid);
   }
   __syncthreads();
-  uint32_t* gh = hist + (uint64_t)(T.rep0 + tr.local % T.nrep) * MAX_PASSES * RADIX;
-  for (uint32_t i = threadIdx.x; i < np * RADIX; i += NT) {
-    const uint32_t c = h[i];
-    if (c) atomicAdd(&gh[i], c);
-  }
+  b.thist[(uint64_t)blockIdx.x * RADIX + threadIdx.x] = h[threadIdx.x];
 }
 
-// ------------------------------------------------------------- k_digits
-// Sum a trace's histogram replicas and scan them into digit bases, written
-// over the trace's first replica.
+// ------------------------------------------------------------ k_upsweep
+// Tile histogram of radix digit `pass` (keys in the buffer that pass reads).
 
-__global__ __launch_bounds__(NT) void k_digits(const TraceDesc* __restrict__ desc, const TraceLayout* __restrict__ lay,
-                                               uint32_t* hist) {
-  __shared__ uint32_t sc[NWAVE];
-  const uint32_t trace = blockIdx.x;
-  const TraceDesc T = desc[trace];
-  const uint32_t np = lay[trace].npasses;
-  uint32_t* gh = hist + (uint64_t)T.rep0 * MAX_PASSES * RADIX;
-  for (uint32_t q = 0; q < np; q++) {
-    uint32_t v = 0;
-    for (uint32_t r = 0; r < T.nrep; r++) v += gh[(uint64_t)r * MAX_PASSES * RADIX + q * RADIX + threadIdx.x];
-    uint32_t tot;
-    const uint32_t ex = block_excl_sum(v, sc, &tot);
-    gh[q * RADIX + threadIdx.x] = ex;
+__global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
+  __shared__ uint32_t h[RADIX];
+  const TileRef tr = b.tiles[blockIdx.x];
+  const TraceDesc T = b.desc[tr.trace];
+  const TraceLayout L = b.layout[tr.trace];
+  if (pass >= L.npasses) return;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t shift = 2 + RADIX_BITS * pass;
+  const uint64_t start = (uint64_t)tr.local * TILE;
+  const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
+  const uint64_t* src = b.keys[pass & 1] + T.off + start;
+  uint64_t k[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++) {
+    const uint32_t j = threadIdx.x + r * NT;
+    k[r] = j < n_in ? src[j] : 0ull;
   }
+#pragma unroll
+  for (int r = 0; r < ITEMS; r++)
+    wave_hist_add(h, (uint32_t)(k[r] >> shift) & (RADIX - 1), threadIdx.x + r * NT < n_in);
+  __syncthreads();
+  b.thist[(uint64_t)blockIdx.x * RADIX + threadIdx.x] = h[threadIdx.x];
 }
 
-// ---------------------------------------------------------- k_sort_pass
+// ------------------------------------------------------------ k_scatter
 //
 // One stable LSD pass on the 8-bit digit at bits [2 + 8 pass, 10 + 8 pass).
-// Launched cooperatively: every workgroup is resident, and workgroup b
-// handles tiles b, b + G, b + 2G, ... in order, so the lowest unfinished
-// tile never waits on an unfinished one and the look-back always ends.
 // Keys are loaded wave-striped (key index = wave * 1024 + item * 64 + lane)
 // so that lane order within an item is key order.  Each item's digit is
 // matched across the wave with eight ballots; the lowest matching lane
 // advances the wave's per-digit counter, which gives every key a stable
-// rank within its wave.  Per-digit wave offsets, the tile's digit counts
-// and the look-back over earlier tiles of the trace (eight predecessors per
-// round trip) give each key its destination; keys are staged in LDS in
-// destination order and written out in runs per digit.
+// rank within its wave.  Per-digit wave offsets, the tile's digit starts and
+// the offsets left by the upsweep give each key its destination; keys are
+// staged in LDS in destination order and written out in runs per digit.
 
-__global__ __launch_bounds__(NT) void k_sort_pass(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
-                                                  const TraceDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
-                                                  const TraceLayout* __restrict__ lay, const uint32_t* __restrict__ hist,
-                                                  uint64_t* status, Ctrl* ctrl, uint32_t n_tiles, uint32_t pass,
-                                                  uint32_t tag) {
+__global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
   __shared__ uint64_t s_keys[TILE];
   __shared__ uint32_t s_wh[NWAVE][RADIX];
   __shared__ uint32_t s_dstart[RADIX];
   __shared__ uint64_t s_gbase[RADIX];
   __shared__ uint32_t s_scan[NWAVE];
 
+  const uint32_t tile = blockIdx.x;
+  const TileRef tr = b.tiles[tile];
+  const TraceDesc T = b.desc[tr.trace];
+  const TraceLayout L = b.layout[tr.trace];
+  if (pass >= L.npasses) return;  // uniform over the workgroup
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   const uint32_t d = threadIdx.x;
+  const uint32_t shift = 2 + RADIX_BITS * pass;
+  const uint64_t start = (uint64_t)tr.local * TILE;
+  const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
+  const uint64_t* src = b.keys[pass & 1] + T.off + start;
+  uint64_t* kout = b.keys[(pass + 1) & 1];
 
-  for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const TileRef tr = tiles[tile];
-    const TraceDesc T = desc[tr.trace];
-    const TraceLayout L = lay[tr.trace];
-    if (pass >= L.npasses) continue;  // uniform over the workgroup
-    const uint32_t shift = 2 + RADIX_BITS * pass;
-    const uint64_t start = (uint64_t)tr.local * TILE;
-    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const uint64_t* src = kin + T.off + start;
-
-    for (uint32_t i = threadIdx.x; i < NWAVE * RADIX; i += NT) (&s_wh[0][0])[i] = 0;
-    __syncthreads();
-
-    uint64_t key[ITEMS];
-    uint32_t rank[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
-      key[i] = (j < n_in) ? src[j] : ~0ull;  // padding sorts last (digit 255, after every real key)
+  for (int w = 0; w < NWAVE; w++) s_wh[w][d] = 0;
+  // destination base of each digit: group base + offset within the group
+  const uint64_t gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] +
+                      b.thist[(uint64_t)tile * RADIX + d];  // offset within the group
+  __syncthreads();
+
+  uint64_t key[ITEMS];
+  uint32_t rank[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+    key[i] = (j < n_in) ? src[j] : ~0ull;  // padding sorts last (digit 255, after every real key)
+  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+    uint64_t m = ~0ull;
+#pragma unroll
+    for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
+      const uint64_t bal = __ballot((dg >> bt) & 1u);
+      m &= ((dg >> bt) & 1u) ? bal : ~bal;
     }
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-      uint64_t m = ~0ull;
-#pragma unroll
-      for (int b = 0; b < (int)RADIX_BITS; b++) {
-        const uint64_t bal = __ballot((dg >> b) & 1u);
-        m &= ((dg >> b) & 1u) ? bal : ~bal;
-      }
-      const uint32_t before = (uint32_t)__popcll(m & lt_mask);
-      const uint32_t old = s_wh[wave][dg];
-      if (before == 0) s_wh[wave][dg] = old + (uint32_t)__popcll(m);
-      rank[i] = old + before;
-    }
-    __syncthreads();
+    const uint32_t before = (uint32_t)__popcll(m & lt_mask);
+    const uint32_t old = s_wh[wave][dg];
+    if (before == 0) s_wh[wave][dg] = old + (uint32_t)__popcll(m);
+    rank[i] = old + before;
+  }
+  __syncthreads();
 
-    // per digit: offsets of the waves, tile count, tile-local start
-    uint32_t cnt = 0;
+  // per digit: offsets of the waves, tile count, tile-local start
+  uint32_t cnt = 0;
 #pragma unroll
-    for (int w = 0; w < NWAVE; w++) {
-      const uint32_t c = s_wh[w][d];
-      s_wh[w][d] = cnt;
-      cnt += c;
-    }
-    uint32_t tot;
-    const uint32_t dstart = block_excl_sum(cnt, s_scan, &tot);
-    s_dstart[d] = dstart;
-    const uint32_t pub = (d == RADIX - 1) ? cnt - (TILE - n_in) : cnt;  // padding is not published
-
-    uint64_t* st = status + (uint64_t)tile * RADIX;
-    uint32_t excl = 0;
-    if (tr.local == 0) {
-      st_agent(&st[d], status_word(tag, FLAG_INCL, pub));
-    } else {
-      st_agent(&st[d], status_word(tag, FLAG_AGG, pub));
-      // Look back over earlier tiles of this trace, LOOKBACK at a time.  The
-      // first tile of a trace always publishes an inclusive count.
-      int64_t p = (int64_t)tile - 1;
-      const int64_t first = (int64_t)T.tile0;
-      uint32_t spins = 0;
-      bool done = false;
-      while (!done) {
-        uint64_t w[LOOKBACK];
-#pragma unroll
-        for (uint32_t k = 0; k < LOOKBACK; k++)
-          w[k] = (p - (int64_t)k >= first) ? ld_agent(&status[(uint64_t)(p - k) * RADIX + d]) : 0ull;
-        uint32_t k = 0;
-        for (; k < LOOKBACK && p - (int64_t)k >= first; k++) {
-          if (status_tag(w[k]) != tag || status_flag(w[k]) == 0) break;
-          excl += (uint32_t)w[k];
-          if (status_flag(w[k]) == FLAG_INCL) {
-            done = true;
-            break;
-          }
-        }
-        if (done) break;
-        p -= k;
-        if (k < LOOKBACK && spin_exhausted(spins, ctrl)) break;
-      }
-      st_agent(&st[d], status_word(tag, FLAG_INCL, excl + pub));
-    }
-    const uint32_t* base = hist + (uint64_t)T.rep0 * MAX_PASSES * RADIX + (uint64_t)pass * RADIX;
-    s_gbase[d] = T.off + (uint64_t)base[d] + excl - dstart;
-    __syncthreads();
+  for (int w = 0; w < NWAVE; w++) {
+    const uint32_t c = s_wh[w][d];
+    s_wh[w][d] = cnt;
+    cnt += c;
+  }
+  uint32_t tot;
+  const uint32_t dstart = block_excl_sum(cnt, s_scan, &tot);
+  s_dstart[d] = dstart;
+  s_gbase[d] = gb - dstart;
+  __syncthreads();
 
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-      s_keys[s_dstart[dd] + s_wh[wave][dd] + rank[i]] = key[i];
-    }
-    __syncthreads();
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+    s_keys[s_dstart[dd] + s_wh[wave][dd] + rank[i]] = key[i];
+  }
+  __syncthreads();
 #pragma unroll 4
-    for (int r = 0; r < ITEMS; r++) {
-      const uint32_t j = threadIdx.x + r * NT;
-      if (j < n_in) {
-        const uint64_t k = s_keys[j];
-        const uint32_t dd = (uint32_t)(k >> shift) & (RADIX - 1);
-        const uint64_t dst = s_gbase[dd] + j;
-        if (dst - T.off < T.n) kout[dst] = k;
-        else atomicOr(&ctrl->error_flags, ERR_INTERNAL_BOUNDS);
-      }
+  for (int r = 0; r < ITEMS; r++) {
+    const uint32_t j = threadIdx.x + r * NT;
+    if (j < n_in) {
+      const uint64_t k = s_keys[j];
+      const uint32_t dd = (uint32_t)(k >> shift) & (RADIX - 1);
+      const uint64_t dst = s_gbase[dd] + j;
+      if (dst - T.off < T.n) kout[dst] = k;
+      else atomicOr(&b.ctrl->error_flags, ERR_INTERNAL_BOUNDS);
     }
-    __syncthreads();  // LDS is reused by the next tile
   }
 }
 
@@ -503,15 +553,22 @@ __device__ __forceinline__ uint32_t cnt16(uint64_t packed, uint32_t q) { return 
 
 // Pairs of one element of class c against the open-run counts run[] (the
 // counts of earlier elements of its location / block / epoch / thread runs
-// inside the tile).
+// inside the tile, three 16-bit class fields per word).  The runs are
+// nested, so the field-wise differences location - block and epoch - thread
+// are plain 64-bit subtractions without borrows.
 __device__ __forceinline__ void tile_pairs(uint32_t c, const uint64_t run[4], uint32_t v[5]) {
-  uint32_t xb[3], in[3];
-#pragma unroll
-  for (int q = 0; q < 3; q++) {
-    xb[q] = cnt16(run[0], q) - cnt16(run[1], q);
-    in[q] = cnt16(run[2], q) - cnt16(run[3], q);
-  }
-  element_pairs<uint32_t>(c, xb, in, v);
+  const uint64_t xbp = run[0] - run[1];          // other blocks of the location
+  const uint64_t tot = xbp + (run[2] - run[3]);  // + other threads of the block and epoch
+  const uint32_t tR = (uint32_t)tot & 0xFFFFu, tW = (uint32_t)(tot >> 16) & 0xFFFFu;
+  const uint32_t tA = (uint32_t)(tot >> 32) & 0xFFFFu;
+  const uint32_t xR = (uint32_t)xbp & 0xFFFFu, xW = (uint32_t)(xbp >> 16) & 0xFFFFu;
+  const uint32_t xA = (uint32_t)(xbp >> 32) & 0xFFFFu;
+  const bool r = c == CLS_R, w = c == CLS_W, a = c == CLS_A;
+  v[K_WW] = w ? tW : 0u;
+  v[K_RW] = r ? tW : (w ? tR : 0u);
+  v[K_AW] = w ? tA : (a ? tW : 0u);
+  v[K_AR] = r ? tA : (a ? tR : 0u);
+  v[K_XB] = (r ? 0u : xR) + xW + (a ? 0u : xA);
 }
 
 __device__ __forceinline__ uint32_t state_word(const State& s, int i) {
@@ -650,8 +707,14 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
   uint64_t exA[4], totA[4];
   block_seg_scan<4>(aggA, exA, totA, s_scanA);
 
-  // ---- pass B: pairs per element, summed per location run; lead data
+  // ---- pass B: pairs per element, summed per location run; lead data.
+  //      Locations that end in this thread are counted here when they also
+  //      start in it; the thread's first location (it may start in an
+  //      earlier thread) is settled after the scan.
   uint64_t aggB[3] = {0, 0, 0};
+  uint32_t n_emit = 0;
+  bool pend = false;
+  uint64_t pend0 = 0, pend1 = 0;
   {
     uint64_t run[4];
     bool seen[4];
@@ -660,6 +723,8 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
       run[l] = exA[l] & ~SEGF;
       seen[l] = (exA[l] & SEGF) != 0;
     }
+    // only threads before the tile's first location head hold lead elements
+    const bool lead_thread = !seen[0];
     uint32_t leadc[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     uint32_t leads[5] = {0, 0, 0, 0, 0};
 #pragma unroll
@@ -679,26 +744,47 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
       aggB[1] += (uint64_t)v[K_AW] | ((uint64_t)v[K_AR] << 32);
       aggB[2] += (uint64_t)v[K_XB];
 #pragma unroll
-      for (int l = 0; l < 4; l++) {
-        if (!seen[l]) leadc[l][c]++;
-        run[l] += 1ull << (16 * c);
-      }
-      if (!seen[0]) {
+      for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
+      if (lead_thread) {
 #pragma unroll
-        for (int k = 0; k < 5; k++) leads[k] += v[k];
+        for (int l = 0; l < 4; l++)
+          if (!seen[l]) leadc[l][c]++;
+        if (!seen[0]) {
+#pragma unroll
+          for (int k = 0; k < 5; k++) leads[k] += v[k];
+        }
+      }
+      const uint32_t j = ITEMS * tid + i;
+      bool last;
+      if (j + 1 == n_in) last = s_taillast != 0;
+      else if (i + 1 < ITEMS) last = (meta[i + 1] & 7u) == 0;
+      else last = s_firstlv[tid + 1] == 0;
+      if (!last) continue;
+      if (aggB[0] & SEGF) {  // the location started in this thread
+        if (((aggB[0] | aggB[1]) & ~SEGF) != 0) n_emit++;
+      } else {
+        pend = true;
+        pend0 = aggB[0];
+        pend1 = aggB[1];
       }
     }
+    if (lead_thread) {
 #pragma unroll
-    for (int l = 0; l < 4; l++)
+      for (int l = 0; l < 4; l++)
 #pragma unroll
-      for (int q = 0; q < 3; q++)
-        if (leadc[l][q]) atomicAdd(&s_lead[l * 3 + q], leadc[l][q]);
+        for (int q = 0; q < 3; q++)
+          if (leadc[l][q]) atomicAdd(&s_lead[l * 3 + q], leadc[l][q]);
 #pragma unroll
-    for (int k = 0; k < 5; k++)
-      if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
+      for (int k = 0; k < 5; k++)
+        if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
+    }
   }
   uint64_t exB[3], totB[3];
   block_seg_scan<3>(aggB, exB, totB, s_scanB);  // contains a barrier: s_lead and s_min are complete after it
+  // the thread's first location: complete here only if it started in the
+  // tile (a location head in an earlier thread); otherwise it belongs to an
+  // earlier tile and is finished by k_scan_cross
+  if (pend && (exB[0] & SEGF) && ((((exB[0] + pend0) | (exB[1] + pend1)) & ~SEGF) != 0)) n_emit++;
 
   // ---- the tile summary (lanes of wave 0 write its words)
   if (wave == 0) {
@@ -732,8 +818,8 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
   }
 
   // ---- complete locations: started after the tile's first location head
-  //      and ended inside the tile.  Reported at their last element.
-  uint32_t n_emit = 0;
+  //      and ended inside the tile.  Written (rarely: only threads that
+  //      counted one) at their last element.
   auto walk_emit = [&](RaceOut* dst, uint32_t cap, uint32_t pos) {
     uint64_t run[4];
 #pragma unroll
@@ -770,15 +856,10 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
       S[K_AW] = (uint32_t)s1; S[K_AR] = (uint32_t)(s1 >> 32);
       S[K_XB] = (uint32_t)s2;
       if (S[K_WW] + S[K_RW] + S[K_AW] + S[K_AR] == 0) continue;
-      if (dst) {
-        if (pos < cap) write_entry(dst + pos, tr.trace, L, key[i], S);
-        pos++;
-      } else {
-        n_emit++;
-      }
+      if (pos < cap) write_entry(dst + pos, tr.trace, L, key[i], S);
+      pos++;
     }
   };
-  walk_emit(nullptr, 0, 0);
   uint32_t tile_emit;
   const uint32_t my_off = block_excl_sum(n_emit, s_scan32, &tile_emit);
   uint32_t cap;
@@ -966,9 +1047,7 @@ __global__ void k_reset_errors(Ctrl* ctrl, uint32_t mask) {
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 hipError_t launch_init(const Buffers& b, hipStream_t s) {
-  const uint64_t nh = (uint64_t)b.n_reps * MAX_PASSES * RADIX;
-  const uint32_t grid = max(1u, min(2048u, cdiv(nh, NT)));
-  hipLaunchKernelGGL(k_init, dim3(grid), dim3(NT), 0, s, b.hist, nh, b.ctrl);
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, b.ctrl);
   return hipGetLastError();
 }
 hipError_t launch_stats(const Buffers& b, hipStream_t s) {
@@ -984,29 +1063,26 @@ hipError_t launch_layout(const Buffers& b, hipStream_t s) {
 }
 hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_keygen, dim3(b.n_tiles), dim3(NT), 0, s, (const ulonglong2*)b.records, b.desc, b.tiles,
-                     b.layout, b.keys[0], b.hist);
+  hipLaunchKernelGGL(k_keygen, dim3(b.n_tiles), dim3(NT), 0, s, b);
   return hipGetLastError();
 }
-hipError_t launch_digits(const Buffers& b, hipStream_t s) {
-  if (!b.n_traces) return hipSuccess;
-  hipLaunchKernelGGL(k_digits, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.layout, b.hist);
-  return hipGetLastError();
-}
-hipError_t launch_sort_pass(const Buffers& b, uint32_t pass, uint32_t tag, hipStream_t s) {
+hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
-  const uint64_t* kin = b.keys[pass & 1];
-  uint64_t* kout = b.keys[(pass + 1) & 1];
-  const TraceDesc* desc = b.desc;
-  const TileRef* tiles = b.tiles;
-  const TraceLayout* lay = b.layout;
-  const uint32_t* hist = b.hist;
-  uint64_t* status = b.sort_status;
-  Ctrl* ctrl = b.ctrl;
-  uint32_t n_tiles = b.n_tiles;
-  void* args[] = {&kin, &kout, &desc, &tiles, &lay, &hist, &status, &ctrl, &n_tiles, &pass, &tag};
-  const uint32_t grid = min(b.n_tiles, b.sort_grid);
-  return hipLaunchCooperativeKernel((const void*)k_sort_pass, dim3(grid), dim3(NT), args, 0, s);
+  if (pass > 0) {  // digit 0's histograms come from k_keygen
+    hipLaunchKernelGGL(k_upsweep, dim3(b.n_tiles), dim3(NT), 0, s, b, pass);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_group_offsets, dim3(b.n_groups), dim3(OT), 0, s, b, pass);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_trace_offsets, dim3(b.n_traces), dim3(OT), 0, s, b, pass);
+  return hipGetLastError();
+}
+hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s) {
+  if (!b.n_tiles) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(b.n_tiles), dim3(NT), 0, s, b, pass);
+  return hipGetLastError();
 }
 hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
@@ -1033,12 +1109,6 @@ hipError_t launch_scan_out(const Buffers& b, uint32_t passes_done, hipStream_t s
 hipError_t launch_reset_errors(const Buffers& b, uint32_t mask, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_errors, dim3(1), dim3(64), 0, s, b.ctrl, mask);
   return hipGetLastError();
-}
-
-int sort_pass_blocks_per_cu() {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_sort_pass, NT, 0) != hipSuccess) return 0;
-  return nb;
 }
 
 }  // namespace sc

@@ -13,8 +13,7 @@ constexpr int ITEMS = 16;          // keys per thread
 constexpr int TILE = NT * ITEMS;   // keys per tile (sort and scan)
 constexpr int SW = 45;             // 32-bit words of a serialised segment State
 constexpr int GROUP = 256;         // tiles per group of the output prefix
-constexpr uint32_t TAG_MAX = (1u << 24) - 1;
-constexpr uint32_t REP_TILES = 256; // tiles sharing one histogram replica
+constexpr uint32_t MAX_HGROUP_SHIFT = 12; // histogram groups hold at most 4096 tiles
 
 // kernel-side error flags beyond the per-trace layout errors of keys.h
 enum : uint32_t { ERR_STAGE_OVERFLOW = 16 };
@@ -25,14 +24,20 @@ struct TraceDesc {   // one trace of a call (host-filled)
   uint32_t tpb;      // threads per block
   uint32_t tile0;    // first tile
   uint32_t ntiles;
-  uint32_t rep0;     // first histogram replica
-  uint32_t nrep;     // histogram replicas (ceil(ntiles / REP_TILES))
-  uint32_t pad;
+  uint32_t group0;   // first histogram group (runs of 2^gshift tiles of this trace)
+  uint32_t ngroups;
+  uint32_t gshift;   // log2 of the tiles per histogram group (about sqrt(ntiles))
+  uint32_t pad[3];
 };
 
 struct TileRef {     // tile -> (trace, tile within trace)
   uint32_t trace;
   uint32_t local;
+};
+
+struct GroupRef {    // histogram group -> trace
+  uint32_t trace;
+  uint32_t pad;
 };
 
 struct TileOut {     // per tile, from the tile scan
@@ -61,9 +66,11 @@ struct Buffers {            // device pointers of one call
   const TileRef* tiles;
   TraceStats* stats_part;   // [tile]
   TraceLayout* layout;      // [trace]
-  uint32_t* hist;           // [replica][MAX_PASSES][RADIX]; replica rep0 of a trace ends up holding digit bases
   uint64_t* keys[2];
-  uint64_t* sort_status;    // [tile][RADIX]
+  const GroupRef* groups;   // [group]
+  uint32_t* thist;          // [tile][RADIX] digit counts of the current pass -> offsets within the group
+  uint32_t* gtot;           // [group][RADIX] group totals
+  uint64_t* gbase;          // [group][RADIX] absolute digit bases of the group
   uint32_t* agg;            // [tile][SW]
   TileOut* tout;            // [tile]
   RaceOut* cross;           // [tile]
@@ -76,23 +83,21 @@ struct Buffers {            // device pointers of one call
   uint64_t out_cap;
   uint32_t n_traces;
   uint32_t n_tiles;
-  uint32_t n_reps;
-  uint32_t sort_grid;       // co-resident workgroups of the cooperative radix pass
+  uint32_t n_groups;        // histogram groups
 };
 
 // Kernel stages, in launch order.
-enum Stage { ST_INIT = 0, ST_STATS, ST_LAYOUT, ST_KEYGEN, ST_DIGITS, ST_SORT, ST_SCAN, ST_CROSS, ST_OUT, ST_COUNT };
+enum Stage { ST_INIT = 0, ST_STATS, ST_LAYOUT, ST_KEYGEN, ST_UPSWEEP, ST_SORT, ST_SCAN, ST_CROSS, ST_OUT, ST_COUNT };
 
 hipError_t launch_init(const Buffers& b, hipStream_t s);
 hipError_t launch_stats(const Buffers& b, hipStream_t s);
 hipError_t launch_layout(const Buffers& b, hipStream_t s);
 hipError_t launch_keygen(const Buffers& b, hipStream_t s);
-hipError_t launch_digits(const Buffers& b, hipStream_t s);
-hipError_t launch_sort_pass(const Buffers& b, uint32_t pass, uint32_t tag, hipStream_t s);
+hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s);  // histograms and offsets
+hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s);
 hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t s);
 hipError_t launch_scan_cross(const Buffers& b, uint32_t passes_done, hipStream_t s);
 hipError_t launch_scan_out(const Buffers& b, uint32_t passes_done, hipStream_t s);
 hipError_t launch_reset_errors(const Buffers& b, uint32_t mask, hipStream_t s);
-int sort_pass_blocks_per_cu();
 
 }  // namespace sc

@@ -208,6 +208,35 @@ def test_results_identical_across_repeats_and_contexts(ctx):
         other.close()
 
 
+def test_graph_replays_match_eager():
+    """Graph mode: the first call of a shape is captured, later ones replay
+    the graph.  Replays are interleaved with eager work of other shapes and
+    host synchronisations, and every result is checked."""
+    import paper_1905_01833_amd as pkg
+
+    g = pkg.Context(0, graphs=True)
+    try:
+        r, _ = tracegen.c1(n_blocks=16, inject_rate=1e-3, seed=99)
+        want, wsum = oracle.closed_form(r, tpb=256)
+        dev = torch.from_numpy(r.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+        other = tracegen.c0()
+        other_want, _ = oracle.closed_form(other, tpb=256)
+        stream = torch.cuda.Stream()
+        for rep in range(6):
+            say(f"graph replay {rep}")
+            with torch.cuda.stream(stream):
+                got, gsum = g.check_traces_device(dev, None, 256, stream=stream.cuda_stream)
+            assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes(), rep
+            torch.cuda.synchronize()
+            if rep % 2 == 1:  # a different shape in between forces a new capture
+                o, _ = g.check_traces(other, None, 256)
+                assert o.tobytes() == other_want.tobytes()
+            x = torch.randn(1 << 20, device="cuda:0").sum().item()  # unrelated eager work
+            assert x == x
+    finally:
+        g.close()
+
+
 # ------------------------------------------------------------ error paths
 
 def test_error_paths_leave_context_usable(ctx):
