@@ -38,7 +38,7 @@ METRIC = "access records checked/sec and achieved HBM GB/s (batched vs plain, bi
 #   scan   reads every 8-byte key once (tile scan; the crossing-location
 #          and output kernels touch per-tile data only)
 BYTES_PER_RECORD = {"stats": 16, "keygen": 24, "sort_pass": 16, "scan_tiles": 8}
-KERNEL_SYMBOL = {"stats": "k_stats", "keygen": "k_keygen", "sort_pass": "k_sort_pass", "scan_tiles": "k_scan_tiles"}
+KERNEL_SYMBOL = {"stats": "k_stats", "keygen": "k_keygen", "sort_pass": "k_scatter", "scan_tiles": "k_scan_tiles"}
 
 
 def workload(name):
@@ -101,6 +101,89 @@ def pmc_traffic(stage, n_records):
     return d.get("bytes_per_launch")
 
 
+def profile_roofline(stage_ms, stage_launches, steps, n):
+    """Roofline of the dominant kernel from per-stage event times."""
+    dom = max(BYTES_PER_RECORD, key=lambda s: stage_ms.get(s, 0.0))
+    avg_ms = stage_ms[dom] / max(1, stage_launches[dom])
+    alg_bytes = BYTES_PER_RECORD[dom] * n
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    return dom, {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
+                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                 "traffic": pmc_traffic(dom, n), "avg_launch_ms": round(avg_ms, 5),
+                 "launches_per_step": stage_launches[dom] / steps, "alg_bytes_per_launch": alg_bytes}
+
+
+def batched_leg(pkg, torch, steps, log):
+    """The batched workload (4096 traces of uneven size): one autotuned,
+    graph-replayed call over all traces against one plain call per trace
+    (default shape, no graph) on the same device records."""
+    log("batched: generating c3")
+    recs, offsets, tpb, desc = workload("c3")
+    n = int(len(recs))
+    n_tr = len(offsets) - 1
+    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    sptr = side.cuda_stream
+    bctx = pkg.Context(0, graphs=True)
+    log("batched: autotune")
+    with torch.cuda.stream(side):
+        tuning = bctx.autotune(dev, offsets, tpb, stream=sptr, reps=1)
+        races, summ = bctx.check_traces_device(dev, offsets, tpb, stream=sptr)  # capture
+    torch.cuda.synchronize()
+    log("batched: timed")
+    t0 = time.perf_counter()
+    with torch.cuda.stream(side):
+        for _ in range(steps):
+            races, summ = bctx.check_traces_device(dev, offsets, tpb, stream=sptr)
+    torch.cuda.synchronize()
+    b_s = (time.perf_counter() - t0) / steps
+    bctx.close()
+
+    # stage times of the same call shape (events, no graph)
+    pctx = pkg.Context(0, profile=True)
+    pctx.set_tuning(tuning["size_class"], tuning)
+    stage_ms, stage_launches = {}, {}
+    for _ in range(2):
+        pctx.check_traces_device(dev, offsets, tpb, stream=sptr)
+        for name, (ms, launches) in pctx.stage_times().items():
+            stage_ms[name] = stage_ms.get(name, 0.0) + ms
+            stage_launches[name] = stage_launches.get(name, 0) + launches
+    pctx.close()
+    _, roof = profile_roofline(stage_ms, stage_launches, 2, n)
+
+    log("batched: plain per-trace calls")
+    plain = pkg.Context(0)
+    views = [dev[int(offsets[i]) : int(offsets[i + 1])] for i in range(n_tr)]
+    for i in range(min(8, n_tr)):  # warm the buffers
+        plain.check_traces_device(views[i], None, int(tpb[i]), stream=sptr)
+    per = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_tr):
+        per.append(plain.check_traces_device(views[i], None, int(tpb[i]), stream=sptr))
+    torch.cuda.synchronize()
+    p_s = time.perf_counter() - t0
+    plain.close()
+    # the batched entries are the per-trace entries with trace numbers
+    parts = []
+    for i, (r, _) in enumerate(per):
+        r = r.copy()
+        r["trace"] = i
+        parts.append(r)
+    joined = np.concatenate(parts) if parts else races[:0]
+    same = joined.tobytes() == races.tobytes() and all(
+        summ[i].tobytes() == per[i][1][0].tobytes() for i in range(n_tr))
+    return {
+        "workload": desc["workload"], "traces": n_tr, "records": n,
+        "value": n / b_s, "unit": "records/s", "ms_per_step": 1e3 * b_s, "steps": steps,
+        "plain_value": n / p_s, "plain_ms": 1e3 * p_s, "speedup_vs_plain": p_s / b_s,
+        "racing_locations": int(len(races)), "tuning": tuning, "roofline": roof,
+        "stage_ms_per_step": {k: round(v / 2, 4) for k, v in stage_ms.items()},
+        "batched_equals_per_trace": bool(same),
+    }, (recs, offsets, tpb, races, summ)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +192,8 @@ def main():
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3"])
     ap.add_argument("--cpu-budget", type=int, default=1 << 24, help="records in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--batched-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this check runs on one GPU; --gpus {args.gpus} is not supported "
@@ -119,6 +204,9 @@ def main():
 
     import paper_1905_01833_amd as pkg
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     recs, offsets, tpb, desc = workload(args.workload)
     n = int(len(recs))
     dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
@@ -126,6 +214,7 @@ def main():
     ctx = pkg.Context(0, profile=True)
     stream = torch.cuda.current_stream().cuda_stream
 
+    log(f"{args.workload}: warmup")
     for _ in range(args.warmup):
         ctx.check_traces_device(dev, offsets, tpb, stream=stream)
     torch.cuda.synchronize()
@@ -140,21 +229,11 @@ def main():
             stage_launches[name] = stage_launches.get(name, 0) + launches
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    log(f"{args.workload}: timed {args.steps} steps")
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
-
-    # dominant kernel and its roofline
-    dom = max(BYTES_PER_RECORD, key=lambda s: stage_ms.get(s, 0.0))
-    avg_ms = stage_ms[dom] / max(1, stage_launches[dom])
-    alg_bytes = BYTES_PER_RECORD[dom] * n
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = pmc_traffic(dom, n)
-    roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": traffic, "avg_launch_ms": round(avg_ms, 5),
-                "launches_per_step": stage_launches[dom] / args.steps,
-                "alg_bytes_per_launch": alg_bytes}
+    _, roofline = profile_roofline(stage_ms, stage_launches, args.steps, n)
     passes = stage_launches.get("sort_pass", 0) / args.steps
     pipe_bytes = n * (16 + 24 + 16 * passes + 8)
     stages = {k: round(v / args.steps, 4) for k, v in stage_ms.items()}
@@ -180,7 +259,9 @@ def main():
         "roofline": roofline,
     }
 
+    ok = True
     if not args.no_cpu:
+        log("cpu baseline (oracle)")
         want, wsum, n_cpu, k_cpu, dt = cpu_baseline(recs, offsets, tpb, args.cpu_budget)
         if k_cpu == len(offsets) - 1:
             parity = races.tobytes() == want.tobytes() and summ.tobytes() == wsum.tobytes()
@@ -191,11 +272,31 @@ def main():
                                "sample": f"first {k_cpu} trace(s) of the workload, {n_cpu} records, oracle group-count "
                                          f"tier, {dt:.2f} s"}
         out["parity"] = "bit-exact" if parity else "MISMATCH"
-        if not parity:
-            print(json.dumps(out))
-            sys.exit(1)
+        ok = ok and parity
     ctx.close()
+    del dev
+
+    if not args.no_batched and args.workload != "c3":
+        b, (brecs, boff, btpb, braces, bsumm) = batched_leg(pkg, torch, args.batched_steps, log)
+        if not args.no_cpu:
+            # oracle on the leading traces of the batch (about 2^21 records)
+            k = 1
+            while k < len(boff) - 1 and int(boff[k + 1]) <= (1 << 21):
+                k += 1
+            import oracle
+
+            want, wsum = oracle.closed_form(brecs[: int(boff[k])], boff[: k + 1], btpb[:k])
+            sub = braces[braces["trace"] < k]
+            b["parity"] = ("bit-exact" if sub.tobytes() == want.tobytes() and bsumm[:k].tobytes() == wsum.tobytes()
+                           else "MISMATCH")
+            b["parity_sample"] = f"oracle on the first {k} traces ({int(boff[k])} records); all traces against " \
+                                 "per-trace plain calls"
+            ok = ok and b["parity"] == "bit-exact"
+        ok = ok and b["batched_equals_per_trace"]
+        out["batched"] = b
     print(json.dumps(out))
+    if not ok:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -180,6 +180,48 @@ typedef struct sim_stage_time {
 int sim_stage_times(const sim_ctx* ctx, sim_stage_time* out, int cap);
 const char* sim_stage_name(int stage);
 
+/* ----------------------------------------------------------------- tuning */
+
+/* Launch shape of the tile kernels (tiles are 4096 records of one trace).
+ * Shapes change speed only: every shape gives the same result.  A context
+ * keeps one shape per size class; class k covers calls of 2^(k-1) ..
+ * 2^k - 1 records in total (k = 0 .. 32, see sim_size_class).  A call uses
+ * its class's shape, else that of the nearest class that has one, else the
+ * default (all fields 0).                                                  */
+typedef struct sim_tuning {
+  uint32_t stream_wgs_per_cu; /* statistics, key and histogram kernels: workgroups per CU, each looping
+                                 over tiles (0: one workgroup per tile); at most 64 */
+  uint32_t sort_wgs_per_cu;   /* radix scatter kernel, same meaning */
+  uint32_t scan_wgs_per_cu;   /* tile-scan kernel, same meaning */
+  int32_t group_shift_bias;   /* added to log2 of the tiles per histogram group (by default about the
+                                 square root of a trace's tiles); the result is clamped to 0 .. 12 */
+  double ms;                  /* sim_autotune: median time of one call in the chosen shape; else 0 */
+} sim_tuning;
+
+#define SIM_SIZE_CLASSES 33
+
+/* Size class of a call of `total_records` records: its bit length (capped at 32). */
+uint32_t sim_size_class(uint64_t total_records);
+
+/* Set the shape of one size class (t = NULL: back to the default).
+ * SIM_EINVAL for a class >= SIM_SIZE_CLASSES or fields out of range.      */
+int sim_set_tuning(sim_ctx* ctx, uint32_t size_class, const sim_tuning* t);
+
+/* Shape of one size class; returns 1 if the class has one (set or tuned),
+ * 0 if it uses the default (then *t is all zero), SIM_EINVAL on bad
+ * arguments.                                                               */
+int sim_get_tuning(const sim_ctx* ctx, uint32_t size_class, sim_tuning* t);
+
+/* Autotuner: time complete calls on the given input (arguments as for
+ * sim_check_traces_device) under candidate shapes -- coordinate descent over
+ * the workgroups per CU of the scatter (0, 1, 2, 4, 8), of the tile scan,
+ * of the streaming kernels, then the histogram-group bias (-1, +1) -- each
+ * candidate the median wall time of `reps` calls (0: 3).  The fastest shape
+ * is stored for the input's size class and written to *best.  Results of
+ * the trial calls are discarded; on error the class keeps its old shape.  */
+int sim_autotune(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
+                 const uint32_t* threads_per_block, void* stream, uint32_t reps, sim_tuning* best);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,6 +9,7 @@ is no fallback.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -35,8 +36,11 @@ STAGES = ["init", "stats", "layout", "keygen", "upsweep", "sort_pass", "scan_til
 # Symbols declared in include/simcheck.h.
 EXPORTS = [
     "sim_create", "sim_destroy", "sim_last_error", "sim_check_traces", "sim_check_traces_device",
-    "sim_result_free", "sim_stage_times", "sim_stage_name",
+    "sim_result_free", "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning",
+    "sim_get_tuning", "sim_autotune",
 ]
+SIM_SIZE_CLASSES = 33
+TUNING_FIELDS = ("stream_wgs_per_cu", "sort_wgs_per_cu", "scan_wgs_per_cu", "group_shift_bias")
 
 
 class SimError(RuntimeError):
@@ -60,6 +64,22 @@ class _Config(ctypes.Structure):
 
 class _StageTime(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [
+        ("stream_wgs_per_cu", ctypes.c_uint32),
+        ("sort_wgs_per_cu", ctypes.c_uint32),
+        ("scan_wgs_per_cu", ctypes.c_uint32),
+        ("group_shift_bias", ctypes.c_int32),
+        ("ms", ctypes.c_double),
+    ]
+
+
+def _tuning_dict(t: _Tuning) -> dict:
+    d = {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+    d["ms"] = float(t.ms)
+    return d
 
 
 _lib = None
@@ -94,6 +114,14 @@ def load() -> ctypes.CDLL:
     lib.sim_stage_times.argtypes = [P, ctypes.POINTER(_StageTime), ctypes.c_int]
     lib.sim_stage_name.restype = ctypes.c_char_p
     lib.sim_stage_name.argtypes = [ctypes.c_int]
+    lib.sim_size_class.restype = ctypes.c_uint32
+    lib.sim_size_class.argtypes = [ctypes.c_uint64]
+    lib.sim_set_tuning.restype = ctypes.c_int
+    lib.sim_set_tuning.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(_Tuning)]
+    lib.sim_get_tuning.restype = ctypes.c_int
+    lib.sim_get_tuning.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(_Tuning)]
+    lib.sim_autotune.restype = ctypes.c_int
+    lib.sim_autotune.argtypes = [P, P, P, ctypes.c_uint32, P, P, ctypes.c_uint32, ctypes.POINTER(_Tuning)]
     _lib = lib
     return lib
 
@@ -184,6 +212,44 @@ def sim_stage_times(ctx):
     return {lib.sim_stage_name(i).decode(): (arr[i].ms, arr[i].launches) for i in range(n)}
 
 
+def sim_size_class(total_records: int) -> int:
+    return int(load().sim_size_class(int(total_records)))
+
+
+def sim_set_tuning(ctx, size_class: int, tuning: dict | None) -> None:
+    """Set the launch shape of one size class (None: back to the default)."""
+    t = None
+    if tuning is not None:
+        t = _Tuning(*(int(tuning.get(f, 0)) for f in TUNING_FIELDS), float(tuning.get("ms", 0.0)))
+    rc = load().sim_set_tuning(ctx, size_class, ctypes.byref(t) if t is not None else None)
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+
+
+def sim_get_tuning(ctx, size_class: int):
+    """(is_set, shape) of one size class."""
+    t = _Tuning()
+    rc = load().sim_get_tuning(ctx, size_class, ctypes.byref(t))
+    if rc < 0:
+        raise SimError(rc, "bad size class")
+    return rc == 1, _tuning_dict(t)
+
+
+def sim_autotune(ctx, d_records_ptr: int, n_records: int, offsets=None, threads_per_block=1, stream=None,
+                 reps: int = 3) -> dict:
+    """Time candidate launch shapes on the given device records; the best is
+    kept for the input's size class and returned."""
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, n_records)
+    if int(offsets[-1]) != n_records:
+        raise ValueError("offsets[-1] must equal the number of device records")
+    t = _Tuning()
+    rc = load().sim_autotune(ctx, ctypes.c_void_p(d_records_ptr) if n_records else None, offsets.ctypes.data,
+                             n_traces, tpb.ctypes.data, ctypes.c_void_p(stream or 0), reps, ctypes.byref(t))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return _tuning_dict(t)
+
+
 # ----------------------------------------------------------- convenience
 
 class Context:
@@ -209,6 +275,11 @@ class Context:
     def check_traces_device(self, tensor, offsets=None, threads_per_block=1, stream=None):
         """tensor: a device tensor whose storage holds sim_record entries
         (16 bytes each, e.g. uint8 [n, 16] or int64 [n, 2])."""
+        ptr, n, stream = self._device_args(tensor, stream)
+        return sim_check_traces_device(self._ctx, ptr, n, offsets, threads_per_block, stream)
+
+    @staticmethod
+    def _device_args(tensor, stream):
         nbytes = tensor.numel() * tensor.element_size()
         if nbytes % 16:
             raise ValueError("tensor size is not a multiple of 16 bytes")
@@ -218,11 +289,61 @@ class Context:
             import torch
 
             stream = torch.cuda.current_stream(tensor.device).cuda_stream
-        return sim_check_traces_device(self._ctx, tensor.data_ptr(), nbytes // 16, offsets, threads_per_block,
-                                       stream)
+        return tensor.data_ptr(), nbytes // 16, stream
 
     def stage_times(self):
         return sim_stage_times(self._ctx)
 
+    def autotune(self, tensor, offsets=None, threads_per_block=1, stream=None, reps: int = 3) -> dict:
+        """Autotune the launch shape for calls the size of this input (device
+        tensor as in check_traces_device); returns the shape, with its size
+        class under "size_class"."""
+        ptr, n, stream = self._device_args(tensor, stream)
+        d = sim_autotune(self._ctx, ptr, n, offsets, threads_per_block, stream, reps)
+        d["size_class"] = sim_size_class(n)
+        return d
+
+    def set_tuning(self, size_class: int, tuning: dict | None) -> None:
+        sim_set_tuning(self._ctx, size_class, tuning)
+
+    def tuning(self, size_class: int):
+        return sim_get_tuning(self._ctx, size_class)
+
+    def save_tuning(self, path: str) -> None:
+        """Write every set size class's shape to a JSON file (the tuning
+        cache), merged with what the file already holds."""
+        data = load_tuning_file(path)
+        for k in range(SIM_SIZE_CLASSES):
+            is_set, t = self.tuning(k)
+            if is_set:
+                data[str(k)] = t
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump({"format": "simcheck-tuning-1", "classes": data}, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+
+    def load_tuning(self, path: str) -> int:
+        """Set the shapes stored in a tuning cache file; returns how many."""
+        data = load_tuning_file(path)
+        for k, t in data.items():
+            self.set_tuning(int(k), t)
+        return len(data)
+
     def last_error(self) -> str:
         return sim_last_error(self._ctx)
+
+
+def load_tuning_file(path: str) -> dict:
+    """Size class -> shape from a tuning cache file ({} if it is absent)."""
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("format") != "simcheck-tuning-1":
+        raise ValueError(f"{path}: not a tuning cache file")
+    out = {}
+    for k, t in d.get("classes", {}).items():
+        if not (0 <= int(k) < SIM_SIZE_CLASSES):
+            raise ValueError(f"{path}: size class {k} out of range")
+        out[str(int(k))] = {f: int(t[f]) for f in TUNING_FIELDS} | {"ms": float(t.get("ms", 0.0))}
+    return out

@@ -10,12 +10,15 @@
 // slice holds, or more racing locations than the output buffer holds.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/simcheck.h"
 #include "launch.h"
@@ -42,6 +45,7 @@ struct DevBuf {
 
 struct sim_ctx {
   int device = 0;
+  uint32_t n_cu = 256;           // compute units of the device
   hipStream_t stream = nullptr;  // used by sim_check_traces
   uint32_t flags = 0;
   uint32_t pass_guess = 0;  // radix passes the previous call needed
@@ -54,7 +58,14 @@ struct sim_ctx {
     hipStream_t stream = nullptr;
     uint64_t total = 0, table_hash = 0, gen = 0;
     uint32_t n_traces = 0, n_tiles = 0, guess = 0;
+    uint64_t tuning_gen = 0;
   } graph;
+
+  // launch shapes per size class (set by hand or by sim_autotune)
+  sim_tuning tuning[SIM_SIZE_CLASSES] = {};
+  bool tuned[SIM_SIZE_CLASSES] = {};
+  uint64_t tuning_gen = 0;
+  const sim_tuning* force = nullptr;  // sim_autotune's candidate
   std::string err;
 
   DevBuf records, keys0, keys1, desc, tiles, groups, stats_part, layout, thist, gtot, gbase, agg, tout, cross, cross_flag,
@@ -158,6 +169,33 @@ sim_result* alloc_result(uint64_t n_races, uint32_t n_traces) {
   return r;
 }
 
+uint32_t size_class(uint64_t total) {
+  uint32_t k = 0;
+  while (k < 64 && (total >> k) != 0) k++;
+  return k < SIM_SIZE_CLASSES ? k : SIM_SIZE_CLASSES - 1;
+}
+
+// Launch shape of a call of `total` records: the forced candidate while
+// autotuning, else the shape of its size class, else of the nearest tuned
+// class, else one workgroup per tile and no group-size bias.
+sim_tuning pick_tuning(const sim_ctx* c, uint64_t total) {
+  if (c->force) return *c->force;
+  const int k = (int)size_class(total);
+  int best = -1;
+  for (int d = 0; d < SIM_SIZE_CLASSES && best < 0; d++) {
+    if (k - d >= 0 && c->tuned[k - d]) best = k - d;
+    else if (k + d < SIM_SIZE_CLASSES && c->tuned[k + d]) best = k + d;
+  }
+  return best >= 0 ? c->tuning[best] : sim_tuning{0, 0, 0, 0, 0.0};
+}
+
+int group_shift(uint64_t n_tiles, int bias) {
+  int gs = 0;
+  while (gs < (int)MAX_HGROUP_SHIFT && (1ull << (2 * gs)) < n_tiles) gs++;
+  gs += bias;
+  return gs < 0 ? 0 : (gs > (int)MAX_HGROUP_SHIFT ? (int)MAX_HGROUP_SHIFT : gs);
+}
+
 int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces, const uint32_t* tpb,
         hipStream_t s, sim_result** out) {
   uint64_t total = 0;
@@ -177,11 +215,11 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   // ---- per-call tables (pinned); histogram groups of about sqrt(ntiles)
   // tiles keep both serial offset loops of the radix kernels short
   hipError_t e;
+  const sim_tuning tune = pick_tuning(c, total);
   uint64_t n_hgroups64 = 0;
   for (uint32_t i = 0; i < n_traces; i++) {
     const uint64_t nt = (offsets[i + 1] - offsets[i] + TILE - 1) / TILE;
-    uint32_t gs = 0;
-    while (gs < MAX_HGROUP_SHIFT && (1ull << (2 * gs)) < nt) gs++;
+    const int gs = group_shift(nt, tune.group_shift_bias);
     n_hgroups64 += (nt + (1ull << gs) - 1) >> gs;
   }
   const size_t meta_bytes = (size_t)n_traces * sizeof(TraceDesc) + (size_t)n_tiles * sizeof(TileRef) +
@@ -201,8 +239,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   for (uint32_t i = 0; i < n_traces; i++) {
     const uint64_t n = offsets[i + 1] - offsets[i];
     const uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
-    uint32_t gs = 0;
-    while (gs < MAX_HGROUP_SHIFT && (1ull << (2 * gs)) < nt) gs++;
+    const uint32_t gs = (uint32_t)group_shift(nt, tune.group_shift_bias);
     const uint32_t ng = (nt + (1u << gs) - 1) >> gs;
     hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
     for (uint32_t k = 0; k < nt; k++) ht[t0 + k] = TileRef{i, k};
@@ -273,6 +310,9 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.n_traces = n_traces;
   b.n_tiles = n_tiles;
   b.n_groups = n_hgroups;
+  b.grid_stream = tile_grid(n_tiles, tune.stream_wgs_per_cu, c->n_cu);
+  b.grid_sort = tile_grid(n_tiles, tune.sort_wgs_per_cu, c->n_cu);
+  b.grid_scan = tile_grid(n_tiles, tune.scan_wgs_per_cu, c->n_cu);
 
   // ---- the pipeline.  Radix passes: the context remembers how many the
   // previous call needed and launches that many; the scan kernels do
@@ -346,7 +386,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   auto& G = c->graph;
   const bool replay = use_graph && G.exec && G.records == d_records && G.stream == s && G.total == total &&
                       G.n_traces == n_traces && G.n_tiles == n_tiles && G.table_hash == th && G.gen == c->alloc_gen &&
-                      G.guess == guess;
+                      G.guess == guess && G.tuning_gen == c->tuning_gen;
   if (replay) {
     e = hipGraphLaunch(G.exec, s);
   } else if (use_graph) {
@@ -370,6 +410,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       G.table_hash = th;
       G.gen = c->alloc_gen;
       G.guess = guess;
+      G.tuning_gen = c->tuning_gen;
       e = hipGraphLaunch(G.exec, s);
     } else {  // capture not possible here: run the launches directly
       (void)hipGetLastError();
@@ -467,6 +508,7 @@ int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg) {
   if (!c) return SIM_ENOMEM;
   c->device = hip_device;
   c->flags = cfg ? cfg->flags : 0;
+  c->n_cu = prop.multiProcessorCount > 0 ? (uint32_t)prop.multiProcessorCount : 256u;
   DeviceGuard g(hip_device);
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
@@ -551,5 +593,98 @@ int sim_stage_times(const sim_ctx* c, sim_stage_time* out, int cap) {
 }
 
 const char* sim_stage_name(int stage) { return (stage >= 0 && stage < N_STAGE) ? kStageNames[stage] : ""; }
+
+uint32_t sim_size_class(uint64_t total_records) { return size_class(total_records); }
+
+int sim_set_tuning(sim_ctx* c, uint32_t cls, const sim_tuning* t) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (cls >= SIM_SIZE_CLASSES) return fail(c, SIM_EINVAL, "size class %u out of range", cls);
+  if (t && (t->stream_wgs_per_cu > 64 || t->sort_wgs_per_cu > 64 || t->scan_wgs_per_cu > 64 ||
+            t->group_shift_bias < -12 || t->group_shift_bias > 12))
+    return fail(c, SIM_EINVAL, "tuning out of range (workgroups per CU <= 64, |bias| <= 12)");
+  c->tuned[cls] = t != nullptr;
+  c->tuning[cls] = t ? *t : sim_tuning{0, 0, 0, 0, 0.0};
+  c->tuning_gen++;
+  return SIM_OK;
+}
+
+int sim_get_tuning(const sim_ctx* c, uint32_t cls, sim_tuning* t) {
+  if (!c || !t || cls >= SIM_SIZE_CLASSES) return SIM_EINVAL;
+  *t = c->tuning[cls];
+  return c->tuned[cls] ? 1 : 0;
+}
+
+int sim_autotune(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
+                 const uint32_t* threads_per_block, void* stream, uint32_t reps, sim_tuning* best) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (!best) return fail(c, SIM_EINVAL, "best is NULL");
+  DeviceGuard g(c->device);
+  uint64_t total = 0;
+  uint32_t n_tiles = 0;
+  sim_result* scratch = nullptr;
+  int rc = validate(c, offsets, n_traces, threads_per_block, &scratch, &total, &n_tiles);
+  if (rc) return rc;
+  if (reps == 0) reps = 3;
+  const uint32_t saved_flags = c->flags;
+  c->flags &= ~(uint32_t)(SIM_CFG_GRAPHS | SIM_CFG_PROFILE);  // plain launches, timed on the host
+  hipStream_t s = (hipStream_t)stream;
+  // median wall time of `reps` complete calls with shape t
+  auto measure = [&](const sim_tuning& t, double* ms) -> int {
+    c->force = &t;
+    std::vector<double> v;
+    for (uint32_t r = 0; r < reps; r++) {
+      sim_result* res = nullptr;
+      const auto t0 = std::chrono::steady_clock::now();
+      const int rc1 = run(c, d_records, offsets, n_traces, threads_per_block, s, &res);
+      const auto t1 = std::chrono::steady_clock::now();
+      sim_result_free(res);
+      if (rc1) {
+        c->force = nullptr;
+        return rc1;
+      }
+      v.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+    }
+    c->force = nullptr;
+    std::sort(v.begin(), v.end());
+    *ms = v[v.size() / 2];
+    return SIM_OK;
+  };
+  sim_tuning cur{0, 0, 0, 0, 0.0};
+  double cur_ms = 0;
+  double warm = 0;
+  rc = measure(cur, &warm);  // buffers, pass count
+  if (!rc) rc = measure(cur, &cur_ms);
+  // coordinate descent over the four knobs, one at a time
+  static const uint32_t kWgs[] = {0, 1, 2, 4, 8};
+  static const int32_t kBias[] = {-1, 1};
+  for (int knob = 0; knob < 4 && !rc; knob++) {
+    const int nval = knob == 3 ? 2 : 5;
+    const int32_t bias0 = cur.group_shift_bias;
+    for (int q = 0; q < nval && !rc; q++) {
+      sim_tuning t = cur;
+      if (knob == 0) { if (t.sort_wgs_per_cu == kWgs[q]) continue; t.sort_wgs_per_cu = kWgs[q]; }
+      if (knob == 1) { if (t.scan_wgs_per_cu == kWgs[q]) continue; t.scan_wgs_per_cu = kWgs[q]; }
+      if (knob == 2) { if (t.stream_wgs_per_cu == kWgs[q]) continue; t.stream_wgs_per_cu = kWgs[q]; }
+      if (knob == 3) t.group_shift_bias = bias0 + kBias[q];
+      double ms = 0;
+      rc = measure(t, &ms);
+      if (!rc && ms < cur_ms) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+  }
+  c->flags = saved_flags;
+  if (rc) return rc;
+  cur.ms = cur_ms;
+  const uint32_t cls = size_class(total);
+  c->tuning[cls] = cur;
+  c->tuned[cls] = true;
+  c->tuning_gen++;
+  *best = cur;
+  return SIM_OK;
+}
 
 }  // extern "C"

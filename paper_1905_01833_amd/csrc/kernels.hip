@@ -161,57 +161,65 @@ __global__ void k_init(Ctrl* ctrl) {
 // -------------------------------------------------------------- k_stats
 // Per-tile partial statistics; k_layout reduces them per trace.
 
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ recs, const TraceDesc* __restrict__ desc,
-                                              const TileRef* __restrict__ tiles, TraceStats* __restrict__ part) {
+                                              const TileRef* __restrict__ tiles, uint32_t n_tiles,
+                                              TraceStats* __restrict__ part) {
   __shared__ uint64_t s64[5][NWAVE];
   __shared__ uint32_t s32[2][NWAVE];
-  const TileRef tr = tiles[blockIdx.x];
-  const TraceDesc T = desc[tr.trace];
-  const uint64_t start = (uint64_t)tr.local * TILE;
-  const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-  const ulonglong2* p = recs + T.off + start;
-  uint64_t gmin = ~0ull, gmax = 0, smin = ~0ull, smax = 0, bad = ~0ull;
-  uint32_t mt = 0, me = 0;
+  const TileWalk tw = tile_walk(n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    __syncthreads();  // LDS of the previous tile is free
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    const TileRef tr = tiles[tile];
+    const TraceDesc T = desc[tr.trace];
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
+    const ulonglong2* p = recs + T.off + start;
+    uint64_t gmin = ~0ull, gmax = 0, smin = ~0ull, smax = 0, bad = ~0ull;
+    uint32_t mt = 0, me = 0;
 #pragma unroll 4
-  for (int r = 0; r < ITEMS; r++) {
-    const uint32_t j = threadIdx.x + r * NT;
-    if (j < n_in) {
-      const Rec x = unpack_rec(p[j]);
-      if (x.action > 2 || x.space > 1) {
-        bad = min<uint64_t>(bad, start + j);
-      } else {
-        if (x.space == 0) {
-          gmin = min(gmin, x.unit);
-          gmax = max(gmax, x.unit);
+    for (int r = 0; r < ITEMS; r++) {
+      const uint32_t j = tx + r * NT;
+      if (j < n_in) {
+        const Rec x = unpack_rec(p[j]);
+        if (x.action > 2 || x.space > 1) {
+          bad = min<uint64_t>(bad, start + j);
         } else {
-          smin = min(smin, x.unit);
-          smax = max(smax, x.unit);
+          if (x.space == 0) {
+            gmin = min(gmin, x.unit);
+            gmax = max(gmax, x.unit);
+          } else {
+            smin = min(smin, x.unit);
+            smax = max(smax, x.unit);
+          }
+          mt = max(mt, x.tid);
+          me = max(me, x.epoch);
         }
-        mt = max(mt, x.tid);
-        me = max(me, x.epoch);
       }
     }
-  }
-  gmin = wave_min(gmin); smin = wave_min(smin); bad = wave_min(bad);
-  gmax = wave_max(gmax); smax = wave_max(smax);
-  mt = wave_max(mt); me = wave_max(me);
-  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    s64[0][wave] = gmin; s64[1][wave] = gmax; s64[2][wave] = smin; s64[3][wave] = smax; s64[4][wave] = bad;
-    s32[0][wave] = mt; s32[1][wave] = me;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < NWAVE; w++) {
-      gmin = min(gmin, s64[0][w]); gmax = max(gmax, s64[1][w]);
-      smin = min(smin, s64[2][w]); smax = max(smax, s64[3][w]);
-      bad = min(bad, s64[4][w]);
-      mt = max(mt, s32[0][w]); me = max(me, s32[1][w]);
+    gmin = wave_min(gmin); smin = wave_min(smin); bad = wave_min(bad);
+    gmax = wave_max(gmax); smax = wave_max(smax);
+    mt = wave_max(mt); me = wave_max(me);
+    const uint32_t lane = tx & 63u, wave = tx >> 6;
+    if (lane == 0) {
+      s64[0][wave] = gmin; s64[1][wave] = gmax; s64[2][wave] = smin; s64[3][wave] = smax; s64[4][wave] = bad;
+      s32[0][wave] = mt; s32[1][wave] = me;
     }
-    TraceStats S;
-    S.gmin = gmin; S.gmax = gmax; S.smin = smin; S.smax = smax; S.bad_index = bad;
-    S.max_tid = mt; S.max_epoch = me;
-    part[blockIdx.x] = S;
+    __syncthreads();
+    if (tx == 0) {
+      for (int w = 1; w < NWAVE; w++) {
+        gmin = min(gmin, s64[0][w]); gmax = max(gmax, s64[1][w]);
+        smin = min(smin, s64[2][w]); smax = max(smax, s64[3][w]);
+        bad = min(bad, s64[4][w]);
+        mt = max(mt, s32[0][w]); me = max(me, s32[1][w]);
+      }
+      TraceStats S;
+      S.gmin = gmin; S.gmax = gmax; S.smin = smin; S.smax = smax; S.bad_index = bad;
+      S.max_tid = mt; S.max_epoch = me;
+      part[tile] = S;
+    }
   }
 }
 
@@ -383,60 +391,74 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool val
 // ------------------------------------------------------------- k_keygen
 // Records -> keys, and the tile histogram of radix digit 0.
 
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
   __shared__ uint32_t h[RADIX];
-  const TileRef tr = b.tiles[blockIdx.x];
-  const TraceDesc T = b.desc[tr.trace];
-  const TraceLayout L = b.layout[tr.trace];
-  if (L.npasses == 0) return;
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t start = (uint64_t)tr.local * TILE;
-  const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-  const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
-  uint64_t* kout = b.keys[0] + T.off + start;
+  const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    __syncthreads();  // LDS of the previous tile is free
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    const TileRef tr = b.tiles[tile];
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    if (L.npasses == 0) continue;
+    h[tx] = 0;
+    __syncthreads();
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
+    const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
+    uint64_t* kout = b.keys[0] + T.off + start;
 #pragma unroll 4
-  for (int r = 0; r < ITEMS; r++) {
-    const uint32_t j = threadIdx.x + r * NT;
-    const bool valid = j < n_in;
-    uint64_t k = 0;
-    if (valid) {
-      const Rec x = unpack_rec(p[j]);
-      k = make_key(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
-      kout[j] = k;
+    for (int r = 0; r < ITEMS; r++) {
+      const uint32_t j = tx + r * NT;
+      const bool valid = j < n_in;
+      uint64_t k = 0;
+      if (valid) {
+        const Rec x = unpack_rec(p[j]);
+        k = make_key(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
+        kout[j] = k;
+      }
+      wave_hist_add(h, (uint32_t)(k >> 2) & (RADIX - 1), valid);
     }
-    wave_hist_add(h, (uint32_t)(k >> 2) & (RADIX - 1), valid);
+    __syncthreads();
+    b.thist[(uint64_t)tile * RADIX + tx] = h[tx];
   }
-  __syncthreads();
-  b.thist[(uint64_t)blockIdx.x * RADIX + threadIdx.x] = h[threadIdx.x];
 }
 
 // ------------------------------------------------------------ k_upsweep
 // Tile histogram of radix digit `pass` (keys in the buffer that pass reads).
 
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
   __shared__ uint32_t h[RADIX];
-  const TileRef tr = b.tiles[blockIdx.x];
-  const TraceDesc T = b.desc[tr.trace];
-  const TraceLayout L = b.layout[tr.trace];
-  if (pass >= L.npasses) return;
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t shift = 2 + RADIX_BITS * pass;
-  const uint64_t start = (uint64_t)tr.local * TILE;
-  const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-  const uint64_t* src = b.keys[pass & 1] + T.off + start;
-  uint64_t k[ITEMS];
+  const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    __syncthreads();  // LDS of the previous tile is free
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    const TileRef tr = b.tiles[tile];
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    if (pass >= L.npasses) continue;
+    h[tx] = 0;
+    __syncthreads();
+    const uint32_t shift = 2 + RADIX_BITS * pass;
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
+    const uint64_t* src = b.keys[pass & 1] + T.off + start;
+    uint64_t k[ITEMS];
 #pragma unroll
-  for (int r = 0; r < ITEMS; r++) {
-    const uint32_t j = threadIdx.x + r * NT;
-    k[r] = j < n_in ? src[j] : 0ull;
+    for (int r = 0; r < ITEMS; r++) {
+      const uint32_t j = tx + r * NT;
+      k[r] = j < n_in ? src[j] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++)
+      wave_hist_add(h, (uint32_t)(k[r] >> shift) & (RADIX - 1), tx + r * NT < n_in);
+    __syncthreads();
+    b.thist[(uint64_t)tile * RADIX + tx] = h[tx];
   }
-#pragma unroll
-  for (int r = 0; r < ITEMS; r++)
-    wave_hist_add(h, (uint32_t)(k[r] >> shift) & (RADIX - 1), threadIdx.x + r * NT < n_in);
-  __syncthreads();
-  b.thist[(uint64_t)blockIdx.x * RADIX + threadIdx.x] = h[threadIdx.x];
 }
 
 // ------------------------------------------------------------ k_scatter
@@ -450,6 +472,7 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
 // the offsets left by the upsweep give each key its destination; keys are
 // staged in LDS in destination order and written out in runs per digit.
 
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
   __shared__ uint64_t s_keys[TILE];
   __shared__ uint32_t s_wh[NWAVE][RADIX];
@@ -457,79 +480,84 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
   __shared__ uint64_t s_gbase[RADIX];
   __shared__ uint32_t s_scan[NWAVE];
 
-  const uint32_t tile = blockIdx.x;
-  const TileRef tr = b.tiles[tile];
-  const TraceDesc T = b.desc[tr.trace];
-  const TraceLayout L = b.layout[tr.trace];
-  if (pass >= L.npasses) return;  // uniform over the workgroup
-  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
-  const uint32_t d = threadIdx.x;
-  const uint32_t shift = 2 + RADIX_BITS * pass;
-  const uint64_t start = (uint64_t)tr.local * TILE;
-  const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-  const uint64_t* src = b.keys[pass & 1] + T.off + start;
-  uint64_t* kout = b.keys[(pass + 1) & 1];
+  const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    __syncthreads();  // LDS of the previous tile is free
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    const TileRef tr = b.tiles[tile];
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    if (pass >= L.npasses) continue;  // uniform over the workgroup
+    const uint32_t lane = tx & 63u, wave = tx >> 6;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    const uint32_t d = tx;
+    const uint32_t shift = 2 + RADIX_BITS * pass;
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
+    const uint64_t* src = b.keys[pass & 1] + T.off + start;
+    uint64_t* kout = b.keys[(pass + 1) & 1];
 
 #pragma unroll
-  for (int w = 0; w < NWAVE; w++) s_wh[w][d] = 0;
-  // destination base of each digit: group base + offset within the group
-  const uint64_t gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] +
-                      b.thist[(uint64_t)tile * RADIX + d];  // offset within the group
-  __syncthreads();
+    for (int w = 0; w < NWAVE; w++) s_wh[w][d] = 0;
+    // destination base of each digit: group base + offset within the group
+    const uint64_t gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] +
+                        b.thist[(uint64_t)tile * RADIX + d];  // offset within the group
+    __syncthreads();
 
-  uint64_t key[ITEMS];
-  uint32_t rank[ITEMS];
+    uint64_t key[ITEMS];
+    uint32_t rank[ITEMS];
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
-    key[i] = (j < n_in) ? src[j] : ~0ull;  // padding sorts last (digit 255, after every real key)
-  }
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-    uint64_t m = ~0ull;
-#pragma unroll
-    for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
-      const uint64_t bal = __ballot((dg >> bt) & 1u);
-      m &= ((dg >> bt) & 1u) ? bal : ~bal;
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+      key[i] = (j < n_in) ? src[j] : ~0ull;  // padding sorts last (digit 255, after every real key)
     }
-    const uint32_t before = (uint32_t)__popcll(m & lt_mask);
-    const uint32_t old = s_wh[wave][dg];
-    if (before == 0) s_wh[wave][dg] = old + (uint32_t)__popcll(m);
-    rank[i] = old + before;
-  }
-  __syncthreads();
-
-  // per digit: offsets of the waves, tile count, tile-local start
-  uint32_t cnt = 0;
 #pragma unroll
-  for (int w = 0; w < NWAVE; w++) {
-    const uint32_t c = s_wh[w][d];
-    s_wh[w][d] = cnt;
-    cnt += c;
-  }
-  uint32_t tot;
-  const uint32_t dstart = block_excl_sum(cnt, s_scan, &tot);
-  s_dstart[d] = dstart;
-  s_gbase[d] = gb - dstart;
-  __syncthreads();
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+      uint64_t m = ~0ull;
+#pragma unroll
+      for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
+        const uint64_t bal = __ballot((dg >> bt) & 1u);
+        m &= ((dg >> bt) & 1u) ? bal : ~bal;
+      }
+      const uint32_t before = (uint32_t)__popcll(m & lt_mask);
+      const uint32_t old = s_wh[wave][dg];
+      if (before == 0) s_wh[wave][dg] = old + (uint32_t)__popcll(m);
+      rank[i] = old + before;
+    }
+    __syncthreads();
+
+    // per digit: offsets of the waves, tile count, tile-local start
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) {
+      const uint32_t c = s_wh[w][d];
+      s_wh[w][d] = cnt;
+      cnt += c;
+    }
+    uint32_t tot;
+    const uint32_t dstart = block_excl_sum(cnt, s_scan, &tot);
+    s_dstart[d] = dstart;
+    s_gbase[d] = gb - dstart;
+    __syncthreads();
 
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-    s_keys[s_dstart[dd] + s_wh[wave][dd] + rank[i]] = key[i];
-  }
-  __syncthreads();
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+      s_keys[s_dstart[dd] + s_wh[wave][dd] + rank[i]] = key[i];
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int r = 0; r < ITEMS; r++) {
-    const uint32_t j = threadIdx.x + r * NT;
-    if (j < n_in) {
-      const uint64_t k = s_keys[j];
-      const uint32_t dd = (uint32_t)(k >> shift) & (RADIX - 1);
-      const uint64_t dst = s_gbase[dd] + j;
-      if (dst - T.off < T.n) kout[dst] = k;
-      else atomicOr(&b.ctrl->error_flags, ERR_INTERNAL_BOUNDS);
+    for (int r = 0; r < ITEMS; r++) {
+      const uint32_t j = tx + r * NT;
+      if (j < n_in) {
+        const uint64_t k = s_keys[j];
+        const uint32_t dd = (uint32_t)(k >> shift) & (RADIX - 1);
+        const uint64_t dst = s_gbase[dd] + j;
+        if (dst - T.off < T.n) kout[dst] = k;
+        else atomicOr(&b.ctrl->error_flags, ERR_INTERNAL_BOUNDS);
+      }
     }
   }
 }
@@ -627,6 +655,7 @@ __device__ __forceinline__ RaceOut* stage_of(const Buffers& b, uint32_t tile, co
   return (RaceOut*)(b.keys[(L.npasses & 1u) ^ 1u] + T.off + start);
 }
 
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_done) {
   __shared__ uint64_t s_keys[LDS_PAD(TILE) + 1];
   __shared__ uint64_t s_scanA[NWAVE][4];
@@ -642,232 +671,237 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
   // trace needs (the host then runs the missing passes and scans again)
   if (b.ctrl->error_flags) return;
   if (b.ctrl->max_passes > passes_done) return;
-  const uint32_t tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-  const uint32_t tile = blockIdx.x;
-  if (tid < 17) s_lead[tid] = 0;
-  if (tid == 0) s_min = NO_HEAD;
-  const TileRef tr = b.tiles[tile];
-  const TraceDesc T = b.desc[tr.trace];
-  const TraceLayout L = b.layout[tr.trace];
-  const uint64_t* keys = b.keys[L.npasses & 1u];
-  const uint64_t start = (uint64_t)tr.local * TILE;
-  const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-  const uint64_t* src = keys + T.off + start;
-  const bool trace_end = start + n_in == T.n;
+  const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    __syncthreads();  // LDS of the previous tile is free
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    const uint32_t tid = tx, lane = tx & 63u, wave = tx >> 6;
+    if (tid < 17) s_lead[tid] = 0;
+    if (tid == 0) s_min = NO_HEAD;
+    const TileRef tr = b.tiles[tile];
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    const uint64_t* keys = b.keys[L.npasses & 1u];
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
+    const uint64_t* src = keys + T.off + start;
+    const bool trace_end = start + n_in == T.n;
 
-  for (uint32_t j = tid; j < (uint32_t)TILE; j += NT) s_keys[LDS_PAD(j)] = (j < n_in) ? src[j] : 0ull;
-  if (tid == 0) {
-    s_prev = tr.local > 0 ? src[-1] : 0ull;
-    s_next = trace_end ? 0ull : src[n_in];
-  }
-  __syncthreads();
-  if (tid == 0) s_taillast = trace_end ? 1u : (head_level(L, s_keys[LDS_PAD(n_in - 1)], s_next) == 0 ? 1u : 0u);
+    for (uint32_t j = tid; j < (uint32_t)TILE; j += NT) s_keys[LDS_PAD(j)] = (j < n_in) ? src[j] : 0ull;
+    if (tid == 0) {
+      s_prev = tr.local > 0 ? src[-1] : 0ull;
+      s_next = trace_end ? 0ull : src[n_in];
+    }
+    __syncthreads();
+    if (tid == 0) s_taillast = trace_end ? 1u : (head_level(L, s_keys[LDS_PAD(n_in - 1)], s_next) == 0 ? 1u : 0u);
 
-  // ---- element metadata: head level (3 bits) and class (2 bits)
-  uint64_t key[ITEMS];
-  uint32_t meta[ITEMS];
-  uint32_t local_min = NO_HEAD;
-  {
-    uint64_t prev = tid > 0 ? s_keys[LDS_PAD(ITEMS * tid - 1)] : s_prev;
+    // ---- element metadata: head level (3 bits) and class (2 bits)
+    uint64_t key[ITEMS];
+    uint32_t meta[ITEMS];
+    uint32_t local_min = NO_HEAD;
+    {
+      uint64_t prev = tid > 0 ? s_keys[LDS_PAD(ITEMS * tid - 1)] : s_prev;
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t j = ITEMS * tid + i;
-      const uint64_t k = s_keys[LDS_PAD(j)];
-      key[i] = k;
-      uint32_t lv, c;
-      if (j < n_in) {
-        lv = (j == 0 && tr.local == 0) ? 0u : head_level(L, prev, k);
-        c = action_class(k);
-        local_min = min(local_min, lv);
-      } else {
-        lv = 4;
-        c = CLS_NONE;
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t j = ITEMS * tid + i;
+        const uint64_t k = s_keys[LDS_PAD(j)];
+        key[i] = k;
+        uint32_t lv, c;
+        if (j < n_in) {
+          lv = (j == 0 && tr.local == 0) ? 0u : head_level(L, prev, k);
+          c = action_class(k);
+          local_min = min(local_min, lv);
+        } else {
+          lv = 4;
+          c = CLS_NONE;
+        }
+        meta[i] = lv | (c << 3);
+        prev = k;
       }
-      meta[i] = lv | (c << 3);
-      prev = k;
+      s_firstlv[tid] = (uint8_t)(meta[0] & 7u);
     }
-    s_firstlv[tid] = (uint8_t)(meta[0] & 7u);
-  }
-  local_min = wave_min(local_min);
-  if (lane == 0 && local_min < NO_HEAD) atomicMin(&s_min, local_min);
+    local_min = wave_min(local_min);
+    if (lane == 0 && local_min < NO_HEAD) atomicMin(&s_min, local_min);
 
-  // ---- pass A: segmented class counts per level
-  uint64_t aggA[4] = {0, 0, 0, 0};
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    const uint32_t lv = meta[i] & 7u, c = meta[i] >> 3;
-#pragma unroll
-    for (int l = 0; l < 4; l++)
-      if (lv <= (uint32_t)l) aggA[l] = SEGF;
-    if (c != CLS_NONE) {
-#pragma unroll
-      for (int l = 0; l < 4; l++) aggA[l] += 1ull << (16 * c);
-    }
-  }
-  uint64_t exA[4], totA[4];
-  block_seg_scan<4>(aggA, exA, totA, s_scanA);
-
-  // ---- pass B: pairs per element, summed per location run; lead data.
-  //      Locations that end in this thread are counted here when they also
-  //      start in it; the thread's first location (it may start in an
-  //      earlier thread) is settled after the scan.
-  uint64_t aggB[3] = {0, 0, 0};
-  uint32_t n_emit = 0;
-  bool pend = false;
-  uint64_t pend0 = 0, pend1 = 0;
-  {
-    uint64_t run[4];
-    bool seen[4];
-#pragma unroll
-    for (int l = 0; l < 4; l++) {
-      run[l] = exA[l] & ~SEGF;
-      seen[l] = (exA[l] & SEGF) != 0;
-    }
-    // only threads before the tile's first location head hold lead elements
-    const bool lead_thread = !seen[0];
-    uint32_t leadc[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    uint32_t leads[5] = {0, 0, 0, 0, 0};
+    // ---- pass A: segmented class counts per level
+    uint64_t aggA[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t lv = meta[i] & 7u, c = meta[i] >> 3;
 #pragma unroll
       for (int l = 0; l < 4; l++)
-        if (lv <= (uint32_t)l) {
-          run[l] = 0;
-          seen[l] = true;
-        }
-      if (c == CLS_NONE) continue;
-      uint32_t v[5];
-      tile_pairs(c, run, v);
-      if (lv == 0) aggB[0] = aggB[1] = aggB[2] = SEGF;
-      aggB[0] += (uint64_t)v[K_WW] | ((uint64_t)v[K_RW] << 32);
-      aggB[1] += (uint64_t)v[K_AW] | ((uint64_t)v[K_AR] << 32);
-      aggB[2] += (uint64_t)v[K_XB];
+        if (lv <= (uint32_t)l) aggA[l] = SEGF;
+      if (c != CLS_NONE) {
 #pragma unroll
-      for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
+        for (int l = 0; l < 4; l++) aggA[l] += 1ull << (16 * c);
+      }
+    }
+    uint64_t exA[4], totA[4];
+    block_seg_scan<4>(aggA, exA, totA, s_scanA);
+
+    // ---- pass B: pairs per element, summed per location run; lead data.
+    //      Locations that end in this thread are counted here when they also
+    //      start in it; the thread's first location (it may start in an
+    //      earlier thread) is settled after the scan.
+    uint64_t aggB[3] = {0, 0, 0};
+    uint32_t n_emit = 0;
+    bool pend = false;
+    uint64_t pend0 = 0, pend1 = 0;
+    {
+      uint64_t run[4];
+      bool seen[4];
+#pragma unroll
+      for (int l = 0; l < 4; l++) {
+        run[l] = exA[l] & ~SEGF;
+        seen[l] = (exA[l] & SEGF) != 0;
+      }
+      // only threads before the tile's first location head hold lead elements
+      const bool lead_thread = !seen[0];
+      uint32_t leadc[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      uint32_t leads[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t lv = meta[i] & 7u, c = meta[i] >> 3;
+#pragma unroll
+        for (int l = 0; l < 4; l++)
+          if (lv <= (uint32_t)l) {
+            run[l] = 0;
+            seen[l] = true;
+          }
+        if (c == CLS_NONE) continue;
+        uint32_t v[5];
+        tile_pairs(c, run, v);
+        if (lv == 0) aggB[0] = aggB[1] = aggB[2] = SEGF;
+        aggB[0] += (uint64_t)v[K_WW] | ((uint64_t)v[K_RW] << 32);
+        aggB[1] += (uint64_t)v[K_AW] | ((uint64_t)v[K_AR] << 32);
+        aggB[2] += (uint64_t)v[K_XB];
+#pragma unroll
+        for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
+        if (lead_thread) {
+#pragma unroll
+          for (int l = 0; l < 4; l++)
+            if (!seen[l]) leadc[l][c]++;
+          if (!seen[0]) {
+#pragma unroll
+            for (int k = 0; k < 5; k++) leads[k] += v[k];
+          }
+        }
+        const uint32_t j = ITEMS * tid + i;
+        bool last;
+        if (j + 1 == n_in) last = s_taillast != 0;
+        else if (i + 1 < ITEMS) last = (meta[i + 1] & 7u) == 0;
+        else last = s_firstlv[tid + 1] == 0;
+        if (!last) continue;
+        if (aggB[0] & SEGF) {  // the location started in this thread
+          if (((aggB[0] | aggB[1]) & ~SEGF) != 0) n_emit++;
+        } else {
+          pend = true;
+          pend0 = aggB[0];
+          pend1 = aggB[1];
+        }
+      }
       if (lead_thread) {
 #pragma unroll
         for (int l = 0; l < 4; l++)
-          if (!seen[l]) leadc[l][c]++;
-        if (!seen[0]) {
 #pragma unroll
-          for (int k = 0; k < 5; k++) leads[k] += v[k];
+          for (int q = 0; q < 3; q++)
+            if (leadc[l][q]) atomicAdd(&s_lead[l * 3 + q], leadc[l][q]);
+#pragma unroll
+        for (int k = 0; k < 5; k++)
+          if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
+      }
+    }
+    uint64_t exB[3], totB[3];
+    block_seg_scan<3>(aggB, exB, totB, s_scanB);  // contains a barrier: s_lead and s_min are complete after it
+    // the thread's first location: complete here only if it started in the
+    // tile (a location head in an earlier thread); otherwise it belongs to an
+    // earlier tile and is finished by k_scan_cross
+    if (pend && (exB[0] & SEGF) && ((((exB[0] + pend0) | (exB[1] + pend1)) & ~SEGF) != 0)) n_emit++;
+
+    // ---- the tile summary (lanes of wave 0 write its words)
+    if (wave == 0) {
+      State agg;
+      agg.m = s_min;
+#pragma unroll
+      for (int l = 0; l < 4; l++)
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+          agg.lead[l][q] = s_lead[l * 3 + q];
+          agg.trail[l][q] = cnt16(totA[l], q);
         }
-      }
-      const uint32_t j = ITEMS * tid + i;
-      bool last;
-      if (j + 1 == n_in) last = s_taillast != 0;
-      else if (i + 1 < ITEMS) last = (meta[i + 1] & 7u) == 0;
-      else last = s_firstlv[tid + 1] == 0;
-      if (!last) continue;
-      if (aggB[0] & SEGF) {  // the location started in this thread
-        if (((aggB[0] | aggB[1]) & ~SEGF) != 0) n_emit++;
+#pragma unroll
+      for (int k = 0; k < 5; k++) agg.leadsum[k] = s_lead[12 + k];
+      if (agg.m == 0) {
+        agg.trailsum[K_WW] = (uint32_t)totB[0];
+        agg.trailsum[K_RW] = (uint32_t)(totB[0] >> 32) & 0x7FFFFFFFu;
+        agg.trailsum[K_AW] = (uint32_t)totB[1];
+        agg.trailsum[K_AR] = (uint32_t)(totB[1] >> 32) & 0x7FFFFFFFu;
+        agg.trailsum[K_XB] = (uint32_t)totB[2];
       } else {
-        pend = true;
-        pend0 = aggB[0];
-        pend1 = aggB[1];
+#pragma unroll
+        for (int k = 0; k < 5; k++) agg.trailsum[k] = 0;
       }
+      uint32_t w = 0;
+#pragma unroll
+      for (int i = 0; i < SW; i++)
+        if ((int)lane == i) w = state_word(agg, i);
+      if (lane < (uint32_t)SW) b.agg[(uint64_t)tile * SW + lane] = w;
+      if (lane == 0) b.tout[tile].owns = (agg.m == 0 && !s_taillast) ? 1u : 0u;
     }
-    if (lead_thread) {
-#pragma unroll
-      for (int l = 0; l < 4; l++)
-#pragma unroll
-        for (int q = 0; q < 3; q++)
-          if (leadc[l][q]) atomicAdd(&s_lead[l * 3 + q], leadc[l][q]);
-#pragma unroll
-      for (int k = 0; k < 5; k++)
-        if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
-    }
-  }
-  uint64_t exB[3], totB[3];
-  block_seg_scan<3>(aggB, exB, totB, s_scanB);  // contains a barrier: s_lead and s_min are complete after it
-  // the thread's first location: complete here only if it started in the
-  // tile (a location head in an earlier thread); otherwise it belongs to an
-  // earlier tile and is finished by k_scan_cross
-  if (pend && (exB[0] & SEGF) && ((((exB[0] + pend0) | (exB[1] + pend1)) & ~SEGF) != 0)) n_emit++;
 
-  // ---- the tile summary (lanes of wave 0 write its words)
-  if (wave == 0) {
-    State agg;
-    agg.m = s_min;
+    // ---- complete locations: started after the tile's first location head
+    //      and ended inside the tile.  Written (rarely: only threads that
+    //      counted one) at their last element.
+    auto walk_emit = [&](RaceOut* dst, uint32_t cap, uint32_t pos) {
+      uint64_t run[4];
 #pragma unroll
-    for (int l = 0; l < 4; l++)
+      for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
+      uint64_t s0 = exB[0] & ~SEGF, s1 = exB[1] & ~SEGF, s2 = exB[2] & ~SEGF;
+      bool seen0 = (exB[0] & SEGF) != 0;
 #pragma unroll
-      for (int q = 0; q < 3; q++) {
-        agg.lead[l][q] = s_lead[l * 3 + q];
-        agg.trail[l][q] = cnt16(totA[l], q);
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t lv = meta[i] & 7u, c = meta[i] >> 3;
+#pragma unroll
+        for (int l = 0; l < 4; l++)
+          if (lv <= (uint32_t)l) run[l] = 0;
+        if (c == CLS_NONE) continue;
+        if (lv == 0) {
+          s0 = s1 = s2 = 0;
+          seen0 = true;
+        }
+        uint32_t v[5];
+        tile_pairs(c, run, v);
+        s0 += (uint64_t)v[K_WW] | ((uint64_t)v[K_RW] << 32);
+        s1 += (uint64_t)v[K_AW] | ((uint64_t)v[K_AR] << 32);
+        s2 += (uint64_t)v[K_XB];
+#pragma unroll
+        for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
+        if (!seen0) continue;  // the location entering the tile belongs to an earlier tile
+        const uint32_t j = ITEMS * tid + i;
+        bool last;
+        if (j + 1 == n_in) last = s_taillast != 0;
+        else if (i + 1 < ITEMS) last = (meta[i + 1] & 7u) == 0;
+        else last = s_firstlv[tid + 1] == 0;
+        if (!last) continue;
+        uint64_t S[5];
+        S[K_WW] = (uint32_t)s0; S[K_RW] = (uint32_t)(s0 >> 32);
+        S[K_AW] = (uint32_t)s1; S[K_AR] = (uint32_t)(s1 >> 32);
+        S[K_XB] = (uint32_t)s2;
+        if (S[K_WW] + S[K_RW] + S[K_AW] + S[K_AR] == 0) continue;
+        if (pos < cap) write_entry(dst + pos, tr.trace, L, key[i], S);
+        pos++;
       }
-#pragma unroll
-    for (int k = 0; k < 5; k++) agg.leadsum[k] = s_lead[12 + k];
-    if (agg.m == 0) {
-      agg.trailsum[K_WW] = (uint32_t)totB[0];
-      agg.trailsum[K_RW] = (uint32_t)(totB[0] >> 32) & 0x7FFFFFFFu;
-      agg.trailsum[K_AW] = (uint32_t)totB[1];
-      agg.trailsum[K_AR] = (uint32_t)(totB[1] >> 32) & 0x7FFFFFFFu;
-      agg.trailsum[K_XB] = (uint32_t)totB[2];
-    } else {
-#pragma unroll
-      for (int k = 0; k < 5; k++) agg.trailsum[k] = 0;
+    };
+    uint32_t tile_emit;
+    const uint32_t my_off = block_excl_sum(n_emit, s_scan32, &tile_emit);
+    uint32_t cap;
+    RaceOut* stage = stage_of(b, tile, T, L, start, n_in, &cap);
+    if (n_emit) walk_emit(stage, cap, my_off);
+    if (tid == 0) {
+      b.tout[tile].in_count = tile_emit;
+      if (tile_emit > cap) atomicOr(&b.ctrl->error_flags, ERR_STAGE_OVERFLOW);
     }
-    uint32_t w = 0;
-#pragma unroll
-    for (int i = 0; i < SW; i++)
-      if ((int)lane == i) w = state_word(agg, i);
-    if (lane < (uint32_t)SW) b.agg[(uint64_t)tile * SW + lane] = w;
-    if (lane == 0) b.tout[tile].owns = (agg.m == 0 && !s_taillast) ? 1u : 0u;
-  }
-
-  // ---- complete locations: started after the tile's first location head
-  //      and ended inside the tile.  Written (rarely: only threads that
-  //      counted one) at their last element.
-  auto walk_emit = [&](RaceOut* dst, uint32_t cap, uint32_t pos) {
-    uint64_t run[4];
-#pragma unroll
-    for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
-    uint64_t s0 = exB[0] & ~SEGF, s1 = exB[1] & ~SEGF, s2 = exB[2] & ~SEGF;
-    bool seen0 = (exB[0] & SEGF) != 0;
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t lv = meta[i] & 7u, c = meta[i] >> 3;
-#pragma unroll
-      for (int l = 0; l < 4; l++)
-        if (lv <= (uint32_t)l) run[l] = 0;
-      if (c == CLS_NONE) continue;
-      if (lv == 0) {
-        s0 = s1 = s2 = 0;
-        seen0 = true;
-      }
-      uint32_t v[5];
-      tile_pairs(c, run, v);
-      s0 += (uint64_t)v[K_WW] | ((uint64_t)v[K_RW] << 32);
-      s1 += (uint64_t)v[K_AW] | ((uint64_t)v[K_AR] << 32);
-      s2 += (uint64_t)v[K_XB];
-#pragma unroll
-      for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
-      if (!seen0) continue;  // the location entering the tile belongs to an earlier tile
-      const uint32_t j = ITEMS * tid + i;
-      bool last;
-      if (j + 1 == n_in) last = s_taillast != 0;
-      else if (i + 1 < ITEMS) last = (meta[i + 1] & 7u) == 0;
-      else last = s_firstlv[tid + 1] == 0;
-      if (!last) continue;
-      uint64_t S[5];
-      S[K_WW] = (uint32_t)s0; S[K_RW] = (uint32_t)(s0 >> 32);
-      S[K_AW] = (uint32_t)s1; S[K_AR] = (uint32_t)(s1 >> 32);
-      S[K_XB] = (uint32_t)s2;
-      if (S[K_WW] + S[K_RW] + S[K_AW] + S[K_AR] == 0) continue;
-      if (pos < cap) write_entry(dst + pos, tr.trace, L, key[i], S);
-      pos++;
-    }
-  };
-  uint32_t tile_emit;
-  const uint32_t my_off = block_excl_sum(n_emit, s_scan32, &tile_emit);
-  uint32_t cap;
-  RaceOut* stage = stage_of(b, tile, T, L, start, n_in, &cap);
-  if (n_emit) walk_emit(stage, cap, my_off);
-  if (tid == 0) {
-    b.tout[tile].in_count = tile_emit;
-    if (tile_emit > cap) atomicOr(&b.ctrl->error_flags, ERR_STAGE_OVERFLOW);
   }
 }
 
@@ -1046,14 +1080,26 @@ __global__ void k_reset_errors(Ctrl* ctrl, uint32_t mask) {
 
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// The tile walk needs grids that are non-zero multiples of the XCD count.
+static inline bool grids_ok(const Buffers& b) {
+  for (uint32_t g : {b.grid_stream, b.grid_sort, b.grid_scan})
+    if (g == 0 || g % N_XCD != 0) return false;
+  return true;
+}
+
+// Whether a grid leaves some workgroup more than one tile (the looping
+// variant of a tile kernel), or at most one each (the one-tile variant).
+static inline bool loops(const Buffers& b, uint32_t grid) { return grid / N_XCD < cdiv(b.n_tiles, N_XCD); }
+
 hipError_t launch_init(const Buffers& b, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, b.ctrl);
   return hipGetLastError();
 }
 hipError_t launch_stats(const Buffers& b, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_stats, dim3(b.n_tiles), dim3(NT), 0, s, (const ulonglong2*)b.records, b.desc, b.tiles,
-                     b.stats_part);
+  if (!grids_ok(b)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(loops(b, b.grid_stream) ? k_stats<true> : k_stats<false>, dim3(b.grid_stream), dim3(NT), 0, s,
+                     (const ulonglong2*)b.records, b.desc, b.tiles, b.n_tiles, b.stats_part);
   return hipGetLastError();
 }
 hipError_t launch_layout(const Buffers& b, hipStream_t s) {
@@ -1063,13 +1109,15 @@ hipError_t launch_layout(const Buffers& b, hipStream_t s) {
 }
 hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_keygen, dim3(b.n_tiles), dim3(NT), 0, s, b);
+  if (!grids_ok(b)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(loops(b, b.grid_stream) ? k_keygen<true> : k_keygen<false>, dim3(b.grid_stream), dim3(NT), 0, s, b);
   return hipGetLastError();
 }
 hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
+  if (!grids_ok(b)) return hipErrorInvalidConfiguration;
   if (pass > 0) {  // digit 0's histograms come from k_keygen
-    hipLaunchKernelGGL(k_upsweep, dim3(b.n_tiles), dim3(NT), 0, s, b, pass);
+    hipLaunchKernelGGL(loops(b, b.grid_stream) ? k_upsweep<true> : k_upsweep<false>, dim3(b.grid_stream), dim3(NT), 0, s, b, pass);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1081,12 +1129,14 @@ hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s) {
 }
 hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3(b.n_tiles), dim3(NT), 0, s, b, pass);
+  if (!grids_ok(b)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(loops(b, b.grid_sort) ? k_scatter<true> : k_scatter<false>, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
   return hipGetLastError();
 }
 hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_tiles, dim3(b.n_tiles), dim3(NT), 0, s, b, passes_done);
+  if (!grids_ok(b)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(loops(b, b.grid_scan) ? k_scan_tiles<true> : k_scan_tiles<false>, dim3(b.grid_scan), dim3(NT), 0, s, b, passes_done);
   return hipGetLastError();
 }
 hipError_t launch_scan_cross(const Buffers& b, uint32_t passes_done, hipStream_t s) {

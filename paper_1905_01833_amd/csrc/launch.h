@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "keys.h"
+#include "tilewalk.h"
 
 namespace sc {
 
@@ -84,6 +85,9 @@ struct Buffers {            // device pointers of one call
   uint32_t n_traces;
   uint32_t n_tiles;
   uint32_t n_groups;        // histogram groups
+  uint32_t grid_stream;     // workgroups of k_stats / k_keygen / k_upsweep (multiple of 8)
+  uint32_t grid_sort;       // workgroups of k_scatter
+  uint32_t grid_scan;       // workgroups of k_scan_tiles
 };
 
 // Kernel stages, in launch order.

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../paper_1905_01833_amd/csrc/segstate.h"
+#include "../paper_1905_01833_amd/csrc/tilewalk.h"
 
 struct rec {
   uint64_t unit;
@@ -154,4 +155,25 @@ extern "C" int hs_assoc(uint64_t seed, int trials) {
     }
   }
   return 0;
+}
+
+// Tile walk of a launch as the tile kernels run it: the grid for `per_cu`
+// workgroups per CU over n_cu CUs, every workgroup's tiles counted in
+// count[n].  One-tile kernels (grid / 8 >= the tiles per XCD) visit only the
+// first tile of their walk.  Returns the grid; *max_per_wg receives the most
+// tiles any workgroup visited.
+extern "C" uint32_t hs_tile_walk(uint32_t n, uint32_t per_cu, uint32_t n_cu, uint32_t* count, uint32_t* max_per_wg) {
+  const uint32_t grid = tile_grid(n, per_cu, n_cu);
+  const bool loop = grid / N_XCD < (n + N_XCD - 1) / N_XCD;
+  *max_per_wg = 0;
+  for (uint32_t wg = 0; wg < grid; wg++) {
+    const TileWalk w = tile_walk(n, grid, wg);
+    uint32_t k = 0;
+    for (uint32_t t = w.first; t < w.end; t = loop ? t + w.step : w.end) {
+      count[t]++;
+      k++;
+    }
+    *max_per_wg = std::max(*max_per_wg, k);
+  }
+  return grid;
 }

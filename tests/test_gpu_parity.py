@@ -284,3 +284,81 @@ def test_c1_full_size(ctx):
     for e in inj:
         blk = int(e["block"]) if int(e["space"]) == 1 else 0xFFFFFFFF
         assert (int(e["space"]), blk, int(e["unit"])) in keys
+
+
+# ------------------------------------------------------ launch shapes (batched)
+
+SHAPES = [
+    {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 0, "scan_wgs_per_cu": 0, "group_shift_bias": 0},
+    {"stream_wgs_per_cu": 1, "sort_wgs_per_cu": 1, "scan_wgs_per_cu": 1, "group_shift_bias": -1},
+    {"stream_wgs_per_cu": 2, "sort_wgs_per_cu": 1, "scan_wgs_per_cu": 1, "group_shift_bias": 1},
+    {"stream_wgs_per_cu": 8, "sort_wgs_per_cu": 4, "scan_wgs_per_cu": 2, "group_shift_bias": -12},
+    {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 2, "scan_wgs_per_cu": 0, "group_shift_bias": 12},
+]
+
+
+def test_every_launch_shape_bit_exact(ctx):
+    """Persistent (looping) and one-tile-per-workgroup kernels, and histogram
+    groups from one tile to whole traces, give identical results.  The
+    input has more tiles than one workgroup per CU, so the small grids loop."""
+    big, _ = tracegen.c1(n_blocks=96, inject_rate=3e-4, seed=123)
+    shapes = tracegen.c3_shapes(40, log2_max=17, seed=5)
+    small, off, tpb, _ = tracegen.batch(shapes, inject_rate=5e-4)
+    recs = np.concatenate([small, big])
+    off = np.concatenate([off, [off[-1] + len(big)]]).astype(np.uint64)
+    tpb = np.concatenate([tpb, [256]]).astype(np.uint32)
+    assert (len(recs) + 4095) // 4096 > 300
+    want, wsum = oracle.closed_form(recs, off, tpb)
+    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    cls = tracegen_size_class(len(recs))
+    try:
+        for sh in SHAPES:
+            say(f"shape {sh}")
+            ctx.set_tuning(cls, sh)
+            got, gsum = ctx.check_traces_device(dev, off, tpb)
+            torch.cuda.synchronize()
+            assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes(), sh
+    finally:
+        ctx.set_tuning(cls, None)
+
+
+def tracegen_size_class(n):
+    import paper_1905_01833_amd as pkg
+
+    return pkg.sim_size_class(n)
+
+
+def test_autotune_and_tuning_cache(ctx, tmp_path):
+    import paper_1905_01833_amd as pkg
+
+    shapes = tracegen.c3_shapes(64, log2_max=16, seed=6)
+    recs, off, tpb, _ = tracegen.batch(shapes, inject_rate=5e-4)
+    want, wsum = oracle.closed_form(recs, off, tpb)
+    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    say("autotune 64 traces")
+    g = pkg.Context(0, graphs=True)
+    try:
+        best = g.autotune(dev, off, tpb, reps=1)
+        assert best["ms"] > 0
+        is_set, t = g.tuning(best["size_class"])
+        assert is_set and all(t[f] == best[f] for f in pkg.TUNING_FIELDS)
+        for rep in range(3):  # graph capture and replays with the tuned shape
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                got, gsum = g.check_traces_device(dev, off, tpb, stream=stream.cuda_stream)
+            assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes(), rep
+        path = str(tmp_path / "tuning.json")
+        g.save_tuning(path)
+    finally:
+        g.close()
+    h = pkg.Context(0)
+    try:
+        assert h.load_tuning(path) == 1
+        is_set, t = h.tuning(best["size_class"])
+        assert is_set and all(t[f] == best[f] for f in pkg.TUNING_FIELDS)
+        got, _ = h.check_traces(recs, off, tpb)
+        assert got.tobytes() == want.tobytes()
+    finally:
+        h.close()
+    with pytest.raises(pkg.SimError):
+        ctx.set_tuning(40, None)

@@ -29,6 +29,9 @@ def _hostsim():
     lib.hs_check.restype = ctypes.c_int64
     lib.hs_check.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                                      ctypes.c_uint64, ctypes.c_void_p]
+    lib.hs_tile_walk.restype = ctypes.c_uint32
+    lib.hs_tile_walk.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_uint32)]
     lib.hs_assoc.restype = ctypes.c_int
     lib.hs_assoc.argtypes = [ctypes.c_uint64, ctypes.c_int]
     return lib
@@ -79,11 +82,30 @@ def test_host_model_generated_and_mega_location():
         assert got.tobytes() == want.tobytes()
 
 
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 63, 64, 65, 1000, 4097, 131075])
+@pytest.mark.parametrize("per_cu", [0, 1, 2, 4, 8, 64])
+def test_tile_walk_covers_every_tile_once(n, per_cu):
+    """Every launch shape visits each tile of the queue exactly once; the
+    one-workgroup-per-tile shape gives no workgroup a second tile; a
+    persistent grid stays within its per-CU budget (rounded to 8)."""
+    lib = _hostsim()
+    for n_cu in (256, 3, 80):
+        count = np.zeros(n, dtype=np.uint32)
+        mx = ctypes.c_uint32(0)
+        grid = lib.hs_tile_walk(n, per_cu, n_cu, count.ctypes.data, ctypes.byref(mx))
+        assert (count == 1).all(), (n, per_cu, n_cu)
+        assert grid % 8 == 0 and grid >= 8
+        if per_cu == 0:
+            assert mx.value == 1 and grid < n + 8
+        else:
+            assert grid <= max(8, -(-min(n, per_cu * n_cu) // 8) * 8)
+
+
 def test_header_exports_match_library():
     import paper_1905_01833_amd as pkg
 
     hdr = open(os.path.join(ROOT, "include", "simcheck.h")).read()
-    declared = set(re.findall(r"^(?:int|void|const char\*)\s+(sim_\w+)\(", hdr, re.M))
+    declared = set(re.findall(r"^(?:int|void|uint32_t|const char\*)\s+(sim_\w+)\(", hdr, re.M))
     assert declared == set(pkg.EXPORTS)
     lib = pkg.load()
     for name in declared:

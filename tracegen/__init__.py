@@ -91,6 +91,9 @@ def _load():
             ctypes.c_uint64,
             ctypes.c_int,
         ]
+        lib.tg_generate_batch.restype = ctypes.c_int64
+        lib.tg_generate_batch.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.tg_tree_reduction.restype = ctypes.c_int64
         lib.tg_tree_reduction.argtypes = [ctypes.c_int, ctypes.c_void_p]
         lib.tg_splitmix64.restype = ctypes.c_uint64
@@ -230,21 +233,27 @@ def c3_shapes(n_traces: int = 4096, seed: int = 0x5EED0003, log2_min: float = 8.
 
 def batch(shapes, inject_rate: float = 1e-4, threads: int | None = None):
     """Generate a batch of traces; returns (records, offsets, tpb, injections)
-    where injections carry a 'trace' column."""
+    with injections a list of (trace index, injection log).  Trace i is the
+    same as ``generate`` with shape i (c1 distributions, 256 threads per
+    block); traces are generated in parallel."""
     sizes = np.array([s[0] for s in shapes], dtype=np.uint64)
     offsets = np.zeros(len(shapes) + 1, dtype=np.uint64)
     np.cumsum(sizes, out=offsets[1:])
     recs = np.zeros(int(offsets[-1]), dtype=RECORD_DTYPE)
     tpb = np.full(len(shapes), 256, dtype=np.uint32)
-    inj = []
+    params = (_Params * max(1, len(shapes)))()
+    caps = np.zeros(len(shapes) + 1, dtype=np.uint64)
     for i, (n, nb, k, s) in enumerate(shapes):
-        view = recs[int(offsets[i]) : int(offsets[i + 1])]
-        _, log = generate(
-            nb, 256, k, n_records=n, per_epoch=16, p_read=0.75, p_write=0.25, p_shared=0.5,
-            shared_words=12288, global_read_log2=24, atomic_bins_log2=16, zipf_s=1.1,
-            inject_rate=inject_rate, seed=s, trace_id=i, out=view, threads=threads,
-        )
-        inj.append((i, log))
+        params[i] = _Params(nb, 256, k, 16, 0.75, 0.25, 0.5, 12288, 24, 16, 1.1, n, inject_rate,
+                            int(s) & 0xFFFFFFFFFFFFFFFF, i)
+        caps[i + 1] = caps[i] + max(1, int(round(inject_rate * n)))
+    logs = np.zeros(max(1, int(caps[-1])), dtype=INJ_DTYPE)
+    counts = np.zeros(max(1, len(shapes)), dtype=np.int64)
+    rc = _load().tg_generate_batch(params, len(shapes), recs.ctypes.data, offsets.ctypes.data, logs.ctypes.data,
+                                   caps.ctypes.data, counts.ctypes.data, threads or _threads())
+    if rc < 0:
+        raise ValueError("tg_generate_batch rejected its parameters")
+    inj = [(i, logs[int(caps[i]) : int(caps[i]) + int(counts[i])]) for i in range(len(shapes))]
     return recs, offsets, tpb, inj
 
 

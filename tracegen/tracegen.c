@@ -344,18 +344,22 @@ static int64_t inject(const tg_params* P, const rng_t* g, tg_record* out, tg_inj
 /* Generate one trace.  `out` holds n_records records; `log` (nullable)
  * receives up to log_cap injections.  Returns the number of injections, or a
  * negative value on bad parameters. */
+static int params_ok(const tg_params* P) {
+  if (!P || P->tpb == 0 || P->k == 0 || P->n_blocks == 0) return 0;
+  if ((uint64_t)P->n_blocks * P->tpb * P->k < P->n_records) return 0;
+  if (P->shared_words == 0 || P->global_read_log2 > 40 || P->atomic_bins_log2 > 32) return 0;
+  if ((uint64_t)P->n_blocks * P->tpb > 0xFFFFFFFFull) return 0;
+  if ((P->k + (P->per_epoch ? P->per_epoch : P->k) - 1) / (P->per_epoch ? P->per_epoch : P->k) > 65536u) return 0;
+  return 1;
+}
+
 int64_t tg_generate(const tg_params* P, tg_record* out, tg_injection* log, uint64_t log_cap, int n_threads) {
-  if (!P || !out || P->tpb == 0 || P->k == 0 || P->n_blocks == 0) return -1;
-  if ((uint64_t)P->n_blocks * P->tpb * P->k < P->n_records) return -1;
-  if (P->shared_words == 0 || P->global_read_log2 > 40 || P->atomic_bins_log2 > 32) return -1;
-  if ((uint64_t)P->n_blocks * P->tpb > 0xFFFFFFFFull) return -1;
-  if ((P->k + (P->per_epoch ? P->per_epoch : P->k) - 1) / (P->per_epoch ? P->per_epoch : P->k) > 65536u) return -1;
+  if (!out || !params_ok(P)) return -1;
   rng_t g = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32), P->trace_id};
   zipf_t zr, za;
   zipf_init(&zr, 1ull << P->global_read_log2, P->zipf_s);
   zipf_init(&za, 1ull << P->atomic_bins_log2, P->zipf_s);
   const int64_t nb = P->n_blocks;
-  (void)n_threads;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
   {
     int32_t* writer = (int32_t*)malloc(sizeof(int32_t) * P->shared_words);
@@ -364,6 +368,59 @@ int64_t tg_generate(const tg_params* P, tg_record* out, tg_injection* log, uint6
     free(writer);
   }
   return inject(P, &g, out, log, log_cap);
+}
+
+typedef struct {
+  uint64_t n, i;
+} size_by_index;
+
+static int larger_first(const void* a, const void* b) {
+  const size_by_index *x = (const size_by_index*)a, *y = (const size_by_index*)b;
+  if (x->n != y->n) return x->n > y->n ? -1 : 1;
+  return x->i < y->i ? -1 : (x->i > y->i);
+}
+
+/* Many traces at once: trace i (parameters P[i]) is written to
+ * out + offsets[i] and its injections to log + log_off[i] (capacity
+ * log_off[i+1] - log_off[i]); n_inj[i] receives the injection count.  The
+ * records are the same as n_traces calls of tg_generate; the work is spread
+ * over traces rather than over the blocks of one trace.  Returns 0, or -1
+ * (nothing written) when some trace's parameters are invalid. */
+int64_t tg_generate_batch(const tg_params* P, uint64_t n_traces, tg_record* out, const uint64_t* offsets,
+                          tg_injection* log, const uint64_t* log_off, int64_t* n_inj, int n_threads) {
+  if (!P || !out || !offsets || !log || !log_off || !n_inj) return -1;
+  for (uint64_t i = 0; i < n_traces; i++)
+    if (!params_ok(&P[i]) || offsets[i + 1] - offsets[i] != P[i].n_records) return -1;
+  /* largest traces first, for balance */
+  size_by_index* order = (size_by_index*)malloc(sizeof(size_by_index) * (n_traces ? n_traces : 1));
+  if (!order) return -1;
+  for (uint64_t i = 0; i < n_traces; i++) { order[i].n = P[i].n_records; order[i].i = i; }
+  qsort(order, n_traces, sizeof(size_by_index), larger_first);
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
+  {
+    uint32_t cap = 0;
+    int32_t* writer = NULL;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t j = 0; j < (int64_t)n_traces; j++) {
+      const uint64_t i = order[j].i;
+      const tg_params* p = &P[i];
+      if (p->shared_words > cap) {
+        free(writer);
+        cap = p->shared_words;
+        writer = (int32_t*)malloc(sizeof(int32_t) * cap);
+      }
+      rng_t g = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32), p->trace_id};
+      zipf_t zr, za;
+      zipf_init(&zr, 1ull << p->global_read_log2, p->zipf_s);
+      zipf_init(&za, 1ull << p->atomic_bins_log2, p->zipf_s);
+      tg_record* o = out + offsets[i];
+      for (uint32_t b = 0; b < p->n_blocks; b++) gen_block(p, &g, &zr, &za, b, o, writer);
+      n_inj[i] = inject(p, &g, o, log + log_off[i], log_off[i + 1] - log_off[i]);
+    }
+    free(writer);
+  }
+  free(order);
+  return 0;
 }
 
 /* ---------------- hand-built trace: shared-memory tree reduction ----------
