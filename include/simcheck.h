@@ -119,6 +119,7 @@ enum {
   SIM_ERECORD = -2, /* action > 2 or space > 1; sim_last_error() names the first bad index */
   SIM_ENOMEM = -3,  /* device or host allocation failed */
   SIM_EDEVICE = -4, /* HIP runtime error (text in sim_last_error()) */
+  SIM_EAGAIN = -5,  /* serving: result not ready yet, or the pending queue is full */
   SIM_ERANGE = -6   /* a trace's sort key would need more than 64 bits */
 };
 
@@ -221,6 +222,86 @@ int sim_get_tuning(const sim_ctx* ctx, uint32_t size_class, sim_tuning* t);
  * the trial calls are discarded; on error the class keeps its old shape.  */
 int sim_autotune(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
                  const uint32_t* threads_per_block, void* stream, uint32_t reps, sim_tuning* best);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A server checks requests (each one call's worth of traces: records,
+ * offsets, threads per block, as for sim_check_traces) that arrive over
+ * time, with continuous batching: `slots` worker threads each own a context
+ * (its own stream and device buffers); a free worker takes the pending
+ * requests in arrival order, as many as fit its batch limits and the HBM
+ * budget, checks them as ONE call (one trace list, so small requests share
+ * every launch), and hands each request its own part of the result.
+ * Requests that arrive while batches run wait for the next free worker;
+ * batches of different workers overlap on the GPU.  A request's result is
+ * the result sim_check_traces gives for it alone (trace numbers relative
+ * to the request), including its error code: when a batch fails, its
+ * requests are checked one by one so that one bad request fails alone.
+ *
+ * Admission by device-memory footprint: a request needs about
+ * 36 bytes per record + 4.5 KiB per 4096-record tile + 128 bytes per
+ * trace (records, two key buffers, per-tile and per-trace tables, output);
+ * the footprints of the batches on the GPU never exceed the budget, and a
+ * worker releases its buffers after a batch when they exceed its share
+ * (budget / slots).  A request whose footprint alone exceeds the budget is
+ * refused at submission (SIM_ENOMEM).
+ *
+ * All server calls are thread-safe.                                        */
+typedef struct sim_server sim_server;
+
+typedef struct sim_server_config {
+  uint64_t hbm_budget_bytes;   /* footprint of the batches on the GPU at most (0: 8 GiB) */
+  uint64_t max_batch_records;  /* records per batch at most (0: 2^26; a larger request runs alone) */
+  uint32_t slots;              /* worker threads = batches on the GPU at once (0: 2; at most 16) */
+  uint32_t max_batch_requests; /* requests per batch at most (0: 1024) */
+  uint32_t max_pending;        /* submitted requests not yet taken by a worker at most (0: 65536) */
+  uint32_t reserved;
+} sim_server_config;
+
+typedef struct sim_server_stats {
+  uint64_t submitted, completed, failed; /* requests */
+  uint64_t batches;                      /* batches run */
+  uint64_t records;                      /* records of completed requests */
+  double p50_ms, p99_ms, max_ms, mean_ms; /* latency of completed requests, submission to result ready */
+  double records_per_s;                  /* records of completed requests / (last completion - first submission) */
+  double mean_batch_requests;            /* completed requests per batch */
+  uint64_t peak_inflight_bytes;          /* largest sum of footprints on the GPU */
+  uint64_t device_bytes;                 /* device buffers the workers hold now */
+} sim_server_stats;
+
+/* Create a server on HIP device `hip_device` (gfx950).  cfg may be NULL.  */
+int sim_server_create(sim_server** out, int hip_device, const sim_server_config* cfg);
+
+/* Finish every submitted request, stop the workers, free all results not
+ * yet collected and the server.  NULL is ignored.                          */
+void sim_server_destroy(sim_server* srv);
+
+/* Submit one request (arguments as for sim_check_traces; host memory).
+ * offsets and threads_per_block are copied; the records are read by a
+ * worker later and must stay valid and unchanged until the request's
+ * result has been collected (sim_poll / sim_wait returned something other
+ * than SIM_EAGAIN).  *ticket identifies the request.  Errors: SIM_EINVAL
+ * (bad tables), SIM_ENOMEM (footprint above the budget), SIM_EAGAIN
+ * (max_pending requests wait already).                                     */
+int sim_submit(sim_server* srv, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
+               const uint32_t* threads_per_block, uint64_t* ticket);
+
+/* Collect a request's result: SIM_EAGAIN while it is pending; otherwise the
+ * request's own return code, with *out set on success (caller frees it with
+ * sim_result_free).  The ticket is consumed unless SIM_EAGAIN is returned;
+ * an unknown ticket gives SIM_EINVAL.                                      */
+int sim_poll(sim_server* srv, uint64_t ticket, sim_result** out);
+
+/* As sim_poll, but blocks until the result is ready or timeout_ms passes
+ * (negative: no limit; SIM_EAGAIN on timeout).                             */
+int sim_wait(sim_server* srv, uint64_t ticket, int64_t timeout_ms, sim_result** out);
+
+/* Counters and latency percentiles since creation or the last reset.      */
+int sim_server_get_stats(sim_server* srv, sim_server_stats* out, int reset);
+
+/* Text of the error of the last sim_submit / sim_poll / sim_wait that
+ * failed on the calling thread ("" if none).                              */
+const char* sim_server_last_error(void);
 
 #ifdef __cplusplus
 }

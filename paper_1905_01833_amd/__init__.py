@@ -37,8 +37,10 @@ STAGES = ["init", "stats", "layout", "keygen", "upsweep", "sort_pass", "scan_til
 EXPORTS = [
     "sim_create", "sim_destroy", "sim_last_error", "sim_check_traces", "sim_check_traces_device",
     "sim_result_free", "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning",
-    "sim_get_tuning", "sim_autotune",
+    "sim_get_tuning", "sim_autotune", "sim_server_create", "sim_server_destroy", "sim_submit", "sim_poll",
+    "sim_wait", "sim_server_get_stats", "sim_server_last_error",
 ]
+SIM_EAGAIN = -5
 SIM_SIZE_CLASSES = 33
 TUNING_FIELDS = ("stream_wgs_per_cu", "sort_wgs_per_cu", "scan_wgs_per_cu", "group_shift_bias")
 
@@ -82,6 +84,27 @@ def _tuning_dict(t: _Tuning) -> dict:
     return d
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("max_batch_records", ctypes.c_uint64),
+        ("slots", ctypes.c_uint32),
+        ("max_batch_requests", ctypes.c_uint32),
+        ("max_pending", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+        ("batches", ctypes.c_uint64), ("records", ctypes.c_uint64),
+        ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+        ("mean_ms", ctypes.c_double), ("records_per_s", ctypes.c_double), ("mean_batch_requests", ctypes.c_double),
+        ("peak_inflight_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+    ]
+
+
 _lib = None
 
 
@@ -122,6 +145,20 @@ def load() -> ctypes.CDLL:
     lib.sim_get_tuning.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(_Tuning)]
     lib.sim_autotune.restype = ctypes.c_int
     lib.sim_autotune.argtypes = [P, P, P, ctypes.c_uint32, P, P, ctypes.c_uint32, ctypes.POINTER(_Tuning)]
+    lib.sim_server_create.restype = ctypes.c_int
+    lib.sim_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(_ServerConfig)]
+    lib.sim_server_destroy.restype = None
+    lib.sim_server_destroy.argtypes = [P]
+    lib.sim_submit.restype = ctypes.c_int
+    lib.sim_submit.argtypes = [P, P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.sim_poll.restype = ctypes.c_int
+    lib.sim_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.POINTER(_Result))]
+    lib.sim_wait.restype = ctypes.c_int
+    lib.sim_wait.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ctypes.POINTER(_Result))]
+    lib.sim_server_get_stats.restype = ctypes.c_int
+    lib.sim_server_get_stats.argtypes = [P, ctypes.POINTER(_ServerStats), ctypes.c_int]
+    lib.sim_server_last_error.restype = ctypes.c_char_p
+    lib.sim_server_last_error.argtypes = []
     _lib = lib
     return lib
 
@@ -347,3 +384,74 @@ def load_tuning_file(path: str) -> dict:
             raise ValueError(f"{path}: size class {k} out of range")
         out[str(int(k))] = {f: int(t[f]) for f in TUNING_FIELDS} | {"ms": float(t.get("ms", 0.0))}
     return out
+
+
+# ---------------------------------------------------------------- serving
+
+class Server:
+    """Request loop with continuous batching (sim_server_* of the C ABI).
+
+    submit() keeps a reference to the request's arrays until its result is
+    collected, as the C ABI requires."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, slots: int = 0, max_batch_records: int = 0,
+                 max_batch_requests: int = 0, max_pending: int = 0):
+        lib = load()
+        cfg = _ServerConfig(hbm_budget_bytes, max_batch_records, slots, max_batch_requests, max_pending, 0)
+        self._srv = ctypes.c_void_p()
+        rc = lib.sim_server_create(ctypes.byref(self._srv), device, ctypes.byref(cfg))
+        if rc != SIM_OK:
+            raise SimError(rc, lib.sim_server_last_error().decode())
+        self._keep = {}
+
+    def close(self):
+        if self._srv:
+            load().sim_server_destroy(self._srv)
+            self._srv = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, records: np.ndarray, offsets=None, threads_per_block=1) -> int:
+        lib = load()
+        records = np.ascontiguousarray(records)
+        if records.dtype.itemsize != 16:
+            raise TypeError("records must be 16-byte sim_record entries")
+        offsets, n_traces, tpb = _tables(offsets, threads_per_block, len(records))
+        t = ctypes.c_uint64(0)
+        rc = lib.sim_submit(self._srv, records.ctypes.data if len(records) else None, offsets.ctypes.data, n_traces,
+                            tpb.ctypes.data, ctypes.byref(t))
+        if rc != SIM_OK:
+            raise SimError(rc, lib.sim_server_last_error().decode())
+        self._keep[t.value] = records
+        return t.value
+
+    def _collect(self, rc, ticket, out):
+        lib = load()
+        if rc == SIM_EAGAIN:
+            return None
+        self._keep.pop(ticket, None)
+        if rc != SIM_OK:
+            raise SimError(rc, lib.sim_server_last_error().decode())
+        return _take_result(out)
+
+    def poll(self, ticket: int):
+        """(races, summaries) when ready, None while pending; raises the
+        request's error."""
+        out = ctypes.POINTER(_Result)()
+        return self._collect(load().sim_poll(self._srv, ticket, ctypes.byref(out)), ticket, out)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        out = ctypes.POINTER(_Result)()
+        return self._collect(load().sim_wait(self._srv, ticket, timeout_ms, ctypes.byref(out)), ticket, out)
+
+    def stats(self, reset: bool = False) -> dict:
+        st = _ServerStats()
+        rc = load().sim_server_get_stats(self._srv, ctypes.byref(st), 1 if reset else 0)
+        if rc != SIM_OK:
+            raise SimError(rc, "stats")
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libsimcheck.so")
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "api.cpp")]
+SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "serve.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -17,6 +17,7 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    "-pthread",
     # no packed fp32 instructions in any HIP code of this project
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

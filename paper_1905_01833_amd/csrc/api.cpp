@@ -493,6 +493,33 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
 
 }  // namespace
 
+// ---- internal hooks for the serving runtime (serve.cpp)
+namespace sc {
+
+size_t ctx_device_bytes(const sim_ctx* c) {
+  size_t t = 0;
+  for (const DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->groups, &c->stats_part,
+                          &c->layout, &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag,
+                          &c->group_sum, &c->group_off, &c->stage, &c->ctrl, &c->out})
+    t += b->cap;
+  return t;
+}
+
+// Release every device buffer of an idle context (they grow again on use).
+void ctx_trim(sim_ctx* c) {
+  DeviceGuard g(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->groups, &c->stats_part, &c->layout,
+                    &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum,
+                    &c->group_off, &c->stage, &c->ctrl, &c->out})
+    release(*b);
+  if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
+  c->graph.exec = nullptr;
+  c->alloc_gen++;
+}
+
+}  // namespace sc
+
 extern "C" {
 
 int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg) {

@@ -124,3 +124,20 @@ def test_create_fails_cleanly_without_gpu():
     with pytest.raises(pkg.SimError) as ei:
         pkg.Context(0)
     assert ei.value.code == pkg.SIM_EDEVICE
+
+
+def test_server_create_fails_cleanly_without_gpu():
+    import paper_1905_01833_amd as pkg
+
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(pkg.SimError) as ei:
+        pkg.Server(0, slots=2)
+    assert ei.value.code == pkg.SIM_EDEVICE
+    with pytest.raises(pkg.SimError) as ei:
+        pkg.Server(0, slots=17)
+    assert ei.value.code == pkg.SIM_EINVAL
