@@ -260,6 +260,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain copy kernel of known size (256 MiB read, 256 MiB written; three launches) "
+                         "whose HBM counters scale the pipeline's")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this check runs on one GPU; --gpus {args.gpus} is not supported "
@@ -272,6 +275,14 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        a = torch.arange(1 << 26, dtype=torch.int32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     recs, offsets, tpb, desc = workload(args.workload)
     n = int(len(recs))

@@ -576,6 +576,12 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
 // Counts inside a tile fit 16 bits and pair sums 32 bits.
 
 constexpr uint32_t LDS_PAD(uint32_t j) { return j + (j >> 4); }
+#define META(i) ((mp[(i) / 6] >> (5 * ((i) % 6))) & 31u)
+// the same for a loop index that is not unrolled (no dynamic register indexing)
+__device__ __forceinline__ uint32_t meta_at(const uint32_t mp[3], uint32_t i) {
+  const uint32_t w = i < 6 ? mp[0] : (i < 12 ? mp[1] : mp[2]);
+  return (w >> (5 * (i % 6))) & 31u;
+}
 
 __device__ __forceinline__ uint32_t cnt16(uint64_t packed, uint32_t q) { return (uint32_t)(packed >> (16 * q)) & 0xFFFFu; }
 
@@ -697,8 +703,8 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
     if (tid == 0) s_taillast = trace_end ? 1u : (head_level(L, s_keys[LDS_PAD(n_in - 1)], s_next) == 0 ? 1u : 0u);
 
     // ---- element metadata: head level (3 bits) and class (2 bits)
-    uint64_t key[ITEMS];
-    uint32_t meta[ITEMS];
+    // head level (3 bits) and class (2 bits) of item i: bits 5 (i % 6) of mp[i / 6]
+    uint32_t mp[3] = {0u, 0u, 0u};
     uint32_t local_min = NO_HEAD;
     {
       uint64_t prev = tid > 0 ? s_keys[LDS_PAD(ITEMS * tid - 1)] : s_prev;
@@ -706,7 +712,6 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t j = ITEMS * tid + i;
         const uint64_t k = s_keys[LDS_PAD(j)];
-        key[i] = k;
         uint32_t lv, c;
         if (j < n_in) {
           lv = (j == 0 && tr.local == 0) ? 0u : head_level(L, prev, k);
@@ -716,10 +721,10 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
           lv = 4;
           c = CLS_NONE;
         }
-        meta[i] = lv | (c << 3);
+        mp[i / 6] |= (lv | (c << 3)) << (5 * (i % 6));
         prev = k;
       }
-      s_firstlv[tid] = (uint8_t)(meta[0] & 7u);
+      s_firstlv[tid] = (uint8_t)(mp[0] & 7u);
     }
     local_min = wave_min(local_min);
     if (lane == 0 && local_min < NO_HEAD) atomicMin(&s_min, local_min);
@@ -728,7 +733,7 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
     uint64_t aggA[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      const uint32_t lv = meta[i] & 7u, c = meta[i] >> 3;
+      const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
 #pragma unroll
       for (int l = 0; l < 4; l++)
         if (lv <= (uint32_t)l) aggA[l] = SEGF;
@@ -750,25 +755,14 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
     uint64_t pend0 = 0, pend1 = 0;
     {
       uint64_t run[4];
-      bool seen[4];
 #pragma unroll
-      for (int l = 0; l < 4; l++) {
-        run[l] = exA[l] & ~SEGF;
-        seen[l] = (exA[l] & SEGF) != 0;
-      }
-      // only threads before the tile's first location head hold lead elements
-      const bool lead_thread = !seen[0];
-      uint32_t leadc[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      uint32_t leads[5] = {0, 0, 0, 0, 0};
+      for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
-        const uint32_t lv = meta[i] & 7u, c = meta[i] >> 3;
+        const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
 #pragma unroll
         for (int l = 0; l < 4; l++)
-          if (lv <= (uint32_t)l) {
-            run[l] = 0;
-            seen[l] = true;
-          }
+          if (lv <= (uint32_t)l) run[l] = 0;
         if (c == CLS_NONE) continue;
         uint32_t v[5];
         tile_pairs(c, run, v);
@@ -778,19 +772,10 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
         aggB[2] += (uint64_t)v[K_XB];
 #pragma unroll
         for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
-        if (lead_thread) {
-#pragma unroll
-          for (int l = 0; l < 4; l++)
-            if (!seen[l]) leadc[l][c]++;
-          if (!seen[0]) {
-#pragma unroll
-            for (int k = 0; k < 5; k++) leads[k] += v[k];
-          }
-        }
         const uint32_t j = ITEMS * tid + i;
         bool last;
         if (j + 1 == n_in) last = s_taillast != 0;
-        else if (i + 1 < ITEMS) last = (meta[i + 1] & 7u) == 0;
+        else if (i + 1 < ITEMS) last = (META(i + 1) & 7u) == 0;
         else last = s_firstlv[tid + 1] == 0;
         if (!last) continue;
         if (aggB[0] & SEGF) {  // the location started in this thread
@@ -801,16 +786,51 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
           pend1 = aggB[1];
         }
       }
-      if (lead_thread) {
+    }
+    // ---- lead data: the class counts before the tile's first head at each
+    //      level, and the pairs of the elements before its first location
+    //      head.  Only threads before that head hold such elements; they
+    //      walk their items again (a separate loop keeps the registers of
+    //      the main pass low).
+    if ((exA[0] & SEGF) == 0) {
+      uint64_t run[4];
+      bool seen[4];
+#pragma unroll
+      for (int l = 0; l < 4; l++) {
+        run[l] = exA[l] & ~SEGF;
+        seen[l] = (exA[l] & SEGF) != 0;
+      }
+      uint32_t leadc[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      uint32_t leads[5] = {0, 0, 0, 0, 0};
+#pragma unroll 1
+      for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
+        const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
 #pragma unroll
         for (int l = 0; l < 4; l++)
+          if (lv <= (uint32_t)l) {
+            run[l] = 0;
+            seen[l] = true;
+          }
+        if (seen[0]) break;  // a location head: nothing after it is lead
+        if (c == CLS_NONE) continue;
+        uint32_t v[5];
+        tile_pairs(c, run, v);
 #pragma unroll
-          for (int q = 0; q < 3; q++)
-            if (leadc[l][q]) atomicAdd(&s_lead[l * 3 + q], leadc[l][q]);
+        for (int l = 0; l < 4; l++)
+          if (!seen[l]) leadc[l][c]++;
 #pragma unroll
-        for (int k = 0; k < 5; k++)
-          if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
+        for (int k = 0; k < 5; k++) leads[k] += v[k];
+#pragma unroll
+        for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
       }
+#pragma unroll
+      for (int l = 0; l < 4; l++)
+#pragma unroll
+        for (int q = 0; q < 3; q++)
+          if (leadc[l][q]) atomicAdd(&s_lead[l * 3 + q], leadc[l][q]);
+#pragma unroll
+      for (int k = 0; k < 5; k++)
+        if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
     }
     uint64_t exB[3], totB[3];
     block_seg_scan<3>(aggB, exB, totB, s_scanB);  // contains a barrier: s_lead and s_min are complete after it
@@ -859,9 +879,9 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
       for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
       uint64_t s0 = exB[0] & ~SEGF, s1 = exB[1] & ~SEGF, s2 = exB[2] & ~SEGF;
       bool seen0 = (exB[0] & SEGF) != 0;
-#pragma unroll
-      for (int i = 0; i < ITEMS; i++) {
-        const uint32_t lv = meta[i] & 7u, c = meta[i] >> 3;
+#pragma unroll 1
+      for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
+        const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
 #pragma unroll
         for (int l = 0; l < 4; l++)
           if (lv <= (uint32_t)l) run[l] = 0;
@@ -881,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
         const uint32_t j = ITEMS * tid + i;
         bool last;
         if (j + 1 == n_in) last = s_taillast != 0;
-        else if (i + 1 < ITEMS) last = (meta[i + 1] & 7u) == 0;
+        else if (i + 1 < (uint32_t)ITEMS) last = (meta_at(mp, i + 1) & 7u) == 0;
         else last = s_firstlv[tid + 1] == 0;
         if (!last) continue;
         uint64_t S[5];
@@ -889,7 +909,7 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
         S[K_AW] = (uint32_t)s1; S[K_AR] = (uint32_t)(s1 >> 32);
         S[K_XB] = (uint32_t)s2;
         if (S[K_WW] + S[K_RW] + S[K_AW] + S[K_AR] == 0) continue;
-        if (pos < cap) write_entry(dst + pos, tr.trace, L, key[i], S);
+        if (pos < cap) write_entry(dst + pos, tr.trace, L, s_keys[LDS_PAD(ITEMS * tid + i)], S);
         pos++;
       }
     };
