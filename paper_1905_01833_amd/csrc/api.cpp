@@ -235,12 +235,14 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   TraceDesc* hd = (TraceDesc*)c->h_meta;
   TileRef* ht = (TileRef*)(hd + n_traces);
   GroupRef* hg = (GroupRef*)(ht + n_tiles);
-  uint32_t t0 = 0, g0 = 0;
+  uint32_t t0 = 0, g0 = 0, max_group_tiles = 1, max_trace_groups = 1;
   for (uint32_t i = 0; i < n_traces; i++) {
     const uint64_t n = offsets[i + 1] - offsets[i];
     const uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
     const uint32_t gs = (uint32_t)group_shift(nt, tune.group_shift_bias);
     const uint32_t ng = (nt + (1u << gs) - 1) >> gs;
+    max_group_tiles = std::max(max_group_tiles, std::min(nt, 1u << gs));
+    max_trace_groups = std::max(max_trace_groups, ng);
     hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
     for (uint32_t k = 0; k < nt; k++) ht[t0 + k] = TileRef{i, k};
     for (uint32_t k = 0; k < ng; k++) hg[g0 + k] = GroupRef{i, 0};
@@ -313,6 +315,8 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.grid_stream = tile_grid(n_tiles, tune.stream_wgs_per_cu, c->n_cu);
   b.grid_sort = tile_grid(n_tiles, tune.sort_wgs_per_cu, c->n_cu);
   b.grid_scan = tile_grid(n_tiles, tune.scan_wgs_per_cu, c->n_cu);
+  b.max_group_tiles = max_group_tiles;
+  b.max_trace_groups = max_trace_groups;
 
   // ---- the pipeline.  Radix passes: the context remembers how many the
   // previous call needed and launches that many; the scan kernels do

@@ -286,16 +286,15 @@ __global__ __launch_bounds__(NT) void k_layout(const TraceDesc* __restrict__ des
 // waits on another.
 
 constexpr uint32_t CHUNK = 16;   // rows loaded ahead in the serial offset loops
-constexpr int OT = 1024;         // threads of the offset kernels: 4 row ranges per digit
-constexpr int OPARTS = OT / (int)RADIX;
+constexpr int MAX_PARTS = 4;     // offset kernels: up to 4 row ranges per digit (1024 threads)
 
 // Exclusive prefix over `n` rows (stride RADIX) of one digit column, split
-// over OPARTS row ranges handled by the threads d, d + 256, d + 512, d + 768.
-// Returns the column total; rows are rewritten with `base` + prefix.
-template <typename In, typename Out>
+// over PARTS row ranges handled by the threads d, d + 256, ... .  Returns
+// the column total; rows are rewritten with `base` + prefix.
+template <int PARTS, typename In, typename Out>
 __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t base, uint64_t (*s_part)[RADIX]) {
   const uint32_t d = threadIdx.x % RADIX, part = threadIdx.x / RADIX;
-  const uint32_t per = (n + OPARTS - 1) / OPARTS;
+  const uint32_t per = (n + PARTS - 1) / PARTS;
   const uint32_t r0 = min(n, part * per), r1 = min(n, r0 + per);
   uint64_t sum = 0;
   for (uint32_t k0 = r0; k0 < r1; k0 += CHUNK) {
@@ -307,7 +306,7 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   __syncthreads();
   uint64_t run = base, total = 0;
 #pragma unroll
-  for (int q = 0; q < OPARTS; q++) {
+  for (int q = 0; q < PARTS; q++) {
     const uint64_t x = s_part[q][d];
     if (q < (int)part) run += x;
     total += x;
@@ -327,8 +326,15 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   return total;
 }
 
-__global__ __launch_bounds__(OT) void k_group_offsets(Buffers b, uint32_t pass) {
-  __shared__ uint64_t s_part[OPARTS][RADIX];
+// Row ranges per digit for a column of n rows: one range per CHUNK rows, at
+// most MAX_PARTS (short columns need no more than one 256-thread workgroup).
+SC_HD uint32_t offset_parts(uint32_t max_rows) {
+  return max_rows <= CHUNK ? 1u : (max_rows <= 2 * CHUNK ? 2u : 4u);
+}
+
+template <int PARTS>
+__global__ __launch_bounds__(RADIX * PARTS) void k_group_offsets(Buffers b, uint32_t pass) {
+  __shared__ uint64_t s_part[PARTS][RADIX];
   const uint32_t g = blockIdx.x;
   const GroupRef gr = b.groups[g];
   const TraceDesc T = b.desc[gr.trace];
@@ -336,21 +342,22 @@ __global__ __launch_bounds__(OT) void k_group_offsets(Buffers b, uint32_t pass) 
   const uint32_t g_first = (g - T.group0) << T.gshift;
   const uint32_t g_n = min(1u << T.gshift, T.ntiles - g_first);
   uint32_t* rows = b.thist + (uint64_t)(T.tile0 + g_first) * RADIX;
-  const uint64_t total = column_prefix(rows, rows, g_n, 0, s_part);
+  const uint64_t total = column_prefix<PARTS>(rows, rows, g_n, 0, s_part);
   if (threadIdx.x < RADIX) b.gtot[(uint64_t)g * RADIX + threadIdx.x] = (uint32_t)total;
 }
 
-__global__ __launch_bounds__(OT) void k_trace_offsets(Buffers b, uint32_t pass) {
-  __shared__ uint64_t s_part[OPARTS][RADIX];
+template <int PARTS>
+__global__ __launch_bounds__(RADIX * PARTS) void k_trace_offsets(Buffers b, uint32_t pass) {
+  __shared__ uint64_t s_part[PARTS][RADIX];
   __shared__ uint64_t s_base[RADIX];
-  __shared__ uint32_t s_sc[OT / 64];
+  __shared__ uint32_t s_sc[PARTS * RADIX / 64];
   const uint32_t t = blockIdx.x;
   const TraceDesc T = b.desc[t];
   if (pass >= b.layout[t].npasses) return;  // uniform over the workgroup
   const uint32_t d = threadIdx.x % RADIX;
   const uint32_t* gt = b.gtot + (uint64_t)T.group0 * RADIX;
   // digit totals of the trace -> digit bases (first 256 threads)
-  const uint32_t part = threadIdx.x / RADIX, per = (T.ngroups + OPARTS - 1) / OPARTS;
+  const uint32_t part = threadIdx.x / RADIX, per = (T.ngroups + PARTS - 1) / PARTS;
   const uint32_t r0 = min(T.ngroups, part * per), r1 = min(T.ngroups, r0 + per);
   uint64_t sum = 0;
   for (uint32_t k = r0; k < r1; k++) sum += gt[(uint64_t)k * RADIX + d];
@@ -361,14 +368,14 @@ __global__ __launch_bounds__(OT) void k_trace_offsets(Buffers b, uint32_t pass) 
   uint64_t tot = 0;
   if (threadIdx.x < RADIX) {
 #pragma unroll
-    for (int q = 0; q < OPARTS; q++) tot += s_part[q][d];
+    for (int q = 0; q < PARTS; q++) tot += s_part[q][d];
   }
   uint32_t all;
-  const uint32_t ex = block_excl_sum_n<OT / 64>((uint32_t)tot, s_sc, &all);
+  const uint32_t ex = block_excl_sum_n<PARTS * RADIX / 64>((uint32_t)tot, s_sc, &all);
   if (threadIdx.x < RADIX) s_base[d] = T.off + ex;
   __syncthreads();
   // absolute base of every group: digit base + earlier groups
-  (void)column_prefix(gt, b.gbase + (uint64_t)T.group0 * RADIX, T.ngroups, s_base[d], s_part);
+  (void)column_prefix<PARTS>(gt, b.gbase + (uint64_t)T.group0 * RADIX, T.ngroups, s_base[d], s_part);
 }
 
 // Add one digit per lane of the wave to an LDS histogram.  Lanes holding the
@@ -1141,10 +1148,18 @@ hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_group_offsets, dim3(b.n_groups), dim3(OT), 0, s, b, pass);
+  switch (offset_parts(b.max_group_tiles)) {
+    case 1: hipLaunchKernelGGL(k_group_offsets<1>, dim3(b.n_groups), dim3(RADIX), 0, s, b, pass); break;
+    case 2: hipLaunchKernelGGL(k_group_offsets<2>, dim3(b.n_groups), dim3(2 * RADIX), 0, s, b, pass); break;
+    default: hipLaunchKernelGGL(k_group_offsets<4>, dim3(b.n_groups), dim3(4 * RADIX), 0, s, b, pass); break;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trace_offsets, dim3(b.n_traces), dim3(OT), 0, s, b, pass);
+  switch (offset_parts(b.max_trace_groups)) {
+    case 1: hipLaunchKernelGGL(k_trace_offsets<1>, dim3(b.n_traces), dim3(RADIX), 0, s, b, pass); break;
+    case 2: hipLaunchKernelGGL(k_trace_offsets<2>, dim3(b.n_traces), dim3(2 * RADIX), 0, s, b, pass); break;
+    default: hipLaunchKernelGGL(k_trace_offsets<4>, dim3(b.n_traces), dim3(4 * RADIX), 0, s, b, pass); break;
+  }
   return hipGetLastError();
 }
 hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s) {

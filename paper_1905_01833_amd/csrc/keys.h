@@ -108,17 +108,14 @@ SC_HD uint64_t make_key(const TraceLayout& L, uint64_t unit, uint32_t tid, uint3
 // key p of the same trace: 0 new location, 1 new block (global only),
 // 2 new epoch, 3 new thread, 4 same (location, block, epoch, thread).
 SC_HD uint32_t head_level(const TraceLayout& L, uint64_t p, uint64_t x) {
+  // written with selects only: it runs for every key of the tile scan
   const uint64_t d = (x ^ p) & ~3ull;
-  if (d == 0) return 4;
-  const uint32_t hb = 63u - (uint32_t)__builtin_clzll(d);  // highest differing bit
+  const uint32_t hb = d ? 63u - (uint32_t)__builtin_clzll(d) : 0u;  // highest differing bit
   const bool shared = ((x >> L.shift_space) & 1ull) != 0;
-  if (shared) {
-    if (hb >= L.shift_b) return 0;
-    return hb >= L.shift_e ? 2 : 3;
-  }
-  if (hb >= L.shift_ug) return 0;
-  if (hb >= L.shift_b) return 1;
-  return hb >= L.shift_e ? 2 : 3;
+  const uint32_t inner = hb >= L.shift_e ? 2u : 3u;          // epoch or thread
+  const uint32_t lv_s = hb >= L.shift_b ? 0u : inner;        // shared: block is part of the location
+  const uint32_t lv_g = hb >= L.shift_ug ? 0u : (hb >= L.shift_b ? 1u : inner);
+  return d == 0 ? 4u : (shared ? lv_s : lv_g);
 }
 
 // Location of a key: space, owning block (shared) or 0xFFFFFFFF, unit.
