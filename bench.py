@@ -260,6 +260,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shape (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain copy kernel of known size (256 MiB read, 256 MiB written; three launches) "
                          "whose HBM counters scale the pipeline's")
@@ -293,8 +294,11 @@ def main():
     # timed steps: the production configuration (autotuned launch shape,
     # launch sequence captured once and replayed as a HIP graph)
     ctx = pkg.Context(0, graphs=True)
-    log(f"{args.workload}: autotune")
-    tuning = ctx.autotune(dev, offsets, tpb, stream=stream, reps=3)
+    if args.no_autotune:
+        tuning = dict(ctx.tuning(pkg.sim_size_class(n))[1], size_class=pkg.sim_size_class(n))
+    else:
+        log(f"{args.workload}: autotune")
+        tuning = ctx.autotune(dev, offsets, tpb, stream=stream, reps=3)
     log(f"{args.workload}: warmup")
     for _ in range(args.warmup):
         ctx.check_traces_device(dev, offsets, tpb, stream=stream)
