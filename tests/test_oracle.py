@@ -355,3 +355,22 @@ def test_injected_locations_are_found_and_spot_checked():
             continue
         bf, _ = oracle.brute_force(sub, tpb=256)
         assert as_dict(bf).get(key) == got.get(key)
+
+
+def test_batch_injection_logs_stay_with_their_trace():
+    """rate * n = 28.5 and 2.5: the generator rounds half away from zero;
+    each trace's log holds exactly its own injections, and the oracle
+    reports every logged location in that trace."""
+    shapes = [(285000, 194, 6, 8434942963311516179), (25000, 3, 33, 77), (4096, 1, 16, 5)]
+    recs, off, tpb, inj = tracegen.batch(shapes, inject_rate=1e-4)
+    counts = [len(log) for _, log in inj]
+    assert counts == [29, 3, 0]
+    for i, log in inj:
+        lo, hi = int(off[i]), int(off[i + 1])
+        want, _ = oracle.closed_form(recs[lo:hi], tpb=256)
+        for e in log:
+            assert int(e["x_index"]) < hi - lo and int(e["y_index"]) < hi - lo
+            hit = (want["unit"] == e["unit"]) & (want["space"] == e["space"])
+            if int(e["space"]) == 1:
+                hit &= want["block"] == e["block"]
+            assert hit.any(), (i, e)

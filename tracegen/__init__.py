@@ -130,6 +130,12 @@ def _threads() -> int:
     return max(1, min(16, n))
 
 
+def _n_injections(rate: float, n: int) -> int:
+    """Injections the C generator makes for a trace of n records: rate * n
+    rounded half away from zero (llround), not Python's half-to-even."""
+    return int(math.floor(rate * n + 0.5)) if rate > 0 else 0
+
+
 def generate(
     n_blocks: int,
     tpb: int,
@@ -165,7 +171,7 @@ def generate(
     else:
         recs = out
         assert recs.dtype == RECORD_DTYPE and recs.shape == (n,) and recs.flags.c_contiguous
-    m = int(round(inject_rate * n))
+    m = _n_injections(inject_rate, n)
     log = np.zeros(max(m, 1), dtype=INJ_DTYPE)
     got = _load().tg_generate(
         ctypes.byref(p), recs.ctypes.data, log.ctypes.data, m, threads or _threads()
@@ -246,14 +252,15 @@ def batch(shapes, inject_rate: float = 1e-4, threads: int | None = None):
     for i, (n, nb, k, s) in enumerate(shapes):
         params[i] = _Params(nb, 256, k, 16, 0.75, 0.25, 0.5, 12288, 24, 16, 1.1, n, inject_rate,
                             int(s) & 0xFFFFFFFFFFFFFFFF, i)
-        caps[i + 1] = caps[i] + max(1, int(round(inject_rate * n)))
+        caps[i + 1] = caps[i] + max(1, _n_injections(inject_rate, n))
     logs = np.zeros(max(1, int(caps[-1])), dtype=INJ_DTYPE)
     counts = np.zeros(max(1, len(shapes)), dtype=np.int64)
     rc = _load().tg_generate_batch(params, len(shapes), recs.ctypes.data, offsets.ctypes.data, logs.ctypes.data,
                                    caps.ctypes.data, counts.ctypes.data, threads or _threads())
     if rc < 0:
         raise ValueError("tg_generate_batch rejected its parameters")
-    inj = [(i, logs[int(caps[i]) : int(caps[i]) + int(counts[i])]) for i in range(len(shapes))]
+    inj = [(i, logs[int(caps[i]) : int(caps[i]) + min(int(counts[i]), int(caps[i + 1] - caps[i]))])
+           for i in range(len(shapes))]
     return recs, offsets, tpb, inj
 
 
