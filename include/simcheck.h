@@ -216,7 +216,7 @@ int sim_get_tuning(const sim_ctx* ctx, uint32_t size_class, sim_tuning* t);
 /* Autotuner: time complete calls on the given input (arguments as for
  * sim_check_traces_device) under candidate shapes -- coordinate descent over
  * the workgroups per CU of the scatter (0, 1, 2, 4, 8), of the tile scan,
- * of the streaming kernels, then the histogram-group bias (-1, +1) -- each
+ * of the streaming kernels, then the histogram-group bias (-2 .. +2) -- each
  * candidate the median wall time of `reps` calls (0: 3).  The fastest shape
  * is stored for the input's size class and written to *best.  Results of
  * the trial calls are discarded; on error the class keeps its old shape.  */

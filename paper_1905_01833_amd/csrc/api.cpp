@@ -689,9 +689,9 @@ int sim_autotune(sim_ctx* c, const sim_record* d_records, const uint64_t* offset
   if (!rc) rc = measure(cur, &cur_ms);
   // coordinate descent over the four knobs, one at a time
   static const uint32_t kWgs[] = {0, 1, 2, 4, 8};
-  static const int32_t kBias[] = {-1, 1};
+  static const int32_t kBias[] = {-2, -1, 1, 2};
   for (int knob = 0; knob < 4 && !rc; knob++) {
-    const int nval = knob == 3 ? 2 : 5;
+    const int nval = knob == 3 ? 4 : 5;
     const int32_t bias0 = cur.group_shift_bias;
     for (int q = 0; q < nval && !rc; q++) {
       sim_tuning t = cur;
