@@ -317,6 +317,13 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.grid_scan = tile_grid(n_tiles, tune.scan_wgs_per_cu, c->n_cu);
   b.max_group_tiles = max_group_tiles;
   b.max_trace_groups = max_trace_groups;
+  // radix digit 0 is tid mod 256 when threads per block is a power of two
+  // >= 256 (the local-tid field then fills key bits [2, 10)): stats build
+  // its histograms and key generation does pass 0
+  b.fuse0 = 1;
+  for (uint32_t i = 0; i < n_traces; i++)
+    if (tpb[i] < 256 || (tpb[i] & (tpb[i] - 1)) != 0) b.fuse0 = 0;
+  const uint32_t first_pass = b.fuse0 ? 1u : 0u;
 
   // ---- the pipeline.  Radix passes: the context remembers how many the
   // previous call needed and launches that many; the scan kernels do
@@ -365,17 +372,21 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   };
 
   const uint32_t guess = c->pass_guess < MAX_PASSES ? c->pass_guess : MAX_PASSES;
+  int first_scan_ev = 0;  // events of the first round before its scan
   auto first_round = [&]() -> hipError_t {
     hipError_t e1;
     if ((e1 = timed(ST_INIT, true, [&] { return launch_init(b, s); })) ||
         (e1 = timed(ST_STATS, true, [&] { return launch_stats(b, s); })) ||
-        (e1 = timed(ST_LAYOUT, true, [&] { return launch_layout(b, s); })) ||
-        (e1 = timed(ST_KEYGEN, true, [&] { return launch_keygen(b, s); })) || (e1 = sort_passes(0, guess)))
+        (e1 = timed(ST_LAYOUT, true, [&] { return launch_layout(b, s); })))
       return e1;
+    if (b.fuse0 && (e1 = timed(ST_UPSWEEP, true, [&] { return launch_upsweep(b, 0, s); }))) return e1;
+    if ((e1 = timed(ST_KEYGEN, true, [&] { return launch_keygen(b, s); })) ||
+        (e1 = sort_passes(first_pass, guess)))
+      return e1;
+    first_scan_ev = nev / 2;
     if (guess && (e1 = scan(guess, true))) return e1;
     return hipMemcpyAsync(c->h_ctrl, c->ctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
   };
-  const int first_scan_ev = 5 + 2 * (int)guess - 1;  // events of the first round before its scan
   // Graph mode: the first round (every launch up to the control download)
   // is captured once per call shape and replayed while the shape, the
   // buffers and the pass count stay the same.
@@ -436,7 +447,8 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   if (needed > guess) {
     // too few passes ran: the scan kernels above returned at once
     for (int k = first_scan_ev; k < nev / 2; k++) ev_counts[k] = false;
-    if ((e = sort_passes(guess, needed)) || (e = scan(needed, true)) || (e = sync_ctrl()))
+    if ((e = sort_passes(guess > first_pass ? guess : first_pass, needed)) || (e = scan(needed, true)) ||
+        (e = sync_ctrl()))
       return hip_fail(c, e, "pipeline");
     ctl = *c->h_ctrl;
   }

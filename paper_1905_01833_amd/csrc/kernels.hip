@@ -158,15 +158,35 @@ __global__ void k_init(Ctrl* ctrl) {
   }
 }
 
+// Add one digit per lane of the wave to an LDS histogram.  Lanes holding the
+// same digit are matched with eight ballots and only the lowest of them adds
+// the group's size, so a skewed digit (the top key bits often take a handful
+// of values) costs one LDS atomic instead of 64 conflicting ones.
+__device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool valid) {
+  const uint64_t live = __ballot(valid);
+  if (!live) return;
+  uint64_t m = live;
+#pragma unroll
+  for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
+    const uint64_t bal = __ballot((dg >> bt) & 1u);
+    m &= ((dg >> bt) & 1u) ? bal : ~bal;
+  }
+  const uint64_t lt = (1ull << __lane_id()) - 1ull;
+  if (valid && (m & lt) == 0) atomicAdd(&h[dg], (uint32_t)__popcll(m));
+}
+
 // -------------------------------------------------------------- k_stats
 // Per-tile partial statistics; k_layout reduces them per trace.
 
-template <bool LOOP>
+// HIST: also the tile histogram of radix digit 0 for calls whose digit 0 is
+// tid mod 256 (see k_keygen_scatter).
+template <bool LOOP, bool HIST>
 __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ recs, const TraceDesc* __restrict__ desc,
                                               const TileRef* __restrict__ tiles, uint32_t n_tiles,
-                                              TraceStats* __restrict__ part) {
+                                              TraceStats* __restrict__ part, uint32_t* __restrict__ thist) {
   __shared__ uint64_t s64[5][NWAVE];
   __shared__ uint32_t s32[2][NWAVE];
+  __shared__ uint32_t h[RADIX];
   const TileWalk tw = tile_walk(n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -179,11 +199,18 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
     const ulonglong2* p = recs + T.off + start;
     uint64_t gmin = ~0ull, gmax = 0, smin = ~0ull, smax = 0, bad = ~0ull;
     uint32_t mt = 0, me = 0;
+    if (HIST) {
+      h[tx] = 0;
+      __syncthreads();
+    }
 #pragma unroll 4
     for (int r = 0; r < ITEMS; r++) {
       const uint32_t j = tx + r * NT;
-      if (j < n_in) {
-        const Rec x = unpack_rec(p[j]);
+      const bool valid = j < n_in;
+      const ulonglong2 v = valid ? p[j] : ulonglong2{0ull, 0ull};
+      if (HIST) wave_hist_add(h, (uint32_t)v.y & (RADIX - 1), valid);  // tid mod 256
+      if (valid) {
+        const Rec x = unpack_rec(v);
         if (x.action > 2 || x.space > 1) {
           bad = min<uint64_t>(bad, start + j);
         } else {
@@ -220,6 +247,7 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
       S.max_tid = mt; S.max_epoch = me;
       part[tile] = S;
     }
+    if (HIST) thist[(uint64_t)tile * RADIX + tx] = h[tx];
   }
 }
 
@@ -378,22 +406,6 @@ __global__ __launch_bounds__(RADIX * PARTS) void k_trace_offsets(Buffers b, uint
   (void)column_prefix<PARTS>(gt, b.gbase + (uint64_t)T.group0 * RADIX, T.ngroups, s_base[d], s_part);
 }
 
-// Add one digit per lane of the wave to an LDS histogram.  Lanes holding the
-// same digit are matched with eight ballots and only the lowest of them adds
-// the group's size, so a skewed digit (the top key bits often take a handful
-// of values) costs one LDS atomic instead of 64 conflicting ones.
-__device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool valid) {
-  const uint64_t live = __ballot(valid);
-  if (!live) return;
-  uint64_t m = live;
-#pragma unroll
-  for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
-    const uint64_t bal = __ballot((dg >> bt) & 1u);
-    m &= ((dg >> bt) & 1u) ? bal : ~bal;
-  }
-  const uint64_t lt = (1ull << __lane_id()) - 1ull;
-  if (valid && (m & lt) == 0) atomicAdd(&h[dg], (uint32_t)__popcll(m));
-}
 
 // ------------------------------------------------------------- k_keygen
 // Records -> keys, and the tile histogram of radix digit 0.
@@ -479,14 +491,81 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
 // the offsets left by the upsweep give each key its destination; keys are
 // staged in LDS in destination order and written out in runs per digit.
 
+// LDS of one scatter tile.
+struct ScatterLds {
+  uint64_t keys[TILE];
+  uint32_t wh[NWAVE][RADIX];
+  uint32_t dstart[RADIX];
+  uint64_t gbase[RADIX];
+  uint32_t scan[NWAVE];
+};
+
+// One stable pass over one tile: key[] holds the tile's keys wave-striped
+// (key index = wave * 1024 + item * 64 + lane; ~0 past the end, which sorts
+// last); they go to their places in `kout`.
+__device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, uint32_t tile, uint32_t tx,
+                                             const TileRef& tr, const TraceDesc& T, uint32_t n_in,
+                                             uint64_t (&key)[ITEMS], uint64_t* kout, ScatterLds& S) {
+  const uint32_t lane = tx & 63u, wave = tx >> 6;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  const uint32_t d = tx;
+  const uint32_t shift = 2 + RADIX_BITS * pass;
+  uint32_t rank[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+    uint64_t m = ~0ull;
+#pragma unroll
+    for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
+      const uint64_t bal = __ballot((dg >> bt) & 1u);
+      m &= ((dg >> bt) & 1u) ? bal : ~bal;
+    }
+    const uint32_t before = (uint32_t)__popcll(m & lt_mask);
+    const uint32_t old = S.wh[wave][dg];
+    if (before == 0) S.wh[wave][dg] = old + (uint32_t)__popcll(m);
+    rank[i] = old + before;
+  }
+  // destination base of each digit: group base + offset within the group
+  const uint64_t gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] +
+                      b.thist[(uint64_t)tile * RADIX + d];
+  __syncthreads();
+
+  // per digit: offsets of the waves, tile count, tile-local start
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; w++) {
+    const uint32_t c = S.wh[w][d];
+    S.wh[w][d] = cnt;
+    cnt += c;
+  }
+  uint32_t tot;
+  const uint32_t dstart = block_excl_sum(cnt, S.scan, &tot);
+  S.dstart[d] = dstart;
+  S.gbase[d] = gb - dstart;
+  __syncthreads();
+
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+    S.keys[S.dstart[dd] + S.wh[wave][dd] + rank[i]] = key[i];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int r = 0; r < ITEMS; r++) {
+    const uint32_t j = tx + r * NT;
+    if (j < n_in) {
+      const uint64_t k = S.keys[j];
+      const uint32_t dd = (uint32_t)(k >> shift) & (RADIX - 1);
+      const uint64_t dst = S.gbase[dd] + j;
+      if (dst - T.off < T.n) kout[dst] = k;
+      else atomicOr(&b.ctrl->error_flags, ERR_INTERNAL_BOUNDS);
+    }
+  }
+}
+
 template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
-  __shared__ uint64_t s_keys[TILE];
-  __shared__ uint32_t s_wh[NWAVE][RADIX];
-  __shared__ uint32_t s_dstart[RADIX];
-  __shared__ uint64_t s_gbase[RADIX];
-  __shared__ uint32_t s_scan[NWAVE];
-
+  __shared__ ScatterLds S;
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -497,75 +576,62 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
     const TraceLayout L = b.layout[tr.trace];
     if (pass >= L.npasses) continue;  // uniform over the workgroup
     const uint32_t lane = tx & 63u, wave = tx >> 6;
-    const uint64_t lt_mask = (1ull << lane) - 1ull;
-    const uint32_t d = tx;
-    const uint32_t shift = 2 + RADIX_BITS * pass;
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
     const uint64_t* src = b.keys[pass & 1] + T.off + start;
-    uint64_t* kout = b.keys[(pass + 1) & 1];
-
 #pragma unroll
-    for (int w = 0; w < NWAVE; w++) s_wh[w][d] = 0;
-    // destination base of each digit: group base + offset within the group
-    const uint64_t gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] +
-                        b.thist[(uint64_t)tile * RADIX + d];  // offset within the group
-    __syncthreads();
-
+    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
     uint64_t key[ITEMS];
-    uint32_t rank[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
       key[i] = (j < n_in) ? src[j] : ~0ull;  // padding sorts last (digit 255, after every real key)
     }
+    __syncthreads();
+    scatter_tile(b, pass, tile, tx, tr, T, n_in, key, b.keys[(pass + 1) & 1], S);
+  }
+}
+
+// ------------------------------------------------- k_keygen_scatter
+// Key generation fused with radix pass 0, for calls whose digit 0 is the
+// low byte of the thread id (threads per block a power of two >= 256, so
+// bits [2, 10) of the key are tid mod 256): k_stats has built the tile
+// histograms of that digit and the offset kernels have turned them into
+// scatter offsets, so keys go straight from the records to their places
+// after pass 0, in the buffer pass 1 reads.  The ranking is over records in
+// the same wave-striped order as k_scatter's, so the result is identical
+// to k_keygen followed by k_scatter(pass 0).
+
+template <bool LOOP>
+__global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
+  __shared__ ScatterLds S;
+  const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    __syncthreads();  // LDS of the previous tile is free
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    const TileRef tr = b.tiles[tile];
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    if (L.npasses == 0) continue;  // uniform over the workgroup
+    const uint32_t lane = tx & 63u, wave = tx >> 6;
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
+    const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
+    uint64_t key[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-      const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-      uint64_t m = ~0ull;
-#pragma unroll
-      for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
-        const uint64_t bal = __ballot((dg >> bt) & 1u);
-        m &= ((dg >> bt) & 1u) ? bal : ~bal;
-      }
-      const uint32_t before = (uint32_t)__popcll(m & lt_mask);
-      const uint32_t old = s_wh[wave][dg];
-      if (before == 0) s_wh[wave][dg] = old + (uint32_t)__popcll(m);
-      rank[i] = old + before;
-    }
-    __syncthreads();
-
-    // per digit: offsets of the waves, tile count, tile-local start
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int w = 0; w < NWAVE; w++) {
-      const uint32_t c = s_wh[w][d];
-      s_wh[w][d] = cnt;
-      cnt += c;
-    }
-    uint32_t tot;
-    const uint32_t dstart = block_excl_sum(cnt, s_scan, &tot);
-    s_dstart[d] = dstart;
-    s_gbase[d] = gb - dstart;
-    __syncthreads();
-
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-      s_keys[s_dstart[dd] + s_wh[wave][dd] + rank[i]] = key[i];
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int r = 0; r < ITEMS; r++) {
-      const uint32_t j = tx + r * NT;
+      const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+      key[i] = ~0ull;
       if (j < n_in) {
-        const uint64_t k = s_keys[j];
-        const uint32_t dd = (uint32_t)(k >> shift) & (RADIX - 1);
-        const uint64_t dst = s_gbase[dd] + j;
-        if (dst - T.off < T.n) kout[dst] = k;
-        else atomicOr(&b.ctrl->error_flags, ERR_INTERNAL_BOUNDS);
+        const Rec x = unpack_rec(p[j]);
+        key[i] = make_key(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
       }
     }
+    __syncthreads();
+    scatter_tile(b, 0, tile, tx, tr, T, n_in, key, b.keys[1], S);
   }
 }
 
@@ -1125,8 +1191,11 @@ hipError_t launch_init(const Buffers& b, hipStream_t s) {
 hipError_t launch_stats(const Buffers& b, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(loops(b, b.grid_stream) ? k_stats<true> : k_stats<false>, dim3(b.grid_stream), dim3(NT), 0, s,
-                     (const ulonglong2*)b.records, b.desc, b.tiles, b.n_tiles, b.stats_part);
+  const bool lp = loops(b, b.grid_stream);
+  auto kern = b.fuse0 ? (lp ? k_stats<true, true> : k_stats<false, true>)
+                      : (lp ? k_stats<true, false> : k_stats<false, false>);
+  hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, (const ulonglong2*)b.records, b.desc, b.tiles,
+                     b.n_tiles, b.stats_part, b.thist);
   return hipGetLastError();
 }
 hipError_t launch_layout(const Buffers& b, hipStream_t s) {
@@ -1137,7 +1206,12 @@ hipError_t launch_layout(const Buffers& b, hipStream_t s) {
 hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(loops(b, b.grid_stream) ? k_keygen<true> : k_keygen<false>, dim3(b.grid_stream), dim3(NT), 0, s, b);
+  if (b.fuse0)  // pass 0's offsets come first (launch_upsweep(b, 0)); the keys go straight to pass 1's buffer
+    hipLaunchKernelGGL(loops(b, b.grid_sort) ? k_keygen_scatter<true> : k_keygen_scatter<false>, dim3(b.grid_sort),
+                       dim3(NT), 0, s, b);
+  else
+    hipLaunchKernelGGL(loops(b, b.grid_stream) ? k_keygen<true> : k_keygen<false>, dim3(b.grid_stream), dim3(NT), 0,
+                       s, b);
   return hipGetLastError();
 }
 hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s) {

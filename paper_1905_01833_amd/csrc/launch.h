@@ -90,6 +90,8 @@ struct Buffers {            // device pointers of one call
   uint32_t grid_scan;       // workgroups of k_scan_tiles
   uint32_t max_group_tiles; // most tiles in one histogram group of the call
   uint32_t max_trace_groups;// most histogram groups in one trace of the call
+  uint32_t fuse0;           // 1: digit 0 is tid mod 256 in every trace; k_stats builds its histograms
+                            // and k_keygen_scatter does radix pass 0 (see kernels.hip)
 };
 
 // Kernel stages, in launch order.
@@ -98,7 +100,7 @@ enum Stage { ST_INIT = 0, ST_STATS, ST_LAYOUT, ST_KEYGEN, ST_UPSWEEP, ST_SORT, S
 hipError_t launch_init(const Buffers& b, hipStream_t s);
 hipError_t launch_stats(const Buffers& b, hipStream_t s);
 hipError_t launch_layout(const Buffers& b, hipStream_t s);
-hipError_t launch_keygen(const Buffers& b, hipStream_t s);
+hipError_t launch_keygen(const Buffers& b, hipStream_t s);  // with fuse0: keys + radix pass 0
 hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s);  // histograms and offsets
 hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s);
 hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t s);
