@@ -13,7 +13,7 @@
 //   k_scan_tiles  racing-pair counts of every location inside a tile, and
 //                 the tile's summary for locations that cross tiles
 //   k_scan_cross  pair counts of the locations that cross tiles
-//   k_group_* / k_scan_out  ordered output (two-level prefix over tiles)
+//   k_group_sums / k_scan_out  ordered output (two-level prefix over tiles)
 //
 // No kernel waits on another workgroup.  Radix offsets are computed
 // reduce-then-scan style: every tile stores its digit histogram, two small
@@ -208,7 +208,9 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
       const uint32_t j = tx + r * NT;
       const bool valid = j < n_in;
       const ulonglong2 v = valid ? p[j] : ulonglong2{0ull, 0ull};
-      if (HIST) wave_hist_add(h, (uint32_t)v.y & (RADIX - 1), valid);  // tid mod 256
+      // tid mod 256: neighbouring records mostly belong to different threads,
+      // so plain LDS atomics rarely conflict here
+      if (HIST && valid) atomicAdd(&h[(uint32_t)v.y & (RADIX - 1)], 1u);
       if (valid) {
         const Rec x = unpack_rec(v);
         if (x.action > 2 || x.space > 1) {
@@ -1123,26 +1125,17 @@ __global__ __launch_bounds__(NT) void k_group_sums(Buffers b, uint32_t passes_do
   if (threadIdx.x == 0) b.group_sum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(NT) void k_group_scan(Buffers b, uint32_t n_groups, uint32_t passes_done) {
-  __shared__ uint32_t sc[NWAVE];
-  if (b.ctrl->error_flags || b.ctrl->max_passes > passes_done) return;
-  const uint32_t per = (n_groups + NT - 1) / NT;
-  const uint32_t g0 = threadIdx.x * per;
-  uint64_t mine = 0;
-  for (uint32_t g = g0; g < min(n_groups, g0 + per); g++) mine += b.group_sum[g];
-  uint32_t tot;
-  const uint32_t ex = block_excl_sum((uint32_t)mine, sc, &tot);
-  uint64_t run = ex;
-  for (uint32_t g = g0; g < min(n_groups, g0 + per); g++) {
-    b.group_off[g] = run;
-    run += b.group_sum[g];
-  }
-  if (threadIdx.x == 0) b.ctrl->total_entries = tot;
-}
-
 __global__ __launch_bounds__(NT) void k_scan_out(Buffers b, uint32_t passes_done) {
   __shared__ uint32_t sc[NWAVE];
   if (b.ctrl->error_flags || b.ctrl->max_passes > passes_done) return;
+  // entries of the earlier groups (each workgroup sums the group totals
+  // before it; the last one also publishes the call's total)
+  uint64_t before = 0;
+  for (uint32_t g = threadIdx.x; g < blockIdx.x; g += NT) before += b.group_sum[g];
+  uint32_t all;
+  (void)block_excl_sum((uint32_t)before, sc, &all);
+  const uint64_t group_base = all;
+  if (blockIdx.x + 1 == gridDim.x && threadIdx.x == 0) b.ctrl->total_entries = group_base + b.group_sum[blockIdx.x];
   const uint32_t t = blockIdx.x * GROUP + threadIdx.x;
   const bool valid = t < b.n_tiles;
   const uint32_t inc = valid ? b.tout[t].in_count : 0u;
@@ -1150,7 +1143,7 @@ __global__ __launch_bounds__(NT) void k_scan_out(Buffers b, uint32_t passes_done
   uint32_t tot;
   const uint32_t ex = block_excl_sum(inc + cf, sc, &tot);
   if (!valid || inc + cf == 0) return;
-  uint64_t pos = b.group_off[blockIdx.x] + ex;
+  uint64_t pos = group_base + ex;
   if (inc) {
     const TileRef tr = b.tiles[t];
     const TraceDesc T = b.desc[tr.trace];
@@ -1258,9 +1251,6 @@ hipError_t launch_scan_out(const Buffers& b, uint32_t passes_done, hipStream_t s
   const uint32_t n_groups = cdiv(b.n_tiles, GROUP);
   hipLaunchKernelGGL(k_group_sums, dim3(n_groups), dim3(NT), 0, s, b, passes_done);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(NT), 0, s, b, n_groups, passes_done);
-  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_scan_out, dim3(n_groups), dim3(NT), 0, s, b, passes_done);
   return hipGetLastError();

@@ -77,7 +77,6 @@ struct Buffers {            // device pointers of one call
   RaceOut* cross;           // [tile]
   uint32_t* cross_flag;     // [tile]
   uint32_t* group_sum;      // [group]
-  uint64_t* group_off;      // [group]
   RaceOut* stage;           // dedicated staging ([tile][TILE/2 + 1]) or nullptr: the idle key buffer
   Ctrl* ctrl;
   RaceOut* out;
