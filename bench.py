@@ -38,7 +38,8 @@ METRIC = "access records checked/sec and achieved HBM GB/s (batched vs plain, bi
 #   scan   reads every 8-byte key once (tile scan; the crossing-location
 #          and output kernels touch per-tile data only)
 BYTES_PER_RECORD = {"stats": 16, "keygen": 24, "sort_pass": 16, "scan_tiles": 8}
-KERNEL_SYMBOL = {"stats": "k_stats", "keygen": "k_keygen", "sort_pass": "k_scatter", "scan_tiles": "k_scan_tiles"}
+KERNEL_SYMBOL = {"stats": "k_stats", "keygen": "k_keygen or k_keygen_scatter", "sort_pass": "k_scatter",
+                 "scan_tiles": "k_scan_tiles"}
 
 
 def workload(name):
