@@ -158,21 +158,20 @@ __global__ void k_init(Ctrl* ctrl) {
   }
 }
 
-// Add one digit per lane of the wave to an LDS histogram.  Lanes holding the
-// same digit are matched with eight ballots and only the lowest of them adds
-// the group's size, so a skewed digit (the top key bits often take a handful
-// of values) costs one LDS atomic instead of 64 conflicting ones.
+// Add one digit per lane of the wave to an LDS histogram.  When every live
+// lane holds the same digit (a skewed digit: the top key bits often take a
+// handful of values) the first live lane adds the count once; otherwise
+// each lane adds 1, which rarely conflicts for a spread digit.
 __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool valid) {
   const uint64_t live = __ballot(valid);
   if (!live) return;
-  uint64_t m = live;
-#pragma unroll
-  for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
-    const uint64_t bal = __ballot((dg >> bt) & 1u);
-    m &= ((dg >> bt) & 1u) ? bal : ~bal;
+  const uint32_t lead = (uint32_t)__ffsll((unsigned long long)live) - 1u;
+  const uint32_t d0 = __shfl(dg, (int)lead, 64);
+  if (__ballot(valid && dg == d0) == live) {
+    if (__lane_id() == lead) atomicAdd(&h[d0], (uint32_t)__popcll(live));
+  } else if (valid) {
+    atomicAdd(&h[dg], 1u);
   }
-  const uint64_t lt = (1ull << __lane_id()) - 1ull;
-  if (valid && (m & lt) == 0) atomicAdd(&h[dg], (uint32_t)__popcll(m));
 }
 
 // -------------------------------------------------------------- k_stats
