@@ -325,8 +325,15 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   const uint32_t d = threadIdx.x % RADIX, part = threadIdx.x / RADIX;
   const uint32_t per = (n + PARTS - 1) / PARTS;
   const uint32_t r0 = min(n, part * per), r1 = min(n, r0 + per);
+  // the first chunk stays in registers for the write loop (a range of at
+  // most CHUNK rows is read once)
+  uint64_t first[CHUNK];
+#pragma unroll
+  for (uint32_t k = 0; k < CHUNK; k++) first[k] = (r0 + k < r1) ? (uint64_t)in[(uint64_t)(r0 + k) * RADIX + d] : 0ull;
   uint64_t sum = 0;
-  for (uint32_t k0 = r0; k0 < r1; k0 += CHUNK) {
+#pragma unroll
+  for (uint32_t k = 0; k < CHUNK; k++) sum += first[k];
+  for (uint32_t k0 = r0 + CHUNK; k0 < r1; k0 += CHUNK) {
 #pragma unroll
     for (uint32_t k = 0; k < CHUNK; k++)
       if (k0 + k < r1) sum += in[(uint64_t)(k0 + k) * RADIX + d];
@@ -340,7 +347,13 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
     if (q < (int)part) run += x;
     total += x;
   }
-  for (uint32_t k0 = r0; k0 < r1; k0 += CHUNK) {
+#pragma unroll
+  for (uint32_t k = 0; k < CHUNK; k++)
+    if (r0 + k < r1) {
+      out[(uint64_t)(r0 + k) * RADIX + d] = (Out)run;
+      run += first[k];
+    }
+  for (uint32_t k0 = r0 + CHUNK; k0 < r1; k0 += CHUNK) {
     uint64_t c[CHUNK];
 #pragma unroll
     for (uint32_t k = 0; k < CHUNK; k++) c[k] = (k0 + k < r1) ? (uint64_t)in[(uint64_t)(k0 + k) * RADIX + d] : 0ull;
