@@ -320,8 +320,13 @@ constexpr int MAX_PARTS = 4;     // offset kernels: up to 4 row ranges per digit
 // Exclusive prefix over `n` rows (stride RADIX) of one digit column, split
 // over PARTS row ranges handled by the threads d, d + 256, ... .  Returns
 // the column total; rows are rewritten with `base` + prefix.
-template <int PARTS, typename In, typename Out>
-__device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t base, uint64_t (*s_part)[RADIX]) {
+// DIGIT_BASE: `base` is the trace's first record and every digit's column
+// starts at base + (totals of the smaller digits) -- the digit bases of a
+// radix pass -- computed here from the same reads.  s_sc holds one word per
+// wave of the workgroup and s_base one 64-bit word per digit.
+template <int PARTS, bool DIGIT_BASE, typename In, typename Out>
+__device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t base, uint64_t (*s_part)[RADIX],
+                                  uint32_t* s_sc = nullptr, uint64_t* s_base = nullptr) {
   const uint32_t d = threadIdx.x % RADIX, part = threadIdx.x / RADIX;
   const uint32_t per = (n + PARTS - 1) / PARTS;
   const uint32_t r0 = min(n, part * per), r1 = min(n, r0 + per);
@@ -340,13 +345,23 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   }
   s_part[part][d] = sum;
   __syncthreads();
-  uint64_t run = base, total = 0;
+  uint64_t total = 0, within = 0;
 #pragma unroll
   for (int q = 0; q < PARTS; q++) {
     const uint64_t x = s_part[q][d];
-    if (q < (int)part) run += x;
+    if (q < (int)part) within += x;
     total += x;
   }
+  if (DIGIT_BASE) {
+    // every thread takes part in the scan (it holds barriers); threads past
+    // the first 256 contribute 0 and come after them
+    uint32_t all;
+    const uint32_t ex = block_excl_sum_n<PARTS * RADIX / 64>(part == 0 ? (uint32_t)total : 0u, s_sc, &all);
+    if (part == 0) s_base[d] = base + ex;
+    __syncthreads();
+    base = s_base[d];
+  }
+  uint64_t run = base + within;
 #pragma unroll
   for (uint32_t k = 0; k < CHUNK; k++)
     if (r0 + k < r1) {
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(RADIX * PARTS) void k_group_offsets(Buffers b, uint
   const uint32_t g_first = (g - T.group0) << T.gshift;
   const uint32_t g_n = min(1u << T.gshift, T.ntiles - g_first);
   uint32_t* rows = b.thist + (uint64_t)(T.tile0 + g_first) * RADIX;
-  const uint64_t total = column_prefix<PARTS>(rows, rows, g_n, 0, s_part);
+  const uint64_t total = column_prefix<PARTS, false>(rows, rows, g_n, 0, s_part);
   if (threadIdx.x < RADIX) b.gtot[(uint64_t)g * RADIX + threadIdx.x] = (uint32_t)total;
 }
 
@@ -396,28 +411,10 @@ __global__ __launch_bounds__(RADIX * PARTS) void k_trace_offsets(Buffers b, uint
   const uint32_t t = blockIdx.x;
   const TraceDesc T = b.desc[t];
   if (pass >= b.layout[t].npasses) return;  // uniform over the workgroup
-  const uint32_t d = threadIdx.x % RADIX;
-  const uint32_t* gt = b.gtot + (uint64_t)T.group0 * RADIX;
-  // digit totals of the trace -> digit bases (first 256 threads)
-  const uint32_t part = threadIdx.x / RADIX, per = (T.ngroups + PARTS - 1) / PARTS;
-  const uint32_t r0 = min(T.ngroups, part * per), r1 = min(T.ngroups, r0 + per);
-  uint64_t sum = 0;
-  for (uint32_t k = r0; k < r1; k++) sum += gt[(uint64_t)k * RADIX + d];
-  s_part[part][d] = sum;
-  __syncthreads();
-  // every thread takes part in the scan (it holds barriers); threads past
-  // the first 256 contribute 0 and come after them
-  uint64_t tot = 0;
-  if (threadIdx.x < RADIX) {
-#pragma unroll
-    for (int q = 0; q < PARTS; q++) tot += s_part[q][d];
-  }
-  uint32_t all;
-  const uint32_t ex = block_excl_sum_n<PARTS * RADIX / 64>((uint32_t)tot, s_sc, &all);
-  if (threadIdx.x < RADIX) s_base[d] = T.off + ex;
-  __syncthreads();
-  // absolute base of every group: digit base + earlier groups
-  (void)column_prefix<PARTS>(gt, b.gbase + (uint64_t)T.group0 * RADIX, T.ngroups, s_base[d], s_part);
+  // group rows of the trace -> digit bases (from the column totals) and the
+  // absolute base of every group (digit base + earlier groups)
+  (void)column_prefix<PARTS, true>(b.gtot + (uint64_t)T.group0 * RADIX, b.gbase + (uint64_t)T.group0 * RADIX,
+                                    T.ngroups, T.off, s_part, s_sc, s_base);
 }
 
 
