@@ -207,7 +207,7 @@ def serving_leg(pkg, log, rate=2000.0, duration=3.0, pool_size=256, seed=0x5EED0
     alone = [ctx.check_traces(r, o, t) for r, o, t in pool]
     ctx.close()
 
-    srv = pkg.Server(0, hbm_budget_bytes=16 << 30, slots=4, max_batch_requests=256)
+    srv = pkg.Server(0, hbm_budget_bytes=16 << 30, slots=4, max_batch_requests=256, reserve_records=1 << 23)
     for r, o, t in pool[:16]:  # warm the workers' buffers
         srv.wait(srv.submit(r, o, t))
     srv.stats(reset=True)
@@ -239,7 +239,8 @@ def serving_leg(pkg, log, rate=2000.0, duration=3.0, pool_size=256, seed=0x5EED0
     srv.close()
     return {
         "workload": "c4: Poisson arrivals, 2000 requests/s, one trace per request, sizes lognormal (median 2^14, "
-                    "sigma 1.5, max 2^22 records), c1 distributions, 4 worker slots, 16 GiB HBM budget",
+                    "sigma 1.5, max 2^22 records), c1 distributions, 4 worker slots, 16 GiB HBM budget, buffers "
+                    "reserved for batches of 2^23 records",
         "requests": n_req, "offered_rate": rate, "achieved_rate": n_req / wall,
         "submit_lag_s": round(late, 4), "records": recs_done,
         "records_per_s": st["records_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],

@@ -98,9 +98,10 @@ typedef struct sim_result {
 } sim_result;
 
 typedef struct sim_config {
-  uint64_t reserve_records; /* pre-size device buffers for this many records (0: grow on demand) */
+  uint64_t reserve_records; /* allocate at creation every device buffer of a call of this many records
+                               (0: grow on demand); later calls up to that size allocate nothing */
   uint32_t flags;           /* SIM_CFG_* */
-  uint32_t reserved;
+  uint32_t reserve_traces;  /* ... in this many traces (0: 1) */
 } sim_config;
 
 enum {
@@ -258,6 +259,10 @@ typedef struct sim_server_config {
   uint32_t max_batch_requests; /* requests per batch at most (0: 1024) */
   uint32_t max_pending;        /* submitted requests not yet taken by a worker at most (0: 65536) */
   uint32_t reserved;
+  uint64_t reserve_records;    /* each worker allocates its device buffers (records included) for a batch of
+                                  this many records (in up to max_batch_requests traces) at creation, so
+                                  that batches up to that size allocate nothing (0: grow on demand).  Its
+                                  footprint must fit budget / slots (else SIM_EINVAL). */
 } sim_server_config;
 
 typedef struct sim_server_stats {

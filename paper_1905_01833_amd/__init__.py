@@ -61,7 +61,7 @@ class _Result(ctypes.Structure):
 
 
 class _Config(ctypes.Structure):
-    _fields_ = [("reserve_records", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+    _fields_ = [("reserve_records", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserve_traces", ctypes.c_uint32)]
 
 
 class _StageTime(ctypes.Structure):
@@ -92,6 +92,7 @@ class _ServerConfig(ctypes.Structure):
         ("max_batch_requests", ctypes.c_uint32),
         ("max_pending", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("reserve_records", ctypes.c_uint64),
     ]
 
 
@@ -166,11 +167,11 @@ def load() -> ctypes.CDLL:
 # ------------------------------------------------------------ C-named API
 
 def sim_create(hip_device: int = 0, profile: bool = False, reserve_records: int = 0,
-               graphs: bool = False) -> ctypes.c_void_p:
+               graphs: bool = False, reserve_traces: int = 0) -> ctypes.c_void_p:
     lib = load()
     ctx = ctypes.c_void_p()
     flags = (SIM_CFG_PROFILE if profile else 0) | (SIM_CFG_GRAPHS if graphs else 0)
-    cfg = _Config(reserve_records, flags, 0)
+    cfg = _Config(reserve_records, flags, reserve_traces)
     rc = lib.sim_create(ctypes.byref(ctx), hip_device, ctypes.byref(cfg))
     if rc != SIM_OK:
         raise SimError(rc, f"sim_create failed on device {hip_device} (needs a gfx950 GPU)")
@@ -292,8 +293,10 @@ def sim_autotune(ctx, d_records_ptr: int, n_records: int, offsets=None, threads_
 class Context:
     """One library context on one GPU."""
 
-    def __init__(self, device: int = 0, profile: bool = False, reserve_records: int = 0, graphs: bool = False):
-        self._ctx = sim_create(device, profile=profile, reserve_records=reserve_records, graphs=graphs)
+    def __init__(self, device: int = 0, profile: bool = False, reserve_records: int = 0, graphs: bool = False,
+                 reserve_traces: int = 0):
+        self._ctx = sim_create(device, profile=profile, reserve_records=reserve_records, graphs=graphs,
+                               reserve_traces=reserve_traces)
 
     def close(self):
         if self._ctx:
@@ -395,9 +398,10 @@ class Server:
     collected, as the C ABI requires."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, slots: int = 0, max_batch_records: int = 0,
-                 max_batch_requests: int = 0, max_pending: int = 0):
+                 max_batch_requests: int = 0, max_pending: int = 0, reserve_records: int = 0):
         lib = load()
-        cfg = _ServerConfig(hbm_budget_bytes, max_batch_records, slots, max_batch_requests, max_pending, 0)
+        cfg = _ServerConfig(hbm_budget_bytes, max_batch_records, slots, max_batch_requests, max_pending, 0,
+                            reserve_records)
         self._srv = ctypes.c_void_p()
         rc = lib.sim_server_create(ctypes.byref(self._srv), device, ctypes.byref(cfg))
         if rc != SIM_OK:

@@ -196,6 +196,40 @@ int group_shift(uint64_t n_tiles, int bias) {
   return gs < 0 ? 0 : (gs > (int)MAX_HGROUP_SHIFT ? (int)MAX_HGROUP_SHIFT : gs);
 }
 
+// Grow the device buffers of a call of `total` records in `n_traces`
+// traces, `n_tiles` tiles and `n_hgroups` histogram groups.
+hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups) {
+  const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
+  const uint64_t cap0 = total < 65536 ? total : 65536;
+  struct {
+    DevBuf* b;
+    size_t bytes;
+  } need[] = {
+      {&c->keys0, total * 8},
+      {&c->keys1, total * 8},
+      {&c->desc, (size_t)n_traces * sizeof(TraceDesc)},
+      {&c->tiles, (size_t)n_tiles * sizeof(TileRef)},
+      {&c->stats_part, (size_t)n_tiles * sizeof(TraceStats)},
+      {&c->layout, (size_t)n_traces * sizeof(TraceLayout)},
+      {&c->groups, (size_t)n_hgroups * sizeof(GroupRef)},
+      {&c->thist, (size_t)n_tiles * RADIX * 4},
+      {&c->gtot, (size_t)n_hgroups * RADIX * 4},
+      {&c->gbase, (size_t)n_hgroups * RADIX * 8},
+      {&c->agg, (size_t)n_tiles * SW * 4},
+      {&c->tout, (size_t)n_tiles * sizeof(TileOut)},
+      {&c->cross, (size_t)n_tiles * sizeof(RaceOut)},
+      {&c->cross_flag, (size_t)n_tiles * 4},
+      {&c->group_sum, (size_t)n_groups * 4},
+      {&c->ctrl, sizeof(Ctrl)},
+      {&c->out, (size_t)(c->out.cap ? c->out.cap : cap0 * sizeof(RaceOut))},
+  };
+  for (auto& nb : need) {
+    const hipError_t e = ensure(*nb.b, nb.bytes, false, &c->alloc_gen);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces, const uint32_t* tpb,
         hipStream_t s, sim_result** out) {
   uint64_t total = 0;
@@ -253,34 +287,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
 
   // ---- device buffers
-  const uint64_t cap0 = total < 65536 ? total : 65536;
-  struct {
-    DevBuf* b;
-    size_t bytes;
-    bool zero;
-  } need[] = {
-      {&c->keys0, total * 8, false},
-      {&c->keys1, total * 8, false},
-      {&c->desc, (size_t)n_traces * sizeof(TraceDesc), false},
-      {&c->tiles, (size_t)n_tiles * sizeof(TileRef), false},
-      {&c->stats_part, (size_t)n_tiles * sizeof(TraceStats), false},
-      {&c->layout, (size_t)n_traces * sizeof(TraceLayout), false},
-      {&c->groups, (size_t)n_hgroups * sizeof(GroupRef), false},
-      {&c->thist, (size_t)n_tiles * RADIX * 4, false},
-      {&c->gtot, (size_t)n_hgroups * RADIX * 4, false},
-      {&c->gbase, (size_t)n_hgroups * RADIX * 8, false},
-      {&c->agg, (size_t)n_tiles * SW * 4, false},
-      {&c->tout, (size_t)n_tiles * sizeof(TileOut), false},
-      {&c->cross, (size_t)n_tiles * sizeof(RaceOut), false},
-      {&c->cross_flag, (size_t)n_tiles * 4, false},
-      {&c->group_sum, (size_t)n_groups * 4, false},
-      {&c->ctrl, sizeof(Ctrl), false},
-      {&c->out, (size_t)(c->out.cap ? c->out.cap : cap0 * sizeof(RaceOut)), false},
-  };
-  for (auto& nb : need) {
-    e = ensure(*nb.b, nb.bytes, nb.zero, &c->alloc_gen);
-    if (e != hipSuccess) return hip_fail(c, e, "device allocation");
-  }
+  if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups)) != hipSuccess) return hip_fail(c, e, "device allocation");
   if ((e = hipMemcpyAsync(c->desc.p, hd, (size_t)n_traces * sizeof(TraceDesc), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(c->tiles.p, ht, (size_t)n_tiles * sizeof(TileRef), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(c->groups.p, hg, (size_t)n_hgroups * sizeof(GroupRef), hipMemcpyHostToDevice, s)))
@@ -560,9 +567,12 @@ int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg) {
       sim_destroy(c);
       return SIM_EDEVICE;
     }
-  if (cfg && cfg->reserve_records) {
+  if (cfg && cfg->reserve_records) {  // every buffer of a call this large, allocated now
     const uint64_t n_rec = cfg->reserve_records;
-    if (ensure(c->records, n_rec * 16) || ensure(c->keys0, n_rec * 8) || ensure(c->keys1, n_rec * 8)) {
+    const uint32_t n_tr = cfg->reserve_traces ? cfg->reserve_traces : 1;
+    const uint64_t tiles = (n_rec + TILE - 1) / TILE + n_tr;
+    if (n_rec >= (1ull << 32) || tiles >= (1ull << 32) || ensure(c->records, n_rec * 16) ||
+        size_buffers(c, n_rec, n_tr, (uint32_t)tiles, tiles) != hipSuccess) {
       sim_destroy(c);
       return SIM_ENOMEM;
     }

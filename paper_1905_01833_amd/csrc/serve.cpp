@@ -3,11 +3,12 @@
 // footprint, latency statistics (the sim_server_* / sim_submit / sim_poll /
 // sim_wait entry points of include/simcheck.h).
 //
-// Each worker owns a context (own stream, own grow-only device buffers) and
-// a pinned staging buffer.  A free worker takes pending requests in arrival
-// order while they fit its batch limits and the unused part of the budget,
-// copies their records into its staging buffer as one trace list, runs one
-// check over all of them, and splits the result by request.  Workers run
+// Each worker owns a context (grow-only device buffers), a stream and a
+// device buffer for records.  A free worker takes pending requests in
+// arrival order while they fit its batch limits and the unused part of the
+// budget, copies their records straight from the callers' memory into its
+// device buffer as one trace list, runs one check over all of them on its
+// stream, and splits the result by request.  Workers run
 // independently, so the batches of different workers overlap on the GPU
 // while new requests queue for the next free worker.
 #include <hip/hip_runtime.h>
@@ -87,11 +88,20 @@ struct Request {
 
 struct Worker {
   sim_ctx* ctx = nullptr;
-  void* pinned = nullptr;
-  size_t pinned_cap = 0;
-  size_t held = 0;  // device bytes of the context, updated under the server lock
+  hipStream_t stream = nullptr;
+  void* drec = nullptr;  // the batch's records, device memory
+  size_t drec_cap = 0;
+  size_t held = 0;  // device bytes of the worker, updated under the server lock
   std::thread th;
 };
+
+size_t worker_bytes(const Worker& w) { return ctx_device_bytes(w.ctx) + w.drec_cap; }
+
+void release_records(Worker& w) {
+  if (w.drec) (void)hipFree(w.drec);
+  w.drec = nullptr;
+  w.drec_cap = 0;
+}
 
 }  // namespace
 
@@ -128,24 +138,31 @@ void check_batch(sim_server* S, Worker& w, const std::vector<Request*>& batch) {
     nt += r->n_traces;
   }
   const size_t need = (size_t)(n ? n : 1) * sizeof(sim_record);
-  if (w.pinned_cap < need) {
-    if (w.pinned) (void)hipHostFree(w.pinned);
-    w.pinned = nullptr;
-    w.pinned_cap = 0;
-    if (hipHostMalloc(&w.pinned, need, hipHostMallocDefault) != hipSuccess) {
+  if (w.drec_cap < need) {
+    release_records(w);
+    if (hipMalloc(&w.drec, need) != hipSuccess) {
+      w.drec = nullptr;
       for (Request* r : batch) {
         r->rc = SIM_ENOMEM;
-        r->err = "pinned staging allocation failed";
+        r->err = "device allocation for the batch's records failed";
       }
       return;
     }
-    w.pinned_cap = need;
+    w.drec_cap = need;
   }
   std::vector<uint64_t> off(nt + 1, 0);
   std::vector<uint32_t> tpb(nt ? nt : 1, 1);
   uint64_t rb = 0, tb = 0;
   for (Request* r : batch) {
-    if (r->n) std::memcpy((sim_record*)w.pinned + rb, r->records, r->n * sizeof(sim_record));
+    if (r->n &&
+        hipMemcpyAsync((sim_record*)w.drec + rb, r->records, r->n * sizeof(sim_record), hipMemcpyHostToDevice,
+                       w.stream) != hipSuccess) {
+      for (Request* q : batch) {
+        q->rc = SIM_EDEVICE;
+        q->err = "record upload failed";
+      }
+      return;
+    }
     for (uint32_t i = 0; i < r->n_traces; i++) {
       off[tb + i + 1] = rb + r->offsets[i + 1];
       tpb[tb + i] = r->tpb[i];
@@ -154,7 +171,8 @@ void check_batch(sim_server* S, Worker& w, const std::vector<Request*>& batch) {
     tb += r->n_traces;
   }
   sim_result* res = nullptr;
-  const int rc = sim_check_traces(w.ctx, (const sim_record*)w.pinned, off.data(), (uint32_t)nt, tpb.data(), &res);
+  const int rc = sim_check_traces_device(w.ctx, (const sim_record*)w.drec, off.data(), (uint32_t)nt, tpb.data(),
+                                         w.stream, &res);
   if (rc != SIM_OK) {
     if (batch.size() == 1) {
       batch[0]->rc = rc;
@@ -238,8 +256,11 @@ void worker_loop(sim_server* S, Worker* w) {
     S->cv_work.notify_all();
     lk.unlock();
     // keep an idle worker's device buffers within its share of the budget
-    if (ctx_device_bytes(w->ctx) > share) ctx_trim(w->ctx);
-    const size_t held = ctx_device_bytes(w->ctx);
+    if (worker_bytes(*w) > share) {
+      ctx_trim(w->ctx);
+      release_records(*w);
+    }
+    const size_t held = worker_bytes(*w);
     lk.lock();
     w->held = held;
   }
@@ -275,13 +296,38 @@ int sim_server_create(sim_server** out, int hip_device, const sim_server_config*
     delete S;
     return fail(SIM_EINVAL, "at most 16 slots");
   }
+  const uint64_t rsv = S->cfg.reserve_records;
+  if (rsv) {
+    const uint64_t tiles = (rsv + TILE - 1) / TILE + S->cfg.max_batch_requests;
+    if (rsv >= (1ull << 32) ||
+        footprint(rsv, S->cfg.max_batch_requests, tiles) > S->cfg.hbm_budget_bytes / S->cfg.slots) {
+      delete S;
+      return fail(SIM_EINVAL, "reserve_records does not fit the budget share of a worker");
+    }
+  }
   S->workers.resize(S->cfg.slots);
   for (Worker& w : S->workers) {
-    const int rc = sim_create(&w.ctx, hip_device, nullptr);
+    const sim_config wc{rsv, 0u, S->cfg.max_batch_requests};
+    const int rc = sim_create(&w.ctx, hip_device, &wc);
     if (rc != SIM_OK) {
       sim_server_destroy(S);
-      return fail(rc, "sim_create failed (needs a gfx950 device)");
+      return fail(rc, "sim_create failed (needs a gfx950 device, or the reservation did not fit)");
     }
+    (void)hipSetDevice(hip_device);
+    if (hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) != hipSuccess) {
+      w.stream = nullptr;
+      sim_server_destroy(S);
+      return fail(SIM_EDEVICE, "stream creation failed");
+    }
+    if (rsv) {
+      if (hipMalloc(&w.drec, rsv * sizeof(sim_record)) != hipSuccess) {
+        w.drec = nullptr;
+        sim_server_destroy(S);
+        return fail(SIM_ENOMEM, "device allocation for records failed");
+      }
+      w.drec_cap = rsv * sizeof(sim_record);
+    }
+    w.held = worker_bytes(w);
   }
   for (Worker& w : S->workers) w.th = std::thread(worker_loop, S, &w);
   *out = S;
@@ -303,7 +349,9 @@ void sim_server_destroy(sim_server* S) {
   }
   for (Worker& w : S->workers) {
     sim_destroy(w.ctx);
-    if (w.pinned) (void)hipHostFree(w.pinned);
+    if (w.drec || w.stream) (void)hipSetDevice(S->device);
+    release_records(w);
+    if (w.stream) (void)hipStreamDestroy(w.stream);
   }
   delete S;
 }

@@ -140,3 +140,29 @@ def test_admission_and_tickets(pkg):
     for _ in range(20):
         srv.submit(recs, off, tpb)
     srv.close()
+
+
+def test_reserved_buffers(pkg):
+    """Workers allocate their buffers at creation when asked; a reservation
+    beyond a worker's budget share is refused."""
+    with pytest.raises(pkg.SimError) as ei:
+        pkg.Server(0, hbm_budget_bytes=64 << 20, slots=2, reserve_records=1 << 22)
+    assert ei.value.code == pkg.SIM_EINVAL
+    srv = pkg.Server(0, hbm_budget_bytes=1 << 30, slots=2, reserve_records=1 << 18)
+    try:
+        st = srv.stats()
+        assert st["device_bytes"] >= 2 * (1 << 18) * 32
+        recs, off, tpb = request_pool(1, seed=9, log2_max=17)[0]
+        want, wsum = oracle.closed_form(recs, off, tpb)
+        got = srv.wait(srv.submit(recs, off, tpb))
+        assert got[0].tobytes() == want.tobytes() and got[1].tobytes() == wsum.tobytes()
+        assert srv.stats()["device_bytes"] == st["device_bytes"]  # nothing grew
+    finally:
+        srv.close()
+    ctx = pkg.Context(0, reserve_records=1 << 18, reserve_traces=8)
+    try:
+        r = tracegen.c0()
+        want, _ = oracle.closed_form(r, tpb=256)
+        assert ctx.check_traces(r, None, 256)[0].tobytes() == want.tobytes()
+    finally:
+        ctx.close()
