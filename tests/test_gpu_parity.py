@@ -453,3 +453,35 @@ def test_c3_full_size_sampled(ctx):
         mine["trace"] = 0
         assert mine.tobytes() == want.tobytes(), i
         assert summ[i].tobytes() == wsum[0].tobytes(), i
+
+
+def test_widest_keys_and_mixed_pass_counts(ctx):
+    """A trace whose key takes all 64 bits (8 radix passes: unit range 2^33,
+    1024 blocks, 1024 epochs, 256 threads per block) batched with traces of
+    2-pass keys, on a fresh context (no remembered pass count) and again on
+    a warm one; also alone, where fewer passes were remembered."""
+    import paper_1905_01833_amd as pkg
+
+    rng = np.random.default_rng(64)
+    n = 60000
+    w = np.zeros(n, dtype=RECORD_DTYPE)
+    w["unit"] = rng.integers(0, 1 << 33, n, dtype=np.uint64)
+    w["unit"][: n // 2] = rng.integers(0, 64, n // 2)  # collisions in the low units
+    w["unit"][n - 1] = (1 << 33) - 1  # the full unit range: 33 bits
+    w["tid"] = rng.integers(0, 1024 * 256, n)
+    w["tid"][:8] = [0, 1024 * 256 - 1, 5, 6, 7, 8, 9, 10]
+    w["epoch"] = rng.integers(0, 1024, n)
+    w["epoch"][0] = 1023
+    w["action"] = rng.integers(0, 3, n)
+    w["space"] = 0
+    small = tracegen.random_small(rng, 3000, units=6, blocks=2, tpb=4, epochs=2)
+    recs, off = batch_of([small, w, small[:100]])
+    tpb = [4, 256, 4]
+    fresh = pkg.Context(0)
+    try:
+        assert_parity(fresh, recs, off, tpb, name="64-bit keys batched, fresh context")
+        assert_parity(fresh, recs, off, tpb, name="64-bit keys batched, warm context")
+        assert_parity(fresh, small, None, 4, name="2-pass trace after 8")
+        assert_parity(fresh, w, None, 256, name="64-bit keys alone after 2")
+    finally:
+        fresh.close()
