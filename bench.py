@@ -88,6 +88,19 @@ def cpu_baseline(recs, offsets, tpb, budget_records):
     return races, summ, n, k, dt
 
 
+KERNEL_SOURCES = ["kernels.hip", "launch.h", "keys.h", "segstate.h", "tilewalk.h"]
+
+
+def kernel_source_hash():
+    """SHA-256 over the device code's sources (the kernels and the headers
+    they include), in a fixed order."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1905_01833_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def pmc_traffic(stage, n_records):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
@@ -96,8 +109,7 @@ def pmc_traffic(stage, n_records):
         return None
     with open(path) as f:
         d = json.load(f)
-    src = open(os.path.join(ROOT, "paper_1905_01833_amd", "csrc", "kernels.hip"), "rb").read()
-    if d.get("kernels_sha256") != hashlib.sha256(src).hexdigest() or d.get("records") != n_records:
+    if d.get("kernels_sha256") != kernel_source_hash() or d.get("records") != n_records:
         return None
     return d.get("bytes_per_launch")
 

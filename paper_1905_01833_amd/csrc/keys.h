@@ -97,7 +97,8 @@ SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
 // Key of one record (fields must be valid and within the trace's ranges).
 SC_HD uint64_t make_key(const TraceLayout& L, uint64_t unit, uint32_t tid, uint32_t epoch, uint32_t action,
                         uint32_t space, uint32_t tpb) {
-  const uint32_t blk = tid / tpb;
+  // a power-of-two block size (tb = log2 tpb) divides by a shift
+  const uint32_t blk = (tpb & (tpb - 1)) == 0 ? tid >> L.tb : tid / tpb;
   const uint32_t loc = tid - blk * tpb;
   const uint64_t low = ((uint64_t)epoch << L.shift_e) | ((uint64_t)loc << 2) | (uint64_t)(action & 3u);
   if (space == 0) return ((unit - L.gmin) << L.shift_ug) | ((uint64_t)blk << L.shift_b) | low;
