@@ -1090,7 +1090,8 @@ __global__ __launch_bounds__(NT) void k_scan_cross(Buffers b, uint32_t passes_do
   // location runs to the end of the trace)
   const uint32_t end = to_end ? last + 1 : k;
   State S = identity();
-  for (uint32_t c0 = j; c0 < end; c0 += 64) {
+  if (end == j + 1) S = load_state(b.agg + (uint64_t)j * SW);  // the common span: no tree needed
+  else for (uint32_t c0 = j; c0 < end; c0 += 64) {
     const uint32_t c = c0 + lane;
     State s = c < end ? load_state(b.agg + (uint64_t)c * SW) : identity();
 #pragma unroll
