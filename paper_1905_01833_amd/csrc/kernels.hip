@@ -5,11 +5,16 @@
 // traces):
 //   k_init        reset per-call state
 //   k_stats       per-tile unit ranges, largest tid and epoch, record checks
+//                 (and the digit-0 histograms when digit 0 is tid mod 256)
 //   k_layout      per-trace reduction of the tile statistics, key layout
-//   k_keygen      records -> 64-bit keys, tile histograms of radix digit 0
+//   k_keygen      records -> 64-bit keys, tile histograms of radix digit 0;
+//                 or k_keygen_scatter: records -> keys in their places after
+//                 radix pass 0 (when k_stats built the digit-0 histograms)
 //   k_upsweep     tile histograms of radix digit p (p >= 1)
 //   k_group_offsets / k_trace_offsets  histograms -> scatter offsets
 //   k_scatter     one stable LSD radix pass, 8-bit digits (x passes)
+// Every tile kernel walks the call's (trace, tile) queue (tilewalk.h), one
+// tile per workgroup or several per workgroup of a persistent grid.
 //   k_scan_tiles  racing-pair counts of every location inside a tile, and
 //                 the tile's summary for locations that cross tiles
 //   k_scan_cross  pair counts of the locations that cross tiles
