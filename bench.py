@@ -197,12 +197,13 @@ def batched_leg(pkg, torch, steps, log):
     }, (recs, offsets, tpb, races, summ)
 
 
-def serving_leg(pkg, log, rate=2000.0, duration=3.0, pool_size=256, seed=0x5EED0004):
+def serving_leg(pkg, log, loads=((2000.0, 3.0),), pool_size=256, seed=0x5EED0004):
     """Serving workload: Poisson arrivals at `rate` requests/s for `duration`
-    seconds, each request one trace with a lognormal size (median 2^14
-    records, sigma 1.5, at most 2^22), c1 distributions, 256 threads per
-    block; requests cycle through a pool of pre-generated traces.  Every
-    result is compared with the same request checked alone."""
+    seconds (one run per (rate, duration) in `loads`), each request one
+    trace with a lognormal size (median 2^14 records, sigma 1.5, at most
+    2^22), c1 distributions, 256 threads per block; requests cycle through
+    a pool of pre-generated traces.  Every result is compared with the same
+    request checked alone."""
     import tracegen
 
     rng = np.random.default_rng(seed)
@@ -222,44 +223,47 @@ def serving_leg(pkg, log, rate=2000.0, duration=3.0, pool_size=256, seed=0x5EED0
     srv = pkg.Server(0, hbm_budget_bytes=16 << 30, slots=4, max_batch_requests=256, reserve_records=1 << 23)
     for r, o, t in pool[:16]:  # warm the workers' buffers
         srv.wait(srv.submit(r, o, t))
-    srv.stats(reset=True)
-    n_req = int(rate * duration)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
-    which = rng.integers(0, pool_size, n_req)
-    log(f"serving: {n_req} requests over {duration:.1f} s")
-    tickets = []
-    t0 = time.perf_counter()
-    for k in range(n_req):
-        while True:
-            ahead = arrivals[k] - (time.perf_counter() - t0)
-            if ahead <= 0:
-                break
-            if ahead > 2e-4:
-                time.sleep(ahead - 1e-4)
-        r, o, t = pool[which[k]]
-        tickets.append(srv.submit(r, o, t))
-    late = (time.perf_counter() - t0) - arrivals[-1]
-    same = True
-    recs_done = 0
-    for k, tk in enumerate(tickets):
-        got = srv.wait(tk)
-        a = alone[which[k]]
-        same = same and got[0].tobytes() == a[0].tobytes() and got[1].tobytes() == a[1].tobytes()
-        recs_done += len(pool[which[k]][0])
-    wall = time.perf_counter() - t0
-    st = srv.stats()
+    out = []
+    for rate, duration in loads:
+        srv.stats(reset=True)
+        n_req = int(rate * duration)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        which = rng.integers(0, pool_size, n_req)
+        log(f"serving: {n_req} requests over {duration:.1f} s")
+        tickets = []
+        t0 = time.perf_counter()
+        for k in range(n_req):
+            while True:
+                ahead = arrivals[k] - (time.perf_counter() - t0)
+                if ahead <= 0:
+                    break
+                if ahead > 2e-4:
+                    time.sleep(ahead - 1e-4)
+            r, o, t = pool[which[k]]
+            tickets.append(srv.submit(r, o, t))
+        late = (time.perf_counter() - t0) - arrivals[-1]
+        same = True
+        recs_done = 0
+        for k, tk in enumerate(tickets):
+            got = srv.wait(tk)
+            a = alone[which[k]]
+            same = same and got[0].tobytes() == a[0].tobytes() and got[1].tobytes() == a[1].tobytes()
+            recs_done += len(pool[which[k]][0])
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        out.append({
+            "workload": f"c4: Poisson arrivals, {rate:.0f} requests/s, one trace per request, sizes lognormal (median "
+                        "2^14, sigma 1.5, max 2^22 records), c1 distributions, 4 worker slots, 16 GiB HBM budget, "
+                        "buffers reserved for batches of 2^23 records",
+            "requests": n_req, "offered_rate": rate, "achieved_rate": n_req / wall,
+            "submit_lag_s": round(late, 4), "records": recs_done,
+            "records_per_s": st["records_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "max_ms": st["max_ms"], "mean_ms": st["mean_ms"], "batches": st["batches"],
+            "mean_batch_requests": st["mean_batch_requests"], "peak_inflight_bytes": st["peak_inflight_bytes"],
+            "alone_equals_mix": bool(same),
+        })
     srv.close()
-    return {
-        "workload": "c4: Poisson arrivals, 2000 requests/s, one trace per request, sizes lognormal (median 2^14, "
-                    "sigma 1.5, max 2^22 records), c1 distributions, 4 worker slots, 16 GiB HBM budget, buffers "
-                    "reserved for batches of 2^23 records",
-        "requests": n_req, "offered_rate": rate, "achieved_rate": n_req / wall,
-        "submit_lag_s": round(late, 4), "records": recs_done,
-        "records_per_s": st["records_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-        "max_ms": st["max_ms"], "mean_ms": st["mean_ms"], "batches": st["batches"],
-        "mean_batch_requests": st["mean_batch_requests"], "peak_inflight_bytes": st["peak_inflight_bytes"],
-        "alone_equals_mix": bool(same),
-    }
+    return out
 
 
 def main():
@@ -401,9 +405,12 @@ def main():
         ok = ok and b["batched_equals_per_trace"]
         out["batched"] = b
     if not args.no_serving:
-        sv = serving_leg(pkg, log, duration=args.serving_seconds)
-        ok = ok and sv["alone_equals_mix"]
+        # the configured rate, then ten times that rate (requests queue while
+        # batches run, so continuous batching merges them)
+        sv, hi = serving_leg(pkg, log, loads=((2000.0, args.serving_seconds), (20000.0, 1.0)))
+        ok = ok and sv["alone_equals_mix"] and hi["alone_equals_mix"]
         out["serving"] = sv
+        out["serving_high_load"] = hi
     print(json.dumps(out))
     if not ok:
         sys.exit(1)
