@@ -121,7 +121,8 @@ enum {
   SIM_ENOMEM = -3,  /* device or host allocation failed */
   SIM_EDEVICE = -4, /* HIP runtime error (text in sim_last_error()) */
   SIM_EAGAIN = -5,  /* serving: result not ready yet, or the pending queue is full */
-  SIM_ERANGE = -6   /* a trace's sort key would need more than 64 bits */
+  SIM_ERANGE = -6   /* a trace's sort key would need more than 128 bits (cannot happen with 32-bit thread
+                       ids and 16-bit epochs: keys take at most 116 bits; kept for the ABI) */
 };
 
 /* --------------------------------------------------------------- context */

@@ -49,6 +49,7 @@ struct sim_ctx {
   hipStream_t stream = nullptr;  // used by sim_check_traces
   uint32_t flags = 0;
   uint32_t pass_guess = 0;  // radix passes the previous call needed
+  bool wide_guess = false;  // the previous call had a trace needing two-word keys
   uint64_t alloc_gen = 0;   // bumped whenever a device buffer is reallocated
 
   // one captured launch sequence, replayed while calls keep the same shape
@@ -59,6 +60,7 @@ struct sim_ctx {
     uint64_t total = 0, table_hash = 0, gen = 0;
     uint32_t n_traces = 0, n_tiles = 0, guess = 0;
     uint64_t tuning_gen = 0;
+    bool wide = false;
   } graph;
 
   // launch shapes per size class (set by hand or by sim_autotune)
@@ -198,15 +200,16 @@ int group_shift(uint64_t n_tiles, int bias) {
 
 // Grow the device buffers of a call of `total` records in `n_traces`
 // traces, `n_tiles` tiles and `n_hgroups` histogram groups.
-hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups) {
+hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups,
+                        uint32_t key_bytes) {
   const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
   const uint64_t cap0 = total < 65536 ? total : 65536;
   struct {
     DevBuf* b;
     size_t bytes;
   } need[] = {
-      {&c->keys0, total * 8},
-      {&c->keys1, total * 8},
+      {&c->keys0, total * key_bytes},
+      {&c->keys1, total * key_bytes},
       {&c->desc, (size_t)n_traces * sizeof(TraceDesc)},
       {&c->tiles, (size_t)n_tiles * sizeof(TileRef)},
       {&c->stats_part, (size_t)n_tiles * sizeof(TraceStats)},
@@ -287,7 +290,10 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
 
   // ---- device buffers
-  if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups)) != hipSuccess) return hip_fail(c, e, "device allocation");
+  const bool wide = c->wide_guess;
+  const uint32_t key_bytes = wide ? 16u : 8u;
+  if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups, key_bytes)) != hipSuccess)
+    return hip_fail(c, e, "device allocation");
   if ((e = hipMemcpyAsync(c->desc.p, hd, (size_t)n_traces * sizeof(TraceDesc), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(c->tiles.p, ht, (size_t)n_tiles * sizeof(TileRef), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(c->groups.p, hg, (size_t)n_hgroups * sizeof(GroupRef), hipMemcpyHostToDevice, s)))
@@ -299,8 +305,10 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.tiles = (const TileRef*)c->tiles.p;
   b.stats_part = (TraceStats*)c->stats_part.p;
   b.layout = (TraceLayout*)c->layout.p;
-  b.keys[0] = (uint64_t*)c->keys0.p;
-  b.keys[1] = (uint64_t*)c->keys1.p;
+  b.keys[0] = c->keys0.p;
+  b.keys[1] = c->keys1.p;
+  b.wide = wide ? 1u : 0u;
+  b.key_bytes = key_bytes;
   b.groups = (const GroupRef*)c->groups.p;
   b.thist = (uint32_t*)c->thist.p;
   b.gtot = (uint32_t*)c->gtot.p;
@@ -406,7 +414,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   auto& G = c->graph;
   const bool replay = use_graph && G.exec && G.records == d_records && G.stream == s && G.total == total &&
                       G.n_traces == n_traces && G.n_tiles == n_tiles && G.table_hash == th && G.gen == c->alloc_gen &&
-                      G.guess == guess && G.tuning_gen == c->tuning_gen;
+                      G.guess == guess && G.tuning_gen == c->tuning_gen && G.wide == wide;
   if (replay) {
     e = hipGraphLaunch(G.exec, s);
   } else if (use_graph) {
@@ -431,6 +439,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       G.gen = c->alloc_gen;
       G.guess = guess;
       G.tuning_gen = c->tuning_gen;
+      G.wide = wide;
       e = hipGraphLaunch(G.exec, s);
     } else {  // capture not possible here: run the launches directly
       (void)hipGetLastError();
@@ -447,7 +456,13 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   if (ctl.error_flags & LAYOUT_ERR_RECORD)
     return fail(c, SIM_ERECORD, "invalid record at index %llu (action > 2 or space > 1)",
                 (unsigned long long)ctl.first_bad);
-  if (ctl.error_flags & LAYOUT_ERR_WIDE) return fail(c, SIM_ERANGE, "a trace's sort key needs more than 64 bits");
+  if (ctl.error_flags & LAYOUT_ERR_WIDE) return fail(c, SIM_ERANGE, "a trace's sort key needs more than 128 bits");
+  if (ctl.error_flags & ERR_NEEDS_WIDE) {
+    // a trace needs two-word keys: run the whole call again in that mode
+    // (the next call starts in it while its traces keep needing it)
+    c->wide_guess = true;
+    return run(c, d_records, offsets, n_traces, tpb, s, out);
+  }
   const uint32_t needed = ctl.max_passes;
   if (needed > guess) {
     // too few passes ran: the scan kernels above returned at once
@@ -458,6 +473,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     ctl = *c->h_ctrl;
   }
   c->pass_guess = needed;
+  c->wide_guess = ctl.wide_traces > 0;
   if (ctl.error_flags & ERR_STAGE_OVERFLOW) {
     // a tile holds more racing locations than its slice of the idle key
     // buffer: scan again with a dedicated staging buffer
@@ -572,7 +588,7 @@ int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg) {
     const uint32_t n_tr = cfg->reserve_traces ? cfg->reserve_traces : 1;
     const uint64_t tiles = (n_rec + TILE - 1) / TILE + n_tr;
     if (n_rec >= (1ull << 32) || tiles >= (1ull << 32) || ensure(c->records, n_rec * 16) ||
-        size_buffers(c, n_rec, n_tr, (uint32_t)tiles, tiles) != hipSuccess) {
+        size_buffers(c, n_rec, n_tr, (uint32_t)tiles, tiles, 8) != hipSuccess) {
       sim_destroy(c);
       return SIM_ENOMEM;
     }

@@ -160,6 +160,7 @@ __global__ void k_init(Ctrl* ctrl) {
     ctrl->error_flags = 0;
     ctrl->first_bad = ~0ull;
     ctrl->total_entries = 0;
+    ctrl->wide_traces = 0;
   }
 }
 
@@ -262,8 +263,12 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
 // key layout.  Global atomics only on rare events (an error, a new maximum
 // pass count).
 
+// wide_call: the call runs with two-word keys.  Otherwise a trace whose key
+// needs two words raises ERR_NEEDS_WIDE, which stops the call's later
+// kernels; the host then runs the call again with two-word keys.
 __global__ __launch_bounds__(NT) void k_layout(const TraceDesc* __restrict__ desc,
-                                               const TraceStats* __restrict__ part, TraceLayout* lay, Ctrl* ctrl) {
+                                               const TraceStats* __restrict__ part, TraceLayout* lay, Ctrl* ctrl,
+                                               uint32_t wide_call) {
   __shared__ uint64_t s64[5][NWAVE];
   __shared__ uint32_t s32[2][NWAVE];
   const uint32_t t = blockIdx.x;
@@ -297,6 +302,13 @@ __global__ __launch_bounds__(NT) void k_layout(const TraceDesc* __restrict__ des
   if (T.n == 0) {
     L.error = 0;
     L.npasses = 0;
+  }
+  if (L.wide && !L.error) {
+    atomicAdd(&ctrl->wide_traces, 1u);
+    if (!wide_call) {
+      atomicOr(&ctrl->error_flags, ERR_NEEDS_WIDE);
+      L.npasses = 0;
+    }
   }
   lay[t] = L;
   if (L.error) {
@@ -426,7 +438,7 @@ __global__ __launch_bounds__(RADIX * PARTS) void k_trace_offsets(Buffers b, uint
 // ------------------------------------------------------------- k_keygen
 // Records -> keys, and the tile histogram of radix digit 0.
 
-template <bool LOOP>
+template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
   __shared__ uint32_t h[RADIX];
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
@@ -443,15 +455,15 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
     const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
-    uint64_t* kout = b.keys[0] + T.off + start;
+    K* kout = (K*)b.keys[0] + T.off + start;
 #pragma unroll 4
     for (int r = 0; r < ITEMS; r++) {
       const uint32_t j = tx + r * NT;
       const bool valid = j < n_in;
-      uint64_t k = 0;
+      K k = 0;
       if (valid) {
         const Rec x = unpack_rec(p[j]);
-        k = make_key(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
+        k = make_key_t<K>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
         kout[j] = k;
       }
       wave_hist_add(h, (uint32_t)(k >> 2) & (RADIX - 1), valid);
@@ -464,7 +476,7 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
 // ------------------------------------------------------------ k_upsweep
 // Tile histogram of radix digit `pass` (keys in the buffer that pass reads).
 
-template <bool LOOP>
+template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
   __shared__ uint32_t h[RADIX];
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
@@ -481,12 +493,12 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
     const uint32_t shift = 2 + RADIX_BITS * pass;
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const uint64_t* src = b.keys[pass & 1] + T.off + start;
-    uint64_t k[ITEMS];
+    const K* src = (const K*)b.keys[pass & 1] + T.off + start;
+    K k[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; r++) {
       const uint32_t j = tx + r * NT;
-      k[r] = j < n_in ? src[j] : 0ull;
+      k[r] = j < n_in ? src[j] : (K)0;
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; r++)
@@ -508,8 +520,9 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
 // staged in LDS in destination order and written out in runs per digit.
 
 // LDS of one scatter tile.
+template <typename K>
 struct ScatterLds {
-  uint64_t keys[TILE];
+  K keys[TILE];
   uint32_t wh[NWAVE][RADIX];
   uint32_t dstart[RADIX];
   uint64_t gbase[RADIX];
@@ -519,9 +532,10 @@ struct ScatterLds {
 // One stable pass over one tile: key[] holds the tile's keys wave-striped
 // (key index = wave * 1024 + item * 64 + lane; ~0 past the end, which sorts
 // last); they go to their places in `kout`.
+template <typename K>
 __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, uint32_t tile, uint32_t tx,
                                              const TileRef& tr, const TraceDesc& T, uint32_t n_in,
-                                             uint64_t (&key)[ITEMS], uint64_t* kout, ScatterLds& S) {
+                                             K (&key)[ITEMS], K* kout, ScatterLds<K>& S) {
   const uint32_t lane = tx & 63u, wave = tx >> 6;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   const uint32_t d = tx;
@@ -570,7 +584,7 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
   for (int r = 0; r < ITEMS; r++) {
     const uint32_t j = tx + r * NT;
     if (j < n_in) {
-      const uint64_t k = S.keys[j];
+      const K k = S.keys[j];
       const uint32_t dd = (uint32_t)(k >> shift) & (RADIX - 1);
       const uint64_t dst = S.gbase[dd] + j;
       if (dst - T.off < T.n) kout[dst] = k;
@@ -579,9 +593,9 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
   }
 }
 
-template <bool LOOP>
+template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
-  __shared__ ScatterLds S;
+  __shared__ ScatterLds<K> S;
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -594,17 +608,17 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
     const uint32_t lane = tx & 63u, wave = tx >> 6;
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const uint64_t* src = b.keys[pass & 1] + T.off + start;
+    const K* src = (const K*)b.keys[pass & 1] + T.off + start;
 #pragma unroll
     for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
-    uint64_t key[ITEMS];
+    K key[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
-      key[i] = (j < n_in) ? src[j] : ~0ull;  // padding sorts last (digit 255, after every real key)
+      key[i] = (j < n_in) ? src[j] : ~(K)0;  // padding sorts last (digit 255, after every real key)
     }
     __syncthreads();
-    scatter_tile(b, pass, tile, tx, tr, T, n_in, key, b.keys[(pass + 1) & 1], S);
+    scatter_tile<K>(b, pass, tile, tx, tr, T, n_in, key, (K*)b.keys[(pass + 1) & 1], S);
   }
 }
 
@@ -618,9 +632,9 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
 // the same wave-striped order as k_scatter's, so the result is identical
 // to k_keygen followed by k_scatter(pass 0).
 
-template <bool LOOP>
+template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
-  __shared__ ScatterLds S;
+  __shared__ ScatterLds<K> S;
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -636,18 +650,18 @@ __global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
     const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
 #pragma unroll
     for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
-    uint64_t key[ITEMS];
+    K key[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
-      key[i] = ~0ull;
+      key[i] = ~(K)0;
       if (j < n_in) {
         const Rec x = unpack_rec(p[j]);
-        key[i] = make_key(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
+        key[i] = make_key_t<K>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
       }
     }
     __syncthreads();
-    scatter_tile(b, 0, tile, tx, tr, T, n_in, key, b.keys[1], S);
+    scatter_tile<K>(b, 0, tile, tx, tr, T, n_in, key, (K*)b.keys[1], S);
   }
 }
 
@@ -720,12 +734,13 @@ __device__ __forceinline__ State load_state(const uint32_t* w) {
   return s;
 }
 
-__device__ __forceinline__ void write_entry(RaceOut* dst, uint32_t trace, const TraceLayout& L, uint64_t key,
+template <typename K>
+__device__ __forceinline__ void write_entry(RaceOut* dst, uint32_t trace, const TraceLayout& L, K key,
                                             const uint64_t S[5]) {
   RaceOut e;
   uint32_t sp, blk;
   uint64_t unit;
-  key_location(L, key, sp, blk, unit);
+  key_location_t<K>(L, key, sp, blk, unit);
   e.trace = trace;
   e.space = (uint8_t)sp;
   e.kinds = (uint8_t)((S[K_WW] ? 1 : 0) | (S[K_RW] ? 2 : 0) | (S[K_AW] ? 4 : 0) | (S[K_AR] ? 8 : 0) |
@@ -746,20 +761,20 @@ __device__ __forceinline__ RaceOut* stage_of(const Buffers& b, uint32_t tile, co
     *cap = TILE / 2 + 1;
     return b.stage + (uint64_t)tile * (TILE / 2 + 1);
   }
-  *cap = n_in / 8;
-  return (RaceOut*)(b.keys[(L.npasses & 1u) ^ 1u] + T.off + start);
+  *cap = n_in * b.key_bytes / (uint32_t)sizeof(RaceOut);
+  return (RaceOut*)((char*)b.keys[(L.npasses & 1u) ^ 1u] + (T.off + start) * b.key_bytes);
 }
 
-template <bool LOOP>
+template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_done) {
-  __shared__ uint64_t s_keys[LDS_PAD(TILE) + 1];
+  __shared__ K s_keys[LDS_PAD(TILE) + 1];
   __shared__ uint64_t s_scanA[NWAVE][4];
   __shared__ uint64_t s_scanB[NWAVE][3];
   __shared__ uint32_t s_scan32[NWAVE];
   __shared__ uint8_t s_firstlv[NT];
   __shared__ uint32_t s_lead[17];  // lead counts [l][c] (12), lead pair sums (5)
   __shared__ uint32_t s_min;
-  __shared__ uint64_t s_prev, s_next;
+  __shared__ K s_prev, s_next;
   __shared__ uint32_t s_taillast;
 
   // nothing to do on an error, or when fewer radix passes ran than some
@@ -777,33 +792,33 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
     const TileRef tr = b.tiles[tile];
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
-    const uint64_t* keys = b.keys[L.npasses & 1u];
+    const K* keys = (const K*)b.keys[L.npasses & 1u];
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const uint64_t* src = keys + T.off + start;
+    const K* src = keys + T.off + start;
     const bool trace_end = start + n_in == T.n;
 
-    for (uint32_t j = tid; j < (uint32_t)TILE; j += NT) s_keys[LDS_PAD(j)] = (j < n_in) ? src[j] : 0ull;
+    for (uint32_t j = tid; j < (uint32_t)TILE; j += NT) s_keys[LDS_PAD(j)] = (j < n_in) ? src[j] : (K)0;
     if (tid == 0) {
-      s_prev = tr.local > 0 ? src[-1] : 0ull;
-      s_next = trace_end ? 0ull : src[n_in];
+      s_prev = tr.local > 0 ? src[-1] : (K)0;
+      s_next = trace_end ? (K)0 : src[n_in];
     }
     __syncthreads();
-    if (tid == 0) s_taillast = trace_end ? 1u : (head_level(L, s_keys[LDS_PAD(n_in - 1)], s_next) == 0 ? 1u : 0u);
+    if (tid == 0) s_taillast = trace_end ? 1u : (head_level_t<K>(L, s_keys[LDS_PAD(n_in - 1)], s_next) == 0 ? 1u : 0u);
 
     // ---- element metadata: head level (3 bits) and class (2 bits)
     // head level (3 bits) and class (2 bits) of item i: bits 5 (i % 6) of mp[i / 6]
     uint32_t mp[3] = {0u, 0u, 0u};
     uint32_t local_min = NO_HEAD;
     {
-      uint64_t prev = tid > 0 ? s_keys[LDS_PAD(ITEMS * tid - 1)] : s_prev;
+      K prev = tid > 0 ? s_keys[LDS_PAD(ITEMS * tid - 1)] : s_prev;
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t j = ITEMS * tid + i;
-        const uint64_t k = s_keys[LDS_PAD(j)];
+        const K k = s_keys[LDS_PAD(j)];
         uint32_t lv, c;
         if (j < n_in) {
-          lv = (j == 0 && tr.local == 0) ? 0u : head_level(L, prev, k);
+          lv = (j == 0 && tr.local == 0) ? 0u : head_level_t<K>(L, prev, k);
           c = action_class(k);
           local_min = min(local_min, lv);
         } else {
@@ -998,7 +1013,7 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
         S[K_AW] = (uint32_t)s1; S[K_AR] = (uint32_t)(s1 >> 32);
         S[K_XB] = (uint32_t)s2;
         if (S[K_WW] + S[K_RW] + S[K_AW] + S[K_AR] == 0) continue;
-        if (pos < cap) write_entry(dst + pos, tr.trace, L, s_keys[LDS_PAD(ITEMS * tid + i)], S);
+        if (pos < cap) write_entry<K>(dst + pos, tr.trace, L, s_keys[LDS_PAD(ITEMS * tid + i)], S);
         pos++;
       }
     };
@@ -1059,6 +1074,7 @@ __device__ __forceinline__ State readlane_state(const State& s, int src) {
   return r;
 }
 
+template <typename K>
 __global__ __launch_bounds__(NT) void k_scan_cross(Buffers b, uint32_t passes_done) {
   if (b.ctrl->error_flags) return;
   if (b.ctrl->max_passes > passes_done) return;
@@ -1120,8 +1136,8 @@ __global__ __launch_bounds__(NT) void k_scan_cross(Buffers b, uint32_t passes_do
     if (racing) {
       const uint64_t start = (uint64_t)tr.local * TILE;
       const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-      const uint64_t key = b.keys[L.npasses & 1u][T.off + start + n_in - 1];
-      write_entry(&b.cross[j], tr.trace, L, key, fin);
+      const K key = ((const K*)b.keys[L.npasses & 1u])[T.off + start + n_in - 1];
+      write_entry<K>(&b.cross[j], tr.trace, L, key, fin);
     }
   }
 }
@@ -1208,25 +1224,33 @@ hipError_t launch_stats(const Buffers& b, hipStream_t s) {
 }
 hipError_t launch_layout(const Buffers& b, hipStream_t s) {
   if (!b.n_traces) return hipSuccess;
-  hipLaunchKernelGGL(k_layout, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl);
+  hipLaunchKernelGGL(k_layout, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl, b.wide);
   return hipGetLastError();
 }
 hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
-  if (b.fuse0)  // pass 0's offsets come first (launch_upsweep(b, 0)); the keys go straight to pass 1's buffer
-    hipLaunchKernelGGL(loops(b, b.grid_sort) ? k_keygen_scatter<true> : k_keygen_scatter<false>, dim3(b.grid_sort),
-                       dim3(NT), 0, s, b);
-  else
-    hipLaunchKernelGGL(loops(b, b.grid_stream) ? k_keygen<true> : k_keygen<false>, dim3(b.grid_stream), dim3(NT), 0,
-                       s, b);
+  if (b.fuse0) {  // pass 0's offsets come first (launch_upsweep(b, 0)); the keys go straight to pass 1's buffer
+    const bool lp = loops(b, b.grid_sort);
+    auto kern = b.wide ? (lp ? k_keygen_scatter<u128, true> : k_keygen_scatter<u128, false>)
+                       : (lp ? k_keygen_scatter<uint64_t, true> : k_keygen_scatter<uint64_t, false>);
+    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b);
+  } else {
+    const bool lp = loops(b, b.grid_stream);
+    auto kern = b.wide ? (lp ? k_keygen<u128, true> : k_keygen<u128, false>)
+                       : (lp ? k_keygen<uint64_t, true> : k_keygen<uint64_t, false>);
+    hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, b);
+  }
   return hipGetLastError();
 }
 hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
   if (pass > 0) {  // digit 0's histograms come from k_keygen
-    hipLaunchKernelGGL(loops(b, b.grid_stream) ? k_upsweep<true> : k_upsweep<false>, dim3(b.grid_stream), dim3(NT), 0, s, b, pass);
+    const bool lp = loops(b, b.grid_stream);
+    auto kern = b.wide ? (lp ? k_upsweep<u128, true> : k_upsweep<u128, false>)
+                       : (lp ? k_upsweep<uint64_t, true> : k_upsweep<uint64_t, false>);
+    hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, b, pass);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1247,18 +1271,25 @@ hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s) {
 hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(loops(b, b.grid_sort) ? k_scatter<true> : k_scatter<false>, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
+  const bool lp = loops(b, b.grid_sort);
+  auto kern = b.wide ? (lp ? k_scatter<u128, true> : k_scatter<u128, false>)
+                     : (lp ? k_scatter<uint64_t, true> : k_scatter<uint64_t, false>);
+  hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
   return hipGetLastError();
 }
 hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(loops(b, b.grid_scan) ? k_scan_tiles<true> : k_scan_tiles<false>, dim3(b.grid_scan), dim3(NT), 0, s, b, passes_done);
+  const bool lp = loops(b, b.grid_scan);
+  auto kern = b.wide ? (lp ? k_scan_tiles<u128, true> : k_scan_tiles<u128, false>)
+                     : (lp ? k_scan_tiles<uint64_t, true> : k_scan_tiles<uint64_t, false>);
+  hipLaunchKernelGGL(kern, dim3(b.grid_scan), dim3(NT), 0, s, b, passes_done);
   return hipGetLastError();
 }
 hipError_t launch_scan_cross(const Buffers& b, uint32_t passes_done, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_cross, dim3(cdiv(b.n_tiles, NWAVE)), dim3(NT), 0, s, b, passes_done);
+  hipLaunchKernelGGL(b.wide ? k_scan_cross<u128> : k_scan_cross<uint64_t>, dim3(cdiv(b.n_tiles, NWAVE)), dim3(NT), 0,
+                     s, b, passes_done);
   return hipGetLastError();
 }
 hipError_t launch_scan_out(const Buffers& b, uint32_t passes_done, hipStream_t s) {

@@ -1,6 +1,6 @@
 // keys.h -- per-trace sort-key layout for the race check.
 //
-// Every record of a trace is packed into one 64-bit key whose order groups
+// Every record of a trace is packed into one key whose order groups
 // the records first by location (the paper's Memory Unit, Sec. 4.2.1: one
 // unit of global memory, or one unit of one block's shared memory, Alg. 3),
 // then by block, by epoch (visit order) and by thread, with the action in
@@ -12,6 +12,8 @@
 // The fields between the space bit and the epoch field span wl = max(ug + bb,
 // bb + us) bits in both layouts.  Field widths come from per-trace minima
 // and maxima, so a key is lossless and the record can be read back from it.
+// A key of at most 64 bits is one word; a wider one (up to 128 bits: a unit
+// span near 2^64 in one trace) is a 128-bit integer, two words.
 // Within a location the key orders records by (block, epoch, thread), which
 // makes every group used by the race count contiguous after sorting.
 //
@@ -48,6 +50,8 @@ struct TraceLayout {
   uint32_t shift_bs;   // block field of shared keys
   uint32_t shift_space;
   uint32_t error;      // LAYOUT_ERR_* bits
+  uint32_t wide;       // 1: the key needs more than 64 bits (two-word keys)
+  uint32_t pad;
 };
 
 // LAYOUT_ERR_* are per-trace layout errors; ERR_INTERNAL_* are raised by the
@@ -57,7 +61,10 @@ enum : uint32_t { LAYOUT_ERR_WIDE = 1, LAYOUT_ERR_RECORD = 2, ERR_INTERNAL_BOUND
 
 constexpr uint32_t RADIX_BITS = 8;
 constexpr uint32_t RADIX = 1u << RADIX_BITS;
-constexpr uint32_t MAX_PASSES = 8;  // ceil(62 / 8)
+constexpr uint32_t MAX_PASSES = 16;  // ceil(126 / 8)
+
+// A key of a trace wider than 64 bits: two words, one 128-bit integer.
+typedef unsigned __int128 u128;
 
 SC_HD uint32_t bits32(uint32_t x) { return x ? 32u - (uint32_t)__builtin_clz(x) : 0u; }
 SC_HD uint32_t bits64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 0u; }
@@ -88,47 +95,68 @@ SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
   L.shift_bs = L.shift_b + L.us;
   L.shift_space = 2 + L.tb + L.eb + L.wl;
   L.error = 0;
-  if (L.key_bits > 64) L.error |= LAYOUT_ERR_WIDE;
+  L.wide = L.key_bits > 64 ? 1u : 0u;
+  L.pad = 0;
+  if (L.key_bits > 128) L.error |= LAYOUT_ERR_WIDE;
   if (s.bad_index != ~0ull) L.error |= LAYOUT_ERR_RECORD;
   L.npasses = L.error ? 0 : (L.key_bits - 2 + RADIX_BITS - 1) / RADIX_BITS;
   return L;
 }
 
-// Key of one record (fields must be valid and within the trace's ranges).
-SC_HD uint64_t make_key(const TraceLayout& L, uint64_t unit, uint32_t tid, uint32_t epoch, uint32_t action,
-                        uint32_t space, uint32_t tpb) {
+// Key of one record (fields must be valid and within the trace's ranges);
+// K is uint64_t for keys of at most 64 bits, u128 otherwise.
+template <typename K>
+SC_HD K make_key_t(const TraceLayout& L, uint64_t unit, uint32_t tid, uint32_t epoch, uint32_t action, uint32_t space,
+                   uint32_t tpb) {
   // a power-of-two block size (tb = log2 tpb) divides by a shift
   const uint32_t blk = (tpb & (tpb - 1)) == 0 ? tid >> L.tb : tid / tpb;
   const uint32_t loc = tid - blk * tpb;
-  const uint64_t low = ((uint64_t)epoch << L.shift_e) | ((uint64_t)loc << 2) | (uint64_t)(action & 3u);
-  if (space == 0) return ((unit - L.gmin) << L.shift_ug) | ((uint64_t)blk << L.shift_b) | low;
-  return (1ull << L.shift_space) | ((uint64_t)blk << L.shift_bs) | ((unit - L.smin) << L.shift_b) | low;
+  const K low = ((K)epoch << L.shift_e) | ((K)loc << 2) | (K)(action & 3u);
+  if (space == 0) return ((K)(unit - L.gmin) << L.shift_ug) | ((K)blk << L.shift_b) | low;
+  return ((K)1 << L.shift_space) | ((K)blk << L.shift_bs) | ((K)(unit - L.smin) << L.shift_b) | low;
+}
+SC_HD uint64_t make_key(const TraceLayout& L, uint64_t unit, uint32_t tid, uint32_t epoch, uint32_t action,
+                        uint32_t space, uint32_t tpb) {
+  return make_key_t<uint64_t>(L, unit, tid, epoch, action, space, tpb);
+}
+
+// Highest set bit of a nonzero key.
+SC_HD uint32_t top_bit(uint64_t x) { return 63u - (uint32_t)__builtin_clzll(x); }
+SC_HD uint32_t top_bit(u128 x) {
+  const uint64_t hi = (uint64_t)(x >> 64);
+  return hi ? 127u - (uint32_t)__builtin_clzll(hi) : 63u - (uint32_t)__builtin_clzll((uint64_t)x);
 }
 
 // Nesting level at which key x starts a new group relative to the previous
 // key p of the same trace: 0 new location, 1 new block (global only),
 // 2 new epoch, 3 new thread, 4 same (location, block, epoch, thread).
-SC_HD uint32_t head_level(const TraceLayout& L, uint64_t p, uint64_t x) {
+template <typename K>
+SC_HD uint32_t head_level_t(const TraceLayout& L, K p, K x) {
   // written with selects only: it runs for every key of the tile scan
-  const uint64_t d = (x ^ p) & ~3ull;
-  const uint32_t hb = d ? 63u - (uint32_t)__builtin_clzll(d) : 0u;  // highest differing bit
-  const bool shared = ((x >> L.shift_space) & 1ull) != 0;
+  const K d = (x ^ p) & ~(K)3;
+  const uint32_t hb = d != 0 ? top_bit(d) : 0u;  // highest differing bit
+  const bool shared = ((x >> L.shift_space) & 1u) != 0;
   const uint32_t inner = hb >= L.shift_e ? 2u : 3u;          // epoch or thread
   const uint32_t lv_s = hb >= L.shift_b ? 0u : inner;        // shared: block is part of the location
   const uint32_t lv_g = hb >= L.shift_ug ? 0u : (hb >= L.shift_b ? 1u : inner);
   return d == 0 ? 4u : (shared ? lv_s : lv_g);
 }
+SC_HD uint32_t head_level(const TraceLayout& L, uint64_t p, uint64_t x) { return head_level_t<uint64_t>(L, p, x); }
 
 // Location of a key: space, owning block (shared) or 0xFFFFFFFF, unit.
-SC_HD void key_location(const TraceLayout& L, uint64_t k, uint32_t& space, uint32_t& block, uint64_t& unit) {
-  space = (uint32_t)((k >> L.shift_space) & 1ull);
+template <typename K>
+SC_HD void key_location_t(const TraceLayout& L, K k, uint32_t& space, uint32_t& block, uint64_t& unit) {
+  space = (uint32_t)((k >> L.shift_space) & 1u);
   if (space == 0) {
     block = 0xFFFFFFFFu;
-    unit = ((k >> L.shift_ug) & lowmask(L.ug)) + L.gmin;
+    unit = ((uint64_t)(k >> L.shift_ug) & lowmask(L.ug)) + L.gmin;
   } else {
-    block = (uint32_t)((k >> L.shift_bs) & lowmask(L.bb));
-    unit = ((k >> L.shift_b) & lowmask(L.us)) + L.smin;
+    block = (uint32_t)((uint64_t)(k >> L.shift_bs) & lowmask(L.bb));
+    unit = ((uint64_t)(k >> L.shift_b) & lowmask(L.us)) + L.smin;
   }
+}
+SC_HD void key_location(const TraceLayout& L, uint64_t k, uint32_t& space, uint32_t& block, uint64_t& unit) {
+  key_location_t<uint64_t>(L, k, space, block, unit);
 }
 
 }  // namespace sc

@@ -17,7 +17,7 @@ constexpr int GROUP = 256;         // tiles per group of the output prefix
 constexpr uint32_t MAX_HGROUP_SHIFT = 12; // histogram groups hold at most 4096 tiles
 
 // kernel-side error flags beyond the per-trace layout errors of keys.h
-enum : uint32_t { ERR_STAGE_OVERFLOW = 16 };
+enum : uint32_t { ERR_STAGE_OVERFLOW = 16, ERR_NEEDS_WIDE = 32 };
 
 struct TraceDesc {   // one trace of a call (host-filled)
   uint64_t off;      // first record
@@ -51,6 +51,8 @@ struct Ctrl {               // per-call control block (device)
   uint32_t error_flags;     // LAYOUT_ERR_* / ERR_* of any trace or kernel
   uint64_t first_bad;       // smallest global index of an invalid record
   uint64_t total_entries;   // racing locations of the call
+  uint32_t wide_traces;     // traces whose key needs two words
+  uint32_t pad;
 };
 
 struct RaceOut {            // mirrors sim_race (64 bytes)
@@ -67,7 +69,7 @@ struct Buffers {            // device pointers of one call
   const TileRef* tiles;
   TraceStats* stats_part;   // [tile]
   TraceLayout* layout;      // [trace]
-  uint64_t* keys[2];
+  void* keys[2];             // uint64_t[] (one-word keys) or u128[] (two-word keys, `wide`)
   const GroupRef* groups;   // [group]
   uint32_t* thist;          // [tile][RADIX] digit counts of the current pass -> offsets within the group
   uint32_t* gtot;           // [group][RADIX] group totals
@@ -91,6 +93,8 @@ struct Buffers {            // device pointers of one call
   uint32_t max_trace_groups;// most histogram groups in one trace of the call
   uint32_t fuse0;           // 1: digit 0 is tid mod 256 in every trace; k_stats builds its histograms
                             // and k_keygen_scatter does radix pass 0 (see kernels.hip)
+  uint32_t wide;            // 1: two-word keys for every trace of the call
+  uint32_t key_bytes;       // 8 or 16
 };
 
 // Kernel stages, in launch order.

@@ -153,5 +153,6 @@ SC_HD void push(State& s, uint32_t lv, uint32_t c) {
 }
 
 SC_HD uint32_t action_class(uint64_t key) { return (uint32_t)(key & 3ull); }
+SC_HD uint32_t action_class(u128 key) { return (uint32_t)((uint64_t)key & 3ull); }
 
 }  // namespace sc

@@ -34,14 +34,15 @@ struct race {
 
 using namespace sc;
 
-static void emit(std::vector<race>& out, uint32_t tr, const TraceLayout& L, uint64_t key, const uint64_t s[5]) {
+template <typename K>
+static void emit(std::vector<race>& out, uint32_t tr, const TraceLayout& L, K key, const uint64_t s[5]) {
   if (s[K_WW] + s[K_RW] + s[K_AW] + s[K_AR] == 0) return;
   race e;
   std::memset(&e, 0, sizeof e);
   e.trace = tr;
   uint32_t sp, blk;
   uint64_t unit;
-  key_location(L, key, sp, blk, unit);
+  key_location_t<K>(L, key, sp, blk, unit);
   e.space = (uint8_t)sp;
   e.block = blk;
   e.unit = unit;
@@ -50,8 +51,11 @@ static void emit(std::vector<race>& out, uint32_t tr, const TraceLayout& L, uint
   out.push_back(e);
 }
 
-extern "C" int64_t hs_check(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
-                            uint32_t tile, uint32_t chunk, race* out, uint64_t cap, uint32_t* max_passes) {
+// K = uint64_t: one-word keys (a trace wider than 64 bits is an error, as
+// in the GPU path's one-word mode); K = u128: two-word keys for every trace.
+template <typename K>
+static int64_t check_impl(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                          uint32_t tile, uint32_t chunk, race* out, uint64_t cap, uint32_t* max_passes) {
   std::vector<race> res;
   uint32_t mp = 0;
   for (uint32_t tr = 0; tr < n_traces; tr++) {
@@ -69,18 +73,19 @@ extern "C" int64_t hs_check(const rec* recs, const uint64_t* off, uint32_t n_tra
     }
     const TraceLayout L = make_layout(S, tpb[tr]);
     if (L.error) return -(int64_t)L.error;
+    if (L.wide && sizeof(K) == 8) return -(int64_t)LAYOUT_ERR_WIDE;
     mp = std::max(mp, L.npasses);
-    std::vector<uint64_t> k(n);
+    std::vector<K> k(n);
     for (uint64_t i = 0; i < n; i++) {
       const rec& r = recs[lo + i];
-      k[i] = make_key(L, r.unit, r.tid, r.epoch, r.action, r.space, tpb[tr]);
+      k[i] = make_key_t<K>(L, r.unit, r.tid, r.epoch, r.action, r.space, tpb[tr]);
     }
     std::sort(k.begin(), k.end());
     // tile summaries, carry-free (as the tile scan computes them)
     const uint64_t nt = (n + tile - 1) / tile;
     std::vector<State> agg(nt);
     std::vector<uint32_t> lv(n);
-    for (uint64_t i = 0; i < n; i++) lv[i] = (i == 0) ? 0 : head_level(L, k[i - 1], k[i]);
+    for (uint64_t i = 0; i < n; i++) lv[i] = (i == 0) ? 0 : head_level_t<K>(L, k[i - 1], k[i]);
     for (uint64_t t = 0; t < nt; t++) {
       const uint64_t t0 = t * tile, t1 = std::min<uint64_t>(n, t0 + tile);
       State a = identity();
@@ -123,6 +128,16 @@ extern "C" int64_t hs_check(const rec* recs, const uint64_t* off, uint32_t n_tra
   if (res.size() > cap) return (int64_t)res.size();
   std::memcpy(out, res.data(), res.size() * sizeof(race));
   return (int64_t)res.size();
+}
+
+extern "C" int64_t hs_check(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                            uint32_t tile, uint32_t chunk, race* out, uint64_t cap, uint32_t* max_passes) {
+  return check_impl<uint64_t>(recs, off, n_traces, tpb, tile, chunk, out, cap, max_passes);
+}
+
+extern "C" int64_t hs_check_wide(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                                 uint32_t tile, uint32_t chunk, race* out, uint64_t cap, uint32_t* max_passes) {
+  return check_impl<u128>(recs, off, n_traces, tpb, tile, chunk, out, cap, max_passes);
 }
 
 // Associativity check on random element sequences: fold(push) equals the

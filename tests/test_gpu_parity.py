@@ -261,14 +261,13 @@ def test_error_paths_leave_context_usable(ctx):
     with pytest.raises(pkg.SimError) as ei:
         ctx.check_traces(good, None, 0)
     assert ei.value.code == pkg.SIM_EINVAL
-    say("key wider than 64 bits")
+    say("key wider than 64 bits: two-word keys, same context")
     w = np.zeros(4, dtype=RECORD_DTYPE)
     w["unit"] = [0, 1 << 62, 5, 5]
     w["tid"] = [0, 1 << 20, 3, 1 << 21]
     w["action"] = 1
-    with pytest.raises(pkg.SimError) as ei:
-        ctx.check_traces(w, None, 1024)
-    assert ei.value.code == pkg.SIM_ERANGE
+    got = assert_parity(ctx, w, tpb=1024, name="86-bit keys")
+    assert len(got) == 1 and int(got["unit"][0]) == 5
     assert_parity(ctx, good, tpb=256, name="after errors")
 
 
@@ -485,3 +484,48 @@ def test_widest_keys_and_mixed_pass_counts(ctx):
         assert_parity(fresh, w, None, 256, name="64-bit keys alone after 2")
     finally:
         fresh.close()
+
+
+def test_two_word_keys(ctx):
+    """Traces whose lossless key needs more than 64 bits (units spread over
+    2^62, thread ids up to 2^20, epochs up to 999) run with two-word keys:
+    alone, batched with one-word traces, across tiles, and back to one-word
+    calls on the same context; also under graph replay."""
+    import paper_1905_01833_amd as pkg
+
+    rng = np.random.default_rng(128)
+
+    def wide(n, tpb=64):
+        r = np.zeros(n, dtype=RECORD_DTYPE)
+        pool = rng.integers(0, 1 << 62, 40, dtype=np.uint64)
+        pool[0], pool[1] = 0, (1 << 62) - 1
+        r["unit"] = pool[rng.integers(0, len(pool), n)]
+        r["tid"] = rng.integers(0, 1 << 20, n)
+        few = rng.random(n) < 0.5
+        r["tid"][few] = rng.integers(0, 3 * tpb, int(few.sum()))
+        r["epoch"] = rng.integers(0, 3, n)
+        r["epoch"][0] = 999
+        r["action"] = rng.integers(0, 3, n)
+        r["space"] = (rng.random(n) < 0.3).astype(np.uint8)
+        return r
+
+    w1 = wide(30000)
+    got = assert_parity(ctx, w1, tpb=64, name="two-word keys, 30000 records")
+    assert len(got) > 0
+    narrow = tracegen.random_small(rng, 9000, units=20, blocks=3, tpb=5, epochs=3)
+    recs, off = batch_of([narrow, wide(5000, tpb=256), narrow[:77], wide(12345)])
+    assert_parity(ctx, recs, off, [5, 256, 5, 64], name="two-word and one-word traces batched")
+    assert_parity(ctx, narrow, tpb=5, name="one-word call after two-word calls")
+    assert_parity(ctx, w1, tpb=64, name="two-word call after a one-word call")
+    g = pkg.Context(0, graphs=True)
+    try:
+        want, wsum = oracle.closed_form(w1, tpb=64)
+        dev = torch.from_numpy(w1.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+        stream = torch.cuda.Stream()
+        for rep in range(4):
+            say(f"two-word keys, graph replay {rep}")
+            with torch.cuda.stream(stream):
+                got, gsum = g.check_traces_device(dev, None, 64, stream=stream.cuda_stream)
+            assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes(), rep
+    finally:
+        g.close()

@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 import tracegen
+from tracegen import RECORD_DTYPE
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HOSTSIM = os.path.join(ROOT, "tests", "libhostsim.so")
@@ -29,6 +30,8 @@ def _hostsim():
     lib.hs_check.restype = ctypes.c_int64
     lib.hs_check.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                                      ctypes.c_uint64, ctypes.c_void_p]
+    lib.hs_check_wide.restype = ctypes.c_int64
+    lib.hs_check_wide.argtypes = lib.hs_check.argtypes
     lib.hs_tile_walk.restype = ctypes.c_uint32
     lib.hs_tile_walk.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_uint32)]
@@ -37,16 +40,36 @@ def _hostsim():
     return lib
 
 
-def hs_check(recs, off, tpb, tile, chunk):
+def hs_check(recs, off, tpb, tile, chunk, wide=False, expect_error=False):
     lib = _hostsim()
     off = np.ascontiguousarray(np.asarray(off, dtype=np.uint64))
     tpb = np.ascontiguousarray(np.asarray(tpb, dtype=np.uint32))
     out = np.zeros(len(recs) + 1, dtype=oracle.RACE_DTYPE)
     mp = ctypes.c_uint32(0)
-    n = lib.hs_check(recs.ctypes.data, off.ctypes.data, len(off) - 1, tpb.ctypes.data, tile, chunk,
-                     out.ctypes.data, len(out), ctypes.byref(mp))
+    fn = lib.hs_check_wide if wide else lib.hs_check
+    n = fn(recs.ctypes.data, off.ctypes.data, len(off) - 1, tpb.ctypes.data, tile, chunk,
+           out.ctypes.data, len(out), ctypes.byref(mp))
+    if expect_error:
+        return n
     assert n >= 0, n
     return out[:n], int(mp.value)
+
+
+def wide_trace(rng, n, tpb=64):
+    """Units drawn from a few values spread over 2^62, thread ids up to 2^20,
+    epochs up to 999: the lossless key needs more than 64 bits."""
+    r = np.zeros(n, dtype=RECORD_DTYPE)
+    pool = rng.integers(0, 1 << 62, 12, dtype=np.uint64)
+    pool[0], pool[1] = 0, (1 << 62) - 1
+    r["unit"] = pool[rng.integers(0, len(pool), n)]
+    r["tid"] = rng.integers(0, 1 << 20, n)
+    few = rng.random(n) < 0.5  # half the records in three blocks: same-block races
+    r["tid"][few] = rng.integers(0, 3 * tpb, int(few.sum()))
+    r["epoch"] = rng.integers(0, 3, n)
+    r["epoch"][0] = 999
+    r["action"] = rng.integers(0, 3, n)
+    r["space"] = (rng.random(n) < 0.3).astype(np.uint8)
+    return r
 
 
 def test_monoid_associative():
@@ -141,3 +164,23 @@ def test_server_create_fails_cleanly_without_gpu():
     with pytest.raises(pkg.SimError) as ei:
         pkg.Server(0, slots=17)
     assert ei.value.code == pkg.SIM_EINVAL
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_host_model_two_word_keys(seed):
+    """Keys wider than 64 bits: the one-word model refuses the trace (as the
+    GPU path's one-word mode does), the two-word model matches the oracle;
+    on narrow traces the two models agree."""
+    rng = np.random.default_rng(seed)
+    w = wide_trace(rng, 2500)
+    want, _ = oracle.closed_form(w, tpb=64)
+    assert len(want) > 0
+    assert hs_check(w, [0, len(w)], [64], 4096, 16, expect_error=True) < 0
+    for tile, chunk in [(4096, 16), (97, 5)]:
+        got, mp = hs_check(w, [0, len(w)], [64], tile, chunk, wide=True)
+        assert got.tobytes() == want.tobytes(), (tile, chunk)
+        assert 8 < mp <= 16
+    r = tracegen.random_small(rng, 400, units=5, blocks=3, tpb=3, epochs=3)
+    a, _ = hs_check(r, [0, len(r)], [3], 50, 4)
+    b, _ = hs_check(r, [0, len(r)], [3], 50, 4, wide=True)
+    assert a.tobytes() == b.tobytes()
