@@ -150,7 +150,12 @@ const char* sim_last_error(const sim_ctx* ctx);
  *   out               : receives the result (caller frees it)
  * n_traces = 0 and empty traces are valid.  Inputs are read only and must
  * stay valid until the call returns.  The records are copied to the device
- * on the context's stream.                                                 */
+ * on the context's stream.
+ * Keys: a record's sort key packs its location, block, epoch and thread in
+ * as few bits as the trace's ranges allow.  When some trace of a call needs
+ * more than 64 bits (a unit span near 2^64), the call runs with 128-bit
+ * keys: 16 bytes of key storage per record instead of 8, and a second
+ * device round when the context's previous call did not need them.       */
 int sim_check_traces(sim_ctx* ctx, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
                      const uint32_t* threads_per_block, sim_result** out);
 
@@ -248,7 +253,9 @@ int sim_autotune(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offs
  * the footprints of the batches on the GPU never exceed the budget, and a
  * worker releases its buffers after a batch when they exceed its share
  * (budget / slots).  A request whose footprint alone exceeds the budget is
- * refused at submission (SIM_ENOMEM).
+ * refused at submission (SIM_ENOMEM).  The footprint counts one-word keys; a
+ * request whose traces need two-word keys (see sim_check_traces) holds up to
+ * 16 bytes per record more while it runs.
  *
  * All server calls are thread-safe.                                        */
 typedef struct sim_server sim_server;
