@@ -208,11 +208,15 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
       h[tx] = 0;
       __syncthreads();
     }
-#pragma unroll 4
+    // all loads first: sixteen records in flight per thread
+    ulonglong2 vr[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) vr[r] = tx + r * NT < n_in ? p[tx + r * NT] : ulonglong2{0ull, 0ull};
+#pragma unroll
     for (int r = 0; r < ITEMS; r++) {
       const uint32_t j = tx + r * NT;
       const bool valid = j < n_in;
-      const ulonglong2 v = valid ? p[j] : ulonglong2{0ull, 0ull};
+      const ulonglong2 v = vr[r];
       // tid mod 256: neighbouring records mostly belong to different threads,
       // so plain LDS atomics rarely conflict here
       if (HIST && valid) atomicAdd(&h[(uint32_t)v.y & (RADIX - 1)], 1u);
@@ -456,13 +460,16 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
     const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
     K* kout = (K*)b.keys[0] + T.off + start;
-#pragma unroll 4
+    ulonglong2 vr[ITEMS];  // all loads first
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) vr[r] = tx + r * NT < n_in ? p[tx + r * NT] : ulonglong2{0ull, 0ull};
+#pragma unroll
     for (int r = 0; r < ITEMS; r++) {
       const uint32_t j = tx + r * NT;
       const bool valid = j < n_in;
       K k = 0;
       if (valid) {
-        const Rec x = unpack_rec(p[j]);
+        const Rec x = unpack_rec(vr[r]);
         k = make_key_t<K>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
         kout[j] = k;
       }
