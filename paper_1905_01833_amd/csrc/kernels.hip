@@ -805,7 +805,13 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
     const K* src = keys + T.off + start;
     const bool trace_end = start + n_in == T.n;
 
-    for (uint32_t j = tid; j < (uint32_t)TILE; j += NT) s_keys[LDS_PAD(j)] = (j < n_in) ? src[j] : (K)0;
+    {
+      K v[ITEMS];  // all loads first
+#pragma unroll
+      for (int r = 0; r < ITEMS; r++) v[r] = tid + r * NT < n_in ? src[tid + r * NT] : (K)0;
+#pragma unroll
+      for (int r = 0; r < ITEMS; r++) s_keys[LDS_PAD(tid + r * NT)] = v[r];
+    }
     if (tid == 0) {
       s_prev = tr.local > 0 ? src[-1] : (K)0;
       s_next = trace_end ? (K)0 : src[n_in];
