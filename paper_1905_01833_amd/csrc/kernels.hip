@@ -77,17 +77,45 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+// Cross-lane moves of the wave's data-parallel primitives (DPP): the value
+// of another lane, or 0 where that lane is outside the pattern or the row
+// is masked off.  Row = 16 lanes.
+enum : int {
+  DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118,
+  DPP_WAVE_SHR1 = 0x138,   // lane i gets lane i - 1
+  DPP_ROW_BCAST15 = 0x142, // last lane of each row to the next row
+  DPP_ROW_BCAST31 = 0x143  // lane 31 to rows 2 and 3
+};
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint64_t dpp(uint64_t v) {
+  return ((uint64_t)dpp<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) | dpp<CTRL, ROWS>((uint32_t)v);
+}
+
+// Inclusive scan over the 64 lanes of a wave with an associative operator
+// whose identity is 0: within rows (shifts 1, 2, 4, 8), then across rows
+// (row 0's total into row 1 and row 2's into row 3, then lane 31's into
+// rows 2 and 3).
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_incl_scan(T v, Op op) {
+  v = op(dpp<DPP_ROW_SHR1>(v), v);
+  v = op(dpp<DPP_ROW_SHR2>(v), v);
+  v = op(dpp<DPP_ROW_SHR4>(v), v);
+  v = op(dpp<DPP_ROW_SHR8>(v), v);
+  v = op(dpp<DPP_ROW_BCAST15, 0xa>(v), v);
+  v = op(dpp<DPP_ROW_BCAST31, 0xc>(v), v);
+  return v;
+}
+
 // Exclusive sum over a workgroup of NW waves; *total receives the sum of all
 // values.  Every thread of the workgroup must call it (it holds barriers).
 template <int NW>
 __device__ uint32_t block_excl_sum_n(uint32_t v, uint32_t* lds /* NW */, uint32_t* total) {
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
-  uint32_t inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = __shfl_up(inc, d, 64);
-    if (lane >= (uint32_t)d) inc += o;
-  }
+  const uint32_t inc = wave_incl_scan(v, [](uint32_t a, uint32_t b) { return a + b; });
   if (lane == 63) lds[wave] = inc;
   __syncthreads();
   uint32_t pre = 0, tot = 0;
@@ -118,19 +146,9 @@ __device__ void block_seg_scan(const uint64_t (&v)[K], uint64_t (&ex)[K], uint64
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   uint64_t inc[K];
 #pragma unroll
-  for (int k = 0; k < K; k++) inc[k] = v[k];
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-      const uint64_t o = __shfl_up(inc[k], d, 64);
-      if (lane >= (uint32_t)d) inc[k] = seg_op(o, inc[k]);
-    }
-  }
-#pragma unroll
   for (int k = 0; k < K; k++) {
-    uint64_t e = __shfl_up(inc[k], 1, 64);
-    ex[k] = lane == 0 ? 0ull : e;
+    inc[k] = wave_incl_scan(v[k], seg_op);
+    ex[k] = dpp<DPP_WAVE_SHR1>(inc[k]);
   }
   if (lane == 63) {
 #pragma unroll
@@ -536,6 +554,22 @@ struct ScatterLds {
   uint32_t scan[NWAVE];
 };
 
+// Lanes of the wave whose digit equals this lane's: one ballot per digit
+// bit; a lane keeps the ballot where its own bit is set and the complement
+// where it is clear.  The bit is taken as 0 or all ones (a signed one-bit
+// field), so keeping is an XNOR with the ballot's halves.
+__device__ __forceinline__ uint64_t peer_mask(uint32_t dg) {
+  uint32_t lo = ~0u, hi = ~0u;
+#pragma unroll
+  for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
+    const uint32_t all = (uint32_t)__builtin_amdgcn_sbfe((int)dg, bt, 1);  // 0 or ~0
+    const uint64_t bal = __builtin_amdgcn_uicmp(all, 0u, 33);  // lanes whose bit is set (33: not equal)
+    lo &= ~((uint32_t)bal ^ all);
+    hi &= ~((uint32_t)(bal >> 32) ^ all);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // One stable pass over one tile: key[] holds the tile's keys wave-striped
 // (key index = wave * 1024 + item * 64 + lane; ~0 past the end, which sorts
 // last); they go to their places in `kout`.
@@ -551,12 +585,7 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-    uint64_t m = ~0ull;
-#pragma unroll
-    for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
-      const uint64_t bal = __ballot((dg >> bt) & 1u);
-      m &= ((dg >> bt) & 1u) ? bal : ~bal;
-    }
+    const uint64_t m = peer_mask(dg);
     const uint32_t before = (uint32_t)__popcll(m & lt_mask);
     const uint32_t old = S.wh[wave][dg];
     if (before == 0) S.wh[wave][dg] = old + (uint32_t)__popcll(m);
