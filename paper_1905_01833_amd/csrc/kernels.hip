@@ -30,6 +30,8 @@
 // boundaries.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "launch.h"
 #include "segstate.h"
 
@@ -481,18 +483,24 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
     ulonglong2 vr[ITEMS];  // all loads first
 #pragma unroll
     for (int r = 0; r < ITEMS; r++) vr[r] = tx + r * NT < n_in ? p[tx + r * NT] : ulonglong2{0ull, 0ull};
+    // the block size's form is uniform over the tile: one branch, and each
+    // side computes the block index one way
+    auto keys_of = [&](auto blk_form) {
 #pragma unroll
-    for (int r = 0; r < ITEMS; r++) {
-      const uint32_t j = tx + r * NT;
-      const bool valid = j < n_in;
-      K k = 0;
-      if (valid) {
-        const Rec x = unpack_rec(vr[r]);
-        k = make_key_t<K>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
-        kout[j] = k;
+      for (int r = 0; r < ITEMS; r++) {
+        const uint32_t j = tx + r * NT;
+        const bool valid = j < n_in;
+        K k = 0;
+        if (valid) {
+          const Rec x = unpack_rec(vr[r]);
+          k = make_key_t<K, decltype(blk_form)::value>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
+          kout[j] = k;
+        }
+        wave_hist_add(h, (uint32_t)(k >> 2) & (RADIX - 1), valid);
       }
-      wave_hist_add(h, (uint32_t)(k >> 2) & (RADIX - 1), valid);
-    }
+    };
+    if ((T.tpb & (T.tpb - 1)) == 0) keys_of(std::integral_constant<int, BLK_POW2>{});
+    else keys_of(std::integral_constant<int, BLK_DIV>{});
     __syncthreads();
     b.thist[(uint64_t)tile * RADIX + tx] = h[tx];
   }
@@ -549,7 +557,6 @@ template <typename K>
 struct ScatterLds {
   K keys[TILE];
   uint32_t wh[NWAVE][RADIX];
-  uint32_t dstart[RADIX];
   uint64_t gbase[RADIX];
   uint32_t scan[NWAVE];
 };
@@ -596,24 +603,25 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
                       b.thist[(uint64_t)tile * RADIX + d];
   __syncthreads();
 
-  // per digit: offsets of the waves, tile count, tile-local start
-  uint32_t cnt = 0;
+  // per digit: tile count, tile-local start, and each wave's first slot
+  // (the digit's start + the counts of the earlier waves)
+  uint32_t cnt = 0, wofs[NWAVE];
 #pragma unroll
   for (int w = 0; w < NWAVE; w++) {
-    const uint32_t c = S.wh[w][d];
-    S.wh[w][d] = cnt;
-    cnt += c;
+    wofs[w] = cnt;
+    cnt += S.wh[w][d];
   }
   uint32_t tot;
-  const uint32_t dstart = block_excl_sum(cnt, S.scan, &tot);
-  S.dstart[d] = dstart;
+  const uint32_t dstart = block_excl_sum(cnt, S.scan, &tot);  // its barriers order the reads above
+#pragma unroll
+  for (int w = 0; w < NWAVE; w++) S.wh[w][d] = dstart + wofs[w];
   S.gbase[d] = gb - dstart;
   __syncthreads();
 
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-    S.keys[S.dstart[dd] + S.wh[wave][dd] + rank[i]] = key[i];
+    S.keys[S.wh[wave][dd] + rank[i]] = key[i];
   }
   __syncthreads();
 #pragma unroll 4
@@ -693,7 +701,7 @@ __global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
       key[i] = ~(K)0;
       if (j < n_in) {
         const Rec x = unpack_rec(p[j]);
-        key[i] = make_key_t<K>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
+        key[i] = make_key_t<K, BLK_POW2>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
       }
     }
     __syncthreads();

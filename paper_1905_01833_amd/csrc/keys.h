@@ -103,13 +103,19 @@ SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
   return L;
 }
 
+// How make_key_t finds a thread's block: a shift (the block size is a power
+// of two, tb = log2 tpb), a division, or whichever of the two fits, chosen
+// per call.  Callers that know the block size's form pick the first two:
+// the third computes both on a device.
+enum : int { BLK_ANY = 0, BLK_POW2 = 1, BLK_DIV = 2 };
+
 // Key of one record (fields must be valid and within the trace's ranges);
 // K is uint64_t for keys of at most 64 bits, u128 otherwise.
-template <typename K>
+template <typename K, int BLK = BLK_ANY>
 SC_HD K make_key_t(const TraceLayout& L, uint64_t unit, uint32_t tid, uint32_t epoch, uint32_t action, uint32_t space,
                    uint32_t tpb) {
-  // a power-of-two block size (tb = log2 tpb) divides by a shift
-  const uint32_t blk = (tpb & (tpb - 1)) == 0 ? tid >> L.tb : tid / tpb;
+  const bool pow2 = BLK == BLK_POW2 || (BLK == BLK_ANY && (tpb & (tpb - 1)) == 0);
+  const uint32_t blk = pow2 ? tid >> L.tb : tid / tpb;
   const uint32_t loc = tid - blk * tpb;
   const K low = ((K)epoch << L.shift_e) | ((K)loc << 2) | (K)(action & 3u);
   if (space == 0) return ((K)(unit - L.gmin) << L.shift_ug) | ((K)blk << L.shift_b) | low;
