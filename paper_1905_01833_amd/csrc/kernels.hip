@@ -3,11 +3,12 @@
 // Pipeline for a call over one or more traces (records of a trace are
 // contiguous; kernels work on 4096-record tiles and a tile never spans two
 // traces):
-//   k_init        reset per-call state
-//   k_stats       per-tile unit ranges, largest tid and epoch, record checks
-//                 (and the digit-0 histograms when digit 0 is tid mod 256)
+//   k_stats       per-call state reset (k_init instead for a call without
+//                 records), per-tile unit ranges, largest tid and epoch,
+//                 record checks (and the digit-0 histograms when digit 0 is
+//                 tid mod 256)
 //   k_layout      per-trace reduction of the tile statistics, key layout
-//   k_keygen      records -> 64-bit keys, tile histograms of radix digit 0;
+//   k_keygen      records -> keys, tile histograms of radix digit 0;
 //                 or k_keygen_scatter: records -> keys in their places after
 //                 radix pass 0 (when k_stats built the digit-0 histograms)
 //   k_upsweep     tile histograms of radix digit p (p >= 1)
@@ -174,14 +175,19 @@ __device__ void block_seg_scan(const uint64_t (&v)[K], uint64_t (&ex)[K], uint64
 
 // --------------------------------------------------------------- k_init
 
+// The call's control words start clear.  k_stats does this in its first
+// workgroup (no kernel before k_layout reads them); k_init serves calls
+// without tiles.
+__device__ __forceinline__ void ctrl_reset(Ctrl* ctrl) {
+  ctrl->max_passes = 0;
+  ctrl->error_flags = 0;
+  ctrl->first_bad = ~0ull;
+  ctrl->total_entries = 0;
+  ctrl->wide_traces = 0;
+}
+
 __global__ void k_init(Ctrl* ctrl) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctrl->max_passes = 0;
-    ctrl->error_flags = 0;
-    ctrl->first_bad = ~0ull;
-    ctrl->total_entries = 0;
-    ctrl->wide_traces = 0;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(ctrl);
 }
 
 // Add one digit per lane of the wave to an LDS histogram.  When every live
@@ -208,8 +214,10 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool val
 template <bool LOOP, bool HIST>
 __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ recs, const TraceDesc* __restrict__ desc,
                                               const TileRef* __restrict__ tiles, uint32_t n_tiles,
-                                              TraceStats* __restrict__ part, uint32_t* __restrict__ thist) {
+                                              TraceStats* __restrict__ part, uint32_t* __restrict__ thist,
+                                              Ctrl* ctrl) {
   __shared__ uint64_t s64[5][NWAVE];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(ctrl);
   __shared__ uint32_t s32[2][NWAVE];
   __shared__ uint32_t h[RADIX];
   const TileWalk tw = tile_walk(n_tiles, gridDim.x, blockIdx.x);
@@ -1259,6 +1267,7 @@ static inline bool grids_ok(const Buffers& b) {
 static inline bool loops(const Buffers& b, uint32_t grid) { return grid / N_XCD < cdiv(b.n_tiles, N_XCD); }
 
 hipError_t launch_init(const Buffers& b, hipStream_t s) {
+  if (b.n_tiles) return hipSuccess;  // k_stats clears the control words
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, s, b.ctrl);
   return hipGetLastError();
 }
@@ -1269,7 +1278,7 @@ hipError_t launch_stats(const Buffers& b, hipStream_t s) {
   auto kern = b.fuse0 ? (lp ? k_stats<true, true> : k_stats<false, true>)
                       : (lp ? k_stats<true, false> : k_stats<false, false>);
   hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, (const ulonglong2*)b.records, b.desc, b.tiles,
-                     b.n_tiles, b.stats_part, b.thist);
+                     b.n_tiles, b.stats_part, b.thist, b.ctrl);
   return hipGetLastError();
 }
 hipError_t launch_layout(const Buffers& b, hipStream_t s) {
