@@ -70,9 +70,9 @@ struct sim_ctx {
   const sim_tuning* force = nullptr;  // sim_autotune's candidate
   std::string err;
 
-  DevBuf records, keys0, keys1, desc, tiles, groups, stats_part, layout, thist, gtot, gbase, agg, tout, cross, cross_flag,
+  DevBuf records, keys0, keys1, meta, stats_part, layout, thist, gtot, gbase, agg, tout, cross, cross_flag,
       group_sum, stage, ctrl, out;
-  void* h_meta = nullptr;  // pinned: TraceDesc[] then TileRef[]
+  void* h_meta = nullptr;  // pinned: TraceDesc[], TileRef[], GroupRef[] (the layout of meta)
   size_t h_meta_cap = 0;
   Ctrl* h_ctrl = nullptr;  // pinned
 
@@ -198,6 +198,13 @@ int group_shift(uint64_t n_tiles, int bias) {
   return gs < 0 ? 0 : (gs > (int)MAX_HGROUP_SHIFT ? (int)MAX_HGROUP_SHIFT : gs);
 }
 
+// The call's tables, one block in host and device memory (one upload):
+// trace descriptors, then tile references, then histogram groups.
+static size_t meta_bytes(uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups) {
+  return (size_t)n_traces * sizeof(TraceDesc) + (size_t)n_tiles * sizeof(TileRef) +
+         (size_t)n_hgroups * sizeof(GroupRef);
+}
+
 // Grow the device buffers of a call of `total` records in `n_traces`
 // traces, `n_tiles` tiles and `n_hgroups` histogram groups.
 hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups,
@@ -210,11 +217,9 @@ hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t 
   } need[] = {
       {&c->keys0, total * key_bytes},
       {&c->keys1, total * key_bytes},
-      {&c->desc, (size_t)n_traces * sizeof(TraceDesc)},
-      {&c->tiles, (size_t)n_tiles * sizeof(TileRef)},
+      {&c->meta, meta_bytes(n_traces, n_tiles, n_hgroups)},
       {&c->stats_part, (size_t)n_tiles * sizeof(TraceStats)},
       {&c->layout, (size_t)n_traces * sizeof(TraceLayout)},
-      {&c->groups, (size_t)n_hgroups * sizeof(GroupRef)},
       {&c->thist, (size_t)n_tiles * RADIX * 4},
       {&c->gtot, (size_t)n_hgroups * RADIX * 4},
       {&c->gbase, (size_t)n_hgroups * RADIX * 8},
@@ -259,15 +264,14 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     const int gs = group_shift(nt, tune.group_shift_bias);
     n_hgroups64 += (nt + (1ull << gs) - 1) >> gs;
   }
-  const size_t meta_bytes = (size_t)n_traces * sizeof(TraceDesc) + (size_t)n_tiles * sizeof(TileRef) +
-                            (size_t)n_hgroups64 * sizeof(GroupRef);
-  if (c->h_meta_cap < meta_bytes) {
+  const size_t h_bytes = meta_bytes(n_traces, n_tiles, n_hgroups64);
+  if (c->h_meta_cap < h_bytes) {
     if (c->h_meta) (void)hipHostFree(c->h_meta);
     c->h_meta = nullptr;
     c->h_meta_cap = 0;
-    e = hipHostMalloc(&c->h_meta, meta_bytes + meta_bytes / 8, hipHostMallocDefault);
+    e = hipHostMalloc(&c->h_meta, h_bytes + h_bytes / 8, hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(c, e, "pinned allocation");
-    c->h_meta_cap = meta_bytes + meta_bytes / 8;
+    c->h_meta_cap = h_bytes + h_bytes / 8;
   }
   TraceDesc* hd = (TraceDesc*)c->h_meta;
   TileRef* ht = (TileRef*)(hd + n_traces);
@@ -294,22 +298,20 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   const uint32_t key_bytes = wide ? 16u : 8u;
   if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups, key_bytes)) != hipSuccess)
     return hip_fail(c, e, "device allocation");
-  if ((e = hipMemcpyAsync(c->desc.p, hd, (size_t)n_traces * sizeof(TraceDesc), hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(c->tiles.p, ht, (size_t)n_tiles * sizeof(TileRef), hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(c->groups.p, hg, (size_t)n_hgroups * sizeof(GroupRef), hipMemcpyHostToDevice, s)))
+  if ((e = hipMemcpyAsync(c->meta.p, c->h_meta, meta_bytes(n_traces, n_tiles, n_hgroups), hipMemcpyHostToDevice, s)))
     return hip_fail(c, e, "table upload");
 
   Buffers b;
   b.records = d_records;
-  b.desc = (const TraceDesc*)c->desc.p;
-  b.tiles = (const TileRef*)c->tiles.p;
+  b.desc = (const TraceDesc*)c->meta.p;
+  b.tiles = (const TileRef*)(b.desc + n_traces);
   b.stats_part = (TraceStats*)c->stats_part.p;
   b.layout = (TraceLayout*)c->layout.p;
   b.keys[0] = c->keys0.p;
   b.keys[1] = c->keys1.p;
   b.wide = wide ? 1u : 0u;
   b.key_bytes = key_bytes;
-  b.groups = (const GroupRef*)c->groups.p;
+  b.groups = (const GroupRef*)(b.tiles + n_tiles);
   b.thist = (uint32_t*)c->thist.p;
   b.gtot = (uint32_t*)c->gtot.p;
   b.gbase = (uint64_t*)c->gbase.p;
@@ -535,7 +537,7 @@ namespace sc {
 
 size_t ctx_device_bytes(const sim_ctx* c) {
   size_t t = 0;
-  for (const DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->groups, &c->stats_part,
+  for (const DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part,
                           &c->layout, &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag,
                           &c->group_sum, &c->stage, &c->ctrl, &c->out})
     t += b->cap;
@@ -546,7 +548,7 @@ size_t ctx_device_bytes(const sim_ctx* c) {
 void ctx_trim(sim_ctx* c) {
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->groups, &c->stats_part, &c->layout,
+  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout,
                     &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->stage, &c->ctrl, &c->out})
     release(*b);
   if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
@@ -601,7 +603,7 @@ void sim_destroy(sim_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->desc, &c->tiles, &c->groups, &c->stats_part, &c->layout,
+  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout,
                     &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum,
                     &c->stage, &c->ctrl, &c->out})
     release(*b);
