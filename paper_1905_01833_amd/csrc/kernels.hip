@@ -567,6 +567,7 @@ struct ScatterLds {
   uint32_t wh[NWAVE][RADIX];
   uint64_t gbase[RADIX];
   uint32_t scan[NWAVE];
+  uint32_t bad;  // some digit's destination range leaves the trace
 };
 
 // Lanes of the wave whose digit equals this lane's: one ballot per digit
@@ -619,11 +620,18 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
     wofs[w] = cnt;
     cnt += S.wh[w][d];
   }
+  if (d == 0) S.bad = 0;
   uint32_t tot;
   const uint32_t dstart = block_excl_sum(cnt, S.scan, &tot);  // its barriers order the reads above
 #pragma unroll
   for (int w = 0; w < NWAVE; w++) S.wh[w][d] = dstart + wofs[w];
   S.gbase[d] = gb - dstart;
+  // bounds, once per digit: the tile's keys of digit d go to [gb, gb + real)
+  // (padding past the trace's end ranks last, in the digit of an all-ones
+  // key: 255, or fewer ones in the top pass of a 64- or 128-bit key)
+  const uint32_t pad_digit = (uint32_t)(~(K)0 >> shift) & (RADIX - 1);
+  const uint32_t real = d == pad_digit ? cnt - (uint32_t)(TILE - n_in) : cnt;
+  if (real && (gb < T.off || gb + real > T.off + T.n)) S.bad = 1;
   __syncthreads();
 
 #pragma unroll
@@ -632,15 +640,16 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
     S.keys[S.wh[wave][dd] + rank[i]] = key[i];
   }
   __syncthreads();
+  if (S.bad) {  // uniform: nothing of the tile is written
+    if (tx == 0) atomicOr(&b.ctrl->error_flags, ERR_INTERNAL_BOUNDS);
+    return;
+  }
 #pragma unroll 4
   for (int r = 0; r < ITEMS; r++) {
     const uint32_t j = tx + r * NT;
     if (j < n_in) {
       const K k = S.keys[j];
-      const uint32_t dd = (uint32_t)(k >> shift) & (RADIX - 1);
-      const uint64_t dst = S.gbase[dd] + j;
-      if (dst - T.off < T.n) kout[dst] = k;
-      else atomicOr(&b.ctrl->error_flags, ERR_INTERNAL_BOUNDS);
+      kout[S.gbase[(uint32_t)(k >> shift) & (RADIX - 1)] + j] = k;
     }
   }
 }
@@ -667,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
-      key[i] = (j < n_in) ? src[j] : ~(K)0;  // padding sorts last (digit 255, after every real key)
+      key[i] = (j < n_in) ? src[j] : ~(K)0;  // padding sorts last (the largest digit, after every real key)
     }
     __syncthreads();
     scatter_tile<K>(b, pass, tile, tx, tr, T, n_in, key, (K*)b.keys[(pass + 1) & 1], S);
