@@ -33,7 +33,7 @@ namespace {
 
 constexpr int N_STAGE = ST_COUNT;
 const char* const kStageNames[N_STAGE] = {"init",      "stats",      "layout",     "keygen",  "upsweep",
-                                          "sort_pass", "scan_tiles", "scan_cross", "scan_out"};
+                                          "sort_pass", "scan_tiles", "scan_cross", "scan_out", "sort_small"};
 constexpr int MAX_EV = 96;
 
 struct DevBuf {
@@ -199,10 +199,11 @@ int group_shift(uint64_t n_tiles, int bias) {
 }
 
 // The call's tables, one block in host and device memory (one upload):
-// trace descriptors, then tile references, then histogram groups.
+// trace descriptors, tile references, histogram groups, then the tiles of
+// one-tile traces (at most one per trace).
 static size_t meta_bytes(uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups) {
   return (size_t)n_traces * sizeof(TraceDesc) + (size_t)n_tiles * sizeof(TileRef) +
-         (size_t)n_hgroups * sizeof(GroupRef);
+         (size_t)n_hgroups * sizeof(GroupRef) + (size_t)n_traces * sizeof(uint32_t);
 }
 
 // Grow the device buffers of a call of `total` records in `n_traces`
@@ -276,7 +277,8 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   TraceDesc* hd = (TraceDesc*)c->h_meta;
   TileRef* ht = (TileRef*)(hd + n_traces);
   GroupRef* hg = (GroupRef*)(ht + n_tiles);
-  uint32_t t0 = 0, g0 = 0, max_group_tiles = 1, max_trace_groups = 1;
+  uint32_t* hs = (uint32_t*)(hg + n_hgroups64);
+  uint32_t t0 = 0, g0 = 0, max_group_tiles = 1, max_trace_groups = 1, n_small = 0;
   for (uint32_t i = 0; i < n_traces; i++) {
     const uint64_t n = offsets[i + 1] - offsets[i];
     const uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
@@ -287,6 +289,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
     for (uint32_t k = 0; k < nt; k++) ht[t0 + k] = TileRef{i, k};
     for (uint32_t k = 0; k < ng; k++) hg[g0 + k] = GroupRef{i, 0};
+    if (nt == 1) hs[n_small++] = t0;
     t0 += nt;
     g0 += ng;
   }
@@ -312,6 +315,8 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.wide = wide ? 1u : 0u;
   b.key_bytes = key_bytes;
   b.groups = (const GroupRef*)(b.tiles + n_tiles);
+  b.small_tiles = (const uint32_t*)(b.groups + n_hgroups);
+  b.n_small = n_small;
   b.thist = (uint32_t*)c->thist.p;
   b.gtot = (uint32_t*)c->gtot.p;
   b.gbase = (uint64_t*)c->gbase.p;
@@ -338,7 +343,12 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.fuse0 = 1;
   for (uint32_t i = 0; i < n_traces; i++)
     if (tpb[i] < 256 || (tpb[i] & (tpb[i] - 1)) != 0) b.fuse0 = 0;
+  // a call of one-tile traces only is sorted in LDS from pass 0 on, with no
+  // global pass at all
+  const bool all_small = n_small == n_traces;
+  if (all_small) b.fuse0 = 0;
   const uint32_t first_pass = b.fuse0 ? 1u : 0u;
+  b.small_from = first_pass;
 
   // ---- the pipeline.  Radix passes: the context remembers how many the
   // previous call needed and launches that many; the scan kernels do
@@ -370,6 +380,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     return e1 != hipSuccess ? e1 : hipStreamSynchronize(s);
   };
   auto sort_passes = [&](uint32_t from, uint32_t to) -> hipError_t {
+    if (all_small) return hipSuccess;  // k_sort_small did every pass
     for (uint32_t p = from; p < to; p++) {
       hipError_t e1 = timed(ST_UPSWEEP, true, [&] { return launch_upsweep(b, p, s); });
       if (e1 == hipSuccess) e1 = timed(ST_SORT, true, [&] { return launch_scatter(b, p, s); });
@@ -386,7 +397,8 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     return e1;
   };
 
-  const uint32_t guess = c->pass_guess < MAX_PASSES ? c->pass_guess : MAX_PASSES;
+  // (a call of one-tile traces has all its passes done before the scan)
+  const uint32_t guess = all_small ? MAX_PASSES : (c->pass_guess < MAX_PASSES ? c->pass_guess : MAX_PASSES);
   int first_scan_ev = 0;  // events of the first round before its scan
   auto first_round = [&]() -> hipError_t {
     hipError_t e1;
@@ -396,6 +408,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       return e1;
     if (b.fuse0 && (e1 = timed(ST_UPSWEEP, true, [&] { return launch_upsweep(b, 0, s); }))) return e1;
     if ((e1 = timed(ST_KEYGEN, true, [&] { return launch_keygen(b, s); })) ||
+        (b.n_small && (e1 = timed(ST_SORT_SMALL, true, [&] { return launch_sort_small(b, s); }))) ||
         (e1 = sort_passes(first_pass, guess)))
       return e1;
     first_scan_ev = nev / 2;
@@ -474,7 +487,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       return hip_fail(c, e, "pipeline");
     ctl = *c->h_ctrl;
   }
-  c->pass_guess = needed;
+  if (!all_small) c->pass_guess = needed;  // an LDS-sorted call tells nothing about global passes
   c->wide_guess = ctl.wide_traces > 0;
   if (ctl.error_flags & ERR_STAGE_OVERFLOW) {
     // a tile holds more racing locations than its slice of the idle key

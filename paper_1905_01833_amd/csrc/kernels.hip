@@ -352,6 +352,12 @@ __global__ __launch_bounds__(NT) void k_layout(const TraceDesc* __restrict__ des
     atomicMax(&ctrl->max_passes, L.npasses);
 }
 
+// A trace of one tile is sorted whole in one workgroup's LDS (k_sort_small)
+// from pass b.small_from on; the global pass kernels leave it alone.
+__device__ __forceinline__ bool sorted_in_lds(const Buffers& b, const TraceDesc& T, uint32_t pass) {
+  return T.ntiles == 1 && pass >= b.small_from;
+}
+
 // ----------------------------------------------------- radix offsets
 //
 // Each tile stores the digit histogram of the current pass in thist[tile].
@@ -444,7 +450,7 @@ __global__ __launch_bounds__(RADIX * PARTS) void k_group_offsets(Buffers b, uint
   const uint32_t g = blockIdx.x;
   const GroupRef gr = b.groups[g];
   const TraceDesc T = b.desc[gr.trace];
-  if (pass >= b.layout[gr.trace].npasses) return;
+  if (pass >= b.layout[gr.trace].npasses || sorted_in_lds(b, T, pass)) return;
   const uint32_t g_first = (g - T.group0) << T.gshift;
   const uint32_t g_n = min(1u << T.gshift, T.ntiles - g_first);
   uint32_t* rows = b.thist + (uint64_t)(T.tile0 + g_first) * RADIX;
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(RADIX * PARTS) void k_trace_offsets(Buffers b, uint
   __shared__ uint32_t s_sc[PARTS * RADIX / 64];
   const uint32_t t = blockIdx.x;
   const TraceDesc T = b.desc[t];
-  if (pass >= b.layout[t].npasses) return;  // uniform over the workgroup
+  if (pass >= b.layout[t].npasses || sorted_in_lds(b, T, pass)) return;  // uniform over the workgroup
   // group rows of the trace -> digit bases (from the column totals) and the
   // absolute base of every group (digit base + earlier groups)
   (void)column_prefix<PARTS, true>(b.gtot + (uint64_t)T.group0 * RADIX, b.gbase + (uint64_t)T.group0 * RADIX,
@@ -528,7 +534,7 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
     const TileRef tr = b.tiles[tile];
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
-    if (pass >= L.npasses) continue;
+    if (pass >= L.npasses || sorted_in_lds(b, T, pass)) continue;
     h[tx] = 0;
     __syncthreads();
     const uint32_t shift = 2 + RADIX_BITS * pass;
@@ -586,6 +592,27 @@ __device__ __forceinline__ uint64_t peer_mask(uint32_t dg) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Stable rank of every key of the wave among the wave's keys of its digit
+// (the digit at `shift`), items in order: the lowest lane of each group of
+// equal digits advances the wave's counter wh[wave][digit] (zero on entry)
+// by the group's size.  On return wh[wave][d] counts the wave's keys of
+// digit d.
+template <typename K>
+__device__ __forceinline__ void wave_rank(const K (&key)[ITEMS], uint32_t shift, uint32_t tx,
+                                          uint32_t (*wh)[RADIX], uint32_t (&rank)[ITEMS]) {
+  const uint32_t lane = tx & 63u, wave = tx >> 6;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+    const uint64_t m = peer_mask(dg);
+    const uint32_t before = (uint32_t)__popcll(m & lt_mask);
+    const uint32_t old = wh[wave][dg];
+    if (before == 0) wh[wave][dg] = old + (uint32_t)__popcll(m);
+    rank[i] = old + before;
+  }
+}
+
 // One stable pass over one tile: key[] holds the tile's keys wave-striped
 // (key index = wave * 1024 + item * 64 + lane; ~0 past the end, which sorts
 // last); they go to their places in `kout`.
@@ -593,20 +620,11 @@ template <typename K>
 __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, uint32_t tile, uint32_t tx,
                                              const TileRef& tr, const TraceDesc& T, uint32_t n_in,
                                              K (&key)[ITEMS], K* kout, ScatterLds<K>& S) {
-  const uint32_t lane = tx & 63u, wave = tx >> 6;
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  const uint32_t wave = tx >> 6;
   const uint32_t d = tx;
   const uint32_t shift = 2 + RADIX_BITS * pass;
   uint32_t rank[ITEMS];
-#pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-    const uint64_t m = peer_mask(dg);
-    const uint32_t before = (uint32_t)__popcll(m & lt_mask);
-    const uint32_t old = S.wh[wave][dg];
-    if (before == 0) S.wh[wave][dg] = old + (uint32_t)__popcll(m);
-    rank[i] = old + before;
-  }
+  wave_rank(key, shift, tx, S.wh, rank);
   // destination base of each digit: group base + offset within the group
   const uint64_t gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] +
                       b.thist[(uint64_t)tile * RADIX + d];
@@ -665,7 +683,7 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
     const TileRef tr = b.tiles[tile];
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
-    if (pass >= L.npasses) continue;  // uniform over the workgroup
+    if (pass >= L.npasses || sorted_in_lds(b, T, pass)) continue;  // uniform over the workgroup
     const uint32_t lane = tx & 63u, wave = tx >> 6;
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
@@ -723,6 +741,67 @@ __global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
     }
     __syncthreads();
     scatter_tile<K>(b, 0, tile, tx, tr, T, n_in, key, (K*)b.keys[1], S);
+  }
+}
+
+// ------------------------------------------------------- k_sort_small
+// A trace of one tile: radix passes small_from .. npasses - 1 all in LDS,
+// one workgroup per such trace, with the same stable wave ranking as
+// k_scatter (so the order equals that of the global passes); the sorted
+// keys go to the buffer the scan reads.  Padding past the trace's end holds
+// all-ones keys, which rank after every real key in every pass.
+
+template <typename K>
+__global__ __launch_bounds__(NT) void k_sort_small(Buffers b) {
+  __shared__ ScatterLds<K> S;
+  const uint32_t tx = threadIdx.x, lane = tx & 63u, wave = tx >> 6, d = tx;
+  const uint32_t tile = b.small_tiles[blockIdx.x];
+  const TileRef tr = b.tiles[tile];
+  const TraceDesc T = b.desc[tr.trace];
+  const TraceLayout L = b.layout[tr.trace];
+  if (L.npasses <= b.small_from || T.ntiles != 1) return;  // uniform over the workgroup
+  const uint32_t n_in = (uint32_t)T.n;
+  const K* src = (const K*)b.keys[b.small_from & 1] + T.off;
+  K key[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+    key[i] = (j < n_in) ? src[j] : ~(K)0;
+  }
+  for (uint32_t pass = b.small_from; pass < L.npasses; pass++) {
+    const uint32_t shift = 2 + RADIX_BITS * pass;
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
+    __syncthreads();
+    uint32_t rank[ITEMS];
+    wave_rank(key, shift, tx, S.wh, rank);
+    __syncthreads();
+    uint32_t cnt = 0, wofs[NWAVE];
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) {
+      wofs[w] = cnt;
+      cnt += S.wh[w][d];
+    }
+    uint32_t tot;
+    const uint32_t dstart = block_excl_sum(cnt, S.scan, &tot);  // its barriers order the reads above
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) S.wh[w][d] = dstart + wofs[w];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+      S.keys[S.wh[wave][dd] + rank[i]] = key[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) key[i] = S.keys[wave * (ITEMS * 64) + i * 64 + lane];
+    __syncthreads();  // S.wh and S.keys are reused by the next pass
+  }
+  K* dst = (K*)b.keys[L.npasses & 1u] + T.off;  // the real keys are the first n_in
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+    if (j < n_in) dst[j] = key[i];
   }
 }
 
@@ -1343,6 +1422,11 @@ hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s) {
   auto kern = b.wide ? (lp ? k_scatter<u128, true> : k_scatter<u128, false>)
                      : (lp ? k_scatter<uint64_t, true> : k_scatter<uint64_t, false>);
   hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
+  return hipGetLastError();
+}
+hipError_t launch_sort_small(const Buffers& b, hipStream_t s) {
+  if (!b.n_small) return hipSuccess;
+  hipLaunchKernelGGL(b.wide ? k_sort_small<u128> : k_sort_small<uint64_t>, dim3(b.n_small), dim3(NT), 0, s, b);
   return hipGetLastError();
 }
 hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t s) {

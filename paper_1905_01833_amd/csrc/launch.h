@@ -94,11 +94,16 @@ struct Buffers {            // device pointers of one call
   uint32_t fuse0;           // 1: digit 0 is tid mod 256 in every trace; k_stats builds its histograms
                             // and k_keygen_scatter does radix pass 0 (see kernels.hip)
   uint32_t wide;            // 1: two-word keys for every trace of the call
+  const uint32_t* small_tiles; // [n_small] the tiles of one-tile traces (sorted whole in LDS)
+  uint32_t n_small;
+  uint32_t small_from;      // first radix pass done in LDS for those traces (pass 0 is
+                            // k_keygen_scatter's when fuse0)
   uint32_t key_bytes;       // 8 or 16
 };
 
 // Kernel stages, in launch order.
-enum Stage { ST_INIT = 0, ST_STATS, ST_LAYOUT, ST_KEYGEN, ST_UPSWEEP, ST_SORT, ST_SCAN, ST_CROSS, ST_OUT, ST_COUNT };
+enum Stage { ST_INIT = 0, ST_STATS, ST_LAYOUT, ST_KEYGEN, ST_UPSWEEP, ST_SORT, ST_SCAN, ST_CROSS, ST_OUT,
+             ST_SORT_SMALL, ST_COUNT };
 
 hipError_t launch_init(const Buffers& b, hipStream_t s);
 hipError_t launch_stats(const Buffers& b, hipStream_t s);
@@ -106,6 +111,7 @@ hipError_t launch_layout(const Buffers& b, hipStream_t s);
 hipError_t launch_keygen(const Buffers& b, hipStream_t s);  // with fuse0: keys + radix pass 0
 hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s);  // histograms and offsets
 hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s);
+hipError_t launch_sort_small(const Buffers& b, hipStream_t s);
 hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t s);
 hipError_t launch_scan_cross(const Buffers& b, uint32_t passes_done, hipStream_t s);
 hipError_t launch_scan_out(const Buffers& b, uint32_t passes_done, hipStream_t s);
