@@ -199,8 +199,8 @@ int group_shift(uint64_t n_tiles, int bias) {
 }
 
 // The call's tables, one block in host and device memory (one upload):
-// trace descriptors, tile references, histogram groups, then the tiles of
-// one-tile traces (at most one per trace).
+// trace descriptors, tile references, histogram groups, then the traces
+// sorted whole in LDS (at most one entry per trace).
 static size_t meta_bytes(uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups) {
   return (size_t)n_traces * sizeof(TraceDesc) + (size_t)n_tiles * sizeof(TileRef) +
          (size_t)n_hgroups * sizeof(GroupRef) + (size_t)n_traces * sizeof(uint32_t);
@@ -278,7 +278,10 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   TileRef* ht = (TileRef*)(hd + n_traces);
   GroupRef* hg = (GroupRef*)(ht + n_tiles);
   uint32_t* hs = (uint32_t*)(hg + n_hgroups64);
-  uint32_t t0 = 0, g0 = 0, max_group_tiles = 1, max_trace_groups = 1, n_small = 0;
+  // traces sorted whole in LDS: one tile, or up to four with one-word keys
+  const bool wide = c->wide_guess;
+  const uint32_t small_max_tiles = wide ? 1u : 4u;
+  uint32_t t0 = 0, g0 = 0, max_group_tiles = 1, max_trace_groups = 1, n_small1 = 0, n_small4 = 0;
   for (uint32_t i = 0; i < n_traces; i++) {
     const uint64_t n = offsets[i + 1] - offsets[i];
     const uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
@@ -289,15 +292,16 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
     for (uint32_t k = 0; k < nt; k++) ht[t0 + k] = TileRef{i, k};
     for (uint32_t k = 0; k < ng; k++) hg[g0 + k] = GroupRef{i, 0};
-    if (nt == 1) hs[n_small++] = t0;
+    if (nt == 1) hs[n_small1++] = i;
+    else if (nt >= 2 && nt <= small_max_tiles) hs[n_traces - 1 - n_small4++] = i;  // from the back
     t0 += nt;
     g0 += ng;
   }
   const uint32_t n_hgroups = g0;
   const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
+  if (n_small4) memmove(hs + n_small1, hs + n_traces - n_small4, (size_t)n_small4 * sizeof(uint32_t));
 
   // ---- device buffers
-  const bool wide = c->wide_guess;
   const uint32_t key_bytes = wide ? 16u : 8u;
   if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups, key_bytes)) != hipSuccess)
     return hip_fail(c, e, "device allocation");
@@ -315,8 +319,10 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.wide = wide ? 1u : 0u;
   b.key_bytes = key_bytes;
   b.groups = (const GroupRef*)(b.tiles + n_tiles);
-  b.small_tiles = (const uint32_t*)(b.groups + n_hgroups);
-  b.n_small = n_small;
+  b.small_traces = (const uint32_t*)(b.groups + n_hgroups);
+  b.n_small1 = n_small1;
+  b.n_small4 = n_small4;
+  b.small_max_tiles = small_max_tiles;
   b.thist = (uint32_t*)c->thist.p;
   b.gtot = (uint32_t*)c->gtot.p;
   b.gbase = (uint64_t*)c->gbase.p;
@@ -345,7 +351,9 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     if (tpb[i] < 256 || (tpb[i] & (tpb[i] - 1)) != 0) b.fuse0 = 0;
   // a call of one-tile traces only is sorted in LDS from pass 0 on, with no
   // global pass at all
-  const bool all_small = n_small == n_traces;
+  uint32_t n_empty = 0;
+  for (uint32_t i = 0; i < n_traces; i++) n_empty += offsets[i + 1] == offsets[i] ? 1u : 0u;
+  const bool all_small = n_small1 + n_small4 + n_empty == n_traces;
   if (all_small) b.fuse0 = 0;
   const uint32_t first_pass = b.fuse0 ? 1u : 0u;
   b.small_from = first_pass;
@@ -408,7 +416,8 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       return e1;
     if (b.fuse0 && (e1 = timed(ST_UPSWEEP, true, [&] { return launch_upsweep(b, 0, s); }))) return e1;
     if ((e1 = timed(ST_KEYGEN, true, [&] { return launch_keygen(b, s); })) ||
-        (b.n_small && (e1 = timed(ST_SORT_SMALL, true, [&] { return launch_sort_small(b, s); }))) ||
+        (b.n_small1 + b.n_small4 &&
+         (e1 = timed(ST_SORT_SMALL, true, [&] { return launch_sort_small(b, s); }))) ||
         (e1 = sort_passes(first_pass, guess)))
       return e1;
     first_scan_ev = nev / 2;

@@ -352,10 +352,11 @@ __global__ __launch_bounds__(NT) void k_layout(const TraceDesc* __restrict__ des
     atomicMax(&ctrl->max_passes, L.npasses);
 }
 
-// A trace of one tile is sorted whole in one workgroup's LDS (k_sort_small)
-// from pass b.small_from on; the global pass kernels leave it alone.
+// A trace of at most b.small_max_tiles tiles is sorted whole in one
+// workgroup's LDS (k_sort_small) from pass b.small_from on; the global pass
+// kernels leave it alone.
 __device__ __forceinline__ bool sorted_in_lds(const Buffers& b, const TraceDesc& T, uint32_t pass) {
-  return T.ntiles == 1 && pass >= b.small_from;
+  return T.ntiles <= b.small_max_tiles && pass >= b.small_from;
 }
 
 // ----------------------------------------------------- radix offsets
@@ -745,21 +746,29 @@ __global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
 }
 
 // ------------------------------------------------------- k_sort_small
-// A trace of one tile: radix passes small_from .. npasses - 1 all in LDS,
-// one workgroup per such trace, with the same stable wave ranking as
-// k_scatter (so the order equals that of the global passes); the sorted
-// keys go to the buffer the scan reads.  Padding past the trace's end holds
-// all-ones keys, which rank after every real key in every pass.
+// A short trace (one tile, or up to four with one-word keys): radix passes
+// small_from .. npasses - 1 all in LDS, one workgroup of NTH threads (16
+// keys each) per trace, with the same stable wave ranking as k_scatter (so
+// the order equals that of the global passes); the sorted keys go to the
+// buffer the scan reads.  Padding past the trace's end holds all-ones keys,
+// which rank after every real key in every pass.
 
-template <typename K>
-__global__ __launch_bounds__(NT) void k_sort_small(Buffers b) {
-  __shared__ ScatterLds<K> S;
-  const uint32_t tx = threadIdx.x, lane = tx & 63u, wave = tx >> 6, d = tx;
-  const uint32_t tile = b.small_tiles[blockIdx.x];
-  const TileRef tr = b.tiles[tile];
-  const TraceDesc T = b.desc[tr.trace];
-  const TraceLayout L = b.layout[tr.trace];
-  if (L.npasses <= b.small_from || T.ntiles != 1) return;  // uniform over the workgroup
+template <typename K, int NTH>
+struct SortLds {
+  K keys[NTH * ITEMS];
+  uint32_t wh[NTH / 64][RADIX];
+  uint32_t scan[NTH / 64];
+};
+
+template <typename K, int NTH>
+__global__ __launch_bounds__(NTH) void k_sort_small(Buffers b, const uint32_t* __restrict__ traces) {
+  constexpr int NW = NTH / 64, CAP = NTH * ITEMS;
+  __shared__ SortLds<K, NTH> S;
+  const uint32_t tx = threadIdx.x, lane = tx & 63u, wave = tx >> 6;
+  const uint32_t t = traces[blockIdx.x];
+  const TraceDesc T = b.desc[t];
+  const TraceLayout L = b.layout[t];
+  if (L.npasses <= b.small_from || T.n > (uint64_t)CAP) return;  // uniform over the workgroup
   const uint32_t n_in = (uint32_t)T.n;
   const K* src = (const K*)b.keys[b.small_from & 1] + T.off;
   K key[ITEMS];
@@ -770,22 +779,27 @@ __global__ __launch_bounds__(NT) void k_sort_small(Buffers b) {
   }
   for (uint32_t pass = b.small_from; pass < L.npasses; pass++) {
     const uint32_t shift = 2 + RADIX_BITS * pass;
-#pragma unroll
-    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
+    for (uint32_t k = tx; k < (uint32_t)(NW * RADIX); k += NTH) (&S.wh[0][0])[k] = 0;
     __syncthreads();
     uint32_t rank[ITEMS];
     wave_rank(key, shift, tx, S.wh, rank);
     __syncthreads();
-    uint32_t cnt = 0, wofs[NWAVE];
-#pragma unroll
-    for (int w = 0; w < NWAVE; w++) {
-      wofs[w] = cnt;
-      cnt += S.wh[w][d];
+    // thread d < 256: digit d's count, then each wave's first slot (the
+    // digit's start + the counts of the earlier waves); only thread d
+    // touches column d of S.wh
+    uint32_t cnt = 0;
+    if (tx < RADIX) {
+      for (int w = 0; w < NW; w++) {
+        const uint32_t c = S.wh[w][tx];
+        S.wh[w][tx] = cnt;
+        cnt += c;
+      }
     }
     uint32_t tot;
-    const uint32_t dstart = block_excl_sum(cnt, S.scan, &tot);  // its barriers order the reads above
-#pragma unroll
-    for (int w = 0; w < NWAVE; w++) S.wh[w][d] = dstart + wofs[w];
+    const uint32_t dstart = block_excl_sum_n<NW>(cnt, S.scan, &tot);
+    if (tx < RADIX) {
+      for (int w = 0; w < NW; w++) S.wh[w][tx] += dstart;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
@@ -1425,9 +1439,19 @@ hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_sort_small(const Buffers& b, hipStream_t s) {
-  if (!b.n_small) return hipSuccess;
-  hipLaunchKernelGGL(b.wide ? k_sort_small<u128> : k_sort_small<uint64_t>, dim3(b.n_small), dim3(NT), 0, s, b);
-  return hipGetLastError();
+  if (b.n_small1) {
+    auto kern = b.wide ? k_sort_small<u128, NT> : k_sort_small<uint64_t, NT>;
+    hipLaunchKernelGGL(kern, dim3(b.n_small1), dim3(NT), 0, s, b, b.small_traces);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.n_small4) {  // one-word keys only (the two-word LDS image would not fit)
+    if (b.wide) return hipErrorInvalidValue;
+    auto kern = k_sort_small<uint64_t, 4 * NT>;
+    hipLaunchKernelGGL(kern, dim3(b.n_small4), dim3(4 * NT), 0, s, b, b.small_traces + b.n_small1);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;

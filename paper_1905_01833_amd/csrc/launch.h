@@ -94,8 +94,10 @@ struct Buffers {            // device pointers of one call
   uint32_t fuse0;           // 1: digit 0 is tid mod 256 in every trace; k_stats builds its histograms
                             // and k_keygen_scatter does radix pass 0 (see kernels.hip)
   uint32_t wide;            // 1: two-word keys for every trace of the call
-  const uint32_t* small_tiles; // [n_small] the tiles of one-tile traces (sorted whole in LDS)
-  uint32_t n_small;
+  const uint32_t* small_traces; // traces sorted whole in LDS: n_small1 of one tile, then
+                            // n_small4 of two to four tiles (one-word keys only)
+  uint32_t n_small1, n_small4;
+  uint32_t small_max_tiles; // 4 with one-word keys, 1 with two-word keys
   uint32_t small_from;      // first radix pass done in LDS for those traces (pass 0 is
                             // k_keygen_scatter's when fuse0)
   uint32_t key_bytes;       // 8 or 16

@@ -173,17 +173,18 @@ def test_batched_mixed_sizes(ctx):
             assert hit.any()
 
 
-def test_one_tile_traces_sorted_in_lds():
-    """Traces of at most one tile are sorted whole in one workgroup's LDS:
-    alone (no global pass at all), mixed with multi-tile traces (after the
-    fused pass 0 when every block size is a power of two >= 256, from pass
-    0 otherwise), with key widths from 2 to 8 radix passes, sizes 1..4096,
-    and on a context whose remembered pass count comes from other calls."""
+def test_short_traces_sorted_in_lds():
+    """Traces of up to four tiles (one-word keys) are sorted whole in one
+    workgroup's LDS: alone (no global pass at all), mixed with longer traces
+    (after the fused pass 0 when every block size is a power of two >= 256,
+    from pass 0 otherwise), with key widths from 2 to 8 radix passes, sizes
+    1..16384, and on a context whose remembered pass count comes from other
+    calls."""
     import paper_1905_01833_amd as pkg
 
     rng = np.random.default_rng(77)
 
-    def one_tile(n, unit_bits, tpb, blocks):
+    def gen(n, unit_bits, tpb, blocks):
         r = np.zeros(n, dtype=RECORD_DTYPE)
         r["unit"] = rng.integers(0, 1 << unit_bits, n, dtype=np.uint64)
         r["unit"][: n // 2] = rng.integers(0, 8, n // 2)  # collisions
@@ -193,18 +194,19 @@ def test_one_tile_traces_sorted_in_lds():
         r["space"] = rng.integers(0, 2, n)
         return r
 
-    sizes = [1, 2, 100, 1000, 4095, 4096]
+    sizes = [1, 2, 100, 1000, 4095, 4096, 4097, 8192, 12289, 16384]
     fresh = pkg.Context(0)
     try:
         for tpb, blocks in ((256, 8), (4, 3)):
-            small = [one_tile(n, ub, tpb, blocks) for n in sizes for ub in (3, 20, 33)]
+            small = [gen(n, ub, tpb, blocks) for n in sizes for ub in (3, 20, 33)]
             recs, off = batch_of(small)
-            assert_parity(fresh, recs, off, tpb, name=f"{len(small)} one-tile traces, tpb {tpb}")
-            big = one_tile(3 * 4096 + 17, 33, tpb, blocks)
+            assert_parity(fresh, recs, off, tpb, name=f"{len(small)} short traces, tpb {tpb}")
+            big = gen(4 * 4096 + 17, 33, tpb, blocks)
             recs, off = batch_of(small[:5] + [big] + small[5:])
-            assert_parity(fresh, recs, off, tpb, name=f"one-tile traces around a 4-tile trace, tpb {tpb}")
+            assert_parity(fresh, recs, off, tpb, name=f"short traces around a 5-tile trace, tpb {tpb}")
             assert_parity(fresh, small[4], None, tpb, name=f"one one-tile trace after a mixed call, tpb {tpb}")
-            assert_parity(fresh, big, None, tpb, name=f"the 4-tile trace alone, tpb {tpb}")
+            assert_parity(fresh, small[-1], None, tpb, name=f"one 4-tile trace, tpb {tpb}")
+            assert_parity(fresh, big, None, tpb, name=f"the 5-tile trace alone, tpb {tpb}")
     finally:
         fresh.close()
 
