@@ -730,15 +730,18 @@ __global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
     const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
 #pragma unroll
     for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
+    ulonglong2 vr[ITEMS];  // all loads first: sixteen records in flight per thread
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+      vr[i] = j < n_in ? p[j] : ulonglong2{0ull, 0ull};
+    }
     K key[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
-      key[i] = ~(K)0;
-      if (j < n_in) {
-        const Rec x = unpack_rec(p[j]);
-        key[i] = make_key_t<K, BLK_POW2>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
-      }
+      const Rec x = unpack_rec(vr[i]);
+      key[i] = j < n_in ? make_key_t<K, BLK_POW2>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb) : ~(K)0;
     }
     __syncthreads();
     scatter_tile<K>(b, 0, tile, tx, tr, T, n_in, key, (K*)b.keys[1], S);
