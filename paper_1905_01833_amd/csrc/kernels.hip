@@ -197,8 +197,8 @@ __global__ void k_init(Ctrl* ctrl) {
 __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool valid) {
   const uint64_t live = __ballot(valid);
   if (!live) return;
-  const uint32_t lead = (uint32_t)__ffsll((unsigned long long)live) - 1u;
-  const uint32_t d0 = __shfl(dg, (int)lead, 64);
+  const uint32_t lead = (uint32_t)__ffsll((unsigned long long)live) - 1u;  // uniform
+  const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)dg, (int)lead);
   if (__ballot(valid && dg == d0) == live) {
     if (__lane_id() == lead) atomicAdd(&h[d0], (uint32_t)__popcll(live));
   } else if (valid) {
