@@ -290,7 +290,12 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     max_group_tiles = std::max(max_group_tiles, std::min(nt, 1u << gs));
     max_trace_groups = std::max(max_trace_groups, ng);
     hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
-    for (uint32_t k = 0; k < nt; k++) ht[t0 + k] = TileRef{i, k};
+    const uint32_t short_flag = nt <= small_max_tiles ? TILE_SHORT : 0u;
+    for (uint32_t k = 0; k < nt; k++) {
+      const uint64_t first = offsets[i] + (uint64_t)k * TILE;
+      const uint32_t n_in = (uint32_t)std::min<uint64_t>(TILE, offsets[i + 1] - first);
+      ht[t0 + k] = TileRef{i, k, (uint32_t)first, n_in | short_flag};
+    }
     for (uint32_t k = 0; k < ng; k++) hg[g0 + k] = GroupRef{i, 0};
     if (nt == 1) hs[n_small1++] = i;
     else if (nt >= 2 && nt <= small_max_tiles) hs[n_traces - 1 - n_small4++] = i;  // from the back

@@ -212,7 +212,7 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool val
 // HIST: also the tile histogram of radix digit 0 for calls whose digit 0 is
 // tid mod 256 (see k_keygen_scatter).
 template <bool LOOP, bool HIST>
-__global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ recs, const TraceDesc* __restrict__ desc,
+__global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ recs,
                                               const TileRef* __restrict__ tiles, uint32_t n_tiles,
                                               TraceStats* __restrict__ part, uint32_t* __restrict__ thist,
                                               Ctrl* ctrl) {
@@ -226,10 +226,9 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
     uint32_t tx = threadIdx.x;
     if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
     const TileRef tr = tiles[tile];
-    const TraceDesc T = desc[tr.trace];
     const uint64_t start = (uint64_t)tr.local * TILE;
-    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const ulonglong2* p = recs + T.off + start;
+    const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
+    const ulonglong2* p = recs + tr.first;
     uint64_t gmin = ~0ull, gmax = 0, smin = ~0ull, smax = 0, bad = ~0ull;
     uint32_t mt = 0, me = 0;
     if (HIST) {
@@ -532,22 +531,22 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
     __syncthreads();  // LDS of the previous tile is free
     uint32_t tx = threadIdx.x;
     if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    // the tile reference locates the keys: their loads go out together
+    // with the layout's, one round trip after it
     const TileRef tr = b.tiles[tile];
-    const TraceDesc T = b.desc[tr.trace];
-    const TraceLayout L = b.layout[tr.trace];
-    if (pass >= L.npasses || sorted_in_lds(b, T, pass)) continue;
-    h[tx] = 0;
-    __syncthreads();
-    const uint32_t shift = 2 + RADIX_BITS * pass;
-    const uint64_t start = (uint64_t)tr.local * TILE;
-    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const K* src = (const K*)b.keys[pass & 1] + T.off + start;
+    const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
+    const K* src = (const K*)b.keys[pass & 1] + tr.first;
     K k[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; r++) {
       const uint32_t j = tx + r * NT;
       k[r] = j < n_in ? src[j] : (K)0;
     }
+    const uint32_t npasses = b.layout[tr.trace].npasses;
+    if (pass >= npasses || ((tr.n_flags & TILE_SHORT) && pass >= b.small_from)) continue;
+    h[tx] = 0;
+    __syncthreads();
+    const uint32_t shift = 2 + RADIX_BITS * pass;
 #pragma unroll
     for (int r = 0; r < ITEMS; r++)
       wave_hist_add(h, (uint32_t)(k[r] >> shift) & (RADIX - 1), tx + r * NT < n_in);
@@ -681,22 +680,23 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
     __syncthreads();  // LDS of the previous tile is free
     uint32_t tx = threadIdx.x;
     if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    // the tile reference locates the keys: their loads go out together
+    // with the trace's descriptor and layout, one round trip after it
     const TileRef tr = b.tiles[tile];
-    const TraceDesc T = b.desc[tr.trace];
-    const TraceLayout L = b.layout[tr.trace];
-    if (pass >= L.npasses || sorted_in_lds(b, T, pass)) continue;  // uniform over the workgroup
     const uint32_t lane = tx & 63u, wave = tx >> 6;
-    const uint64_t start = (uint64_t)tr.local * TILE;
-    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const K* src = (const K*)b.keys[pass & 1] + T.off + start;
-#pragma unroll
-    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
+    const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
+    const K* src = (const K*)b.keys[pass & 1] + tr.first;
     K key[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
       key[i] = (j < n_in) ? src[j] : ~(K)0;  // padding sorts last (the largest digit, after every real key)
     }
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    if (pass >= L.npasses || sorted_in_lds(b, T, pass)) continue;  // uniform over the workgroup
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
     __syncthreads();
     scatter_tile<K>(b, pass, tile, tx, tr, T, n_in, key, (K*)b.keys[(pass + 1) & 1], S);
   }
@@ -720,22 +720,23 @@ __global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
     __syncthreads();  // LDS of the previous tile is free
     uint32_t tx = threadIdx.x;
     if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    // the tile reference locates the records: their loads go out together
+    // with the trace's descriptor and layout, one round trip after it
     const TileRef tr = b.tiles[tile];
-    const TraceDesc T = b.desc[tr.trace];
-    const TraceLayout L = b.layout[tr.trace];
-    if (L.npasses == 0) continue;  // uniform over the workgroup
     const uint32_t lane = tx & 63u, wave = tx >> 6;
-    const uint64_t start = (uint64_t)tr.local * TILE;
-    const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
-#pragma unroll
-    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
+    const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
+    const ulonglong2* p = (const ulonglong2*)b.records + tr.first;
     ulonglong2 vr[ITEMS];  // all loads first: sixteen records in flight per thread
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
       const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
       vr[i] = j < n_in ? p[j] : ulonglong2{0ull, 0ull};
     }
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    if (L.npasses == 0) continue;  // uniform over the workgroup
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
     K key[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
@@ -1382,7 +1383,7 @@ hipError_t launch_stats(const Buffers& b, hipStream_t s) {
   const bool lp = loops(b, b.grid_stream);
   auto kern = b.fuse0 ? (lp ? k_stats<true, true> : k_stats<false, true>)
                       : (lp ? k_stats<true, false> : k_stats<false, false>);
-  hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, (const ulonglong2*)b.records, b.desc, b.tiles,
+  hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, (const ulonglong2*)b.records, b.tiles,
                      b.n_tiles, b.stats_part, b.thist, b.ctrl);
   return hipGetLastError();
 }

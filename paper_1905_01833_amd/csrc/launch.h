@@ -31,10 +31,13 @@ struct TraceDesc {   // one trace of a call (host-filled)
   uint32_t pad[3];
 };
 
-struct TileRef {     // tile -> (trace, tile within trace)
+struct TileRef {     // tile -> (trace, tile within trace), and where its records are
   uint32_t trace;
   uint32_t local;
+  uint32_t first;    // call index of the tile's first record (a call holds < 2^32 records)
+  uint32_t n_flags;  // records in the tile (bits 0..30); bit 31: the trace is sorted whole in LDS
 };
+constexpr uint32_t TILE_SHORT = 1u << 31;
 
 struct GroupRef {    // histogram group -> trace
   uint32_t trace;
