@@ -61,24 +61,6 @@ __device__ __forceinline__ Rec unpack_rec(ulonglong2 v) {
   return r;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_min(T v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    T o = __shfl_xor(v, d, 64);
-    v = o < v ? o : v;
-  }
-  return v;
-}
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    T o = __shfl_xor(v, d, 64);
-    v = o > v ? o : v;
-  }
-  return v;
-}
 
 // Cross-lane moves of the wave's data-parallel primitives (DPP): the value
 // of another lane, or 0 where that lane is outside the pattern or the row
@@ -89,13 +71,44 @@ enum : int {
   DPP_ROW_BCAST15 = 0x142, // last lane of each row to the next row
   DPP_ROW_BCAST31 = 0x143  // lane 31 to rows 2 and 3
 };
+// (`old` instead of 0 where the source lane is outside the pattern.)
 template <int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ uint32_t dpp(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+__device__ __forceinline__ uint32_t dpp(uint32_t v, uint32_t old = 0u) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xf, false);
 }
 template <int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ uint64_t dpp(uint64_t v) {
-  return ((uint64_t)dpp<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) | dpp<CTRL, ROWS>((uint32_t)v);
+__device__ __forceinline__ uint64_t dpp(uint64_t v, uint64_t old = 0ull) {
+  return ((uint64_t)dpp<CTRL, ROWS>((uint32_t)(v >> 32), (uint32_t)(old >> 32)) << 32) |
+         dpp<CTRL, ROWS>((uint32_t)v, (uint32_t)old);
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+__device__ __forceinline__ uint64_t readlane(uint64_t v, int lane) {
+  return ((uint64_t)readlane((uint32_t)(v >> 32), lane) << 32) | readlane((uint32_t)v, lane);
+}
+
+// Reduction over the 64 lanes with an associative, commutative operator
+// whose identity is `id`: the scan pattern below ends with the total in
+// lane 63, which every lane then reads.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, T id, Op op) {
+  v = op(dpp<DPP_ROW_SHR1>(v, id), v);
+  v = op(dpp<DPP_ROW_SHR2>(v, id), v);
+  v = op(dpp<DPP_ROW_SHR4>(v, id), v);
+  v = op(dpp<DPP_ROW_SHR8>(v, id), v);
+  v = op(dpp<DPP_ROW_BCAST15, 0xa>(v, id), v);
+  v = op(dpp<DPP_ROW_BCAST31, 0xc>(v, id), v);
+  return readlane(v, 63);
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+  return wave_reduce(v, (T)~(T)0, [](T a, T b) { return a < b ? a : b; });
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+  return wave_reduce(v, (T)0, [](T a, T b) { return a > b ? a : b; });
 }
 
 // Inclusive scan over the 64 lanes of a wave with an associative operator
