@@ -188,7 +188,7 @@ sim_tuning pick_tuning(const sim_ctx* c, uint64_t total) {
     if (k - d >= 0 && c->tuned[k - d]) best = k - d;
     else if (k + d < SIM_SIZE_CLASSES && c->tuned[k + d]) best = k + d;
   }
-  return best >= 0 ? c->tuning[best] : sim_tuning{0, 0, 0, 0, 0.0};
+  return best >= 0 ? c->tuning[best] : sim_tuning{0, 0, 0, 0, 0, 0, 0.0};
 }
 
 int group_shift(uint64_t n_tiles, int bias) {
@@ -345,6 +345,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.n_groups = n_hgroups;
   b.grid_stream = tile_grid(n_tiles, tune.stream_wgs_per_cu, c->n_cu);
   b.grid_sort = tile_grid(n_tiles, tune.sort_wgs_per_cu, c->n_cu);
+  b.scatter_nt = (tune.scatter_threads == 512 && !wide) ? 512u : 256u;
   b.grid_scan = tile_grid(n_tiles, tune.scan_wgs_per_cu, c->n_cu);
   b.max_group_tiles = max_group_tiles;
   b.max_trace_groups = max_trace_groups;
@@ -696,10 +697,12 @@ int sim_set_tuning(sim_ctx* c, uint32_t cls, const sim_tuning* t) {
   c->err.clear();
   if (cls >= SIM_SIZE_CLASSES) return fail(c, SIM_EINVAL, "size class %u out of range", cls);
   if (t && (t->stream_wgs_per_cu > 64 || t->sort_wgs_per_cu > 64 || t->scan_wgs_per_cu > 64 ||
-            t->group_shift_bias < -12 || t->group_shift_bias > 12))
-    return fail(c, SIM_EINVAL, "tuning out of range (workgroups per CU <= 64, |bias| <= 12)");
+            t->group_shift_bias < -12 || t->group_shift_bias > 12 ||
+            (t->scatter_threads != 0 && t->scatter_threads != 256 && t->scatter_threads != 512) || t->reserved))
+    return fail(c, SIM_EINVAL,
+                "tuning out of range (workgroups per CU <= 64, |bias| <= 12, scatter threads 0, 256 or 512)");
   c->tuned[cls] = t != nullptr;
-  c->tuning[cls] = t ? *t : sim_tuning{0, 0, 0, 0, 0.0};
+  c->tuning[cls] = t ? *t : sim_tuning{0, 0, 0, 0, 0, 0, 0.0};
   c->tuning_gen++;
   return SIM_OK;
 }
@@ -745,18 +748,18 @@ int sim_autotune(sim_ctx* c, const sim_record* d_records, const uint64_t* offset
     *ms = *std::min_element(v.begin(), v.end());  // the work is deterministic: noise only adds time
     return SIM_OK;
   };
-  sim_tuning cur{0, 0, 0, 0, 0.0};
+  sim_tuning cur{0, 0, 0, 0, 0, 0, 0.0};
   double cur_ms = 0;
   double warm = 0;
   rc = measure(cur, &warm);  // buffers, pass count
   // short calls are noisier: at least 5 repetitions below 10 ms
   if (!rc && warm < 10.0 && reps < 5) reps = 5;
   if (!rc) rc = measure(cur, &cur_ms);
-  // coordinate descent over the four knobs, one at a time
+  // coordinate descent over the five knobs, one at a time
   static const uint32_t kWgs[] = {0, 1, 2, 4, 8};
   static const int32_t kBias[] = {-2, -1, 1, 2};
-  for (int knob = 0; knob < 4 && !rc; knob++) {
-    const int nval = knob == 3 ? 4 : 5;
+  for (int knob = 0; knob < 5 && !rc; knob++) {
+    const int nval = knob == 3 ? 4 : (knob == 4 ? 1 : 5);
     const int32_t bias0 = cur.group_shift_bias;
     for (int q = 0; q < nval && !rc; q++) {
       sim_tuning t = cur;
@@ -764,6 +767,7 @@ int sim_autotune(sim_ctx* c, const sim_record* d_records, const uint64_t* offset
       if (knob == 1) { if (t.scan_wgs_per_cu == kWgs[q]) continue; t.scan_wgs_per_cu = kWgs[q]; }
       if (knob == 2) { if (t.stream_wgs_per_cu == kWgs[q]) continue; t.stream_wgs_per_cu = kWgs[q]; }
       if (knob == 3) t.group_shift_bias = bias0 + kBias[q];
+      if (knob == 4) t.scatter_threads = 512;  // the other scatter shape (the default is 256)
       double ms = 0;
       rc = measure(t, &ms);
       if (!rc && ms < cur_ms * 0.985) {  // a shape must win clearly to replace the current one

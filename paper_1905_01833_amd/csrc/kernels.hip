@@ -580,12 +580,14 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
 // staged in LDS in destination order and written out in runs per digit.
 
 // LDS of one scatter tile.
-template <typename K>
+// LDS of one scatter workgroup of NTH threads; per-wave digit counters of
+// type C (16 bits suffice: a tile holds 4096 keys).
+template <typename K, int NTH = NT, typename C = uint32_t>
 struct ScatterLds {
   K keys[TILE];
-  uint32_t wh[NWAVE][RADIX];
+  C wh[NTH / 64][RADIX];
   uint64_t gbase[RADIX];
-  uint32_t scan[NWAVE];
+  uint32_t scan[NTH / 64];
   uint32_t bad;  // some digit's destination range leaves the trace
 };
 
@@ -610,18 +612,18 @@ __device__ __forceinline__ uint64_t peer_mask(uint32_t dg) {
 // equal digits advances the wave's counter wh[wave][digit] (zero on entry)
 // by the group's size.  On return wh[wave][d] counts the wave's keys of
 // digit d.
-template <typename K>
-__device__ __forceinline__ void wave_rank(const K (&key)[ITEMS], uint32_t shift, uint32_t tx,
-                                          uint32_t (*wh)[RADIX], uint32_t (&rank)[ITEMS]) {
+template <typename K, int IT, typename C>
+__device__ __forceinline__ void wave_rank(const K (&key)[IT], uint32_t shift, uint32_t tx, C (*wh)[RADIX],
+                                          uint32_t (&rank)[IT]) {
   const uint32_t lane = tx & 63u, wave = tx >> 6;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
+  for (int i = 0; i < IT; i++) {
     const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
     const uint64_t m = peer_mask(dg);
     const uint32_t before = (uint32_t)__popcll(m & lt_mask);
     const uint32_t old = wh[wave][dg];
-    if (before == 0) wh[wave][dg] = old + (uint32_t)__popcll(m);
+    if (before == 0) wh[wave][dg] = (C)(old + (uint32_t)__popcll(m));
     rank[i] = old + before;
   }
 }
@@ -629,44 +631,49 @@ __device__ __forceinline__ void wave_rank(const K (&key)[ITEMS], uint32_t shift,
 // One stable pass over one tile: key[] holds the tile's keys wave-striped
 // (key index = wave * 1024 + item * 64 + lane; ~0 past the end, which sorts
 // last); they go to their places in `kout`.
-template <typename K>
+template <typename K, int NTH = NT, typename C = uint32_t>
 __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, uint32_t tile, uint32_t tx,
                                              const TileRef& tr, const TraceDesc& T, uint32_t n_in,
-                                             K (&key)[ITEMS], K* kout, ScatterLds<K>& S) {
+                                             K (&key)[TILE / NTH], K* kout, ScatterLds<K, NTH, C>& S) {
+  constexpr int IT = TILE / NTH, NW = NTH / 64;
   const uint32_t wave = tx >> 6;
-  const uint32_t d = tx;
+  const uint32_t d = tx;  // digit of the per-digit steps (threads below RADIX)
+  const bool dig = tx < RADIX;
   const uint32_t shift = 2 + RADIX_BITS * pass;
-  uint32_t rank[ITEMS];
+  uint32_t rank[IT];
   wave_rank(key, shift, tx, S.wh, rank);
   // destination base of each digit: group base + offset within the group
-  const uint64_t gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] +
-                      b.thist[(uint64_t)tile * RADIX + d];
+  uint64_t gb = 0;
+  if (dig)
+    gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] + b.thist[(uint64_t)tile * RADIX + d];
   __syncthreads();
 
   // per digit: tile count, tile-local start, and each wave's first slot
   // (the digit's start + the counts of the earlier waves)
-  uint32_t cnt = 0, wofs[NWAVE];
+  uint32_t cnt = 0, wofs[NW];
 #pragma unroll
-  for (int w = 0; w < NWAVE; w++) {
+  for (int w = 0; w < NW; w++) {
     wofs[w] = cnt;
-    cnt += S.wh[w][d];
+    cnt += dig ? (uint32_t)S.wh[w][d] : 0u;
   }
-  if (d == 0) S.bad = 0;
+  if (tx == 0) S.bad = 0;
   uint32_t tot;
-  const uint32_t dstart = block_excl_sum(cnt, S.scan, &tot);  // its barriers order the reads above
+  const uint32_t dstart = block_excl_sum_n<NW>(cnt, S.scan, &tot);  // its barriers order the reads above
+  if (dig) {
 #pragma unroll
-  for (int w = 0; w < NWAVE; w++) S.wh[w][d] = dstart + wofs[w];
-  S.gbase[d] = gb - dstart;
-  // bounds, once per digit: the tile's keys of digit d go to [gb, gb + real)
-  // (padding past the trace's end ranks last, in the digit of an all-ones
-  // key: 255, or fewer ones in the top pass of a 64- or 128-bit key)
-  const uint32_t pad_digit = (uint32_t)(~(K)0 >> shift) & (RADIX - 1);
-  const uint32_t real = d == pad_digit ? cnt - (uint32_t)(TILE - n_in) : cnt;
-  if (real && (gb < T.off || gb + real > T.off + T.n)) S.bad = 1;
+    for (int w = 0; w < NW; w++) S.wh[w][d] = (C)(dstart + wofs[w]);
+    S.gbase[d] = gb - dstart;
+    // bounds, once per digit: the tile's keys of digit d go to [gb, gb + real)
+    // (padding past the trace's end ranks last, in the digit of an all-ones
+    // key: 255, or fewer ones in the top pass of a 64- or 128-bit key)
+    const uint32_t pad_digit = (uint32_t)(~(K)0 >> shift) & (RADIX - 1);
+    const uint32_t real = d == pad_digit ? cnt - (uint32_t)(TILE - n_in) : cnt;
+    if (real && (gb < T.off || gb + real > T.off + T.n)) S.bad = 1;
+  }
   __syncthreads();
 
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
+  for (int i = 0; i < IT; i++) {
     const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
     S.keys[S.wh[wave][dd] + rank[i]] = key[i];
   }
@@ -676,8 +683,8 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
     return;
   }
 #pragma unroll 4
-  for (int r = 0; r < ITEMS; r++) {
-    const uint32_t j = tx + r * NT;
+  for (int r = 0; r < IT; r++) {
+    const uint32_t j = tx + r * NTH;
     if (j < n_in) {
       const K k = S.keys[j];
       kout[S.gbase[(uint32_t)(k >> shift) & (RADIX - 1)] + j] = k;
@@ -685,9 +692,14 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
   }
 }
 
-template <typename K, bool LOOP>
-__global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
-  __shared__ ScatterLds<K> S;
+// NTH threads of TILE / NTH keys each: 256 x 16, or 512 x 8 with 16-bit
+// wave counters (more waves per CU for the same LDS; one-word keys, chosen
+// by the launch shape).
+template <typename K, bool LOOP, int NTH = NT>
+__global__ __launch_bounds__(NTH) void k_scatter(Buffers b, uint32_t pass) {
+  constexpr int IT = TILE / NTH;
+  using C = typename std::conditional<NTH == NT, uint32_t, uint16_t>::type;
+  __shared__ ScatterLds<K, NTH, C> S;
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -699,19 +711,18 @@ __global__ __launch_bounds__(NT) void k_scatter(Buffers b, uint32_t pass) {
     const uint32_t lane = tx & 63u, wave = tx >> 6;
     const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
     const K* src = (const K*)b.keys[pass & 1] + tr.first;
-    K key[ITEMS];
+    K key[IT];
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+    for (int i = 0; i < IT; i++) {
+      const uint32_t j = wave * (IT * 64) + i * 64 + lane;
       key[i] = (j < n_in) ? src[j] : ~(K)0;  // padding sorts last (the largest digit, after every real key)
     }
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
     if (pass >= L.npasses || sorted_in_lds(b, T, pass)) continue;  // uniform over the workgroup
-#pragma unroll
-    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
+    for (uint32_t k = tx; k < (uint32_t)(NTH / 64 * RADIX); k += NTH) (&S.wh[0][0])[k] = 0;
     __syncthreads();
-    scatter_tile<K>(b, pass, tile, tx, tr, T, n_in, key, (K*)b.keys[(pass + 1) & 1], S);
+    scatter_tile<K, NTH, C>(b, pass, tile, tx, tr, T, n_in, key, (K*)b.keys[(pass + 1) & 1], S);
   }
 }
 
@@ -1450,9 +1461,16 @@ hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
   const bool lp = loops(b, b.grid_sort);
-  auto kern = b.wide ? (lp ? k_scatter<u128, true> : k_scatter<u128, false>)
-                     : (lp ? k_scatter<uint64_t, true> : k_scatter<uint64_t, false>);
-  hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
+  if (b.wide) {
+    auto kern = lp ? k_scatter<u128, true> : k_scatter<u128, false>;
+    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
+  } else if (b.scatter_nt == 2 * NT) {
+    auto kern = lp ? k_scatter<uint64_t, true, 2 * NT> : k_scatter<uint64_t, false, 2 * NT>;
+    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(2 * NT), 0, s, b, pass);
+  } else {
+    auto kern = lp ? k_scatter<uint64_t, true> : k_scatter<uint64_t, false>;
+    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
+  }
   return hipGetLastError();
 }
 hipError_t launch_sort_small(const Buffers& b, hipStream_t s) {

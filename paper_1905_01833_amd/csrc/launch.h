@@ -91,6 +91,7 @@ struct Buffers {            // device pointers of one call
   uint32_t n_groups;        // histogram groups
   uint32_t grid_stream;     // workgroups of k_stats / k_keygen / k_upsweep (multiple of 8)
   uint32_t grid_sort;       // workgroups of k_scatter
+  uint32_t scatter_nt;      // threads of a k_scatter workgroup: 256, or 512 (one-word keys)
   uint32_t grid_scan;       // workgroups of k_scan_tiles
   uint32_t max_group_tiles; // most tiles in one histogram group of the call
   uint32_t max_trace_groups;// most histogram groups in one trace of the call
