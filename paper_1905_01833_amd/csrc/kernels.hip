@@ -571,15 +571,14 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
 // ------------------------------------------------------------ k_scatter
 //
 // One stable LSD pass on the 8-bit digit at bits [2 + 8 pass, 10 + 8 pass).
-// Keys are loaded wave-striped (key index = wave * 1024 + item * 64 + lane)
-// so that lane order within an item is key order.  Each item's digit is
+// Keys are loaded wave-striped (key index = wave * 64 * items + item * 64 +
+// lane) so that lane order within an item is key order.  Each item's digit is
 // matched across the wave with eight ballots; the lowest matching lane
 // advances the wave's per-digit counter, which gives every key a stable
 // rank within its wave.  Per-digit wave offsets, the tile's digit starts and
 // the offsets left by the upsweep give each key its destination; keys are
 // staged in LDS in destination order and written out in runs per digit.
 
-// LDS of one scatter tile.
 // LDS of one scatter workgroup of NTH threads; per-wave digit counters of
 // type C (16 bits suffice: a tile holds 4096 keys).
 template <typename K, int NTH = NT, typename C = uint32_t>
@@ -629,8 +628,8 @@ __device__ __forceinline__ void wave_rank(const K (&key)[IT], uint32_t shift, ui
 }
 
 // One stable pass over one tile: key[] holds the tile's keys wave-striped
-// (key index = wave * 1024 + item * 64 + lane; ~0 past the end, which sorts
-// last); they go to their places in `kout`.
+// (key index = wave * 64 * items + item * 64 + lane; ~0 past the end, which
+// sorts last); they go to their places in `kout`.
 template <typename K, int NTH = NT, typename C = uint32_t>
 __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, uint32_t tile, uint32_t tx,
                                              const TileRef& tr, const TraceDesc& T, uint32_t n_in,
