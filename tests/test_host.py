@@ -184,3 +184,33 @@ def test_host_model_two_word_keys(seed):
     a, _ = hs_check(r, [0, len(r)], [3], 50, 4)
     b, _ = hs_check(r, [0, len(r)], [3], 50, 4, wide=True)
     assert a.tobytes() == b.tobytes()
+
+
+def test_abi_structs_match_binding(tmp_path):
+    """The Python binding's ctypes mirrors have the sizes and field offsets
+    of the structs that include/simcheck.h declares (checked with a probe
+    compiled against the header by gcc)."""
+    import subprocess
+
+    import paper_1905_01833_amd as pkg
+
+    pairs = {
+        "sim_result": pkg._Result, "sim_config": pkg._Config, "sim_stage_time": pkg._StageTime,
+        "sim_tuning": pkg._Tuning, "sim_server_config": pkg._ServerConfig, "sim_server_stats": pkg._ServerStats,
+    }
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "simcheck.h"', "int main(void) {"]
+    for c_name, py in pairs.items():
+        lines.append(f'  printf("{c_name} size %zu\\n", sizeof({c_name}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{c_name} {f} %zu\\n", offsetof({c_name}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for c_name, py in pairs.items():
+        assert got[(c_name, "size")] == ctypes.sizeof(py), c_name
+        for f, _ in py._fields_:
+            assert got[(c_name, f)] == getattr(py, f).offset, (c_name, f)
