@@ -859,7 +859,6 @@ __global__ __launch_bounds__(NTH) void k_sort_small(Buffers b, const uint32_t* _
 // k_scan_cross, which finishes the locations that cross tile boundaries.
 // Counts inside a tile fit 16 bits and pair sums 32 bits.
 
-constexpr uint32_t LDS_PAD(uint32_t j) { return j + (j >> 4); }
 #define META(i) ((mp[(i) / 6] >> (5 * ((i) % 6))) & 31u)
 // the same for a loop index that is not unrolled (no dynamic register indexing)
 __device__ __forceinline__ uint32_t meta_at(const uint32_t mp[3], uint32_t i) {
@@ -946,16 +945,23 @@ __device__ __forceinline__ RaceOut* stage_of(const Buffers& b, uint32_t tile, co
   return (RaceOut*)((char*)b.keys[(L.npasses & 1u) ^ 1u] + (T.off + start) * b.key_bytes);
 }
 
+// Occupancy of the tile scan: it is bound by VALU issue, and with no LDS
+// copy of the tile its registers alone set the waves per SIMD.  The
+// one-tile kernel with one-word keys asks for 5 (96 VGPRs, a few values
+// spill) instead of the 4 its natural 110 VGPRs give: measured 132 us
+// instead of 151 us on c1; 6 waves spill too much (144 us).  The looping
+// and two-word variants keep their natural counts (they would spill more).
 template <typename K, bool LOOP>
-__global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_done) {
-  __shared__ K s_keys[LDS_PAD(TILE) + 1];
+constexpr int scan_min_waves() { return (!LOOP && sizeof(K) == 8) ? 5 : 1; }
+
+template <typename K, bool LOOP>
+__global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(Buffers b, uint32_t passes_done) {
   __shared__ uint64_t s_scanA[NWAVE][4];
   __shared__ uint64_t s_scanB[NWAVE][3];
   __shared__ uint32_t s_scan32[NWAVE];
   __shared__ uint8_t s_firstlv[NT];
   __shared__ uint32_t s_lead[17];  // lead counts [l][c] (12), lead pair sums (5)
   __shared__ uint32_t s_min;
-  __shared__ K s_prev, s_next;
   __shared__ uint32_t s_taillast;
 
   // nothing to do on an error, or when fewer radix passes ran than some
@@ -979,30 +985,30 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
     const K* src = keys + T.off + start;
     const bool trace_end = start + n_in == T.n;
 
-    {
-      K v[ITEMS];  // all loads first
+    // each thread's sixteen consecutive keys come straight from memory
+    // (with the key before them), with no LDS copy of the tile: the
+    // kernel's LDS stays under 1 KiB, so registers alone bound occupancy
+    K kk[ITEMS];
 #pragma unroll
-      for (int r = 0; r < ITEMS; r++) v[r] = tid + r * NT < n_in ? src[tid + r * NT] : (K)0;
-#pragma unroll
-      for (int r = 0; r < ITEMS; r++) s_keys[LDS_PAD(tid + r * NT)] = v[r];
+    for (int i = 0; i < ITEMS; i++) kk[i] = ITEMS * tid + i < n_in ? src[ITEMS * tid + i] : (K)0;
+    const uint32_t j0 = ITEMS * tid;
+    K prev = (K)0;
+    if (j0 > 0 && j0 - 1 < n_in) prev = src[j0 - 1];
+    else if (j0 == 0 && tr.local > 0) prev = src[-1];  // the previous tile's last key
+    if (tid == 0) {  // whether the tile's last location ends with the tile
+      const K next = trace_end ? (K)0 : src[n_in];
+      s_taillast = trace_end ? 1u : (head_level_t<K>(L, src[n_in - 1], next) == 0 ? 1u : 0u);
     }
-    if (tid == 0) {
-      s_prev = tr.local > 0 ? src[-1] : (K)0;
-      s_next = trace_end ? (K)0 : src[n_in];
-    }
-    __syncthreads();
-    if (tid == 0) s_taillast = trace_end ? 1u : (head_level_t<K>(L, s_keys[LDS_PAD(n_in - 1)], s_next) == 0 ? 1u : 0u);
 
     // ---- element metadata: head level (3 bits) and class (2 bits)
     // head level (3 bits) and class (2 bits) of item i: bits 5 (i % 6) of mp[i / 6]
     uint32_t mp[3] = {0u, 0u, 0u};
     uint32_t local_min = NO_HEAD;
     {
-      K prev = tid > 0 ? s_keys[LDS_PAD(ITEMS * tid - 1)] : s_prev;
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t j = ITEMS * tid + i;
-        const K k = s_keys[LDS_PAD(j)];
+        const K k = kk[i];
         uint32_t lv, c;
         if (j < n_in) {
           lv = (j == 0 && tr.local == 0) ? 0u : head_level_t<K>(L, prev, k);
@@ -1200,7 +1206,7 @@ __global__ __launch_bounds__(NT) void k_scan_tiles(Buffers b, uint32_t passes_do
         S[K_AW] = (uint32_t)s1; S[K_AR] = (uint32_t)(s1 >> 32);
         S[K_XB] = (uint32_t)s2;
         if (S[K_WW] + S[K_RW] + S[K_AW] + S[K_AR] == 0) continue;
-        if (pos < cap) write_entry<K>(dst + pos, tr.trace, L, s_keys[LDS_PAD(ITEMS * tid + i)], S);
+        if (pos < cap) write_entry<K>(dst + pos, tr.trace, L, src[ITEMS * tid + i], S);
         pos++;
       }
     };
