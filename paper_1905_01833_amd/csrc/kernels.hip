@@ -88,6 +88,10 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, int lane) {
 __device__ __forceinline__ uint64_t readlane(uint64_t v, int lane) {
   return ((uint64_t)readlane((uint32_t)(v >> 32), lane) << 32) | readlane((uint32_t)v, lane);
 }
+__device__ __forceinline__ uint64_t readfirstlane(uint64_t v) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+}
 
 // Reduction over the 64 lanes with an associative, commutative operator
 // whose identity is `id`: the scan pattern below ends with the total in
@@ -181,7 +185,7 @@ __device__ void block_seg_scan(const uint64_t (&v)[K], uint64_t (&ex)[K], uint64
       all = seg_op(all, x);
     }
     ex[k] = seg_op(pre, ex[k]);
-    tot[k] = all;
+    tot[k] = readfirstlane(all);  // uniform: scalar registers hold it
   }
   __syncthreads();
 }
@@ -947,12 +951,13 @@ __device__ __forceinline__ RaceOut* stage_of(const Buffers& b, uint32_t tile, co
 
 // Occupancy of the tile scan: it is bound by VALU issue, and with no LDS
 // copy of the tile its registers alone set the waves per SIMD.  The
-// one-tile kernel with one-word keys asks for 5 (96 VGPRs, a few values
-// spill) instead of the 4 its natural 110 VGPRs give: measured 132 us
-// instead of 151 us on c1; 6 waves spill too much (144 us).  The looping
-// and two-word variants keep their natural counts (they would spill more).
+// one-tile kernels ask for 6 (80 VGPRs, no spill; the block scans' totals
+// live in scalar registers) instead of the 4 that their natural count
+// gave: c1's scan took 151 us at 4 waves, 131 at 5, 129.6 at 6, 128.9 at 7
+// and 140 at 8 (spilling).  The looping variants would spill and keep
+// their natural counts.
 template <typename K, bool LOOP>
-constexpr int scan_min_waves() { return (!LOOP && sizeof(K) == 8) ? 5 : 1; }
+constexpr int scan_min_waves() { return LOOP ? 1 : 6; }
 
 template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(Buffers b, uint32_t passes_done) {
