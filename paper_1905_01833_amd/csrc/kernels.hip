@@ -992,7 +992,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 
     // each thread's sixteen consecutive keys come straight from memory
     // (with the key before them), with no LDS copy of the tile: the
-XX
+    // kernel's LDS stays under 4 KiB, so registers alone bound occupancy
     K kk[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) kk[i] = ITEMS * tid + i < n_in ? src[ITEMS * tid + i] : (K)0;
