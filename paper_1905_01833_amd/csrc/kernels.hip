@@ -538,11 +538,17 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
 }
 
 // ------------------------------------------------------------ k_upsweep
+constexpr int HIST_SPREAD = 8;
+
 // Tile histogram of radix digit `pass` (keys in the buffer that pass reads).
 
 template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
-  __shared__ uint32_t h[RADIX];
+  // HIST_SPREAD copies of every bin, one per group of lanes (lane mod
+  // HIST_SPREAD): the lanes of one atomic instruction that share a digit
+  // mostly hit different copies.  High digits often take a handful of
+  // values, and with one copy their atomics serialised up to 64 deep.
+  __shared__ uint32_t h[RADIX * HIST_SPREAD];
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -561,14 +567,19 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
     }
     const uint32_t npasses = b.layout[tr.trace].npasses;
     if (pass >= npasses || ((tr.n_flags & TILE_SHORT) && pass >= b.small_from)) continue;
-    h[tx] = 0;
+#pragma unroll
+    for (int q = 0; q < HIST_SPREAD; q++) h[q * NT + tx] = 0;
     __syncthreads();
     const uint32_t shift = 2 + RADIX_BITS * pass;
+    const uint32_t copy = tx & (HIST_SPREAD - 1);
 #pragma unroll
     for (int r = 0; r < ITEMS; r++)
-      wave_hist_add(h, (uint32_t)(k[r] >> shift) & (RADIX - 1), tx + r * NT < n_in);
+      if (tx + r * NT < n_in) atomicAdd(&h[((uint32_t)(k[r] >> shift) & (RADIX - 1)) * HIST_SPREAD + copy], 1u);
     __syncthreads();
-    b.thist[(uint64_t)tile * RADIX + tx] = h[tx];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < HIST_SPREAD; q++) sum += h[tx * HIST_SPREAD + q];
+    b.thist[(uint64_t)tile * RADIX + tx] = sum;
   }
 }
 
