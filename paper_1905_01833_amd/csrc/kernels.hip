@@ -746,13 +746,15 @@ __global__ __launch_bounds__(NTH) void k_scatter(Buffers b, uint32_t pass) {
 // bits [2, 10) of the key are tid mod 256): k_stats has built the tile
 // histograms of that digit and the offset kernels have turned them into
 // scatter offsets, so keys go straight from the records to their places
-// after pass 0, in the buffer pass 1 reads.  The ranking is over records in
-// the same wave-striped order as k_scatter's, so the result is identical
+// after pass 0, in the buffer pass 1 reads.  The ranking is stable in record
+// order (as k_scatter's, for any thread count), so the result is identical
 // to k_keygen followed by k_scatter(pass 0).
 
-template <typename K, bool LOOP>
-__global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
-  __shared__ ScatterLds<K> S;
+template <typename K, bool LOOP, int NTH = NT>
+__global__ __launch_bounds__(NTH) void k_keygen_scatter(Buffers b) {
+  constexpr int IT = TILE / NTH;
+  using C = typename std::conditional<NTH == NT, uint32_t, uint16_t>::type;
+  __shared__ ScatterLds<K, NTH, C> S;
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -764,26 +766,25 @@ __global__ __launch_bounds__(NT) void k_keygen_scatter(Buffers b) {
     const uint32_t lane = tx & 63u, wave = tx >> 6;
     const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
     const ulonglong2* p = (const ulonglong2*)b.records + tr.first;
-    ulonglong2 vr[ITEMS];  // all loads first: sixteen records in flight per thread
+    ulonglong2 vr[IT];  // all loads first: every record of the thread in flight
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+    for (int i = 0; i < IT; i++) {
+      const uint32_t j = wave * (IT * 64) + i * 64 + lane;
       vr[i] = j < n_in ? p[j] : ulonglong2{0ull, 0ull};
     }
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
     if (L.npasses == 0) continue;  // uniform over the workgroup
+    for (uint32_t k = tx; k < (uint32_t)(NTH / 64 * RADIX); k += NTH) (&S.wh[0][0])[k] = 0;
+    K key[IT];
 #pragma unroll
-    for (int w = 0; w < NWAVE; w++) S.wh[w][tx] = 0;
-    K key[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
+    for (int i = 0; i < IT; i++) {
+      const uint32_t j = wave * (IT * 64) + i * 64 + lane;
       const Rec x = unpack_rec(vr[i]);
       key[i] = j < n_in ? make_key_t<K, BLK_POW2>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb) : ~(K)0;
     }
     __syncthreads();
-    scatter_tile<K>(b, 0, tile, tx, tr, T, n_in, key, (K*)b.keys[1], S);
+    scatter_tile<K, NTH, C>(b, 0, tile, tx, tr, T, n_in, key, (K*)b.keys[1], S);
   }
 }
 
@@ -1442,9 +1443,13 @@ hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
   if (b.fuse0) {  // pass 0's offsets come first (launch_upsweep(b, 0)); the keys go straight to pass 1's buffer
     const bool lp = loops(b, b.grid_sort);
-    auto kern = b.wide ? (lp ? k_keygen_scatter<u128, true> : k_keygen_scatter<u128, false>)
-                       : (lp ? k_keygen_scatter<uint64_t, true> : k_keygen_scatter<uint64_t, false>);
-    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b);
+    if (b.wide) {
+      auto kern = lp ? k_keygen_scatter<u128, true> : k_keygen_scatter<u128, false>;
+      hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b);
+    } else {  // one-word keys: 512 threads of 8 records (7 waves per SIMD instead of 4)
+      auto kern = lp ? k_keygen_scatter<uint64_t, true, 2 * NT> : k_keygen_scatter<uint64_t, false, 2 * NT>;
+      hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(2 * NT), 0, s, b);
+    }
   } else {
     const bool lp = loops(b, b.grid_stream);
     auto kern = b.wide ? (lp ? k_keygen<u128, true> : k_keygen<u128, false>)
