@@ -228,14 +228,17 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool val
 
 // HIST: also the tile histogram of radix digit 0 for calls whose digit 0 is
 // tid mod 256 (see k_keygen_scatter).
-template <bool LOOP, bool HIST>
-__global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ recs,
-                                              const TileRef* __restrict__ tiles, uint32_t n_tiles,
-                                              TraceStats* __restrict__ part, uint32_t* __restrict__ thist,
-                                              Ctrl* ctrl) {
-  __shared__ uint64_t s64[5][NWAVE];
+// NTH threads of TILE / NTH records each.
+template <bool LOOP, bool HIST, int NTH = NT>
+__global__ __launch_bounds__(NTH) void k_stats(const ulonglong2* __restrict__ recs,
+                                               const TileRef* __restrict__ tiles, uint32_t n_tiles,
+                                               TraceStats* __restrict__ part, uint32_t* __restrict__ thist,
+                                               Ctrl* ctrl) {
+  constexpr int IT = TILE / NTH, NW = NTH / 64;
+  static_assert(NTH >= (int)RADIX, "one thread per histogram bin");
+  __shared__ uint64_t s64[5][NW];
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(ctrl);
-  __shared__ uint32_t s32[2][NWAVE];
+  __shared__ uint32_t s32[2][NW];
   __shared__ uint32_t h[RADIX];
   const TileWalk tw = tile_walk(n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
@@ -249,16 +252,16 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
     uint64_t gmin = ~0ull, gmax = 0, smin = ~0ull, smax = 0, bad = ~0ull;
     uint32_t mt = 0, me = 0;
     if (HIST) {
-      h[tx] = 0;
+      if (tx < RADIX) h[tx] = 0;
       __syncthreads();
     }
-    // all loads first: sixteen records in flight per thread
-    ulonglong2 vr[ITEMS];
+    // all loads first: every record of the thread in flight
+    ulonglong2 vr[IT];
 #pragma unroll
-    for (int r = 0; r < ITEMS; r++) vr[r] = tx + r * NT < n_in ? p[tx + r * NT] : ulonglong2{0ull, 0ull};
+    for (int r = 0; r < IT; r++) vr[r] = tx + r * NTH < n_in ? p[tx + r * NTH] : ulonglong2{0ull, 0ull};
 #pragma unroll
-    for (int r = 0; r < ITEMS; r++) {
-      const uint32_t j = tx + r * NT;
+    for (int r = 0; r < IT; r++) {
+      const uint32_t j = tx + r * NTH;
       const bool valid = j < n_in;
       const ulonglong2 v = vr[r];
       // tid mod 256: neighbouring records mostly belong to different threads,
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
     }
     __syncthreads();
     if (tx == 0) {
-      for (int w = 1; w < NWAVE; w++) {
+      for (int w = 1; w < NW; w++) {
         gmin = min(gmin, s64[0][w]); gmax = max(gmax, s64[1][w]);
         smin = min(smin, s64[2][w]); smax = max(smax, s64[3][w]);
         bad = min(bad, s64[4][w]);
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_stats(const ulonglong2* __restrict__ rec
       S.max_tid = mt; S.max_epoch = me;
       part[tile] = S;
     }
-    if (HIST) thist[(uint64_t)tile * RADIX + tx] = h[tx];
+    if (HIST && tx < RADIX) thist[(uint64_t)tile * RADIX + tx] = h[tx];
   }
 }
 
