@@ -666,19 +666,23 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
   __syncthreads();
 
   // per digit: tile count, tile-local start, and each wave's first slot
-  // (the digit's start + the counts of the earlier waves)
-  uint32_t cnt = 0, wofs[NW];
+  // (the digit's start + the counts of the earlier waves); only thread d
+  // touches column d of S.wh, which holds the earlier waves' count in between
+  uint32_t cnt = 0;
+  if (dig) {
 #pragma unroll
-  for (int w = 0; w < NW; w++) {
-    wofs[w] = cnt;
-    cnt += dig ? (uint32_t)S.wh[w][d] : 0u;
+    for (int w = 0; w < NW; w++) {
+      const uint32_t c = S.wh[w][d];
+      S.wh[w][d] = (C)cnt;
+      cnt += c;
+    }
   }
   if (tx == 0) S.bad = 0;
   uint32_t tot;
-  const uint32_t dstart = block_excl_sum_n<NW>(cnt, S.scan, &tot);  // its barriers order the reads above
+  const uint32_t dstart = block_excl_sum_n<NW>(cnt, S.scan, &tot);
   if (dig) {
 #pragma unroll
-    for (int w = 0; w < NW; w++) S.wh[w][d] = (C)(dstart + wofs[w]);
+    for (int w = 0; w < NW; w++) S.wh[w][d] = (C)(S.wh[w][d] + dstart);
     S.gbase[d] = gb - dstart;
     // bounds, once per digit: the tile's keys of digit d go to [gb, gb + real)
     // (padding past the trace's end ranks last, in the digit of an all-ones
