@@ -317,16 +317,21 @@ __global__ __launch_bounds__(NTH) void k_stats(const ulonglong2* __restrict__ re
 // wide_call: the call runs with two-word keys.  Otherwise a trace whose key
 // needs two words raises ERR_NEEDS_WIDE, which stops the call's later
 // kernels; the host then runs the call again with two-word keys.
-__global__ __launch_bounds__(NT) void k_layout(const TraceDesc* __restrict__ desc,
-                                               const TraceStats* __restrict__ part, TraceLayout* lay, Ctrl* ctrl,
-                                               uint32_t wide_call) {
-  __shared__ uint64_t s64[5][NWAVE];
-  __shared__ uint32_t s32[2][NWAVE];
+// NTH threads per trace: 256, or 1024 for calls of a few long traces (more
+// partial loads in flight per trace; with thousands of traces the wider
+// workgroups only cost launch capacity).
+template <int NTH = NT>
+__global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ desc,
+                                                const TraceStats* __restrict__ part, TraceLayout* lay, Ctrl* ctrl,
+                                                uint32_t wide_call) {
+  constexpr int NW = NTH / 64;
+  __shared__ uint64_t s64[5][NW];
+  __shared__ uint32_t s32[2][NW];
   const uint32_t t = blockIdx.x;
   const TraceDesc T = desc[t];
   TraceStats S;
   stats_init(S);
-  for (uint32_t i = threadIdx.x; i < T.ntiles; i += NT) {
+  for (uint32_t i = threadIdx.x; i < T.ntiles; i += NTH) {
     const TraceStats P = part[T.tile0 + i];
     S.gmin = min(S.gmin, P.gmin); S.gmax = max(S.gmax, P.gmax);
     S.smin = min(S.smin, P.smin); S.smax = max(S.smax, P.smax);
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(NT) void k_layout(const TraceDesc* __restrict__ des
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int w = 1; w < NWAVE; w++) {
+  for (int w = 1; w < NW; w++) {
     S.gmin = min(S.gmin, s64[0][w]); S.gmax = max(S.gmax, s64[1][w]);
     S.smin = min(S.smin, s64[2][w]); S.smax = max(S.smax, s64[3][w]);
     S.bad_index = min(S.bad_index, s64[4][w]);
@@ -1442,7 +1447,11 @@ hipError_t launch_stats(const Buffers& b, hipStream_t s) {
 }
 hipError_t launch_layout(const Buffers& b, hipStream_t s) {
   if (!b.n_traces) return hipSuccess;
-  hipLaunchKernelGGL(k_layout, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl, b.wide);
+  if (b.n_traces <= 64 && b.n_tiles >= 64 * b.n_traces)  // a few long traces
+    hipLaunchKernelGGL(k_layout<4 * NT>, dim3(b.n_traces), dim3(4 * NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl,
+                       b.wide);
+  else
+    hipLaunchKernelGGL(k_layout<NT>, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl, b.wide);
   return hipGetLastError();
 }
 hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
