@@ -203,8 +203,9 @@ typedef struct sim_tuning {
   uint32_t scan_wgs_per_cu;   /* tile-scan kernel, same meaning */
   int32_t group_shift_bias;   /* added to log2 of the tiles per histogram group (by default about the
                                  square root of a trace's tiles); the result is clamped to 0 .. 12 */
-  uint32_t scatter_threads;   /* threads of a radix scatter workgroup: 0 or 256 (16 keys each), or 512
-                                 (8 keys each; one-word keys only, two-word calls use 256) */
+  uint32_t scatter_threads;   /* threads of a radix scatter workgroup: 256 (16 keys each) or 512 (8 keys
+                                 each; one-word keys only, two-word calls use 256); 0: by call size,
+                                 512 up to 16384 tiles, else 256 */
   uint32_t reserved;          /* 0 */
   double ms;                  /* sim_autotune: fastest time of one call in the chosen shape; else 0 */
 } sim_tuning;
@@ -227,7 +228,7 @@ int sim_get_tuning(const sim_ctx* ctx, uint32_t size_class, sim_tuning* t);
  * sim_check_traces_device) under candidate shapes -- coordinate descent over
  * the workgroups per CU of the scatter (0, 1, 2, 4, 8), of the tile scan,
  * of the streaming kernels, then the histogram-group bias (-2 .. +2), then
- * the scatter's thread count (256 or 512).  A
+ * the scatter's other thread count (256 or 512).  A
  * candidate's time is the fastest of `reps` calls (0: 3; at least 5 when a
  * call takes under 10 ms), and it replaces the current shape only when it
  * is at least 1.5 % faster.  The chosen shape is stored for the input's

@@ -191,6 +191,13 @@ sim_tuning pick_tuning(const sim_ctx* c, uint64_t total) {
   return best >= 0 ? c->tuning[best] : sim_tuning{0, 0, 0, 0, 0, 0, 0.0};
 }
 
+// Threads of a scatter workgroup: the shape's, else by call size -- 512 of
+// 8 keys up to 16384 tiles (measured faster on single traces of 2^24
+// records), 256 of 16 keys above (faster on calls of 2^29 records).
+uint32_t scatter_threads(const sim_tuning& t, uint32_t n_tiles) {
+  return t.scatter_threads ? t.scatter_threads : (n_tiles <= 16384 ? 512u : 256u);
+}
+
 int group_shift(uint64_t n_tiles, int bias) {
   int gs = 0;
   while (gs < (int)MAX_HGROUP_SHIFT && (1ull << (2 * gs)) < n_tiles) gs++;
@@ -345,7 +352,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.n_groups = n_hgroups;
   b.grid_stream = tile_grid(n_tiles, tune.stream_wgs_per_cu, c->n_cu);
   b.grid_sort = tile_grid(n_tiles, tune.sort_wgs_per_cu, c->n_cu);
-  b.scatter_nt = (tune.scatter_threads == 512 && !wide) ? 512u : 256u;
+  b.scatter_nt = (scatter_threads(tune, n_tiles) == 512 && !wide) ? 512u : 256u;
   b.grid_scan = tile_grid(n_tiles, tune.scan_wgs_per_cu, c->n_cu);
   b.max_group_tiles = max_group_tiles;
   b.max_trace_groups = max_trace_groups;
@@ -767,7 +774,7 @@ int sim_autotune(sim_ctx* c, const sim_record* d_records, const uint64_t* offset
       if (knob == 1) { if (t.scan_wgs_per_cu == kWgs[q]) continue; t.scan_wgs_per_cu = kWgs[q]; }
       if (knob == 2) { if (t.stream_wgs_per_cu == kWgs[q]) continue; t.stream_wgs_per_cu = kWgs[q]; }
       if (knob == 3) t.group_shift_bias = bias0 + kBias[q];
-      if (knob == 4) t.scatter_threads = 512;  // the other scatter shape (the default is 256)
+      if (knob == 4) t.scatter_threads = scatter_threads(cur, n_tiles) == 512 ? 256 : 512;  // the other shape
       double ms = 0;
       rc = measure(t, &ms);
       if (!rc && ms < cur_ms * 0.985) {  // a shape must win clearly to replace the current one

@@ -335,6 +335,8 @@ SHAPES = [
      "scatter_threads": 512},
     {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 0, "scan_wgs_per_cu": 0, "group_shift_bias": 0,
      "scatter_threads": 512},
+    {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 1, "scan_wgs_per_cu": 0, "group_shift_bias": 0,
+     "scatter_threads": 256},
 ]
 
 
