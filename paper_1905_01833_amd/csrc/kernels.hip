@@ -19,7 +19,8 @@
 //   k_scan_tiles  racing-pair counts of every location inside a tile, and
 //                 the tile's summary for locations that cross tiles
 //   k_scan_cross  pair counts of the locations that cross tiles
-//   k_group_sums / k_scan_out  ordered output (two-level prefix over tiles)
+//   k_group_sums / k_scan_out  ordered output (two-level prefix over tiles;
+//                 calls of at most 32 groups of 256 tiles skip k_group_sums)
 //
 // No kernel waits on another workgroup.  Radix offsets are computed
 // reduce-then-scan style: every tile stores its digit histogram, two small
@@ -1378,23 +1379,34 @@ __global__ __launch_bounds__(NT) void k_group_sums(Buffers b, uint32_t passes_do
   if (threadIdx.x == 0) b.group_sum[blockIdx.x] = tot;
 }
 
+// DIRECT (calls of at most DIRECT_GROUPS groups): each workgroup sums the
+// entry counts of the tiles before its group itself, and k_group_sums is
+// not launched.  Otherwise it sums the group totals k_group_sums left.
+constexpr uint32_t DIRECT_GROUPS = 32;
+
+template <bool DIRECT>
 __global__ __launch_bounds__(NT) void k_scan_out(Buffers b, uint32_t passes_done) {
   __shared__ uint32_t sc[NWAVE];
   if (b.ctrl->error_flags || b.ctrl->max_passes > passes_done) return;
-  // entries of the earlier groups (each workgroup sums the group totals
-  // before it; the last one also publishes the call's total)
+  // entries of the earlier groups
   uint64_t before = 0;
-  for (uint32_t g = threadIdx.x; g < blockIdx.x; g += NT) before += b.group_sum[g];
+  if (DIRECT) {
+#pragma unroll 8
+    for (uint32_t t0 = threadIdx.x; t0 < blockIdx.x * GROUP; t0 += NT) before += b.tout[t0].in_count + b.cross_flag[t0];
+  } else {
+    for (uint32_t g = threadIdx.x; g < blockIdx.x; g += NT) before += b.group_sum[g];
+  }
   uint32_t all;
   (void)block_excl_sum((uint32_t)before, sc, &all);
   const uint64_t group_base = all;
-  if (blockIdx.x + 1 == gridDim.x && threadIdx.x == 0) b.ctrl->total_entries = group_base + b.group_sum[blockIdx.x];
   const uint32_t t = blockIdx.x * GROUP + threadIdx.x;
   const bool valid = t < b.n_tiles;
   const uint32_t inc = valid ? b.tout[t].in_count : 0u;
   const uint32_t cf = valid ? b.cross_flag[t] : 0u;
   uint32_t tot;
   const uint32_t ex = block_excl_sum(inc + cf, sc, &tot);
+  // the last workgroup publishes the call's total
+  if (blockIdx.x + 1 == gridDim.x && threadIdx.x == 0) b.ctrl->total_entries = group_base + tot;
   if (!valid || inc + cf == 0) return;
   uint64_t pos = group_base + ex;
   if (inc) {
@@ -1548,10 +1560,14 @@ hipError_t launch_scan_cross(const Buffers& b, uint32_t passes_done, hipStream_t
 hipError_t launch_scan_out(const Buffers& b, uint32_t passes_done, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   const uint32_t n_groups = cdiv(b.n_tiles, GROUP);
+  if (n_groups <= DIRECT_GROUPS) {
+    hipLaunchKernelGGL(k_scan_out<true>, dim3(n_groups), dim3(NT), 0, s, b, passes_done);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_group_sums, dim3(n_groups), dim3(NT), 0, s, b, passes_done);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_out, dim3(n_groups), dim3(NT), 0, s, b, passes_done);
+  hipLaunchKernelGGL(k_scan_out<false>, dim3(n_groups), dim3(NT), 0, s, b, passes_done);
   return hipGetLastError();
 }
 hipError_t launch_reset_errors(const Buffers& b, uint32_t mask, hipStream_t s) {
