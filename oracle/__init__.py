@@ -176,8 +176,9 @@ def tier_a_py(records, tpb, trace=0):
     return out
 
 
-def races_to_dict(races, trace=0):
-    """Convert a RACE_DTYPE array (one trace) to the tier_a_py form."""
+def races_to_dict(races, trace=0, kinds=False):
+    """Convert a RACE_DTYPE array (one trace) to the tier_a_py form; with
+    kinds=True each entry also carries its kinds bits."""
     out = {}
     for r in races:
         if int(r["trace"]) != trace:
@@ -190,4 +191,6 @@ def races_to_dict(races, trace=0):
             "ar": int(r["pairs_ar"]),
             "xblock": int(r["pairs_xblock"]),
         }
+        if kinds:
+            out[key]["kinds"] = int(r["kinds"])
     return out

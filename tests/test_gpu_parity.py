@@ -84,14 +84,14 @@ def test_truth_table_batched(ctx):
     recs, off = batch_of([r for _, r, _ in rows])
     got = assert_parity(ctx, recs, off, 2, name="truth table")
     for i, (line, _, exp) in enumerate(rows):
-        assert oracle.races_to_dict(got[got["trace"] == i], trace=i) == exp, line
+        assert oracle.races_to_dict(got[got["trace"] == i], trace=i, kinds=True) == exp, line
 
 
-@pytest.mark.parametrize("name", ["fig6_unit.txt", "fig6_unit_write.txt", "kaldi_copy.txt"])
+@pytest.mark.parametrize("name", ["fig6_unit.txt", "fig6_unit_write.txt", "kaldi_copy.txt", "mixed_kinds.txt"])
 def test_fixtures(ctx, name):
     recs, tpb, exp = trace_fixture(name)
     got = assert_parity(ctx, recs, tpb=tpb, name=name)
-    assert oracle.races_to_dict(got) == exp
+    assert oracle.races_to_dict(got, kinds=True) == exp
 
 
 # ------------------------------------------------------------ random cases

@@ -12,12 +12,18 @@ import pytest
 
 import oracle
 import tracegen
-from golden_io import trace_fixture, truth_table
+from golden_io import counts_only, trace_fixture, truth_table
 from tracegen import RECORD_DTYPE
+
+FIXTURES = ["fig6_unit.txt", "fig6_unit_write.txt", "kaldi_copy.txt", "mixed_kinds.txt"]
 
 
 def as_dict(races, trace=0):
     return oracle.races_to_dict(races, trace)
+
+
+def with_kinds(races, trace=0):
+    return oracle.races_to_dict(races, trace, kinds=True)
 
 
 # ---------------------------------------------------------------- fixtures
@@ -27,19 +33,20 @@ def test_truth_table(row):
     line, recs, exp = row
     for fn in (oracle.brute_force, oracle.closed_form):
         races, _ = fn(recs, tpb=2)
-        assert as_dict(races) == exp, (fn.__name__, line)
-    assert oracle.tier_a_py(recs, 2) == exp
+        assert with_kinds(races) == exp, (fn.__name__, line)
+    assert oracle.tier_a_py(recs, 2) == counts_only(exp)
 
 
-@pytest.mark.parametrize("name", ["fig6_unit.txt", "fig6_unit_write.txt", "kaldi_copy.txt"])
+@pytest.mark.parametrize("name", FIXTURES)
 def test_trace_fixtures(name):
     recs, tpb, exp = trace_fixture(name)
     for fn in (oracle.brute_force, oracle.closed_form):
         races, summ = fn(recs, tpb=tpb)
-        assert as_dict(races) == exp
+        assert with_kinds(races) == exp
         assert int(summ[0]["n_records"]) == len(recs)
         assert int(summ[0]["n_race_locs"]) == len(exp)
-    assert oracle.tier_a_py(recs, tpb) == exp
+        assert int(summ[0]["n_pairs"]) == sum(d["ww"] + d["rw"] + d["aw"] + d["ar"] for d in exp.values())
+    assert oracle.tier_a_py(recs, tpb) == counts_only(exp)
 
 
 def test_kaldi_names_the_papers_thread_pair():

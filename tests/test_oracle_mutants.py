@@ -36,6 +36,11 @@ MUTANTS = {
     "closed_epoch_groups_by_block": ("while (je < jb && it[je].epoch == it[ie].epoch)",
                                      "while (je < jb && it[je].block == it[ie].block)"),
     "brute_same_thread_allowed": ("if (x->tid == y->tid) continue;", ""),
+    "kinds_aw_ar_swapped": ("(e->pairs_aw ? 4 : 0) |\n                       (e->pairs_ar ? 8 : 0)",
+                            "(e->pairs_aw ? 8 : 0) |\n                       (e->pairs_ar ? 4 : 0)"),
+    "kinds_xblock_dropped": (" | (e->pairs_xblock ? 16 : 0)", ""),
+    "kinds_rw_from_ww": ("(e->pairs_rw ? 2 : 0)", "(e->pairs_ww ? 2 : 0)"),
+    "kinds_ww_bit_dropped": ("(e->pairs_ww ? 1 : 0) | ", ""),
     "block_from_wrong_tpb": ("const uint32_t T = tpb[tr];\n    for (uint64_t i = 0; i < n; i++) {",
                              "const uint32_t T = tpb[tr] + 1;\n    for (uint64_t i = 0; i < n; i++) {"),
 }
@@ -57,12 +62,12 @@ def _pins_pass():
     """The pin checks, run against whatever library oracle._lib holds."""
     for line, recs, exp in truth_table():
         for fn in (oracle.brute_force, oracle.closed_form):
-            if oracle.races_to_dict(fn(recs, tpb=2)[0]) != exp:
+            if oracle.races_to_dict(fn(recs, tpb=2)[0], kinds=True) != exp:
                 return False
-    for name in ("fig6_unit.txt", "fig6_unit_write.txt", "kaldi_copy.txt"):
+    for name in ("fig6_unit.txt", "fig6_unit_write.txt", "kaldi_copy.txt", "mixed_kinds.txt"):
         recs, tpb, exp = trace_fixture(name)
         for fn in (oracle.brute_force, oracle.closed_form):
-            if oracle.races_to_dict(fn(recs, tpb=tpb)[0]) != exp:
+            if oracle.races_to_dict(fn(recs, tpb=tpb)[0], kinds=True) != exp:
                 return False
     for removed in range(-1, 9):
         recs = tracegen.tree_reduction(removed)
