@@ -8,7 +8,9 @@ Two native tiers live in ``oracle.c`` (built into ``liboracle.so``):
   * ``brute_force`` -- Tier A, the pairwise race definition of Theorem 1
     (Sec. 4.2.3) applied to every pair, O(n^2);
   * ``closed_form`` -- Tier B, group counts by location / block / epoch /
-    thread and inclusion-exclusion over them.
+    thread and inclusion-exclusion over them;
+  * ``closed_form_par`` -- Tier B's same counting spread over OpenMP
+    threads (by trace, and by location-hash bucket within a large trace).
 ``tier_a_py`` is a third, pure-Python rendering of the pairwise definition
 for tiny inputs, written separately so that the C tiers can be checked
 against it.
@@ -58,7 +60,7 @@ class OracleError(Exception):
 def build() -> str:
     """Compile liboracle.so with gcc (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.run(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp], check=True)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp], check=True)
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -84,6 +86,11 @@ def _load():
                 ctypes.c_void_p,
                 ctypes.POINTER(ctypes.c_uint64),
             ]
+        f = lib.orc_closed_form_par
+        f.restype = ctypes.c_int64
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                      ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                      ctypes.c_int, ctypes.c_uint64]
         lib.orc_free.restype = None
         lib.orc_free.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -105,7 +112,7 @@ def _as_batch(records, offsets=None, tpb=None):
     return records, offsets, n_traces, tpb
 
 
-def _run(fname, records, offsets, tpb):
+def _run(fname, records, offsets, tpb, *extra):
     records, offsets, n_traces, tpb = _as_batch(records, offsets, tpb)
     lib = _load()
     out = ctypes.c_void_p()
@@ -119,6 +126,7 @@ def _run(fname, records, offsets, tpb):
         ctypes.byref(out),
         summ.ctypes.data,
         ctypes.byref(bad),
+        *extra,
     )
     if n < 0:
         raise OracleError(int(n), int(bad.value) if n == -2 else None)
@@ -138,6 +146,23 @@ def brute_force(records, offsets=None, tpb=None):
 def closed_form(records, offsets=None, tpb=None):
     """Tier B: inclusion-exclusion over location/block/epoch/thread groups."""
     return _run("orc_closed_form", records, offsets, tpb)
+
+
+def closed_form_par(records, offsets=None, tpb=None, threads=0, bucket_min=1 << 22):
+    """Tier B's counting spread over OpenMP threads (0: every core): traces of
+    at most bucket_min records are independent units, a larger trace is split
+    into location-hash buckets counted separately.  Same result as
+    closed_form."""
+    return _run("orc_closed_form_par", records, offsets, tpb, int(threads), int(bucket_min))
+
+
+def omp_threads():
+    """Threads the parallel tier uses by default (OpenMP's maximum)."""
+    import ctypes.util
+
+    gomp = ctypes.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
+    gomp.omp_get_max_threads.restype = ctypes.c_int
+    return int(gomp.omp_get_max_threads())
 
 
 # ---------------------------------------------------------------------------

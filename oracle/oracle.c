@@ -257,6 +257,77 @@ static int same_loc(const item* x, const item* y) {
   return x->space == y->space && x->lblock == y->lblock && x->unit == y->unit;
 }
 
+/* Tier B's counting over one sorted run of items of trace `tr`: every
+ * location [i, iL) is split into its block, epoch and thread groups, and
+ * its pairs are the inclusion-exclusion of the groups' K values. */
+static int count_sorted(const item* it, uint64_t n, uint32_t tr, race_list* res) {
+  uint64_t i = 0;
+  while (i < n) {
+    /* one location [i, iL) */
+    uint64_t iL = i;
+    counts cL = {0, 0, 0};
+    while (iL < n && same_loc(&it[iL], &it[i])) add(&cL, it[iL++].action);
+    uint64_t KL[4], SB[4] = {0, 0, 0, 0}, SE[4] = {0, 0, 0, 0}, ST[4] = {0, 0, 0, 0}, tmp[4];
+    K(&cL, KL);
+    for (uint64_t ib = i; ib < iL;) { /* block groups */
+      uint64_t jb = ib;
+      counts cB = {0, 0, 0};
+      while (jb < iL && it[jb].block == it[ib].block) add(&cB, it[jb++].action);
+      K(&cB, tmp);
+      for (int k = 0; k < 4; k++) SB[k] += tmp[k];
+      for (uint64_t ie = ib; ie < jb;) { /* epoch groups */
+        uint64_t je = ie;
+        counts cE = {0, 0, 0};
+        while (je < jb && it[je].epoch == it[ie].epoch) add(&cE, it[je++].action);
+        K(&cE, tmp);
+        for (int k = 0; k < 4; k++) SE[k] += tmp[k];
+        for (uint64_t itd = ie; itd < je;) { /* thread groups */
+          uint64_t jt = itd;
+          counts cT = {0, 0, 0};
+          while (jt < je && it[jt].tid == it[itd].tid) add(&cT, it[jt++].action);
+          K(&cT, tmp);
+          for (int k = 0; k < 4; k++) ST[k] += tmp[k];
+          itd = jt;
+        }
+        ie = je;
+      }
+      ib = jb;
+    }
+    uint64_t p[4], xb = 0;
+    for (int k = 0; k < 4; k++) {
+      p[k] = KL[k] - SB[k] + SE[k] - ST[k];
+      xb += KL[k] - SB[k];
+    }
+    if (p[0] + p[1] + p[2] + p[3] > 0) {
+      orc_race e;
+      memset(&e, 0, sizeof e);
+      e.trace = tr;
+      e.space = it[i].space;
+      e.block = it[i].lblock;
+      e.unit = it[i].unit;
+      e.pairs_ww = p[KIND_WW];
+      e.pairs_rw = p[KIND_RW];
+      e.pairs_aw = p[KIND_AW];
+      e.pairs_ar = p[KIND_AR];
+      e.pairs_xblock = xb;
+      finish_entry(&e);
+      if (push(res, &e)) return ORC_ENOMEM;
+    }
+    i = iL;
+  }
+  return ORC_OK;
+}
+
+static void to_item(const orc_record* r, uint32_t T, item* x) {
+  x->unit = r->unit;
+  x->block = r->tid / T;
+  x->lblock = r->space == 1 ? x->block : 0xFFFFFFFFu;
+  x->tid = r->tid;
+  x->epoch = r->epoch;
+  x->space = r->space;
+  x->action = r->action;
+}
+
 int64_t orc_closed_form(const orc_record* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
                         orc_race** out, orc_summary* summary, uint64_t* bad_index) {
   int rc = validate(recs, off, n_traces, tpb, bad_index);
@@ -270,73 +341,186 @@ int64_t orc_closed_form(const orc_record* recs, const uint64_t* off, uint32_t n_
   for (uint32_t tr = 0; tr < n_traces; tr++) {
     const uint64_t lo = off[tr], n = off[tr + 1] - off[tr];
     const uint32_t T = tpb[tr];
-    for (uint64_t i = 0; i < n; i++) {
-      const orc_record* r = &recs[lo + i];
-      it[i].unit = r->unit;
-      it[i].block = r->tid / T;
-      it[i].lblock = r->space == 1 ? it[i].block : 0xFFFFFFFFu;
-      it[i].tid = r->tid;
-      it[i].epoch = r->epoch;
-      it[i].space = r->space;
-      it[i].action = r->action;
-    }
+    for (uint64_t i = 0; i < n; i++) to_item(&recs[lo + i], T, &it[i]);
     if (n) qsort(it, n, sizeof(item), cmp_item);
-    uint64_t i = 0;
-    while (i < n) {
-      /* one location [i, iL) */
-      uint64_t iL = i;
-      counts cL = {0, 0, 0};
-      while (iL < n && same_loc(&it[iL], &it[i])) add(&cL, it[iL++].action);
-      uint64_t KL[4], SB[4] = {0, 0, 0, 0}, SE[4] = {0, 0, 0, 0}, ST[4] = {0, 0, 0, 0}, tmp[4];
-      K(&cL, KL);
-      for (uint64_t ib = i; ib < iL;) { /* block groups */
-        uint64_t jb = ib;
-        counts cB = {0, 0, 0};
-        while (jb < iL && it[jb].block == it[ib].block) add(&cB, it[jb++].action);
-        K(&cB, tmp);
-        for (int k = 0; k < 4; k++) SB[k] += tmp[k];
-        for (uint64_t ie = ib; ie < jb;) { /* epoch groups */
-          uint64_t je = ie;
-          counts cE = {0, 0, 0};
-          while (je < jb && it[je].epoch == it[ie].epoch) add(&cE, it[je++].action);
-          K(&cE, tmp);
-          for (int k = 0; k < 4; k++) SE[k] += tmp[k];
-          for (uint64_t itd = ie; itd < je;) { /* thread groups */
-            uint64_t jt = itd;
-            counts cT = {0, 0, 0};
-            while (jt < je && it[jt].tid == it[itd].tid) add(&cT, it[jt++].action);
-            K(&cT, tmp);
-            for (int k = 0; k < 4; k++) ST[k] += tmp[k];
-            itd = jt;
-          }
-          ie = je;
-        }
-        ib = jb;
-      }
-      uint64_t p[4], xb = 0;
-      for (int k = 0; k < 4; k++) {
-        p[k] = KL[k] - SB[k] + SE[k] - ST[k];
-        xb += KL[k] - SB[k];
-      }
-      if (p[0] + p[1] + p[2] + p[3] > 0) {
-        orc_race e;
-        memset(&e, 0, sizeof e);
-        e.trace = tr;
-        e.space = it[i].space;
-        e.block = it[i].lblock;
-        e.unit = it[i].unit;
-        e.pairs_ww = p[KIND_WW];
-        e.pairs_rw = p[KIND_RW];
-        e.pairs_aw = p[KIND_AW];
-        e.pairs_ar = p[KIND_AR];
-        e.pairs_xblock = xb;
-        finish_entry(&e);
-        if (push(&res, &e)) { free(it); free(res.v); return ORC_ENOMEM; }
-      }
-      i = iL;
-    }
+    if (count_sorted(it, n, tr, &res)) { free(it); free(res.v); return ORC_ENOMEM; }
   }
   free(it);
+  summarise(&res, off, n_traces, summary);
+  *out = res.v;
+  return (int64_t)res.n;
+}
+
+/* ============ Tier B on many cores: the same counting, split up ============
+ *
+ * The work of orc_closed_form is divided among OpenMP threads without any
+ * change to what is computed:
+ *   - traces of at most `bucket_min` records are independent units, handed
+ *     to the threads largest first;
+ *   - a larger trace is split by a hash of the location into buckets; all
+ *     records of one location fall into one bucket, so each bucket is
+ *     sorted and counted by count_sorted exactly as a whole trace is, and
+ *     the trace's entries are the union of its buckets' entries, put back
+ *     in location order.
+ * n_threads = 0 uses every core OpenMP sees. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static uint64_t loc_hash(const item* x) {
+  uint64_t h = x->unit ^ ((uint64_t)x->lblock << 32) ^ ((uint64_t)x->space << 63);
+  h ^= h >> 33;
+  h *= 0xff51afd7ed558ccdull;
+  h ^= h >> 33;
+  h *= 0xc4ceb9fe1a85ec53ull;
+  h ^= h >> 33;
+  return h;
+}
+
+typedef struct {
+  uint32_t trace;
+  uint64_t n;
+} trace_ref;
+
+static int cmp_trace_ref(const void* pa, const void* pb) {
+  const trace_ref* a = (const trace_ref*)pa;
+  const trace_ref* b = (const trace_ref*)pb;
+  if (a->n != b->n) return a->n > b->n ? -1 : 1;
+  return a->trace < b->trace ? -1 : (a->trace > b->trace);
+}
+
+/* One large trace, bucket by bucket on all threads; its entries go to *res. */
+static int big_trace(const orc_record* recs, uint64_t lo, uint64_t n, uint32_t T, uint32_t tr, int nth,
+                     race_list* res) {
+  const uint32_t nb = (uint32_t)(8 * nth);
+  item* it = (item*)malloc(n * sizeof(item));
+  uint64_t* cnt = (uint64_t*)calloc((size_t)nth * nb, sizeof(uint64_t));
+  uint64_t* start = (uint64_t*)calloc((size_t)nb + 1, sizeof(uint64_t));
+  race_list* parts = (race_list*)calloc(nb, sizeof(race_list));
+  int rc = ORC_OK;
+  if (!it || !cnt || !start || !parts) { rc = ORC_ENOMEM; goto done; }
+  /* bucket of every record, counted per thread over fixed chunks */
+#pragma omp parallel num_threads(nth)
+  {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    const uint64_t c0 = n * (uint64_t)t / (uint64_t)nth, c1 = n * (uint64_t)(t + 1) / (uint64_t)nth;
+    item x;
+    for (uint64_t i = c0; i < c1; i++) {
+      to_item(&recs[lo + i], T, &x);
+      cnt[(size_t)t * nb + loc_hash(&x) % nb]++;
+    }
+  }
+  /* bucket b's records go to [start[b], start[b+1]), thread by thread */
+  {
+    uint64_t run = 0;
+    for (uint32_t b = 0; b < nb; b++) {
+      start[b] = run;
+      for (int t = 0; t < nth; t++) {
+        const uint64_t c = cnt[(size_t)t * nb + b];
+        cnt[(size_t)t * nb + b] = run;
+        run += c;
+      }
+    }
+    start[nb] = run;
+  }
+#pragma omp parallel num_threads(nth)
+  {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    const uint64_t c0 = n * (uint64_t)t / (uint64_t)nth, c1 = n * (uint64_t)(t + 1) / (uint64_t)nth;
+    item x;
+    for (uint64_t i = c0; i < c1; i++) {
+      to_item(&recs[lo + i], T, &x);
+      it[cnt[(size_t)t * nb + loc_hash(&x) % nb]++] = x;
+    }
+  }
+  /* each bucket: sort and count as a whole trace */
+  {
+    int err = 0;
+#pragma omp parallel for num_threads(nth) schedule(dynamic, 1) reduction(| : err)
+    for (int64_t b = 0; b < (int64_t)nb; b++) {
+      const uint64_t m = start[b + 1] - start[b];
+      if (m) qsort(it + start[b], m, sizeof(item), cmp_item);
+      if (count_sorted(it + start[b], m, tr, &parts[b])) err |= 1;
+    }
+    if (err) { rc = ORC_ENOMEM; goto done; }
+  }
+  {
+    const uint64_t first = res->n;
+    for (uint32_t b = 0; b < nb && rc == ORC_OK; b++)
+      for (uint64_t k = 0; k < parts[b].n; k++)
+        if (push(res, &parts[b].v[k])) { rc = ORC_ENOMEM; break; }
+    if (rc == ORC_OK && res->n > first) qsort(res->v + first, res->n - first, sizeof(orc_race), cmp_entry);
+  }
+done:
+  if (parts)
+    for (uint32_t b = 0; b < nb; b++) free(parts[b].v);
+  free(parts);
+  free(start);
+  free(cnt);
+  free(it);
+  return rc;
+}
+
+int64_t orc_closed_form_par(const orc_record* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                            orc_race** out, orc_summary* summary, uint64_t* bad_index, int n_threads,
+                            uint64_t bucket_min) {
+  int rc = validate(recs, off, n_traces, tpb, bad_index);
+  if (rc) return rc;
+  int nth = n_threads;
+#ifdef _OPENMP
+  if (nth <= 0) nth = omp_get_max_threads();
+#endif
+  if (nth <= 0) nth = 1;
+  race_list* per = (race_list*)calloc(n_traces ? n_traces : 1, sizeof(race_list));
+  trace_ref* order = (trace_ref*)malloc((n_traces ? n_traces : 1) * sizeof(trace_ref));
+  if (!per || !order) { free(per); free(order); return ORC_ENOMEM; }
+  uint32_t n_small = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t n = off[tr + 1] - off[tr];
+    if (n <= bucket_min) order[n_small++] = (trace_ref){tr, n};
+  }
+  qsort(order, n_small, sizeof(trace_ref), cmp_trace_ref);
+  int err = 0;
+  /* small traces: one unit each, largest first */
+#pragma omp parallel num_threads(nth) reduction(| : err)
+  {
+    item* it = NULL;
+    uint64_t cap = 0;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t k = 0; k < (int64_t)n_small; k++) {
+      const uint32_t tr = order[k].trace;
+      const uint64_t lo = off[tr], n = order[k].n;
+      if (n > cap) {
+        free(it);
+        it = (item*)malloc(n * sizeof(item));
+        cap = it ? n : 0;
+        if (!it) { err |= 1; continue; }
+      }
+      for (uint64_t i = 0; i < n; i++) to_item(&recs[lo + i], tpb[tr], &it[i]);
+      if (n) qsort(it, n, sizeof(item), cmp_item);
+      if (count_sorted(it, n, tr, &per[tr])) err |= 1;
+    }
+    free(it);
+  }
+  /* large traces: one at a time, bucket by bucket on all threads */
+  for (uint32_t tr = 0; tr < n_traces && !err; tr++) {
+    const uint64_t n = off[tr + 1] - off[tr];
+    if (n > bucket_min && big_trace(recs, off[tr], n, tpb[tr], tr, nth, &per[tr])) err |= 1;
+  }
+  race_list res = {0, 0, 0};
+  for (uint32_t tr = 0; tr < n_traces && !err; tr++)
+    for (uint64_t k = 0; k < per[tr].n; k++)
+      if (push(&res, &per[tr].v[k])) { err |= 1; break; }
+  for (uint32_t tr = 0; tr < n_traces; tr++) free(per[tr].v);
+  free(per);
+  free(order);
+  if (err) { free(res.v); return ORC_ENOMEM; }
   summarise(&res, off, n_traces, summary);
   *out = res.v;
   return (int64_t)res.n;

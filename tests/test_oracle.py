@@ -187,6 +187,39 @@ def test_tiers_agree_medium(seed):
     assert len(a) > 0 and len(a) == len(b) and (a == b).all()
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_parallel_tier_b_equals_tier_b(seed):
+    """The OpenMP driver of Tier B (by trace, and by location-hash bucket
+    inside a trace) gives Tier B's result byte for byte: tiny random batches
+    in bucket mode (bucket_min = 0) and trace mode, over 1 to 5 threads."""
+    rng = np.random.default_rng(400 + seed)
+    k = int(rng.integers(1, 6))
+    traces = [tracegen.random_small(rng, int(rng.integers(0, 300)), units=int(rng.integers(1, 30)),
+                                    blocks=int(rng.integers(1, 4)), tpb=4, epochs=3) for _ in range(k)]
+    recs = np.concatenate(traces)
+    off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    want, wsum = oracle.closed_form(recs, off, 4)
+    for threads in (1, 2, 5):
+        for bucket_min in (0, 100, 1 << 22):
+            got, gsum = oracle.closed_form_par(recs, off, 4, threads=threads, bucket_min=bucket_min)
+            assert got.tobytes() == want.tobytes(), (threads, bucket_min)
+            assert gsum.tobytes() == wsum.tobytes()
+
+
+def test_parallel_tier_b_on_generated_traces():
+    """The same on a generated c1-shaped trace (64 blocks, 2^20 records,
+    injected races) split into buckets, and on a batch of 40 traces."""
+    r, _ = tracegen.c1(n_blocks=64, inject_rate=1e-3)
+    want, wsum = oracle.closed_form(r, tpb=256)
+    got, gsum = oracle.closed_form_par(r, tpb=256, threads=4, bucket_min=1 << 16)
+    assert len(want) > 0 and got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes()
+    shapes = tracegen.c3_shapes(40, log2_max=15)
+    recs, off, tpb, _ = tracegen.batch(shapes, inject_rate=1e-3)
+    want, wsum = oracle.closed_form(recs, off, tpb)
+    got, gsum = oracle.closed_form_par(recs, off, tpb, threads=3, bucket_min=1 << 13)
+    assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes()
+
+
 def test_batched_equals_concatenation():
     rng = np.random.default_rng(11)
     traces = [tracegen.random_small(rng, int(rng.integers(0, 200)), units=6, blocks=3, tpb=3) for _ in range(7)]

@@ -31,8 +31,8 @@ MUTANTS = {
     "brute_no_cross_block": ("if (!(bx != by || x->epoch == y->epoch)) continue;",
                              "if (!(x->epoch == y->epoch)) continue;"),
     "brute_shared_not_per_block": ("if (x->space == 1 && bx != by) continue;", ""),
-    "closed_shared_not_per_block": ("it[i].lblock = r->space == 1 ? it[i].block : 0xFFFFFFFFu;",
-                                    "it[i].lblock = 0xFFFFFFFFu;"),
+    "closed_shared_not_per_block": ("x->lblock = r->space == 1 ? x->block : 0xFFFFFFFFu;",
+                                    "x->lblock = 0xFFFFFFFFu;"),
     "closed_epoch_groups_by_block": ("while (je < jb && it[je].epoch == it[ie].epoch)",
                                      "while (je < jb && it[je].block == it[ie].block)"),
     "brute_same_thread_allowed": ("if (x->tid == y->tid) continue;", ""),
@@ -41,8 +41,7 @@ MUTANTS = {
     "kinds_xblock_dropped": (" | (e->pairs_xblock ? 16 : 0)", ""),
     "kinds_rw_from_ww": ("(e->pairs_rw ? 2 : 0)", "(e->pairs_ww ? 2 : 0)"),
     "kinds_ww_bit_dropped": ("(e->pairs_ww ? 1 : 0) | ", ""),
-    "block_from_wrong_tpb": ("const uint32_t T = tpb[tr];\n    for (uint64_t i = 0; i < n; i++) {",
-                             "const uint32_t T = tpb[tr] + 1;\n    for (uint64_t i = 0; i < n; i++) {"),
+    "block_from_wrong_tpb": ("  x->block = r->tid / T;", "  x->block = r->tid / (T + 1);"),
 }
 
 
