@@ -49,6 +49,8 @@ SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pair
 
 KIND_BITS = {"ww": 1, "rw": 2, "aw": 4, "ar": 8, "xblock": 16}
 
+BARRIER_DTYPE = np.dtype([("trace", "<u4"), ("boundary", "<u4"), ("instances", "<u8"), ("racing", "<u8")])
+
 
 class OracleError(Exception):
     def __init__(self, code, bad_index=None):
@@ -91,6 +93,11 @@ def _load():
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
                       ctypes.c_int, ctypes.c_uint64]
+        for name in ("orc_barriers_brute_force", "orc_barriers"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int64
+            f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                          ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64)]
         lib.orc_free.restype = None
         lib.orc_free.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -163,6 +170,65 @@ def omp_threads():
     gomp = ctypes.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
     gomp.omp_get_max_threads.restype = ctypes.c_int
     return int(gomp.omp_get_max_threads())
+
+
+def _run_barriers(fname, records, offsets, tpb):
+    records, offsets, n_traces, tpb = _as_batch(records, offsets, tpb)
+    lib = _load()
+    out = ctypes.c_void_p()
+    bad = ctypes.c_uint64(0)
+    n = getattr(lib, fname)(records.ctypes.data if len(records) else None, offsets.ctypes.data, n_traces,
+                            tpb.ctypes.data, ctypes.byref(out), ctypes.byref(bad))
+    if n < 0:
+        raise OracleError(int(n), int(bad.value) if n == -2 else None)
+    res = np.zeros(n, dtype=BARRIER_DTYPE)
+    if n:
+        ctypes.memmove(res.ctypes.data, out.value, n * BARRIER_DTYPE.itemsize)
+    if out.value:
+        lib.orc_free(out)
+    return res
+
+
+def barriers_brute_force(records, offsets=None, tpb=None):
+    """Barrier instances (Alg. 5, second loop), Tier A: every pair of
+    records tested.  One entry per (trace, boundary) with an instance:
+    instances, racing instances (the barrier is redundant when 0)."""
+    return _run_barriers("orc_barriers_brute_force", records, offsets, tpb)
+
+
+def barriers(records, offsets=None, tpb=None):
+    """Barrier instances, Tier B: adjacent epoch groups of every location
+    and block, compared pair by pair."""
+    return _run_barriers("orc_barriers", records, offsets, tpb)
+
+
+def barriers_py(records, tpb):
+    """Pure-Python rendering for one tiny trace: {boundary: (instances,
+    racing)}.  An instance is a (location, block) with records of that block
+    in epochs b and b+1; it races when a pair across the two epochs has
+    different threads and at least one write, not both atomic."""
+    recs = [tuple(int(v) for v in r) for r in records]  # unit, tid, epoch, action, space
+    groups = {}
+    for u, t, e, a, s in recs:
+        b = t // tpb
+        loc = (s, b if s == 1 else None, u)
+        groups.setdefault((loc, b), {}).setdefault(e, []).append((t, a))
+    out = {}
+    for (_, _), by_epoch in groups.items():
+        for e, xs in by_epoch.items():
+            ys = by_epoch.get(e + 1)
+            if ys is None:
+                continue
+            racing = any(tx != ty and not (ax == 0 and ay == 0) and not (ax == 2 and ay == 2)
+                         for tx, ax in xs for ty, ay in ys)
+            inst, rac = out.get(e, (0, 0))
+            out[e] = (inst + 1, rac + (1 if racing else 0))
+    return out
+
+
+def barriers_to_dict(res, trace=0):
+    """{boundary: (instances, racing)} of one trace from a BARRIER_DTYPE array."""
+    return {int(r["boundary"]): (int(r["instances"]), int(r["racing"])) for r in res if int(r["trace"]) == trace}
 
 
 # ---------------------------------------------------------------------------

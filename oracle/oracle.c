@@ -526,4 +526,195 @@ int64_t orc_closed_form_par(const orc_record* recs, const uint64_t* off, uint32_
   return (int64_t)res.n;
 }
 
+/* =============== Redundant barriers (Alg. 5, second loop) ===============
+ *
+ * Sec. 4.2.3: a barrier is redundant when removing it lets no data race be
+ * detected; Alg. 5 checks, per memory unit, whether the tuples of adjacent
+ * visit orders can be merged without a race, counts the mergeable changes
+ * per barrier, and calls the barrier redundant when that count equals the
+ * number of visit-order changes the barrier causes.
+ *
+ * Here, per trace: the barrier at boundary b of block B ends B's epoch b
+ * (the threads of B pass it between their epoch-b and epoch-(b+1)
+ * accesses).  An instance of it is a location L (a global unit, or a unit of
+ * B's shared memory) on which block B has records in both epochs b and b+1
+ * -- a visit-order change of L's unit that the barrier causes.  The
+ * instance is racing when merging the two epochs would race: some record x
+ * of epoch b and some record y of epoch b+1, both of block B on L, come
+ * from different threads and conflict (at least one writes; not both
+ * atomic).  Records of other blocks are concurrent with both epochs either
+ * way, so the barrier does not separate them from anything.  For every
+ * (trace, boundary) with at least one instance, one entry gives the number
+ * of instances and of racing instances; the barrier is redundant when no
+ * instance is racing.
+ */
+typedef struct {
+  uint32_t trace;
+  uint32_t boundary;
+  uint64_t instances;
+  uint64_t racing;
+} orc_barrier;
+
+typedef struct {
+  orc_barrier* v;
+  uint64_t n, cap;
+} barrier_list;
+
+static int push_barrier(barrier_list* L, const orc_barrier* e) {
+  if (L->n == L->cap) {
+    uint64_t nc = L->cap ? 2 * L->cap : 64;
+    orc_barrier* nv = (orc_barrier*)realloc(L->v, nc * sizeof(orc_barrier));
+    if (!nv) return ORC_ENOMEM;
+    L->v = nv;
+    L->cap = nc;
+  }
+  L->v[L->n++] = *e;
+  return ORC_OK;
+}
+
+/* whether two actions conflict: at least one write, not both atomic */
+static int conflicts(int a, int b) { return kind_of(a, b) >= 0; }
+
+/* One instance found by the brute force: (trace, boundary, location, block)
+ * and whether the pair that found it races. */
+typedef struct {
+  uint32_t trace, boundary, space, lblock, block, racing;
+  uint64_t unit;
+} inst_hit;
+
+static int cmp_inst_hit(const void* pa, const void* pb) {
+  const inst_hit* a = (const inst_hit*)pa;
+  const inst_hit* b = (const inst_hit*)pb;
+  if (a->trace != b->trace) return a->trace < b->trace ? -1 : 1;
+  if (a->boundary != b->boundary) return a->boundary < b->boundary ? -1 : 1;
+  if (a->space != b->space) return a->space < b->space ? -1 : 1;
+  if (a->lblock != b->lblock) return a->lblock < b->lblock ? -1 : 1;
+  if (a->unit != b->unit) return a->unit < b->unit ? -1 : 1;
+  if (a->block != b->block) return a->block < b->block ? -1 : 1;
+  return 0;
+}
+
+/* Instances of one sorted hit list, summed per (trace, boundary). */
+static int collect_instances(inst_hit* hits, uint64_t nh, barrier_list* res) {
+  if (nh) qsort(hits, nh, sizeof(inst_hit), cmp_inst_hit);
+  for (uint64_t i = 0; i < nh;) {
+    orc_barrier e = {hits[i].trace, hits[i].boundary, 0, 0};
+    uint64_t j = i;
+    while (j < nh && hits[j].trace == e.trace && hits[j].boundary == e.boundary) {
+      /* one instance: all hits with the same location and block */
+      uint64_t k = j;
+      uint32_t racing = 0;
+      while (k < nh && cmp_inst_hit(&hits[k], &hits[j]) == 0) racing |= hits[k++].racing;
+      e.instances++;
+      e.racing += racing;
+      j = k;
+    }
+    if (push_barrier(res, &e)) return ORC_ENOMEM;
+    i = j;
+  }
+  return ORC_OK;
+}
+
+/* Tier A: every pair of records of a trace, tested against the definition. */
+int64_t orc_barriers_brute_force(const orc_record* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                                 orc_barrier** out, uint64_t* bad_index) {
+  int rc = validate(recs, off, n_traces, tpb, bad_index);
+  if (rc) return rc;
+  inst_hit* hits = NULL;
+  uint64_t nh = 0, cap = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint32_t T = tpb[tr];
+    for (uint64_t i = off[tr]; i < off[tr + 1]; i++)
+      for (uint64_t j = off[tr]; j < off[tr + 1]; j++) {
+        const orc_record* x = &recs[i];
+        const orc_record* y = &recs[j];
+        const uint32_t bx = x->tid / T, by = y->tid / T;
+        /* x in epoch b, y in epoch b + 1, both of one block, one location */
+        if (bx != by || x->space != y->space || x->unit != y->unit) continue;
+        if ((uint32_t)y->epoch != (uint32_t)x->epoch + 1) continue;
+        if (nh == cap) {
+          cap = cap ? 2 * cap : 256;
+          inst_hit* nv = (inst_hit*)realloc(hits, cap * sizeof(inst_hit));
+          if (!nv) { free(hits); return ORC_ENOMEM; }
+          hits = nv;
+        }
+        inst_hit h;
+        h.trace = tr;
+        h.boundary = x->epoch;
+        h.space = x->space;
+        h.lblock = x->space == 1 ? bx : 0xFFFFFFFFu;
+        h.block = bx;
+        h.unit = x->unit;
+        h.racing = (x->tid != y->tid && conflicts(x->action, y->action)) ? 1u : 0u;
+        hits[nh++] = h;
+      }
+  }
+  barrier_list res = {0, 0, 0};
+  rc = collect_instances(hits, nh, &res);
+  free(hits);
+  if (rc) { free(res.v); return rc; }
+  *out = res.v;
+  return (int64_t)res.n;
+}
+
+/* Tier B: records grouped by location, block and epoch (sorted items); for
+ * every two adjacent epoch groups of one block and location, an instance,
+ * racing when some pair across the two groups races. */
+int64_t orc_barriers(const orc_record* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                     orc_barrier** out, uint64_t* bad_index) {
+  int rc = validate(recs, off, n_traces, tpb, bad_index);
+  if (rc) return rc;
+  uint64_t maxn = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++)
+    if (off[tr + 1] - off[tr] > maxn) maxn = off[tr + 1] - off[tr];
+  item* it = maxn ? (item*)malloc(maxn * sizeof(item)) : NULL;
+  if (maxn && !it) return ORC_ENOMEM;
+  inst_hit* hits = NULL;
+  uint64_t nh = 0, cap = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t lo = off[tr], n = off[tr + 1] - off[tr];
+    for (uint64_t i = 0; i < n; i++) to_item(&recs[lo + i], tpb[tr], &it[i]);
+    if (n) qsort(it, n, sizeof(item), cmp_item);
+    /* epoch groups [g0, g1) and [g1, g2) of one location and block */
+    for (uint64_t g0 = 0; g0 < n;) {
+      uint64_t g1 = g0;
+      while (g1 < n && same_loc(&it[g1], &it[g0]) && it[g1].block == it[g0].block && it[g1].epoch == it[g0].epoch)
+        g1++;
+      if (g1 < n && same_loc(&it[g1], &it[g0]) && it[g1].block == it[g0].block &&
+          (uint32_t)it[g1].epoch == (uint32_t)it[g0].epoch + 1) {
+        uint64_t g2 = g1;
+        while (g2 < n && same_loc(&it[g2], &it[g1]) && it[g2].block == it[g1].block && it[g2].epoch == it[g1].epoch)
+          g2++;
+        uint32_t racing = 0;
+        for (uint64_t a = g0; a < g1 && !racing; a++)
+          for (uint64_t b = g1; b < g2 && !racing; b++)
+            if (it[a].tid != it[b].tid && conflicts(it[a].action, it[b].action)) racing = 1;
+        if (nh == cap) {
+          cap = cap ? 2 * cap : 256;
+          inst_hit* nv = (inst_hit*)realloc(hits, cap * sizeof(inst_hit));
+          if (!nv) { free(hits); free(it); return ORC_ENOMEM; }
+          hits = nv;
+        }
+        inst_hit h;
+        h.trace = tr;
+        h.boundary = it[g0].epoch;
+        h.space = it[g0].space;
+        h.lblock = it[g0].lblock;
+        h.block = it[g0].block;
+        h.unit = it[g0].unit;
+        h.racing = racing;
+        hits[nh++] = h;
+      }
+      g0 = g1;
+    }
+  }
+  free(it);
+  barrier_list res = {0, 0, 0};
+  rc = collect_instances(hits, nh, &res);
+  free(hits);
+  if (rc) { free(res.v); return rc; }
+  *out = res.v;
+  return (int64_t)res.n;
+}
+
 void orc_free(void* p) { free(p); }

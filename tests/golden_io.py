@@ -87,3 +87,25 @@ def trace_fixture(name):
     for i, v in enumerate(recs):
         r[i] = v
     return r, tpb, exp
+
+
+def barrier_fixture(name):
+    """Return (records, tpb, {boundary: (instances, racing)}) of a barrier
+    fixture (rec lines as in trace fixtures, expect_barrier lines)."""
+    tpb = None
+    recs = []
+    exp = {}
+    for line in _lines(name):
+        f = line.split()
+        if f[0] == "tpb":
+            tpb = int(f[1])
+        elif f[0] == "rec":
+            recs.append((int(f[1]), int(f[2]), int(f[3]), ACT[f[4]], SPACE[f[5]]))
+        elif f[0] == "expect_barrier":
+            lhs, rhs = line[len("expect_barrier"):].split("|")
+            inst, rac = (int(v) for v in rhs.split())
+            exp[int(lhs)] = (inst, rac)
+    r = np.zeros(len(recs), dtype=RECORD_DTYPE)
+    for i, v in enumerate(recs):
+        r[i] = v
+    return r, tpb, exp
