@@ -172,6 +172,50 @@ int sim_check_traces_device(sim_ctx* ctx, const sim_record* d_records, const uin
 /* Free a result.  NULL is ignored. */
 void sim_result_free(sim_result* r);
 
+/* ------------------------------------------------------ redundant barriers */
+
+/* One barrier boundary of one trace (24 bytes): the barrier a block passes
+ * between its epoch `boundary` and epoch `boundary + 1` (paper Sec. 4.2.3
+ * and the second loop of Alg. 5).  An instance is a location (a global
+ * unit, or a unit of the block's shared memory) on which one block has
+ * records in both of those epochs: a visit-order change the barrier causes.
+ * The instance is racing when some pair of the block's records across the
+ * barrier would race once the barrier were removed (different threads, at
+ * least one write, not both atomic; the warp clauses are not applied).
+ * Records of different blocks are never separated by a barrier.  The
+ * barrier is redundant when none of its instances is racing: no race is
+ * detected by removing it.  A barrier that several boundaries share (one
+ * barrier statement in a loop) is redundant when all of them are; blocks
+ * are taken to pass the same barrier statements in the same order.       */
+typedef struct sim_barrier {
+  uint32_t trace;     /* index of the trace in the call */
+  uint32_t boundary;  /* epochs boundary and boundary + 1 */
+  uint64_t instances; /* locations a block touches on both sides */
+  uint64_t racing;    /* instances that would race without the barrier */
+} sim_barrier;
+
+typedef struct sim_barrier_result {
+  sim_barrier* barriers; /* n_barriers entries, host memory: every (trace, boundary) with an instance,
+                            ordered by trace, then boundary */
+  uint64_t n_barriers;
+} sim_barrier_result;
+
+/* The race check of sim_check_traces_device and, over the same sorted keys,
+ * the redundant-barrier check: *races as sim_check_traces_device gives it,
+ * *barriers every (trace, boundary) that has an instance.  barriers may be
+ * NULL (then only races).  Arguments, ownership and errors as for
+ * sim_check_traces_device; on error both outputs are NULL.                */
+int sim_check_sync_device(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
+                          const uint32_t* threads_per_block, void* stream, sim_result** races,
+                          sim_barrier_result** barriers);
+
+/* The same for records in host memory (copied to the device first). */
+int sim_check_sync(sim_ctx* ctx, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
+                   const uint32_t* threads_per_block, sim_result** races, sim_barrier_result** barriers);
+
+/* Free a barrier result.  NULL is ignored. */
+void sim_barrier_result_free(sim_barrier_result* r);
+
 /* -------------------------------------------------------------- profiling */
 
 /* Per-stage device time of the last call on a context created with
@@ -252,15 +296,24 @@ int sim_autotune(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offs
  * to the request), including its error code: when a batch fails, its
  * requests are checked one by one so that one bad request fails alone.
  *
- * Admission by device-memory footprint: a request needs about
- * 36 bytes per record + 4.5 KiB per 4096-record tile + 128 bytes per
- * trace (records, two key buffers, per-tile and per-trace tables, output);
- * the footprints of the batches on the GPU never exceed the budget, and a
- * worker releases its buffers after a batch when they exceed its share
- * (budget / slots).  A request whose footprint alone exceeds the budget is
- * refused at submission (SIM_ENOMEM).  The footprint counts one-word keys; a
- * request whose traces need two-word keys (see sim_check_traces) holds up to
- * 16 bytes per record more while it runs.
+ * Admission by device-memory footprint.  A request's footprint is what its
+ * check may hold on the device: its records when they come from host
+ * memory (16 bytes each), two key buffers of 16 bytes per record (two-word
+ * keys are possible until the device has seen the request), about 4.3 KiB
+ * per 4096-record tile and 136 bytes per trace of tables, and the output's
+ * first allocation (up to 64 Ki entries of 64 bytes), each with 1/8 growth
+ * headroom.  Every worker is charged the device bytes it may hold: an idle
+ * worker what it holds, a worker checking a batch the larger of that and
+ * the batch's footprint, and its buffers never grow past its charge (a
+ * worker whose buffers would grow past it releases them and allocates the
+ * batch's sizes afresh).  A batch is admitted only while the charges of all
+ * workers stay within the budget; when the first pending request fits no
+ * worker, idle workers release their buffers.  A request whose output
+ * outgrows the usual estimate (more than 64 Ki racing locations, or a tile
+ * staging overflow) fails within its charge and is queued again, alone,
+ * charged its worst case (an entry for every second record, in the output
+ * and in staging).  A request whose footprint, or worst case when it comes
+ * to that, exceeds the budget fails with SIM_ENOMEM.
  *
  * All server calls are thread-safe.                                        */
 typedef struct sim_server sim_server;
@@ -285,8 +338,9 @@ typedef struct sim_server_stats {
   double p50_ms, p99_ms, max_ms, mean_ms; /* latency of completed requests, submission to result ready */
   double records_per_s;                  /* records of completed requests / (last completion - first submission) */
   double mean_batch_requests;            /* completed requests per batch */
-  uint64_t peak_inflight_bytes;          /* largest sum of footprints on the GPU */
+  uint64_t peak_inflight_bytes;          /* largest sum of the workers' charges (at most the budget) */
   uint64_t device_bytes;                 /* device buffers the workers hold now */
+  uint64_t requeued;                     /* requests queued again, charged their worst case */
 } sim_server_stats;
 
 /* Create a server on HIP device `hip_device` (gfx950).  cfg may be NULL.  */
@@ -305,6 +359,17 @@ void sim_server_destroy(sim_server* srv);
  * (max_pending requests wait already).                                     */
 int sim_submit(sim_server* srv, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
                const uint32_t* threads_per_block, uint64_t* ticket);
+
+/* Submit one request whose records already live in device memory of the
+ * server's GPU (e.g. a torch tensor's storage): the workers read them where
+ * they are, with no copy, so a batch of such requests moves no record over
+ * PCIe.  d_records: offsets[n_traces] records, device memory, caller-owned;
+ * it must stay valid and unchanged until the request's result has been
+ * collected.  offsets and threads_per_block are host arrays, copied as for
+ * sim_submit; errors as for sim_submit.  The footprint does not count the
+ * records.                                                                 */
+int sim_submit_device(sim_server* srv, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
+                      const uint32_t* threads_per_block, uint64_t* ticket);
 
 /* Collect a request's result: SIM_EAGAIN while it is pending; otherwise the
  * request's own return code, with *out set on success (caller frees it with

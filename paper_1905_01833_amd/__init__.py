@@ -8,9 +8,12 @@ is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import json
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -27,6 +30,7 @@ RACE_DTYPE = np.dtype(
     ]
 )
 SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pairs", "<u8")])
+BARRIER_DTYPE = np.dtype([("trace", "<u4"), ("boundary", "<u4"), ("instances", "<u8"), ("racing", "<u8")])
 
 SIM_OK, SIM_EINVAL, SIM_ERECORD, SIM_ENOMEM, SIM_EDEVICE, SIM_ERANGE = 0, -1, -2, -3, -4, -6
 SIM_CFG_PROFILE = 1
@@ -36,8 +40,10 @@ STAGES = ["init", "stats", "layout", "keygen", "upsweep", "sort_pass", "scan_til
 # Symbols declared in include/simcheck.h.
 EXPORTS = [
     "sim_create", "sim_destroy", "sim_last_error", "sim_check_traces", "sim_check_traces_device",
-    "sim_result_free", "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning",
-    "sim_get_tuning", "sim_autotune", "sim_server_create", "sim_server_destroy", "sim_submit", "sim_poll",
+    "sim_result_free", "sim_check_sync_device", "sim_check_sync",
+    "sim_barrier_result_free", "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning",
+    "sim_get_tuning", "sim_autotune", "sim_server_create", "sim_server_destroy", "sim_submit", "sim_submit_device",
+    "sim_poll",
     "sim_wait", "sim_server_get_stats", "sim_server_last_error",
 ]
 SIM_EAGAIN = -5
@@ -58,6 +64,10 @@ class _Result(ctypes.Structure):
         ("traces", ctypes.c_void_p),
         ("n_traces", ctypes.c_uint32),
     ]
+
+
+class _BarrierResult(ctypes.Structure):
+    _fields_ = [("barriers", ctypes.c_void_p), ("n_barriers", ctypes.c_uint64)]
 
 
 class _Config(ctypes.Structure):
@@ -104,7 +114,7 @@ class _ServerStats(ctypes.Structure):
         ("batches", ctypes.c_uint64), ("records", ctypes.c_uint64),
         ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
         ("mean_ms", ctypes.c_double), ("records_per_s", ctypes.c_double), ("mean_batch_requests", ctypes.c_double),
-        ("peak_inflight_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+        ("peak_inflight_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64), ("requeued", ctypes.c_uint64),
     ]
 
 
@@ -134,6 +144,14 @@ def load() -> ctypes.CDLL:
     lib.sim_check_traces.argtypes = [P, P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.POINTER(_Result))]
     lib.sim_check_traces_device.restype = ctypes.c_int
     lib.sim_check_traces_device.argtypes = [P, P, P, ctypes.c_uint32, P, P, ctypes.POINTER(ctypes.POINTER(_Result))]
+    lib.sim_check_sync_device.restype = ctypes.c_int
+    lib.sim_check_sync_device.argtypes = [P, P, P, ctypes.c_uint32, P, P, ctypes.POINTER(ctypes.POINTER(_Result)),
+                                          ctypes.POINTER(ctypes.POINTER(_BarrierResult))]
+    lib.sim_check_sync.restype = ctypes.c_int
+    lib.sim_check_sync.argtypes = [P, P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.POINTER(_Result)),
+                                   ctypes.POINTER(ctypes.POINTER(_BarrierResult))]
+    lib.sim_barrier_result_free.restype = None
+    lib.sim_barrier_result_free.argtypes = [ctypes.POINTER(_BarrierResult)]
     lib.sim_result_free.restype = None
     lib.sim_result_free.argtypes = [ctypes.POINTER(_Result)]
     lib.sim_stage_times.restype = ctypes.c_int
@@ -154,6 +172,8 @@ def load() -> ctypes.CDLL:
     lib.sim_server_destroy.argtypes = [P]
     lib.sim_submit.restype = ctypes.c_int
     lib.sim_submit.argtypes = [P, P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.sim_submit_device.restype = ctypes.c_int
+    lib.sim_submit_device.argtypes = [P, P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.c_uint64)]
     lib.sim_poll.restype = ctypes.c_int
     lib.sim_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.POINTER(_Result))]
     lib.sim_wait.restype = ctypes.c_int
@@ -245,6 +265,51 @@ def sim_check_traces_device(ctx, d_records_ptr: int, n_records: int, offsets=Non
     return _take_result(out)
 
 
+def _take_barriers(res_p):
+    r = res_p.contents
+    out = np.zeros(r.n_barriers, dtype=BARRIER_DTYPE)
+    if r.n_barriers:
+        ctypes.memmove(out.ctypes.data, r.barriers, r.n_barriers * BARRIER_DTYPE.itemsize)
+    load().sim_barrier_result_free(res_p)
+    return out
+
+
+def sim_check_sync_device(ctx, d_records_ptr: int, n_records: int, offsets=None, threads_per_block=1, stream=None):
+    """Race check and redundant-barrier check of device records: returns
+    (races, summaries, barriers), barriers a BARRIER_DTYPE array with one
+    row per (trace, boundary) that has an instance."""
+    lib = load()
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, n_records)
+    if int(offsets[-1]) != n_records:
+        raise ValueError("offsets[-1] must equal the number of device records")
+    out = ctypes.POINTER(_Result)()
+    bar = ctypes.POINTER(_BarrierResult)()
+    rc = lib.sim_check_sync_device(ctx, ctypes.c_void_p(d_records_ptr) if n_records else None, offsets.ctypes.data,
+                                   n_traces, tpb.ctypes.data, ctypes.c_void_p(stream or 0), ctypes.byref(out),
+                                   ctypes.byref(bar))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    races, summ = _take_result(out)
+    return races, summ, _take_barriers(bar)
+
+
+def sim_check_sync(ctx, records: np.ndarray, offsets=None, threads_per_block=1):
+    """sim_check_sync_device for records in host memory."""
+    lib = load()
+    records = np.ascontiguousarray(records)
+    if records.dtype.itemsize != 16:
+        raise TypeError("records must be 16-byte sim_record entries")
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, len(records))
+    out = ctypes.POINTER(_Result)()
+    bar = ctypes.POINTER(_BarrierResult)()
+    rc = lib.sim_check_sync(ctx, records.ctypes.data if len(records) else None, offsets.ctypes.data, n_traces,
+                            tpb.ctypes.data, ctypes.byref(out), ctypes.byref(bar))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    races, summ = _take_result(out)
+    return races, summ, _take_barriers(bar)
+
+
 def sim_stage_times(ctx):
     lib = load()
     arr = (_StageTime * 16)()
@@ -292,6 +357,32 @@ def sim_autotune(ctx, d_records_ptr: int, n_records: int, offsets=None, threads_
 
 # ----------------------------------------------------------- convenience
 
+# Contexts and servers still open at interpreter exit are closed by an
+# atexit hook, while the HIP runtime is fully alive: atexit hooks run at the
+# start of interpreter finalisation, before module teardown and before the
+# C-level exit handlers that finalise the HIP runtime (and a profiler's
+# tool library).  A destructor that runs later, during finalisation, does
+# not call into HIP at all (the handle is left to process exit).
+_open_handles = weakref.WeakSet()
+_atexit_registered = False
+
+
+def _close_open_handles():
+    for h in list(_open_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+def _track(obj):
+    global _atexit_registered
+    if not _atexit_registered:
+        atexit.register(_close_open_handles)
+        _atexit_registered = True
+    _open_handles.add(obj)
+
+
 class Context:
     """One library context on one GPU."""
 
@@ -299,6 +390,7 @@ class Context:
                  reserve_traces: int = 0):
         self._ctx = sim_create(device, profile=profile, reserve_records=reserve_records, graphs=graphs,
                                reserve_traces=reserve_traces)
+        _track(self)
 
     def close(self):
         if self._ctx:
@@ -306,6 +398,8 @@ class Context:
             self._ctx = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -319,6 +413,15 @@ class Context:
         (16 bytes each, e.g. uint8 [n, 16] or int64 [n, 2])."""
         ptr, n, stream = self._device_args(tensor, stream)
         return sim_check_traces_device(self._ctx, ptr, n, offsets, threads_per_block, stream)
+
+    def check_sync(self, records, offsets=None, threads_per_block=1):
+        """Races and barrier instances of host records."""
+        return sim_check_sync(self._ctx, records, offsets, threads_per_block)
+
+    def check_sync_device(self, tensor, offsets=None, threads_per_block=1, stream=None):
+        """Races and barrier instances of a device tensor of records."""
+        ptr, n, stream = self._device_args(tensor, stream)
+        return sim_check_sync_device(self._ctx, ptr, n, offsets, threads_per_block, stream)
 
     @staticmethod
     def _device_args(tensor, stream):
@@ -409,6 +512,7 @@ class Server:
         if rc != SIM_OK:
             raise SimError(rc, lib.sim_server_last_error().decode())
         self._keep = {}
+        _track(self)
 
     def close(self):
         if self._srv:
@@ -417,6 +521,8 @@ class Server:
             self._keep.clear()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -434,6 +540,26 @@ class Server:
         if rc != SIM_OK:
             raise SimError(rc, lib.sim_server_last_error().decode())
         self._keep[t.value] = records
+        return t.value
+
+    def submit_device(self, tensor, offsets=None, threads_per_block=1) -> int:
+        """Submit a request whose records are a device tensor on the server's
+        GPU (16-byte sim_record entries, contiguous); the workers read them
+        in place.  The tensor is kept alive until the result is collected."""
+        lib = load()
+        nbytes = tensor.numel() * tensor.element_size()
+        if nbytes % 16 or not tensor.is_contiguous():
+            raise ValueError("tensor must be contiguous 16-byte sim_record entries")
+        n = nbytes // 16
+        offsets, n_traces, tpb = _tables(offsets, threads_per_block, n)
+        if int(offsets[-1]) != n:
+            raise ValueError("offsets[-1] must equal the number of device records")
+        t = ctypes.c_uint64(0)
+        rc = lib.sim_submit_device(self._srv, ctypes.c_void_p(tensor.data_ptr()) if n else None, offsets.ctypes.data,
+                                   n_traces, tpb.ctypes.data, ctypes.byref(t))
+        if rc != SIM_OK:
+            raise SimError(rc, lib.sim_server_last_error().decode())
+        self._keep[t.value] = tensor
         return t.value
 
     def _collect(self, rc, ticket, out):

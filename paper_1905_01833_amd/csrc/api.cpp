@@ -28,6 +28,7 @@ using namespace sc;
 static_assert(sizeof(sim_record) == 16, "sim_record is 16 bytes");
 static_assert(sizeof(sim_race) == 64, "sim_race is 64 bytes");
 static_assert(sizeof(RaceOut) == sizeof(sim_race), "device entry mirrors sim_race");
+static_assert(sizeof(sim_barrier) == 24, "sim_barrier is 24 bytes");
 
 namespace {
 
@@ -71,8 +72,10 @@ struct sim_ctx {
   std::string err;
 
   DevBuf records, keys0, keys1, meta, stats_part, layout, thist, gtot, gbase, agg, tout, cross, cross_flag,
-      group_sum, stage, ctrl, out;
-  void* h_meta = nullptr;  // pinned: TraceDesc[], TileRef[], GroupRef[] (the layout of meta)
+      group_sum, stage, stage_ref, ctrl, out, bar, bar_base;
+  uint64_t dev_limit = 0;  // device bytes the buffers may hold (0: no limit; set by a server's worker)
+  void* h_meta = nullptr;  // pinned: the call's tables (the layout of meta), then room for the
+                           // per-tile words of a staging overflow (tile counts down, references up)
   size_t h_meta_cap = 0;
   Ctrl* h_ctrl = nullptr;  // pinned
 
@@ -213,52 +216,169 @@ static size_t meta_bytes(uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups
          (size_t)n_hgroups * sizeof(GroupRef) + (size_t)n_traces * sizeof(uint32_t);
 }
 
-// Grow the device buffers of a call of `total` records in `n_traces`
-// traces, `n_tiles` tiles and `n_hgroups` histogram groups.
-hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups,
-                        uint32_t key_bytes) {
-  const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
-  const uint64_t cap0 = total < 65536 ? total : 65536;
-  struct {
-    DevBuf* b;
-    size_t bytes;
-  } need[] = {
-      {&c->keys0, total * key_bytes},
-      {&c->keys1, total * key_bytes},
-      {&c->meta, meta_bytes(n_traces, n_tiles, n_hgroups)},
-      {&c->stats_part, (size_t)n_tiles * sizeof(TraceStats)},
-      {&c->layout, (size_t)n_traces * sizeof(TraceLayout)},
-      {&c->thist, (size_t)n_tiles * RADIX * 4},
-      {&c->gtot, (size_t)n_hgroups * RADIX * 4},
-      {&c->gbase, (size_t)n_hgroups * RADIX * 8},
-      {&c->agg, (size_t)n_tiles * SW * 4},
-      {&c->tout, (size_t)n_tiles * sizeof(TileOut)},
-      {&c->cross, (size_t)n_tiles * sizeof(RaceOut)},
-      {&c->cross_flag, (size_t)n_tiles * 4},
-      {&c->group_sum, (size_t)n_groups * 4},
-      {&c->ctrl, sizeof(Ctrl)},
-      {&c->out, (size_t)(c->out.cap ? c->out.cap : cap0 * sizeof(RaceOut))},
-  };
-  for (auto& nb : need) {
-    const hipError_t e = ensure(*nb.b, nb.bytes, false, &c->alloc_gen);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+// Pinned host bytes of a call: its tables, then two words per tile for a
+// staging overflow (the tiles' entry counts, then their staging references).
+static size_t host_bytes(uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups) {
+  return (meta_bytes(n_traces, n_tiles, n_hgroups) + 15) / 16 * 16 + (size_t)n_tiles * 16;
 }
 
-int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces, const uint32_t* tpb,
-        hipStream_t s, sim_result** out) {
+// The fixed device regions of a call.
+enum { R_KEYS0, R_KEYS1, R_META, R_STATS, R_LAYOUT, R_THIST, R_GTOT, R_GBASE, R_AGG, R_TOUT, R_CROSS, R_CFLAG,
+       R_GSUM, R_CTRL, N_REGION };
+
+void region_bytes(size_t need[N_REGION], uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups,
+                  uint32_t key_bytes) {
+  const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
+  need[R_KEYS0] = total * key_bytes;
+  need[R_KEYS1] = total * key_bytes;
+  need[R_META] = meta_bytes(n_traces, n_tiles, n_hgroups);
+  need[R_STATS] = (size_t)n_tiles * sizeof(TraceStats);
+  need[R_LAYOUT] = (size_t)n_traces * sizeof(TraceLayout);
+  need[R_THIST] = (size_t)n_tiles * RADIX * 4;
+  need[R_GTOT] = (size_t)n_hgroups * RADIX * 4;
+  need[R_GBASE] = (size_t)n_hgroups * RADIX * 8;
+  need[R_AGG] = (size_t)n_tiles * SW * 4;
+  need[R_TOUT] = (size_t)n_tiles * sizeof(TileOut);
+  need[R_CROSS] = (size_t)n_tiles * sizeof(RaceOut);
+  need[R_CFLAG] = (size_t)n_tiles * 4;
+  need[R_GSUM] = (size_t)n_groups * 4;
+  need[R_CTRL] = sizeof(Ctrl);
+}
+
+DevBuf* region_buf(sim_ctx* c, int r) {
+  DevBuf* const bufs[N_REGION] = {&c->keys0, &c->keys1, &c->meta,  &c->stats_part, &c->layout,
+                                  &c->thist, &c->gtot,  &c->gbase, &c->agg,        &c->tout,
+                                  &c->cross, &c->cross_flag, &c->group_sum, &c->ctrl};
+  return bufs[r];
+}
+
+// Capacity ensure() gives a buffer asked for `bytes` (its headroom included).
+size_t grown(size_t bytes) {
+  if (bytes == 0) bytes = 64;
+  return bytes + bytes / 8;
+}
+
+}  // namespace
+
+namespace sc {
+size_t ctx_device_bytes(const sim_ctx* c);
+}  // namespace sc
+
+namespace {
+
+// Grow one buffer within the context's device limit.
+hipError_t grow(sim_ctx* c, DevBuf& b, size_t bytes) {
+  if (b.cap >= bytes) return hipSuccess;
+  if (c->dev_limit && ctx_device_bytes(c) - b.cap + grown(bytes) > c->dev_limit) return hipErrorOutOfMemory;
+  return ensure(b, bytes, false, &c->alloc_gen);
+}
+
+// Grow the context's buffers for a call of `total` records in `n_traces`
+// traces, `n_tiles` tiles and `n_hgroups` histogram groups.  Under a device
+// limit, a context whose grown buffers would exceed it first releases all of
+// them (they are idle between calls) and allocates the call's sizes afresh.
+hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups,
+                        uint32_t key_bytes) {
+  size_t need[N_REGION];
+  region_bytes(need, total, n_traces, n_tiles, n_hgroups, key_bytes);
+  const uint64_t cap0 = total < 65536 ? total : 65536;
+  const size_t out_need = c->out.cap ? c->out.cap : cap0 * sizeof(RaceOut);
+  if (c->dev_limit) {
+    auto after = [&]() {
+      size_t t = ctx_device_bytes(c);
+      for (int r = 0; r < N_REGION; r++) {
+        const DevBuf* b = region_buf(c, r);
+        if (b->cap < need[r]) t += grown(need[r]) - b->cap;
+      }
+      if (c->out.cap < out_need) t += grown(out_need) - c->out.cap;
+      return t;
+    };
+    if (after() > c->dev_limit) {
+      for (int r = 0; r < N_REGION; r++) release(*region_buf(c, r));
+      for (DevBuf* b : {&c->out, &c->stage, &c->stage_ref, &c->bar, &c->bar_base}) release(*b);
+      if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
+      c->graph.exec = nullptr;
+      c->alloc_gen++;
+      if (after() > c->dev_limit) return hipErrorOutOfMemory;
+    }
+  }
+  for (int r = 0; r < N_REGION; r++) {
+    const hipError_t e = ensure(*region_buf(c, r), need[r], false, &c->alloc_gen);
+    if (e != hipSuccess) return e;
+  }
+  return ensure(c->out, out_need, false, &c->alloc_gen);
+}
+
+// Where a call's result goes.
+struct Sink {
+  sim_result** out = nullptr;
+  sim_barrier_result** barriers = nullptr;  // also the redundant-barrier check
+};
+
+void barrier_result_free(sim_barrier_result* r) {
+  if (!r) return;
+  free(r->barriers);
+  free(r);
+}
+
+// One call.  Trace i's records start at trace_recs[i] when trace_recs is
+// given (device pointers, the traces need not be adjacent), else at
+// d_records + offsets[i].
+int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_recs, const uint64_t* offsets,
+        uint32_t n_traces, const uint32_t* tpb, hipStream_t s, const Sink& sink) {
   uint64_t total = 0;
   uint32_t n_tiles = 0;
-  int rc = validate(c, offsets, n_traces, tpb, out, &total, &n_tiles);
+  int rc = validate(c, offsets, n_traces, tpb, sink.out, &total, &n_tiles);
   if (rc) return rc;
-  if (total && !d_records) return fail(c, SIM_EINVAL, "records is NULL");
+  if (total && !d_records && !trace_recs) return fail(c, SIM_EINVAL, "records is NULL");
+  if (trace_recs)
+    for (uint32_t i = 0; i < n_traces; i++)
+      if (offsets[i + 1] > offsets[i] && !trace_recs[i]) return fail(c, SIM_EINVAL, "records of trace %u is NULL", i);
   for (auto& t : c->times) t = sim_stage_time{0.0, 0, 0};
 
-  if (total == 0) {  // nothing to check: summaries only
-    sim_result* r = alloc_result(0, n_traces);
+  // result delivery: summaries from the entry list, entries downloaded from
+  // `dev_out` (n_races of them)
+  auto deliver = [&](uint64_t n_races, const void* dev_out) -> int {
+    sim_result* r = alloc_result(n_races, n_traces);
     if (!r) return fail(c, SIM_ENOMEM, "host allocation failed");
-    *out = r;
+    sim_trace_summary* sums = r->traces;
+    sim_race* races = r->races;
+    hipError_t e;
+    if (n_races && ((e = hipMemcpyAsync(races, dev_out, n_races * sizeof(sim_race), hipMemcpyDeviceToHost, s)) ||
+                    (e = hipStreamSynchronize(s)))) {
+      sim_result_free(r);
+      return hip_fail(c, e, "result download");
+    }
+    for (uint32_t i = 0; i < n_traces; i++) sums[i].n_records = offsets[i + 1] - offsets[i];
+    for (uint64_t k = 0; k < n_races; k++) {
+      const sim_race& x = races[k];
+      if (x.trace >= n_traces) {
+        sim_result_free(r);
+        return fail(c, SIM_EDEVICE, "entry %llu names trace %u", (unsigned long long)k, x.trace);
+      }
+      sums[x.trace].n_race_locs += 1;
+      sums[x.trace].n_pairs += x.pairs_ww + x.pairs_rw + x.pairs_aw + x.pairs_ar;
+    }
+    *sink.out = r;
+    return SIM_OK;
+  };
+
+  if (total == 0) {  // nothing to check: summaries only (and no barrier instances)
+    sim_barrier_result* br = nullptr;
+    if (sink.barriers) {
+      br = (sim_barrier_result*)calloc(1, sizeof(sim_barrier_result));
+      if (br) br->barriers = (sim_barrier*)malloc(sizeof(sim_barrier));
+      if (!br || !br->barriers) {
+        barrier_result_free(br);
+        return fail(c, SIM_ENOMEM, "host allocation failed");
+      }
+    }
+    const int rc0 = deliver(0, nullptr);
+    if (rc0 != SIM_OK) {
+      barrier_result_free(br);
+      return rc0;
+    }
+    if (sink.barriers) *sink.barriers = br;
     return SIM_OK;
   }
 
@@ -272,7 +392,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     const int gs = group_shift(nt, tune.group_shift_bias);
     n_hgroups64 += (nt + (1ull << gs) - 1) >> gs;
   }
-  const size_t h_bytes = meta_bytes(n_traces, n_tiles, n_hgroups64);
+  const size_t h_bytes = host_bytes(n_traces, n_tiles, n_hgroups64);
   if (c->h_meta_cap < h_bytes) {
     if (c->h_meta) (void)hipHostFree(c->h_meta);
     c->h_meta = nullptr;
@@ -298,10 +418,11 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     max_trace_groups = std::max(max_trace_groups, ng);
     hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
     const uint32_t short_flag = nt <= small_max_tiles ? TILE_SHORT : 0u;
+    const sim_record* base = trace_recs ? trace_recs[i] : d_records + offsets[i];
     for (uint32_t k = 0; k < nt; k++) {
       const uint64_t first = offsets[i] + (uint64_t)k * TILE;
       const uint32_t n_in = (uint32_t)std::min<uint64_t>(TILE, offsets[i + 1] - first);
-      ht[t0 + k] = TileRef{i, k, (uint32_t)first, n_in | short_flag};
+      ht[t0 + k] = TileRef{i, k, (uint32_t)first, n_in | short_flag, base + (uint64_t)k * TILE};
     }
     for (uint32_t k = 0; k < ng; k++) hg[g0 + k] = GroupRef{i, 0};
     if (nt == 1) hs[n_small1++] = i;
@@ -310,24 +431,29 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     g0 += ng;
   }
   const uint32_t n_hgroups = g0;
-  const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
   if (n_small4) memmove(hs + n_small1, hs + n_traces - n_small4, (size_t)n_small4 * sizeof(uint32_t));
+  // host words of a staging overflow, after the tables
+  TileOut* h_tout = (TileOut*)((char*)c->h_meta + (meta_bytes(n_traces, n_tiles, n_hgroups) + 15) / 16 * 16);
+  uint64_t* h_sref = (uint64_t*)(h_tout + n_tiles);
 
   // ---- device buffers
   const uint32_t key_bytes = wide ? 16u : 8u;
+  void* reg[N_REGION];
   if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups, key_bytes)) != hipSuccess)
     return hip_fail(c, e, "device allocation");
-  if ((e = hipMemcpyAsync(c->meta.p, c->h_meta, meta_bytes(n_traces, n_tiles, n_hgroups), hipMemcpyHostToDevice, s)))
+  for (int r = 0; r < N_REGION; r++) reg[r] = region_buf(c, r)->p;
+  RaceOut* out_p = (RaceOut*)c->out.p;
+  const uint64_t out_cap = c->out.cap / sizeof(RaceOut);
+  if ((e = hipMemcpyAsync(reg[R_META], c->h_meta, meta_bytes(n_traces, n_tiles, n_hgroups), hipMemcpyHostToDevice, s)))
     return hip_fail(c, e, "table upload");
 
   Buffers b;
-  b.records = d_records;
-  b.desc = (const TraceDesc*)c->meta.p;
+  b.desc = (const TraceDesc*)reg[R_META];
   b.tiles = (const TileRef*)(b.desc + n_traces);
-  b.stats_part = (TraceStats*)c->stats_part.p;
-  b.layout = (TraceLayout*)c->layout.p;
-  b.keys[0] = c->keys0.p;
-  b.keys[1] = c->keys1.p;
+  b.stats_part = (TraceStats*)reg[R_STATS];
+  b.layout = (TraceLayout*)reg[R_LAYOUT];
+  b.keys[0] = reg[R_KEYS0];
+  b.keys[1] = reg[R_KEYS1];
   b.wide = wide ? 1u : 0u;
   b.key_bytes = key_bytes;
   b.groups = (const GroupRef*)(b.tiles + n_tiles);
@@ -335,18 +461,19 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   b.n_small1 = n_small1;
   b.n_small4 = n_small4;
   b.small_max_tiles = small_max_tiles;
-  b.thist = (uint32_t*)c->thist.p;
-  b.gtot = (uint32_t*)c->gtot.p;
-  b.gbase = (uint64_t*)c->gbase.p;
-  b.agg = (uint32_t*)c->agg.p;
-  b.tout = (TileOut*)c->tout.p;
-  b.cross = (RaceOut*)c->cross.p;
-  b.cross_flag = (uint32_t*)c->cross_flag.p;
-  b.group_sum = (uint32_t*)c->group_sum.p;
+  b.thist = (uint32_t*)reg[R_THIST];
+  b.gtot = (uint32_t*)reg[R_GTOT];
+  b.gbase = (uint64_t*)reg[R_GBASE];
+  b.agg = (uint32_t*)reg[R_AGG];
+  b.tout = (TileOut*)reg[R_TOUT];
+  b.cross = (RaceOut*)reg[R_CROSS];
+  b.cross_flag = (uint32_t*)reg[R_CFLAG];
+  b.group_sum = (uint32_t*)reg[R_GSUM];
   b.stage = nullptr;
-  b.ctrl = (Ctrl*)c->ctrl.p;
-  b.out = (RaceOut*)c->out.p;
-  b.out_cap = c->out.cap / sizeof(RaceOut);
+  b.stage_ref = nullptr;
+  b.ctrl = (Ctrl*)reg[R_CTRL];
+  b.out = out_p;
+  b.out_cap = out_cap;
   b.n_traces = n_traces;
   b.n_tiles = n_tiles;
   b.n_groups = n_hgroups;
@@ -397,7 +524,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     return hipSuccess;
   };
   auto sync_ctrl = [&]() -> hipError_t {
-    hipError_t e1 = hipMemcpyAsync(c->h_ctrl, c->ctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+    hipError_t e1 = hipMemcpyAsync(c->h_ctrl, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
     return e1 != hipSuccess ? e1 : hipStreamSynchronize(s);
   };
   auto sort_passes = [&](uint32_t from, uint32_t to) -> hipError_t {
@@ -435,12 +562,13 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       return e1;
     first_scan_ev = nev / 2;
     if (guess && (e1 = scan(guess, true))) return e1;
-    return hipMemcpyAsync(c->h_ctrl, c->ctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+    return hipMemcpyAsync(c->h_ctrl, b.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
   };
   // Graph mode: the first round (every launch up to the control download)
   // is captured once per call shape and replayed while the shape, the
-  // buffers and the pass count stay the same.
-  const bool use_graph = (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0;
+  // buffers and the pass count stay the same.  (Not for gathered traces,
+  // whose record addresses are not part of the shape.)
+  const bool use_graph = (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0 && !trace_recs;
   uint64_t th = 1469598103934665603ull;  // FNV-1a over the per-call tables
   if (use_graph) {
     const unsigned char* q = (const unsigned char*)offsets;
@@ -498,7 +626,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
     // a trace needs two-word keys: run the whole call again in that mode
     // (the next call starts in it while its traces keep needing it)
     c->wide_guess = true;
-    return run(c, d_records, offsets, n_traces, tpb, s, out);
+    return run(c, d_records, trace_recs, offsets, n_traces, tpb, s, sink);
   }
   const uint32_t needed = ctl.max_passes;
   if (needed > guess) {
@@ -512,11 +640,32 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
   if (!all_small) c->pass_guess = needed;  // an LDS-sorted call tells nothing about global passes
   c->wide_guess = ctl.wide_traces > 0;
   if (ctl.error_flags & ERR_STAGE_OVERFLOW) {
-    // a tile holds more racing locations than its slice of the idle key
-    // buffer: scan again with a dedicated staging buffer
-    if ((e = ensure(c->stage, (size_t)n_tiles * (TILE / 2 + 1) * sizeof(RaceOut), false, &c->alloc_gen)))
+    // Some tile holds more racing locations than its slice of the idle key
+    // buffer: give each such tile a range of a dedicated staging buffer, as
+    // large as the entry count this scan found for it, and scan again.
+    if ((e = hipMemcpyAsync(h_tout, b.tout, (size_t)n_tiles * sizeof(TileOut), hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s)))
+      return hip_fail(c, e, "tile counts download");
+    uint64_t staged = 0;
+    for (uint32_t t = 0; t < n_tiles; t++) {
+      const uint32_t n_in = ht[t].n_flags & ~TILE_SHORT;
+      const uint32_t cnt = h_tout[t].in_count;
+      if (cnt > n_in * key_bytes / (uint32_t)sizeof(RaceOut)) {
+        h_sref[t] = (staged << STAGE_CAP_BITS) | cnt;
+        staged += cnt;
+      } else {
+        h_sref[t] = 0;
+      }
+    }
+    if ((e = grow(c, c->stage, (size_t)staged * sizeof(RaceOut))) ||
+        (e = grow(c, c->stage_ref, (size_t)n_tiles * sizeof(uint64_t))))
       return hip_fail(c, e, "device allocation");
-    b.stage = (RaceOut*)c->stage.p;
+    RaceOut* stage = (RaceOut*)c->stage.p;
+    uint64_t* d_sref = (uint64_t*)c->stage_ref.p;
+    if ((e = hipMemcpyAsync(d_sref, h_sref, (size_t)n_tiles * sizeof(uint64_t), hipMemcpyHostToDevice, s)))
+      return hip_fail(c, e, "staging table upload");
+    b.stage = stage;
+    b.stage_ref = d_sref;
     if ((e = launch_reset_errors(b, ERR_STAGE_OVERFLOW, s)) || (e = scan(needed, false)) || (e = sync_ctrl()))
       return hip_fail(c, e, "rescan");
     ctl = *c->h_ctrl;
@@ -526,7 +675,7 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
 
   uint64_t n_races = ctl.total_entries;
   if (n_races > b.out_cap) {  // more racing locations than the output buffer holds
-    if ((e = ensure(c->out, n_races * sizeof(RaceOut), false, &c->alloc_gen))) return hip_fail(c, e, "device allocation");
+    if ((e = grow(c, c->out, n_races * sizeof(RaceOut)))) return hip_fail(c, e, "device allocation");
     b.out = (RaceOut*)c->out.p;
     b.out_cap = c->out.cap / sizeof(RaceOut);
     if ((e = timed(ST_OUT, false, [&] { return launch_scan_out(b, needed, s); })) || (e = sync_ctrl()))
@@ -543,28 +692,58 @@ int run(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32
       c->times[ev_stage[k]].launches += 1;
     }
   }
+  if (!sink.barriers) return deliver(n_races, b.out);
 
-  sim_result* r = alloc_result(n_races, n_traces);
-  if (!r) return fail(c, SIM_ENOMEM, "host allocation failed");
-  if (n_races && ((e = hipMemcpyAsync(r->races, c->out.p, n_races * sizeof(sim_race), hipMemcpyDeviceToHost, s)) ||
-                  (e = hipStreamSynchronize(s)))) {
-    sim_result_free(r);
-    return hip_fail(c, e, "result download");
+  // ---- the redundant-barrier check over the same sorted keys: every
+  // trace's boundaries (0 .. its largest epoch - 1) get a pair of counters
+  std::vector<TraceLayout> lay(n_traces);
+  if ((e = hipMemcpyAsync(lay.data(), b.layout, (size_t)n_traces * sizeof(TraceLayout), hipMemcpyDeviceToHost, s)) ||
+      (e = hipStreamSynchronize(s)))
+    return hip_fail(c, e, "layout download");
+  std::vector<uint64_t> base(n_traces + 1, 0);
+  for (uint32_t i = 0; i < n_traces; i++)
+    base[i + 1] = base[i] + (offsets[i + 1] > offsets[i] ? lay[i].max_epoch : 0u);
+  const uint64_t nb = base[n_traces];
+  const uint32_t copies = nb <= 4096 ? 16u : (nb <= 65536 ? 4u : 1u);
+  if ((e = grow(c, c->bar, (size_t)(nb ? nb : 1) * copies * sizeof(BarrierCount))) ||
+      (e = grow(c, c->bar_base, (size_t)n_traces * sizeof(uint64_t))))
+    return hip_fail(c, e, "device allocation");
+  std::vector<BarrierCount> counts((size_t)nb * copies);
+  if ((e = hipMemcpyAsync(c->bar_base.p, base.data(), (size_t)n_traces * sizeof(uint64_t), hipMemcpyHostToDevice, s)) ||
+      (e = launch_barriers(b, (const uint64_t*)c->bar_base.p, (BarrierCount*)c->bar.p, nb * copies, copies, s)) ||
+      (nb && (e = hipMemcpyAsync(counts.data(), c->bar.p, counts.size() * sizeof(BarrierCount), hipMemcpyDeviceToHost,
+                                 s))) ||
+      (e = hipStreamSynchronize(s)))
+    return hip_fail(c, e, "barrier check");
+  uint64_t n_bar = 0;
+  for (uint64_t k = 0; k < nb; k++) {
+    uint64_t inst = 0;
+    for (uint32_t q = 0; q < copies; q++) inst += counts[k * copies + q].instances;
+    n_bar += inst ? 1 : 0;
   }
-  for (uint32_t i = 0; i < n_traces; i++) r->traces[i].n_records = offsets[i + 1] - offsets[i];
-  for (uint64_t k = 0; k < n_races; k++) {
-    const sim_race& x = r->races[k];
-    if (x.trace >= n_traces) {
-      sim_result_free(r);
-      return fail(c, SIM_EDEVICE, "entry %llu names trace %u", (unsigned long long)k, x.trace);
+  sim_barrier_result* br = (sim_barrier_result*)calloc(1, sizeof(sim_barrier_result));
+  if (br) br->barriers = (sim_barrier*)malloc((n_bar ? n_bar : 1) * sizeof(sim_barrier));
+  if (!br || !br->barriers) {
+    barrier_result_free(br);
+    return fail(c, SIM_ENOMEM, "host allocation failed");
+  }
+  for (uint32_t i = 0; i < n_traces; i++)
+    for (uint64_t k = base[i]; k < base[i + 1]; k++) {
+      sim_barrier x{i, (uint32_t)(k - base[i]), 0, 0};
+      for (uint32_t q = 0; q < copies; q++) {
+        x.instances += counts[k * copies + q].instances;
+        x.racing += counts[k * copies + q].racing;
+      }
+      if (x.instances) br->barriers[br->n_barriers++] = x;
     }
-    r->traces[x.trace].n_race_locs += 1;
-    r->traces[x.trace].n_pairs += x.pairs_ww + x.pairs_rw + x.pairs_aw + x.pairs_ar;
+  const int rc2 = deliver(n_races, b.out);
+  if (rc2 != SIM_OK) {
+    barrier_result_free(br);
+    return rc2;
   }
-  *out = r;
+  *sink.barriers = br;
   return SIM_OK;
 }
-
 }  // namespace
 
 // ---- internal hooks for the serving runtime (serve.cpp)
@@ -572,9 +751,9 @@ namespace sc {
 
 size_t ctx_device_bytes(const sim_ctx* c) {
   size_t t = 0;
-  for (const DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part,
-                          &c->layout, &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag,
-                          &c->group_sum, &c->stage, &c->ctrl, &c->out})
+  for (const DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist,
+                          &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum,
+                          &c->stage, &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base})
     t += b->cap;
   return t;
 }
@@ -583,12 +762,45 @@ size_t ctx_device_bytes(const sim_ctx* c) {
 void ctx_trim(sim_ctx* c) {
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout,
-                    &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->stage, &c->ctrl, &c->out})
+  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist, &c->gtot,
+                    &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->stage,
+                    &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base})
     release(*b);
   if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
   c->graph.exec = nullptr;
   c->alloc_gen++;
+}
+
+// Device bytes the context's buffers may hold from now on (0: no limit).  A
+// call that would need more fails with SIM_ENOMEM.
+void ctx_set_limit(sim_ctx* c, uint64_t bytes) { c->dev_limit = bytes; }
+
+// Device bytes a call of this shape holds at most in an empty context with
+// one-word (8) or two-word (16) keys: every fixed buffer with its growth
+// headroom, the output's first allocation, and a staging overflow of
+// `staged` entries with the output grown to `entries`.
+uint64_t ctx_call_bytes(uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint32_t key_bytes, uint64_t entries,
+                        uint64_t staged) {
+  size_t need[N_REGION];  // histogram groups: at most one per tile
+  region_bytes(need, total, n_traces, n_tiles, n_tiles, key_bytes);
+  uint64_t t = 0;
+  for (int r = 0; r < N_REGION; r++) t += grown(need[r]);
+  const uint64_t cap0 = total < 65536 ? total : 65536;
+  t += grown((entries > cap0 ? entries : cap0) * sizeof(RaceOut));
+  if (staged) t += grown(staged * sizeof(RaceOut)) + grown((uint64_t)n_tiles * 8);
+  return t;
+}
+
+// sim_check_traces_device for traces whose records lie anywhere in device
+// memory: trace i's records start at trace_recs[i]; offsets are the call's
+// CSR offsets as usual (they number the records of the call).
+int ctx_check_gather(sim_ctx* c, const sim_record* const* trace_recs, const uint64_t* offsets, uint32_t n_traces,
+                     const uint32_t* tpb, hipStream_t s, sim_result** out) {
+  c->err.clear();
+  DeviceGuard g(c->device);
+  Sink sink;
+  sink.out = out;
+  return run(c, nullptr, trace_recs, offsets, n_traces, tpb, s, sink);
 }
 
 }  // namespace sc
@@ -638,9 +850,9 @@ void sim_destroy(sim_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout,
-                    &c->thist, &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum,
-                    &c->stage, &c->ctrl, &c->out})
+  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist, &c->gtot,
+                    &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->stage,
+                    &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base})
     release(*b);
   if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
   if (c->h_meta) (void)hipHostFree(c->h_meta);
@@ -658,7 +870,9 @@ int sim_check_traces_device(sim_ctx* c, const sim_record* d_records, const uint6
   if (!c) return SIM_EINVAL;
   c->err.clear();
   DeviceGuard g(c->device);
-  return run(c, d_records, offsets, n_traces, threads_per_block, (hipStream_t)stream, out);
+  Sink sink;
+  sink.out = out;
+  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink);
 }
 
 int sim_check_traces(sim_ctx* c, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
@@ -678,8 +892,50 @@ int sim_check_traces(sim_ctx* c, const sim_record* records, const uint64_t* offs
     e = hipMemcpyAsync(c->records.p, records, total * sizeof(sim_record), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "record upload");
   }
-  return run(c, (const sim_record*)c->records.p, offsets, n_traces, threads_per_block, c->stream, out);
+  Sink sink;
+  sink.out = out;
+  return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink);
 }
+
+int sim_check_sync_device(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
+                          const uint32_t* threads_per_block, void* stream, sim_result** races,
+                          sim_barrier_result** barriers) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (barriers) *barriers = nullptr;
+  if (!races) return fail(c, SIM_EINVAL, "races is NULL");
+  DeviceGuard g(c->device);
+  Sink sink;
+  sink.out = races;
+  sink.barriers = barriers;
+  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink);
+}
+
+int sim_check_sync(sim_ctx* c, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
+                   const uint32_t* threads_per_block, sim_result** races, sim_barrier_result** barriers) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (races) *races = nullptr;
+  if (barriers) *barriers = nullptr;
+  DeviceGuard g(c->device);
+  uint64_t total = 0;
+  uint32_t n_tiles = 0;
+  int rc = validate(c, offsets, n_traces, threads_per_block, races, &total, &n_tiles);
+  if (rc) return rc;
+  if (total && !records) return fail(c, SIM_EINVAL, "records is NULL");
+  if (total) {
+    hipError_t e = ensure(c->records, total * sizeof(sim_record));
+    if (e != hipSuccess) return hip_fail(c, e, "device allocation");
+    e = hipMemcpyAsync(c->records.p, records, total * sizeof(sim_record), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "record upload");
+  }
+  Sink sink;
+  sink.out = races;
+  sink.barriers = barriers;
+  return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink);
+}
+
+void sim_barrier_result_free(sim_barrier_result* r) { barrier_result_free(r); }
 
 void sim_result_free(sim_result* r) {
   if (!r) return;
@@ -742,7 +998,9 @@ int sim_autotune(sim_ctx* c, const sim_record* d_records, const uint64_t* offset
     for (uint32_t r = 0; r < reps; r++) {
       sim_result* res = nullptr;
       const auto t0 = std::chrono::steady_clock::now();
-      const int rc1 = run(c, d_records, offsets, n_traces, threads_per_block, s, &res);
+      Sink sink;
+      sink.out = &res;
+      const int rc1 = run(c, d_records, nullptr, offsets, n_traces, threads_per_block, s, sink);
       const auto t1 = std::chrono::steady_clock::now();
       sim_result_free(res);
       if (rc1) {

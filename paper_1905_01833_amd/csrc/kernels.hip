@@ -32,8 +32,10 @@
 // boundaries.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
+#include "barrier.h"
 #include "launch.h"
 #include "segstate.h"
 
@@ -231,8 +233,7 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool val
 // tid mod 256 (see k_keygen_scatter).
 // NTH threads of TILE / NTH records each.
 template <bool LOOP, bool HIST, int NTH = NT>
-__global__ __launch_bounds__(NTH) void k_stats(const ulonglong2* __restrict__ recs,
-                                               const TileRef* __restrict__ tiles, uint32_t n_tiles,
+__global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles, uint32_t n_tiles,
                                                TraceStats* __restrict__ part, uint32_t* __restrict__ thist,
                                                Ctrl* ctrl) {
   constexpr int IT = TILE / NTH, NW = NTH / 64;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(NTH) void k_stats(const ulonglong2* __restrict__ re
     const TileRef tr = tiles[tile];
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
-    const ulonglong2* p = recs + tr.first;
+    const ulonglong2* p = (const ulonglong2*)tr.rec;
     uint64_t gmin = ~0ull, gmax = 0, smin = ~0ull, smax = 0, bad = ~0ull;
     uint32_t mt = 0, me = 0;
     if (HIST) {
@@ -518,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
     __syncthreads();
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const ulonglong2* p = (const ulonglong2*)b.records + T.off + start;
+    const ulonglong2* p = (const ulonglong2*)tr.rec;
     K* kout = (K*)b.keys[0] + T.off + start;
     ulonglong2 vr[ITEMS];  // all loads first
 #pragma unroll
@@ -778,7 +779,7 @@ __global__ __launch_bounds__(NTH) void k_keygen_scatter(Buffers b) {
     const TileRef tr = b.tiles[tile];
     const uint32_t lane = tx & 63u, wave = tx >> 6;
     const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
-    const ulonglong2* p = (const ulonglong2*)b.records + tr.first;
+    const ulonglong2* p = (const ulonglong2*)tr.rec;
     ulonglong2 vr[IT];  // all loads first: every record of the thread in flight
 #pragma unroll
     for (int i = 0; i < IT; i++) {
@@ -962,13 +963,18 @@ __device__ __forceinline__ void write_entry(RaceOut* dst, uint32_t trace, const 
   *dst = e;
 }
 
-// Staging area of a tile's complete locations: a dedicated buffer, or the
-// tile's slice of the key buffer that no longer holds live keys.
+// Staging area of a tile's complete locations: the tile's slice of the key
+// buffer that no longer holds live keys, or, for a tile whose locations
+// outgrew that slice in an earlier scan of the call, its own range of the
+// dedicated buffer (sized by the host from that scan's counts).
 __device__ __forceinline__ RaceOut* stage_of(const Buffers& b, uint32_t tile, const TraceDesc& T,
                                              const TraceLayout& L, uint64_t start, uint32_t n_in, uint32_t* cap) {
-  if (b.stage) {
-    *cap = TILE / 2 + 1;
-    return b.stage + (uint64_t)tile * (TILE / 2 + 1);
+  if (b.stage_ref) {
+    const uint64_t ref = b.stage_ref[tile];
+    if (ref & STAGE_CAP_MASK) {
+      *cap = (uint32_t)(ref & STAGE_CAP_MASK);
+      return b.stage + (ref >> STAGE_CAP_BITS);
+    }
   }
   *cap = n_in * b.key_bytes / (uint32_t)sizeof(RaceOut);
   return (RaceOut*)((char*)b.keys[(L.npasses & 1u) ^ 1u] + (T.off + start) * b.key_bytes);
@@ -1427,6 +1433,72 @@ __global__ void k_reset_errors(Ctrl* ctrl, uint32_t mask) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ctrl->error_flags &= ~mask;
 }
 
+// ---------------------------------------------------------- k_barriers
+//
+// Redundant-barrier check (Alg. 5, second loop) over the sorted keys of a
+// finished call: one thread per element; an element that heads a barrier
+// instance (barrier.h) reads the two epoch runs around it straight from the
+// key buffer (they are short except on the hottest locations) and counts
+// the instance, racing or not, under its trace and boundary.
+//
+// Counts are summed per tile in LDS (boundaries below 256; later ones go to
+// global memory directly) and added to one of `copies` copies of the
+// trace's counters, chosen by tile, so that the atomics of many workgroups
+// spread over several cache lines.
+
+template <typename K, bool LOOP>
+__global__ __launch_bounds__(NT) void k_barriers(Buffers b, const uint64_t* __restrict__ bar_base,
+                                                 BarrierCount* table, uint32_t copies) {
+  constexpr uint32_t NBIN = 256;
+  __shared__ uint32_t s_inst[NBIN], s_race[NBIN];
+  if (b.ctrl->error_flags) return;
+  const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    __syncthreads();  // LDS of the previous tile is free
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    s_inst[tx] = 0;
+    s_race[tx] = 0;
+    const TileRef tr = b.tiles[tile];
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    const K* keys = (const K*)b.keys[L.npasses & 1u] + T.off;  // the trace's sorted keys
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
+    BarrierCount* counts = table + bar_base[tr.trace] * copies;
+    __syncthreads();
+#pragma unroll 1
+    for (int r = 0; r < ITEMS; r++) {
+      const uint32_t j = tx + r * NT;
+      if (j >= n_in) break;
+      uint32_t e0;
+      bool racing;
+      if (!barrier_instance<K>(L, keys, T.n, start + j, &e0, &racing)) continue;
+      if (e0 < NBIN) {
+        atomicAdd(&s_inst[e0], 1u);
+        if (racing) atomicAdd(&s_race[e0], 1u);
+      } else {
+        BarrierCount* cnt = counts + (uint64_t)e0 * copies + tile % copies;
+        atomicAdd(&cnt->instances, 1ull);
+        if (racing) atomicAdd(&cnt->racing, 1ull);
+      }
+    }
+    __syncthreads();
+    const uint32_t ni = s_inst[tx];
+    if (ni) {  // bins of boundaries the trace has (an instance's boundary is below its max epoch)
+      BarrierCount* cnt = counts + (uint64_t)tx * copies + tile % copies;
+      atomicAdd(&cnt->instances, (unsigned long long)ni);
+      const uint32_t nr = s_race[tx];
+      if (nr) atomicAdd(&cnt->racing, (unsigned long long)nr);
+    }
+  }
+}
+
+__global__ void k_fill_zero(unsigned long long* p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
 // -------------------------------------------------------- launch wrappers
 
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -1453,8 +1525,8 @@ hipError_t launch_stats(const Buffers& b, hipStream_t s) {
   const bool lp = loops(b, b.grid_stream);
   auto kern = b.fuse0 ? (lp ? k_stats<true, true> : k_stats<false, true>)
                       : (lp ? k_stats<true, false> : k_stats<false, false>);
-  hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, (const ulonglong2*)b.records, b.tiles,
-                     b.n_tiles, b.stats_part, b.thist, b.ctrl);
+  hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, b.tiles, b.n_tiles, b.stats_part, b.thist,
+                     b.ctrl);
   return hipGetLastError();
 }
 hipError_t launch_layout(const Buffers& b, hipStream_t s) {
@@ -1572,6 +1644,24 @@ hipError_t launch_scan_out(const Buffers& b, uint32_t passes_done, hipStream_t s
 }
 hipError_t launch_reset_errors(const Buffers& b, uint32_t mask, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_errors, dim3(1), dim3(64), 0, s, b.ctrl, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_barriers(const Buffers& b, const uint64_t* bar_base, BarrierCount* table, uint64_t n_counts,
+                           uint32_t copies, hipStream_t s) {
+  if (n_counts) {
+    const uint64_t words = 2 * n_counts;
+    hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)std::min<uint64_t>(4096, (words + NT - 1) / NT)), dim3(NT), 0, s,
+                       (unsigned long long*)table, words);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (!b.n_tiles || !n_counts) return hipSuccess;
+  if (!grids_ok(b) || copies == 0) return hipErrorInvalidConfiguration;
+  const bool lp = loops(b, b.grid_scan);
+  auto kern = b.wide ? (lp ? k_barriers<u128, true> : k_barriers<u128, false>)
+                     : (lp ? k_barriers<uint64_t, true> : k_barriers<uint64_t, false>);
+  hipLaunchKernelGGL(kern, dim3(b.grid_scan), dim3(NT), 0, s, b, bar_base, table, copies);
   return hipGetLastError();
 }
 

@@ -51,13 +51,13 @@ struct TraceLayout {
   uint32_t shift_space;
   uint32_t error;      // LAYOUT_ERR_* bits
   uint32_t wide;       // 1: the key needs more than 64 bits (two-word keys)
-  uint32_t pad;
+  uint32_t max_epoch;  // largest epoch of the trace (its barrier boundaries are 0 .. max_epoch - 1)
 };
 
-// LAYOUT_ERR_* are per-trace layout errors; ERR_INTERNAL_* are raised by the
-// kernels' own checks (a scatter outside its trace, a look-back wait that
-// did not end) and reported as device errors.
-enum : uint32_t { LAYOUT_ERR_WIDE = 1, LAYOUT_ERR_RECORD = 2, ERR_INTERNAL_BOUNDS = 4, ERR_INTERNAL_SPIN = 8 };
+// LAYOUT_ERR_* are per-trace layout errors; ERR_INTERNAL_BOUNDS is raised by
+// the scatter's own check (a digit's destination range outside its trace)
+// and reported as a device error.
+enum : uint32_t { LAYOUT_ERR_WIDE = 1, LAYOUT_ERR_RECORD = 2, ERR_INTERNAL_BOUNDS = 4 };
 
 constexpr uint32_t RADIX_BITS = 8;
 constexpr uint32_t RADIX = 1u << RADIX_BITS;
@@ -96,7 +96,7 @@ SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
   L.shift_space = 2 + L.tb + L.eb + L.wl;
   L.error = 0;
   L.wide = L.key_bits > 64 ? 1u : 0u;
-  L.pad = 0;
+  L.max_epoch = s.max_epoch;
   if (L.key_bits > 128) L.error |= LAYOUT_ERR_WIDE;
   if (s.bad_index != ~0ull) L.error |= LAYOUT_ERR_RECORD;
   L.npasses = L.error ? 0 : (L.key_bits - 2 + RADIX_BITS - 1) / RADIX_BITS;
@@ -148,6 +148,16 @@ SC_HD uint32_t head_level_t(const TraceLayout& L, K p, K x) {
   return d == 0 ? 4u : (shared ? lv_s : lv_g);
 }
 SC_HD uint32_t head_level(const TraceLayout& L, uint64_t p, uint64_t x) { return head_level_t<uint64_t>(L, p, x); }
+
+// Epoch and block-local thread of a key.
+template <typename K>
+SC_HD uint32_t key_epoch_t(const TraceLayout& L, K k) {
+  return (uint32_t)((uint64_t)(k >> L.shift_e) & lowmask(L.eb));
+}
+template <typename K>
+SC_HD uint32_t key_ltid_t(const TraceLayout& L, K k) {
+  return (uint32_t)((uint64_t)(k >> 2) & lowmask(L.tb));
+}
 
 // Location of a key: space, owning block (shared) or 0xFFFFFFFF, unit.
 template <typename K>

@@ -34,10 +34,17 @@ struct TraceDesc {   // one trace of a call (host-filled)
 struct TileRef {     // tile -> (trace, tile within trace), and where its records are
   uint32_t trace;
   uint32_t local;
-  uint32_t first;    // call index of the tile's first record (a call holds < 2^32 records)
+  uint32_t first;    // call index of the tile's first record: its keys (a call holds < 2^32 records)
   uint32_t n_flags;  // records in the tile (bits 0..30); bit 31: the trace is sorted whole in LDS
+  const void* rec;   // the tile's first record (device memory; the traces of a call need not be adjacent)
 };
 constexpr uint32_t TILE_SHORT = 1u << 31;
+
+// Dedicated staging of a tile whose racing locations outgrow its slice of
+// the idle key buffer: stage_ref[tile] = (first entry in `stage` <<
+// STAGE_CAP_BITS) | capacity, or 0 for a tile that stages in its slice.
+constexpr uint32_t STAGE_CAP_BITS = 16;
+constexpr uint64_t STAGE_CAP_MASK = (1ull << STAGE_CAP_BITS) - 1;
 
 struct GroupRef {    // histogram group -> trace
   uint32_t trace;
@@ -67,7 +74,6 @@ struct RaceOut {            // mirrors sim_race (64 bytes)
 };
 
 struct Buffers {            // device pointers of one call
-  const void* records;      // sim_record[n_total]
   const TraceDesc* desc;
   const TileRef* tiles;
   TraceStats* stats_part;   // [tile]
@@ -82,7 +88,8 @@ struct Buffers {            // device pointers of one call
   RaceOut* cross;           // [tile]
   uint32_t* cross_flag;     // [tile]
   uint32_t* group_sum;      // [group]
-  RaceOut* stage;           // dedicated staging ([tile][TILE/2 + 1]) or nullptr: the idle key buffer
+  RaceOut* stage;           // dedicated staging of the tiles stage_ref names (see STAGE_CAP_BITS)
+  const uint64_t* stage_ref;// [tile], or nullptr: every tile stages in its slice of the idle key buffer
   Ctrl* ctrl;
   RaceOut* out;
   uint64_t out_cap;
@@ -107,6 +114,14 @@ struct Buffers {            // device pointers of one call
   uint32_t key_bytes;       // 8 or 16
 };
 
+// Barrier instances (per trace and boundary) of the redundant-barrier check:
+// `copies` copies of every counter pair, spread over cache lines, summed by
+// the host.  Trace i's boundaries start at bar_base[i].
+struct BarrierCount {
+  unsigned long long instances;
+  unsigned long long racing;
+};
+
 // Kernel stages, in launch order.
 enum Stage { ST_INIT = 0, ST_STATS, ST_LAYOUT, ST_KEYGEN, ST_UPSWEEP, ST_SORT, ST_SCAN, ST_CROSS, ST_OUT,
              ST_SORT_SMALL, ST_COUNT };
@@ -122,5 +137,9 @@ hipError_t launch_scan_tiles(const Buffers& b, uint32_t passes_done, hipStream_t
 hipError_t launch_scan_cross(const Buffers& b, uint32_t passes_done, hipStream_t s);
 hipError_t launch_scan_out(const Buffers& b, uint32_t passes_done, hipStream_t s);
 hipError_t launch_reset_errors(const Buffers& b, uint32_t mask, hipStream_t s);
+// Redundant-barrier check over the sorted keys of a finished call: clears
+// `table` (n_counts entries) and counts every trace's barrier instances.
+hipError_t launch_barriers(const Buffers& b, const uint64_t* bar_base, BarrierCount* table, uint64_t n_counts,
+                           uint32_t copies, hipStream_t s);
 
 }  // namespace sc

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <vector>
 
+#include "../paper_1905_01833_amd/csrc/barrier.h"
 #include "../paper_1905_01833_amd/csrc/segstate.h"
 #include "../paper_1905_01833_amd/csrc/tilewalk.h"
 
@@ -138,6 +139,67 @@ extern "C" int64_t hs_check(const rec* recs, const uint64_t* off, uint32_t n_tra
 extern "C" int64_t hs_check_wide(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
                                  uint32_t tile, uint32_t chunk, race* out, uint64_t cap, uint32_t* max_passes) {
   return check_impl<u128>(recs, off, n_traces, tpb, tile, chunk, out, cap, max_passes);
+}
+
+// Barrier instances as the barrier kernel counts them: keys built and
+// sorted per trace, barrier_instance() at every position, counts summed
+// per (trace, boundary).  Output rows as the oracle's: trace, boundary,
+// instances, racing, in (trace, boundary) order, rows with an instance only.
+struct barrier_row {
+  uint32_t trace, boundary;
+  uint64_t instances, racing;
+};
+
+template <typename K>
+static int64_t barriers_impl(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                             barrier_row* out, uint64_t cap) {
+  std::vector<barrier_row> res;
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t lo = off[tr], n = off[tr + 1] - off[tr];
+    if (n == 0) continue;
+    TraceStats S;
+    stats_init(S);
+    for (uint64_t i = 0; i < n; i++) {
+      const rec& r = recs[lo + i];
+      if (r.space == 0) { S.gmin = std::min(S.gmin, r.unit); S.gmax = std::max(S.gmax, r.unit); }
+      else { S.smin = std::min(S.smin, r.unit); S.smax = std::max(S.smax, r.unit); }
+      S.max_tid = std::max(S.max_tid, r.tid);
+      S.max_epoch = std::max<uint32_t>(S.max_epoch, r.epoch);
+    }
+    const TraceLayout L = make_layout(S, tpb[tr]);
+    if (L.error) return -(int64_t)L.error;
+    if (L.wide && sizeof(K) == 8) return -(int64_t)LAYOUT_ERR_WIDE;
+    std::vector<K> k(n);
+    for (uint64_t i = 0; i < n; i++) {
+      const rec& r = recs[lo + i];
+      k[i] = make_key_t<K>(L, r.unit, r.tid, r.epoch, r.action, r.space, tpb[tr]);
+    }
+    std::sort(k.begin(), k.end());
+    std::vector<uint64_t> inst(L.max_epoch + 1, 0), rac(L.max_epoch + 1, 0);
+    for (uint64_t p = 0; p < n; p++) {
+      uint32_t b;
+      bool racing;
+      if (!barrier_instance<K>(L, k.data(), n, p, &b, &racing)) continue;
+      if (b >= L.max_epoch) return -1000;  // a boundary the trace cannot have
+      inst[b]++;
+      rac[b] += racing ? 1 : 0;
+    }
+    for (uint32_t b = 0; b < L.max_epoch; b++)
+      if (inst[b]) res.push_back(barrier_row{tr, b, inst[b], rac[b]});
+  }
+  if (res.size() > cap) return (int64_t)res.size();
+  std::memcpy(out, res.data(), res.size() * sizeof(barrier_row));
+  return (int64_t)res.size();
+}
+
+extern "C" int64_t hs_barriers(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                               barrier_row* out, uint64_t cap) {
+  return barriers_impl<uint64_t>(recs, off, n_traces, tpb, out, cap);
+}
+
+extern "C" int64_t hs_barriers_wide(const rec* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                                    barrier_row* out, uint64_t cap) {
+  return barriers_impl<u128>(recs, off, n_traces, tpb, out, cap);
 }
 
 // Associativity check on random element sequences: fold(push) equals the

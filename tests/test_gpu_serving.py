@@ -111,7 +111,107 @@ def test_alone_equals_in_mix(pkg):
     assert st["completed"] == len(tickets) - 2 and st["failed"] == 2
     assert st["batches"] < st["completed"]  # requests shared launches
     assert st["peak_inflight_bytes"] <= budget
+    assert st["device_bytes"] <= budget
     assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+
+
+def test_device_requests_alone_equals_in_mix(pkg):
+    """Requests whose records live in device memory (read in place by the
+    workers), mixed with host requests: every result is the request's alone
+    result, and the oracle's on a sample."""
+    pool = request_pool(40, seed=21)
+    say("device requests: alone")
+    ctx = pkg.Context(0)
+    devs = [torch.from_numpy(r.view(np.uint8).reshape(-1, 16)).to("cuda:0") for r, _, _ in pool]
+    torch.cuda.synchronize()
+    alone = [ctx.check_traces_device(d, off, tpb) for d, (_, off, tpb) in zip(devs, pool)]
+    ctx.close()
+    for i in range(0, len(pool), 7):
+        recs, off, tpb = pool[i]
+        want, wsum = oracle.closed_form(recs, off, tpb)
+        assert alone[i][0].tobytes() == want.tobytes() and alone[i][1].tobytes() == wsum.tobytes(), i
+    budget = 256 << 20
+    say("device requests: mix of device and host submissions, 3 slots")
+    srv = pkg.Server(0, hbm_budget_bytes=budget, slots=3, max_batch_requests=32)
+    try:
+        tickets = []
+        for rep in range(3):
+            for i, (recs, off, tpb) in enumerate(pool):
+                if (i + rep) % 3:
+                    tickets.append((i, srv.submit_device(devs[i], off, tpb)))
+                else:
+                    tickets.append((i, srv.submit(recs, off, tpb)))
+        for i, t in tickets:
+            got = srv.wait(t)
+            assert got[0].tobytes() == alone[i][0].tobytes(), i
+            assert got[1].tobytes() == alone[i][1].tobytes(), i
+        st = srv.stats()
+        assert st["completed"] == len(tickets) and st["failed"] == 0
+        assert st["batches"] < st["completed"]
+        assert st["peak_inflight_bytes"] <= budget and st["device_bytes"] <= budget
+    finally:
+        srv.close()
+
+
+def test_output_beyond_estimate_is_retried_within_budget(pkg):
+    """A request with 150k racing locations outgrows the usual footprint
+    (64 Ki entries): it fails within its charge, is queued again charged
+    its worst case, and its result equals the alone result; the workers'
+    charges stay within the budget throughout."""
+    n = 150000
+    r = np.zeros(2 * n, dtype=RECORD_DTYPE)
+    r["unit"] = np.repeat(np.arange(n, dtype=np.uint64) * 3, 2)
+    r["tid"] = np.tile([0, 1], n)
+    r["action"] = 1
+    off = np.array([0, len(r)], dtype=np.uint64)
+    want, wsum = oracle.closed_form(r, off, 2)
+    small = request_pool(6, seed=5, log2_max=14)
+    budget = 96 << 20
+    say("retry: 150k racing locations among small requests, budget 96 MiB")
+    srv = pkg.Server(0, hbm_budget_bytes=budget, slots=2)
+    try:
+        ts = [srv.submit(recs, o, t) for recs, o, t in small[:3]]
+        big = srv.submit(r, off, 2)
+        ts += [srv.submit(recs, o, t) for recs, o, t in small[3:]]
+        got = srv.wait(big)
+        assert len(got[0]) == n
+        assert got[0].tobytes() == want.tobytes() and got[1].tobytes() == wsum.tobytes()
+        for (recs, o, t), tk in zip(small, ts):
+            g = srv.wait(tk)
+            w, ws = oracle.closed_form(recs, o, t)
+            assert g[0].tobytes() == w.tobytes() and g[1].tobytes() == ws.tobytes()
+        st = srv.stats()
+        assert st["failed"] == 0 and st["requeued"] >= 1
+        assert st["peak_inflight_bytes"] <= budget and st["device_bytes"] <= budget
+    finally:
+        srv.close()
+
+
+def test_concurrent_waits_on_one_ticket(pkg):
+    """Two threads wait on the same ticket: one collects the result, the
+    other gets SIM_EINVAL (ticket collected), never freed memory."""
+    recs, off, tpb = request_pool(1, seed=4, log2_max=16)[0]
+    srv = pkg.Server(0, slots=1)
+    try:
+        for _ in range(5):
+            t = srv.submit(recs, off, tpb)
+            out = [None, None]
+
+            def waiter(k):
+                try:
+                    out[k] = srv.wait(t)
+                except pkg.SimError as e:
+                    out[k] = e.code
+
+            ths = [threading.Thread(target=waiter, args=(k,)) for k in range(2)]
+            for th in ths:
+                th.start()
+            for th in ths:
+                th.join()
+            codes = [o for o in out if isinstance(o, int)]
+            assert len(codes) == 1 and codes[0] == pkg.SIM_EINVAL
+    finally:
+        srv.close()
 
 
 def test_admission_and_tickets(pkg):

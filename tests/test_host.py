@@ -37,7 +37,25 @@ def _hostsim():
                                  ctypes.POINTER(ctypes.c_uint32)]
     lib.hs_assoc.restype = ctypes.c_int
     lib.hs_assoc.argtypes = [ctypes.c_uint64, ctypes.c_int]
+    for name in ("hs_barriers", "hs_barriers_wide"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int64
+        f.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_uint64]
     return lib
+
+
+def hs_barriers(recs, off, tpb, wide=False):
+    lib = _hostsim()
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.uint64))
+    tpb = np.ascontiguousarray(np.asarray(tpb, dtype=np.uint32))
+    if tpb.ndim == 0 or len(tpb) != len(off) - 1:
+        tpb = np.full(len(off) - 1, int(np.asarray(tpb).flat[0]), dtype=np.uint32)
+    out = np.zeros(max(1, len(recs)), dtype=oracle.BARRIER_DTYPE)
+    fn = lib.hs_barriers_wide if wide else lib.hs_barriers
+    n = fn(recs.ctypes.data if len(recs) else None, off.ctypes.data, len(off) - 1, tpb.ctypes.data,
+           out.ctypes.data, len(out))
+    assert n >= 0, n
+    return out[:n]
 
 
 def hs_check(recs, off, tpb, tile, chunk, wide=False, expect_error=False):
@@ -214,3 +232,48 @@ def test_abi_structs_match_binding(tmp_path):
         assert got[(c_name, "size")] == ctypes.sizeof(py), c_name
         for f, _ in py._fields_:
             assert got[(c_name, f)] == getattr(py, f).offset, (c_name, f)
+
+
+# ------------------------------------------- barrier instances (host model)
+
+def test_host_barrier_model_tree_family():
+    """The barrier kernel's per-element rule (barrier.h), run on the CPU
+    over sorted keys, against the oracle on the tree-reduction family."""
+    for removed in range(-1, 9):
+        r = tracegen.tree_reduction(removed)
+        off = np.array([0, len(r)], dtype=np.uint64)
+        got = hs_barriers(r, off, 256)
+        want = oracle.barriers(r, tpb=256)
+        assert got.tobytes() == want.tobytes(), removed
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_host_barrier_model_random(seed):
+    rng = np.random.default_rng(2000 + seed)
+    tpb = int(rng.integers(1, 6))
+    k = int(rng.integers(1, 4))
+    traces = [tracegen.random_small(rng, int(rng.integers(0, 200)), units=int(rng.integers(1, 6)),
+                                    blocks=int(rng.integers(1, 4)), tpb=tpb, epochs=int(rng.integers(1, 6)))
+              for _ in range(k)]
+    recs = np.concatenate(traces)
+    off = np.concatenate([[0], np.cumsum([len(t) for t in traces])]).astype(np.uint64)
+    want = oracle.barriers(recs, off, tpb)
+    assert hs_barriers(recs, off, tpb).tobytes() == want.tobytes()
+    assert hs_barriers(recs, off, tpb, wide=True).tobytes() == want.tobytes()
+
+
+def test_host_barrier_model_generated():
+    shapes = tracegen.c3_shapes(24, log2_max=15)
+    recs, off, tpb, _ = tracegen.batch(shapes, inject_rate=1e-3)
+    want = oracle.barriers(recs, off, tpb)
+    assert len(want) > 0 and int(want["racing"].sum()) > 0
+    assert hs_barriers(recs, off, tpb).tobytes() == want.tobytes()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_host_barrier_model_two_word_keys(seed):
+    rng = np.random.default_rng(3000 + seed)
+    r = wide_trace(rng, 3000)
+    off = np.array([0, len(r)], dtype=np.uint64)
+    want = oracle.barriers(r, off, 64)
+    assert hs_barriers(r, off, 64, wide=True).tobytes() == want.tobytes()
