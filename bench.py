@@ -1,6 +1,6 @@
 """Benchmark of the MI355X data-race check.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 One step is one complete check of one batch of synthetic traces through the
 C ABI (sim_check_traces_device): key statistics, key generation, the radix
@@ -8,18 +8,26 @@ passes, the pair count and the download of the racing-location list.  The
 records are generated on the host, copied to HBM once, and stay resident
 while K steps are timed between two device synchronisations.
 
+The headline workload is the batched one (4096 traces of uneven size in one
+call, autotuned launch shape, launch sequence replayed as a HIP graph); the
+same traces checked one call per trace (the plain path) are timed beside it.
+Legs for the single-trace workloads (2^24 and 2^28 records) and for serving
+(Poisson arrivals of device-resident requests, then a load sweep) follow.
+
 The library's profiling mode records HIP events around every kernel on the
-stream the kernels run on; the dominant kernel's average launch time over
-the timed steps gives the roofline figure.  The oracle (CPU, one thread) is
-timed on a bounded sample of the same workload and its output is compared
-with the GPU's, bit for bit.
+stream the kernels run on; the dominant kernel's average launch time gives
+the roofline figure.  Every workload's entry list is compared with the
+oracle's, byte for byte; the oracle (CPU) is timed on a bounded sample on all
+host cores and on one.
 
 Prints one JSON line.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -33,62 +41,65 @@ METRIC = "access records checked/sec and achieved HBM GB/s (batched vs plain, bi
 
 # Algorithmic bytes per record moved by each kernel (one launch):
 #   stats  reads the 16-byte record
-#   keygen reads the record and writes its 8-byte key
+#   keygen reads the record and writes its 8-byte key (fused with radix pass
+#          0 when digit 0 is the thread id's low byte)
+#   upsweep reads every 8-byte key once (tile histograms of one digit)
 #   sort   one radix pass reads and writes every 8-byte key
 #   scan   reads every 8-byte key once (tile scan; the crossing-location
 #          and output kernels touch per-tile data only)
-BYTES_PER_RECORD = {"stats": 16, "keygen": 24, "sort_pass": 16, "scan_tiles": 8}
-KERNEL_SYMBOL = {"stats": "k_stats", "keygen": "k_keygen or k_keygen_scatter", "sort_pass": "k_scatter",
+BYTES_PER_RECORD = {"stats": 16, "keygen": 24, "upsweep": 8, "sort_pass": 16, "scan_tiles": 8}
+KERNEL_SYMBOL = {"stats": "k_stats", "keygen": "k_keygen_scatter", "upsweep": "k_upsweep", "sort_pass": "k_scatter",
                  "scan_tiles": "k_scan_tiles"}
+
+C3_DESC = ("c3: batched, 4096 traces in one call, sizes log-uniform 2^8..2^20 records, 1..256 blocks x 256 threads, "
+           "75% reads, shared window 48 KiB/block, global reads Zipf(1.1) over 64 MiB, barrier every 16 accesses, "
+           "injected races 1e-4, autotuned launch shape, HIP-graph replay")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def b_alg(passes):
+    """Algorithmic bytes per record of the sort-based pipeline with P radix
+    passes of 11-bit digits: stats read 16, key generation 16 + 8, each pass
+    16, scan 8."""
+    return 48 + 16 * passes
+
+
+# Algorithmic bytes per record of each workload, from its key width at
+# 11-bit digits: c1 and the batched traces about 48 bits (5 passes), c2 56
+# bits (6 passes).  Fixed per workload, whatever the kernels as built do.
+B_ALG = {"c1": b_alg(5), "c2": b_alg(6), "c3": b_alg(5)}
 
 
 def workload(name):
     import tracegen
 
-    if name == "c1":
-        recs, inj = tracegen.c1()
-        desc = {"workload": "c1: plain single trace, 1024 blocks x 256 threads, 2^24 records, 75% reads, "
-                            "shared window 48 KiB/block, global reads Zipf(1.1) over 64 MiB, barrier every 16 "
-                            "accesses, injected races 1e-4",
-                "traces": 1, "records": int(len(recs)), "threads_per_block": 256}
-        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([256], dtype=np.uint32), desc
     if name == "c0":
         recs = tracegen.c0()
-        desc = {"workload": "c0: shared-memory tree reduction, 1 block x 256 threads, barrier before level 3 "
-                            "removed", "traces": 1, "records": int(len(recs)), "threads_per_block": 256}
-        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([256], dtype=np.uint32), desc
+        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([256], dtype=np.uint32), {
+            "workload": "c0: shared-memory tree reduction, 1 block x 256 threads, barrier before level 3 removed",
+            "traces": 1, "records": int(len(recs))}
+    if name == "c1":
+        recs, _ = tracegen.c1()
+        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([256], dtype=np.uint32), {
+            "workload": "c1: plain single trace, 1024 blocks x 256 threads, 2^24 records, 75% reads, shared window "
+                        "48 KiB/block, global reads Zipf(1.1) over 64 MiB, barrier every 16 accesses, injected "
+                        "races 1e-4", "traces": 1, "records": int(len(recs))}
     if name == "c2":
-        recs, inj = tracegen.c2()
-        desc = {"workload": "c2: plain large trace, 8192 blocks x 512 threads, 2^28 records, 5% atomics, global "
-                            "reads Zipf(1.1) over 1 GiB, injected races 1e-5",
-                "traces": 1, "records": int(len(recs)), "threads_per_block": 512}
-        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([512], dtype=np.uint32), desc
+        recs, _ = tracegen.c2()
+        return recs, np.array([0, len(recs)], dtype=np.uint64), np.array([512], dtype=np.uint32), {
+            "workload": "c2: plain large trace, 8192 blocks x 512 threads, 2^28 records, 75% reads, 5% atomics, "
+                        "global reads Zipf(1.1) over 1 GiB, injected races 1e-5", "traces": 1,
+            "records": int(len(recs))}
     if name == "c3":
-        shapes = tracegen.c3_shapes(4096)
-        recs, off, tpb, _ = tracegen.batch(shapes, inject_rate=1e-4)
-        desc = {"workload": "c3: 4096 traces, sizes log-uniform 2^8..2^20 records, 1..256 blocks x 256 threads, "
-                            "c1 distributions", "traces": 4096, "records": int(len(recs)), "threads_per_block": 256}
-        return recs, off, tpb, desc
+        recs, off, tpb, _ = tracegen.batch(tracegen.c3_shapes(4096), inject_rate=1e-4)
+        return recs, off, tpb, {"workload": C3_DESC, "traces": 4096, "records": int(len(recs))}
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(recs, offsets, tpb, budget_records):
-    """Oracle (group counts, one thread) on the first traces of the workload
-    up to budget_records records (whole traces only, at least one)."""
-    import oracle
-
-    n_tr = len(offsets) - 1
-    k = 1
-    while k < n_tr and int(offsets[k + 1]) <= budget_records:
-        k += 1
-    n = int(offsets[k])
-    t0 = time.perf_counter()
-    races, summ = oracle.closed_form(recs[:n], offsets[: k + 1], tpb[:k])
-    dt = time.perf_counter() - t0
-    return races, summ, n, k, dt
-
-
-KERNEL_SOURCES = ["kernels.hip", "launch.h", "keys.h", "segstate.h", "tilewalk.h"]
+KERNEL_SOURCES = ["kernels.hip", "launch.h", "keys.h", "segstate.h", "tilewalk.h", "barrier.h"]
 
 
 def kernel_source_hash():
@@ -101,136 +112,272 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def pmc_traffic(stage, n_records):
-    """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter runs, if they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{KERNEL_SYMBOL[stage]}_pmc.json")
+def pmc_traffic(kernel, workload_name):
+    """HBM bytes per launch of a kernel from committed rocprofv3 counter
+    runs (profiles/<kernel>_<workload>_pmc.json), if they were taken on the
+    current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernels_sha256") != kernel_source_hash() or d.get("records") != n_records:
+    if d.get("kernels_sha256") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
 
 
-def profile_roofline(stage_ms, stage_launches, steps, n):
+def stage_profile(pkg, dev, offsets, tpb, tuning, stream, steps):
+    """Per-stage device times of `steps` calls with HIP events around every
+    launch, on the stream the kernels run on."""
+    pctx = pkg.Context(0, profile=True)
+    pctx.set_tuning(tuning["size_class"], tuning)
+    ms, launches = {}, {}
+    try:
+        for _ in range(steps):
+            pctx.check_traces_device(dev, offsets, tpb, stream=stream)
+            for name, (t, k) in pctx.stage_times().items():
+                ms[name] = ms.get(name, 0.0) + t
+                launches[name] = launches.get(name, 0) + k
+    finally:
+        pctx.close()
+    return ms, launches
+
+
+def roofline(stage_ms, stage_launches, steps, n, workload_name):
     """Roofline of the dominant kernel from per-stage event times."""
     dom = max(BYTES_PER_RECORD, key=lambda s: stage_ms.get(s, 0.0))
     avg_ms = stage_ms[dom] / max(1, stage_launches[dom])
-    alg_bytes = BYTES_PER_RECORD[dom] * n
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    return dom, {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1),
-                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                 "traffic": pmc_traffic(dom, n), "avg_launch_ms": round(avg_ms, 5),
-                 "launches_per_step": stage_launches[dom] / steps, "alg_bytes_per_launch": alg_bytes}
+    alg = BYTES_PER_RECORD[dom] * n
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": pmc_traffic(KERNEL_SYMBOL[dom], workload_name), "avg_launch_ms": round(avg_ms, 5),
+            "launches_per_step": stage_launches[dom] / steps, "alg_bytes_per_launch": alg}
 
 
-def batched_leg(pkg, torch, steps, log):
-    """The batched workload (4096 traces of uneven size): one autotuned,
-    graph-replayed call over all traces against one plain call per trace
-    (default shape, no graph) on the same device records."""
-    log("batched: generating c3")
-    recs, offsets, tpb, desc = workload("c3")
+def pipeline(records_per_s, name, passes, stage_ms_per_step):
+    """Whole-pipeline figures: records/s x the workload's algorithmic bytes
+    per record against the HBM peak, and the bytes the kernels as built
+    move (stats 16, key generation with radix pass 0 24, histogram and
+    scatter 24 per further pass, scan 8)."""
+    built = 16 + 24 + 24 * max(0.0, passes - 1) + 8
+    return {"alg_bytes_per_record": B_ALG[name], "gbps": round(records_per_s * B_ALG[name] / 1e9, 1),
+            "frac": round(records_per_s * B_ALG[name] / 1e9 / HBM_PEAK_GBPS, 4), "radix_passes": passes,
+            "built_bytes_per_record": built, "built_gbps": round(records_per_s * built / 1e9, 1),
+            "kernel_ms_per_step": round(sum(stage_ms_per_step.values()), 4)}
+
+
+def timed_calls(ctx, dev, offsets, tpb, stream, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        ctx.check_traces_device(dev, offsets, tpb, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        races, summ = ctx.check_traces_device(dev, offsets, tpb, stream=stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, races, summ
+
+
+def check_workload(pkg, torch, name, steps, warmup, recs, offsets, tpb, desc, autotune_reps=3):
+    """One workload in the production configuration: timed calls, stage
+    profile, roofline and pipeline figures."""
     n = int(len(recs))
-    n_tr = len(offsets) - 1
     dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
     torch.cuda.synchronize()
-    side = torch.cuda.Stream()
-    sptr = side.cuda_stream
-    bctx = pkg.Context(0, graphs=True)
-    log("batched: autotune")
-    with torch.cuda.stream(side):
-        tuning = bctx.autotune(dev, offsets, tpb, stream=sptr, reps=1)
-        races, summ = bctx.check_traces_device(dev, offsets, tpb, stream=sptr)  # capture
-    torch.cuda.synchronize()
-    log("batched: timed")
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = pkg.Context(0, graphs=True)
+    try:
+        log(f"{name}: autotune")
+        tuning = ctx.autotune(dev, offsets, tpb, stream=stream, reps=autotune_reps)
+        log(f"{name}: {steps} timed steps")
+        sec, races, summ = timed_calls(ctx, dev, offsets, tpb, stream, steps, warmup)
+    finally:
+        ctx.close()
+    prof_steps = max(2, min(steps, 5))
+    ms, launches = stage_profile(pkg, dev, offsets, tpb, tuning, stream, prof_steps)
+    passes = launches.get("sort_pass", 0) / prof_steps + (1 if launches.get("keygen", 0) else 0)
+    stages = {k: round(v / prof_steps, 4) for k, v in ms.items()}
+    out = {"workload": desc["workload"], "traces": desc["traces"], "records": n, "value": n / sec,
+           "unit": "records/s", "ms_per_step": 1e3 * sec, "steps": steps,
+           "racing_locations": int(len(races)), "tuning": tuning,
+           "roofline": roofline(ms, launches, prof_steps, n, name),
+           "pipeline": pipeline(n / sec, name, passes, stages), "stage_ms_per_step": stages}
+    return out, dev, races, summ
+
+
+def plain_leg(pkg, torch, dev, offsets, tpb):
+    """The same traces, one sim_check_traces_device call per trace (default
+    launch shape, no graph), on the same device records."""
+    n_tr = len(offsets) - 1
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = pkg.Context(0)
+    try:
+        views = [dev[int(offsets[i]): int(offsets[i + 1])] for i in range(n_tr)]
+        for i in range(min(8, n_tr)):
+            ctx.check_traces_device(views[i], None, int(tpb[i]), stream=stream)
+        torch.cuda.synchronize()
+        per = []
+        t0 = time.perf_counter()
+        for i in range(n_tr):
+            per.append(ctx.check_traces_device(views[i], None, int(tpb[i]), stream=stream))
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+    finally:
+        ctx.close()
+    return sec, per
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(recs, offsets, tpb, budget_records, reps=3):
+    """The oracle's group-count tier on a bounded sample (the first whole
+    traces up to budget_records records): on every host core (its OpenMP
+    driver) and on one core (the plain tier), median of `reps` runs each."""
+    import oracle
+
+    n_tr = len(offsets) - 1
+    k = 1
+    while k < n_tr and int(offsets[k + 1]) <= budget_records:
+        k += 1
+    n = int(offsets[k])
+    sub, off, tp = recs[:n], offsets[: k + 1], tpb[:k]
+    t_all, t_one = [], []
+    want = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        want, wsum = oracle.closed_form_par(sub, off, tp)
+        t_all.append(time.perf_counter() - t0)
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        one, _ = oracle.closed_form(sub, off, tp)
+        t_one.append(time.perf_counter() - t0)
+    assert one.tobytes() == want.tobytes()
+    return {"value": n / float(np.median(t_all)), "unit": "records/s", "cores": oracle.omp_threads(),
+            "kind": "oracle", "one_core_value": n / float(np.median(t_one)), "nproc": os.cpu_count(),
+            "cpu_model": cpu_model(),
+            "sample": f"first {k} traces of the batched workload, {n} records; group-count tier, median of {reps} "
+                      f"runs: {np.median(t_all):.2f} s on all cores, {np.median(t_one):.2f} s on one"}, (want, wsum, k)
+
+
+def tier_a_c0(pkg, torch):
+    """The oracle's brute force (every pair) on the tree reduction, and the
+    GPU on the same trace."""
+    import oracle
+
+    recs, off, tpb, _ = workload("c0")
     t0 = time.perf_counter()
-    with torch.cuda.stream(side):
-        for _ in range(steps):
-            races, summ = bctx.check_traces_device(dev, offsets, tpb, stream=sptr)
-    torch.cuda.synchronize()
-    b_s = (time.perf_counter() - t0) / steps
-    bctx.close()
-
-    # stage times of the same call shape (events, no graph)
-    pctx = pkg.Context(0, profile=True)
-    pctx.set_tuning(tuning["size_class"], tuning)
-    stage_ms, stage_launches = {}, {}
-    for _ in range(2):
-        pctx.check_traces_device(dev, offsets, tpb, stream=sptr)
-        for name, (ms, launches) in pctx.stage_times().items():
-            stage_ms[name] = stage_ms.get(name, 0.0) + ms
-            stage_launches[name] = stage_launches.get(name, 0) + launches
-    pctx.close()
-    _, roof = profile_roofline(stage_ms, stage_launches, 2, n)
-
-    log("batched: plain per-trace calls")
-    plain = pkg.Context(0)
-    views = [dev[int(offsets[i]) : int(offsets[i + 1])] for i in range(n_tr)]
-    for i in range(min(8, n_tr)):  # warm the buffers
-        plain.check_traces_device(views[i], None, int(tpb[i]), stream=sptr)
-    per = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(n_tr):
-        per.append(plain.check_traces_device(views[i], None, int(tpb[i]), stream=sptr))
-    torch.cuda.synchronize()
-    p_s = time.perf_counter() - t0
-    plain.close()
-    # the batched entries are the per-trace entries with trace numbers
-    parts = []
-    for i, (r, _) in enumerate(per):
-        r = r.copy()
-        r["trace"] = i
-        parts.append(r)
-    joined = np.concatenate(parts) if parts else races[:0]
-    same = joined.tobytes() == races.tobytes() and all(
-        summ[i].tobytes() == per[i][1][0].tobytes() for i in range(n_tr))
-    return {
-        "workload": desc["workload"], "traces": n_tr, "records": n,
-        "value": n / b_s, "unit": "records/s", "ms_per_step": 1e3 * b_s, "steps": steps,
-        "plain_value": n / p_s, "plain_ms": 1e3 * p_s, "speedup_vs_plain": p_s / b_s,
-        "racing_locations": int(len(races)), "tuning": tuning, "roofline": roof,
-        "stage_ms_per_step": {k: round(v / 2, 4) for k, v in stage_ms.items()},
-        "batched_equals_per_trace": bool(same),
-    }, (recs, offsets, tpb, races, summ)
+    want, wsum = oracle.brute_force(recs, off, tpb)
+    dt = time.perf_counter() - t0
+    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    ctx = pkg.Context(0)
+    try:
+        ctx.check_traces_device(dev, off, tpb)
+        t0 = time.perf_counter()
+        for _ in range(20):
+            got, gsum = ctx.check_traces_device(dev, off, tpb)
+        g = (time.perf_counter() - t0) / 20
+    finally:
+        ctx.close()
+    return {"records": int(len(recs)), "oracle_brute_force_ms": round(1e3 * dt, 3), "gpu_call_ms": round(1e3 * g, 4),
+            "racing_locations": int(len(got)),
+            "parity": "bit-exact" if got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes()
+            else "MISMATCH"}
 
 
-def serving_leg(pkg, log, loads=((2000.0, 3.0),), pool_size=256, seed=0x5EED0004):
-    """Serving workload: Poisson arrivals at `rate` requests/s for `duration`
-    seconds (one run per (rate, duration) in `loads`), each request one
-    trace with a lognormal size (median 2^14 records, sigma 1.5, at most
-    2^22), c1 distributions, 256 threads per block; requests cycle through
-    a pool of pre-generated traces.  Every result is compared with the same
-    request checked alone."""
+# ------------------------------------------------------------------ serving
+
+def serving_pool(pool_size, seed):
+    """Request traces: sizes lognormal (median 2^14 records, sigma 1.5,
+    clipped to [256, 2^22]), c1 distributions, 256 threads per block."""
     import tracegen
 
     rng = np.random.default_rng(seed)
     shapes = []
     for _ in range(pool_size):
-        n = int(min(1 << 22, max(64, round(np.exp(rng.normal(np.log(1 << 14), 1.5))))))
+        n = int(min(1 << 22, max(256, round(np.exp(rng.normal(np.log(1 << 14), 1.5))))))
         nb = max(1, min(256, -(-n // (256 * 64))))
         shapes.append((n, nb, -(-n // (nb * 256)), int(rng.integers(1, 1 << 62))))
     recs, off, tpb, _ = tracegen.batch(shapes, inject_rate=1e-4)
-    pool = [(recs[int(off[i]) : int(off[i + 1])], np.array([0, off[i + 1] - off[i]], dtype=np.uint64), tpb[i : i + 1])
-            for i in range(pool_size)]
+    return recs, off, tpb, rng
+
+
+def serving_leg(pkg, torch, seconds, sweep_seconds, pool_size=512, seed=0x5EED0004):
+    """Poisson arrivals of device-resident requests at 2000 requests/s for
+    `seconds` (every result compared with the request checked alone), then
+    a sweep doubling the rate for `sweep_seconds` each until p99 latency
+    knees (more than 4x the base p99) or the served rate falls behind the
+    offered one."""
+    recs, off, tpb, rng = serving_pool(pool_size, seed)
+    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    torch.cuda.synchronize()
+    lib = pkg.load()
+    rec_ptr = [dev.data_ptr() + 16 * int(off[i]) for i in range(pool_size)]
+    sizes = np.diff(off).astype(np.int64)
+    offs_c = [np.array([0, sizes[i]], dtype=np.uint64) for i in range(pool_size)]
+    tpb_c = [np.array([tpb[i]], dtype=np.uint32) for i in range(pool_size)]
     log("serving: requests checked alone")
     ctx = pkg.Context(0)
-    alone = [ctx.check_traces(r, o, t) for r, o, t in pool]
+    alone = [ctx.check_traces_device(dev[int(off[i]): int(off[i + 1])], offs_c[i], tpb_c[i]) for i in range(pool_size)]
     ctx.close()
+    alone_bytes = [(a.tobytes(), s.tobytes()) for a, s in alone]
 
-    srv = pkg.Server(0, hbm_budget_bytes=16 << 30, slots=4, max_batch_requests=256, reserve_records=1 << 23)
-    for r, o, t in pool[:16]:  # warm the workers' buffers
-        srv.wait(srv.submit(r, o, t))
-    out = []
-    for rate, duration in loads:
+    budget = 32 << 30
+    srv = pkg.Server(0, hbm_budget_bytes=budget, slots=4, max_batch_requests=512, reserve_records=1 << 24)
+    ticket = ctypes.c_uint64(0)
+
+    def submit(i):
+        rc = lib.sim_submit_device(srv._srv, ctypes.c_void_p(rec_ptr[i]), offs_c[i].ctypes.data, 1,
+                                   tpb_c[i].ctypes.data, ctypes.byref(ticket))
+        if rc != 0:
+            raise RuntimeError(f"sim_submit_device: {rc}")
+        return ticket.value
+
+    out = ctypes.POINTER(pkg._Result)()
+
+    def collect(t, check_i=None):
+        rc = lib.sim_wait(srv._srv, t, -1, ctypes.byref(out))
+        if rc != 0:
+            raise RuntimeError(f"sim_wait: {rc}")
+        same = True
+        if check_i is not None:
+            races, summ = pkg._take_result(out)
+            same = (races.tobytes(), summ.tobytes()) == alone_bytes[check_i]
+        else:
+            lib.sim_result_free(out)
+        return same
+
+    def run(rate, duration, check):
+        import threading
+
         srv.stats(reset=True)
-        n_req = int(rate * duration)
+        n_req = max(1, int(rate * duration))
         arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
         which = rng.integers(0, pool_size, n_req)
-        log(f"serving: {n_req} requests over {duration:.1f} s")
-        tickets = []
+        tickets = [0] * n_req
+        done = threading.Event()
+        result = {"same": True, "records": 0}
+
+        def collector():  # results are collected while requests arrive
+            for k in range(n_req):
+                while tickets[k] == 0:
+                    time.sleep(1e-4)
+                result["same"] &= collect(tickets[k], int(which[k]) if check else None)
+                result["records"] += int(sizes[which[k]])
+            done.set()
+
+        th = threading.Thread(target=collector)
+        th.start()
         t0 = time.perf_counter()
         for k in range(n_req):
             while True:
@@ -239,46 +386,62 @@ def serving_leg(pkg, log, loads=((2000.0, 3.0),), pool_size=256, seed=0x5EED0004
                     break
                 if ahead > 2e-4:
                     time.sleep(ahead - 1e-4)
-            r, o, t = pool[which[k]]
-            tickets.append(srv.submit(r, o, t))
-        late = (time.perf_counter() - t0) - arrivals[-1]
-        same = True
-        recs_done = 0
-        for k, tk in enumerate(tickets):
-            got = srv.wait(tk)
-            a = alone[which[k]]
-            same = same and got[0].tobytes() == a[0].tobytes() and got[1].tobytes() == a[1].tobytes()
-            recs_done += len(pool[which[k]][0])
+            tickets[k] = submit(int(which[k]))
+        submit_s = time.perf_counter() - t0
+        th.join()
         wall = time.perf_counter() - t0
         st = srv.stats()
-        out.append({
-            "workload": f"c4: Poisson arrivals, {rate:.0f} requests/s, one trace per request, sizes lognormal (median "
-                        "2^14, sigma 1.5, max 2^22 records), c1 distributions, 4 worker slots, 16 GiB HBM budget, "
-                        "buffers reserved for batches of 2^23 records",
-            "requests": n_req, "offered_rate": rate, "achieved_rate": n_req / wall,
-            "submit_lag_s": round(late, 4), "records": recs_done,
-            "records_per_s": st["records_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-            "max_ms": st["max_ms"], "mean_ms": st["mean_ms"], "batches": st["batches"],
-            "mean_batch_requests": st["mean_batch_requests"], "peak_inflight_bytes": st["peak_inflight_bytes"],
-            "alone_equals_mix": bool(same),
-        })
-    srv.close()
-    return out
+        served = st["records_per_s"]
+        return {"offered_rate": rate, "requests": n_req, "seconds": round(duration, 2),
+                "submitted_rate": round(n_req / submit_s, 1), "achieved_rate": round(n_req / wall, 1),
+                "records": result["records"], "records_per_s": served,
+                "hbm_frac_of_served": round(served * B_ALG["c3"] / 1e9 / HBM_PEAK_GBPS, 5),
+                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"], "mean_ms": st["mean_ms"],
+                "batches": st["batches"], "mean_batch_requests": st["mean_batch_requests"],
+                "peak_charged_bytes": st["peak_inflight_bytes"], "device_bytes": st["device_bytes"],
+                "alone_equals_mix": bool(result["same"]) if check else None}
+
+    try:
+        for i in range(32):  # warm the workers' buffers
+            collect(submit(i))
+        log(f"serving: 2000 requests/s for {seconds:.0f} s")
+        base = run(2000.0, seconds, True)
+        sweep = []
+        rate = 4000.0
+        while True:
+            log(f"serving sweep: {rate:.0f} requests/s")
+            r = run(rate, sweep_seconds, False)
+            sweep.append(r)
+            knee = r["p99_ms"] > 4 * base["p99_ms"] or r["achieved_rate"] < 0.9 * rate
+            if knee or rate >= 512000:
+                break
+            rate *= 2
+        log("serving: saturation (every request submitted at once)")
+        sat = run(1e9, 8000 / 1e9, False)  # 8000 requests with no gaps: the queue is never empty
+    finally:
+        srv.close()
+    desc = ("c4: Poisson arrivals of device-resident requests (sim_submit_device), one trace per request, sizes "
+            "lognormal (median 2^14, sigma 1.5, clipped to [256, 2^22] records), c1 distributions, 256 threads per "
+            f"block, pool of {pool_size} traces, 4 worker slots, 32 GiB HBM budget, buffers reserved for batches "
+            "of 2^24 records")
+    return {"workload": desc, "base": base, "sweep": sweep, "saturation": sat,
+            "knee_rate": sweep[-1]["offered_rate"] if sweep else None}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3"])
-    ap.add_argument("--cpu-budget", type=int, default=1 << 24, help="records in the oracle's timed sample")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
-    ap.add_argument("--batched-steps", type=int, default=5)
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serving-seconds", type=float, default=3.0)
-    ap.add_argument("--no-autotune", action="store_true", help="default launch shape (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-trace plain calls")
+    ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=30.0)
+    ap.add_argument("--sweep-seconds", type=float, default=2.0)
+    ap.add_argument("--cpu-budget", type=int, default=1 << 25, help="records in the oracle's timed sample")
+    ap.add_argument("--only", choices=["c1", "c2", "c3"], help="one workload's timed calls only (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain copy kernel of known size (256 MiB read, 256 MiB written; three launches) "
                          "whose HBM counters scale the pipeline's")
@@ -292,9 +455,6 @@ def main():
 
     import paper_1905_01833_amd as pkg
 
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
     if args.calibrate_copy:
         a = torch.arange(1 << 26, dtype=torch.int32, device="cuda:0")
         b = torch.empty_like(a)
@@ -303,114 +463,91 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    recs, offsets, tpb, desc = workload(args.workload)
-    n = int(len(recs))
-    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream().cuda_stream
-
-    # timed steps: the production configuration (autotuned launch shape,
-    # launch sequence captured once and replayed as a HIP graph)
-    ctx = pkg.Context(0, graphs=True)
-    if args.no_autotune:
-        tuning = dict(ctx.tuning(pkg.sim_size_class(n))[1], size_class=pkg.sim_size_class(n))
-    else:
-        log(f"{args.workload}: autotune")
-        tuning = ctx.autotune(dev, offsets, tpb, stream=stream, reps=3)
-    log(f"{args.workload}: warmup")
-    for _ in range(args.warmup):
-        ctx.check_traces_device(dev, offsets, tpb, stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        races, summ = ctx.check_traces_device(dev, offsets, tpb, stream=stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"{args.workload}: timed {args.steps} steps")
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = n * args.steps / elapsed
-
-    # per-kernel times: the same calls with HIP events around every launch
-    # (events add gaps between launches, not kernel time)
-    pctx = pkg.Context(0, profile=True)
-    pctx.set_tuning(tuning["size_class"], tuning)
-    stage_ms, stage_launches = {}, {}
-    for _ in range(args.steps):
-        pctx.check_traces_device(dev, offsets, tpb, stream=stream)
-        for name, (ms, launches) in pctx.stage_times().items():
-            stage_ms[name] = stage_ms.get(name, 0.0) + ms
-            stage_launches[name] = stage_launches.get(name, 0) + launches
-    torch.cuda.synchronize()
-    pctx.close()
-    _, roofline = profile_roofline(stage_ms, stage_launches, args.steps, n)
-    passes = stage_launches.get("sort_pass", 0) / args.steps
-    pipe_bytes = n * (16 + 24 + 16 * passes + 8)
-    stages = {k: round(v / args.steps, 4) for k, v in stage_ms.items()}
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "records/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic (seeded generator, shapes of the workload named in config)",
-        "config": desc,
-        "hbm_gbps_pipeline": round(pipe_bytes / (ms_per_step * 1e-3) / 1e9, 1),
-        "radix_passes": passes,
-        "stage_ms_per_step": stages,
-        "racing_locations": int(len(races)),
-        "tuning": tuning,
-        "roofline": roofline,
-    }
+    if args.only:
+        recs, offsets, tpb, desc = workload(args.only)
+        leg, dev, _, _ = check_workload(pkg, torch, args.only, args.steps, args.warmup, recs, offsets, tpb, desc)
+        print(json.dumps(leg))
+        return
 
     ok = True
-    if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        want, wsum, n_cpu, k_cpu, dt = cpu_baseline(recs, offsets, tpb, args.cpu_budget)
-        if k_cpu == len(offsets) - 1:
-            parity = races.tobytes() == want.tobytes() and summ.tobytes() == wsum.tobytes()
-        else:
-            got, gsum = ctx.check_traces_device(dev[:n_cpu], offsets[: k_cpu + 1], tpb[:k_cpu], stream=stream)
-            parity = got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes()
-        out["cpu_baseline"] = {"value": n_cpu / dt, "unit": "records/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first {k_cpu} trace(s) of the workload, {n_cpu} records, oracle group-count "
-                                         f"tier, {dt:.2f} s"}
-        out["parity"] = "bit-exact" if parity else "MISMATCH"
-        ok = ok and parity
-    ctx.close()
+    # ---- headline: the batched workload in one call, against one call per trace
+    log("c3: generating")
+    recs, offsets, tpb, desc = workload("c3")
+    n = int(len(recs))
+    head, dev, races, summ = check_workload(pkg, torch, "c3", args.steps, args.warmup, recs, offsets, tpb, desc,
+                                            autotune_reps=1)
+    out = {
+        "metric": METRIC, "value": head["value"], "unit": "records/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic (seeded generator, shapes of the workload named in config)",
+        "config": {"workload": desc["workload"], "traces": 4096, "records": n, "threads_per_block": 256},
+        "hbm_gbps_pipeline": head["pipeline"]["gbps"], "pipeline": head["pipeline"],
+        "stage_ms_per_step": head["stage_ms_per_step"], "racing_locations": head["racing_locations"],
+        "tuning": head["tuning"], "roofline": head["roofline"],
+    }
+    if not args.no_plain:
+        log("c3: one plain call per trace")
+        p_s, per = plain_leg(pkg, torch, dev, offsets, tpb)
+        parts = []
+        for i, (r, _) in enumerate(per):
+            r = r.copy()
+            r["trace"] = i
+            parts.append(r)
+        joined = np.concatenate(parts) if parts else races[:0]
+        same = joined.tobytes() == races.tobytes() and all(
+            summ[i].tobytes() == per[i][1][0].tobytes() for i in range(len(per)))
+        out["plain"] = {"value": n / p_s, "unit": "records/s", "ms": 1e3 * p_s,
+                        "speedup_batched_vs_plain": (n / head["ms_per_step"] * 1e3) / (n / p_s),
+                        "batched_equals_per_trace": bool(same)}
+        ok = ok and same
+        del per, parts, joined
     del dev
+    torch.cuda.synchronize()
+    if not args.no_cpu:
+        log("c3: oracle on every trace (all host cores)")
+        import oracle
 
-    if not args.no_batched and args.workload != "c3":
-        b, (brecs, boff, btpb, braces, bsumm) = batched_leg(pkg, torch, args.batched_steps, log)
+        t0 = time.perf_counter()
+        want, wsum = oracle.closed_form_par(recs, offsets, tpb)
+        par_s = time.perf_counter() - t0
+        out["parity"] = "bit-exact" if races.tobytes() == want.tobytes() and summ.tobytes() == wsum.tobytes() \
+            else "MISMATCH"
+        out["parity_scope"] = f"all 4096 traces, every entry and summary, against the oracle ({par_s:.1f} s)"
+        ok = ok and out["parity"] == "bit-exact"
+        del want, wsum
+        log("cpu baseline (oracle, all cores and one core)")
+        cb, (want, wsum, k) = cpu_baseline(recs, offsets, tpb, args.cpu_budget)
+        out["cpu_baseline"] = cb
+        out["cpu_baseline_c0_tier_a"] = tier_a_c0(pkg, torch)
+        ok = ok and out["cpu_baseline_c0_tier_a"]["parity"] == "bit-exact"
+    del recs
+
+    # ---- single-trace workloads
+    for name, skip in (("c1", args.no_c1), ("c2", args.no_c2)):
+        if skip:
+            continue
+        log(f"{name}: generating")
+        recs, offsets, tpb, desc = workload(name)
+        leg, dev, races, summ = check_workload(pkg, torch, name, max(3, args.steps // (4 if name == "c2" else 1)),
+                                               2, recs, offsets, tpb, desc)
+        del dev
+        torch.cuda.synchronize()
         if not args.no_cpu:
-            # oracle on the leading traces of the batch (about 2^21 records)
-            k = 1
-            while k < len(boff) - 1 and int(boff[k + 1]) <= (1 << 21):
-                k += 1
+            log(f"{name}: oracle (all host cores)")
             import oracle
 
-            want, wsum = oracle.closed_form(brecs[: int(boff[k])], boff[: k + 1], btpb[:k])
-            sub = braces[braces["trace"] < k]
-            b["parity"] = ("bit-exact" if sub.tobytes() == want.tobytes() and bsumm[:k].tobytes() == wsum.tobytes()
-                           else "MISMATCH")
-            b["parity_sample"] = f"oracle on the first {k} traces ({int(boff[k])} records); all traces against " \
-                                 "per-trace plain calls"
-            ok = ok and b["parity"] == "bit-exact"
-        ok = ok and b["batched_equals_per_trace"]
-        out["batched"] = b
+            want, wsum = oracle.closed_form_par(recs, offsets, tpb)
+            leg["parity"] = "bit-exact" if races.tobytes() == want.tobytes() and summ.tobytes() == wsum.tobytes() \
+                else "MISMATCH"
+            ok = ok and leg["parity"] == "bit-exact"
+            del want, wsum
+        out[name] = leg
+        del recs
+
     if not args.no_serving:
-        # the configured rate, then ten times that rate (requests queue while
-        # batches run, so continuous batching merges them)
-        sv, hi = serving_leg(pkg, log, loads=((2000.0, args.serving_seconds), (20000.0, 1.0)))
-        ok = ok and sv["alone_equals_mix"] and hi["alone_equals_mix"]
+        sv = serving_leg(pkg, torch, args.serving_seconds, args.sweep_seconds)
+        ok = ok and bool(sv["base"]["alone_equals_mix"])
         out["serving"] = sv
-        out["serving_high_load"] = hi
     print(json.dumps(out))
     if not ok:
         sys.exit(1)
