@@ -121,8 +121,10 @@ enum {
   SIM_ENOMEM = -3,  /* device or host allocation failed */
   SIM_EDEVICE = -4, /* HIP runtime error (text in sim_last_error()) */
   SIM_EAGAIN = -5,  /* serving: result not ready yet, or the pending queue is full */
-  SIM_ERANGE = -6   /* a trace's sort key would need more than 128 bits (cannot happen with 32-bit thread
+  SIM_ERANGE = -6,  /* a trace's sort key would need more than 128 bits (cannot happen with 32-bit thread
                        ids and 16-bit epochs: keys take at most 116 bits; kept for the ABI) */
+  SIM_ENOSPC = -7   /* sim_check_traces_device_noalloc: the caller's output buffer, or the scratch, holds
+                       fewer entries than the call has; *n_races gives the number of entries */
 };
 
 /* --------------------------------------------------------------- context */
@@ -168,6 +170,36 @@ int sim_check_traces(sim_ctx* ctx, const sim_record* records, const uint64_t* of
 int sim_check_traces_device(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offsets,
                             uint32_t n_traces, const uint32_t* threads_per_block, void* stream,
                             sim_result** out);
+
+/* The check of sim_check_traces_device without any allocation, for callers
+ * that cannot allocate (code that runs under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Every device buffer of
+ * the call comes from one fixed scratch array of 128 MiB per GPU that the
+ * library holds until the process ends, and the call's tables from pinned
+ * host memory sim_create() allocated; the result goes to the caller's
+ * buffers.  No device, pinned or host memory is allocated by this call
+ * (creating the context, earlier, does allocate).
+ *   d_records, offsets, n_traces, threads_per_block, stream : as for
+ *                       sim_check_traces_device
+ *   races      : host memory, room for races_cap entries; receives the
+ *                entries in the order of sim_check_traces
+ *   n_races    : receives the number of entries (also on SIM_ENOSPC)
+ *   traces     : host memory, n_traces summaries
+ * Limits: at most 4096 traces and 6144 tiles (a trace of n records takes
+ * ceil(n / 4096) tiles), and the call's device buffers must fit the scratch:
+ * 16 bytes per record (32 with two-word keys, see sim_check_traces), about
+ * 4.3 KiB per tile and 128 bytes per trace, the rest holding the entry list
+ * (2^22 records in one trace leave room for about a million entries).  A call
+ * beyond these limits fails with SIM_EINVAL; one with more entries than
+ * races_cap or than the scratch holds with SIM_ENOSPC.  Calls on one GPU
+ * share its scratch: calls that overlap in time on one GPU (from several
+ * threads or contexts) race with each other and must be serialised by the
+ * caller.  The scratch keeps the last call's contents; every call
+ * initialises what it reads.                                               */
+int sim_check_traces_device_noalloc(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offsets,
+                                    uint32_t n_traces, const uint32_t* threads_per_block, void* stream,
+                                    sim_race* races, uint64_t races_cap, uint64_t* n_races,
+                                    sim_trace_summary* traces);
 
 /* Free a result.  NULL is ignored. */
 void sim_result_free(sim_result* r);

@@ -32,7 +32,7 @@ RACE_DTYPE = np.dtype(
 SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pairs", "<u8")])
 BARRIER_DTYPE = np.dtype([("trace", "<u4"), ("boundary", "<u4"), ("instances", "<u8"), ("racing", "<u8")])
 
-SIM_OK, SIM_EINVAL, SIM_ERECORD, SIM_ENOMEM, SIM_EDEVICE, SIM_ERANGE = 0, -1, -2, -3, -4, -6
+SIM_OK, SIM_EINVAL, SIM_ERECORD, SIM_ENOMEM, SIM_EDEVICE, SIM_ERANGE, SIM_ENOSPC = 0, -1, -2, -3, -4, -6, -7
 SIM_CFG_PROFILE = 1
 SIM_CFG_GRAPHS = 2
 STAGES = ["init", "stats", "layout", "keygen", "upsweep", "sort_pass", "scan_tiles", "scan_cross", "scan_out"]
@@ -40,7 +40,7 @@ STAGES = ["init", "stats", "layout", "keygen", "upsweep", "sort_pass", "scan_til
 # Symbols declared in include/simcheck.h.
 EXPORTS = [
     "sim_create", "sim_destroy", "sim_last_error", "sim_check_traces", "sim_check_traces_device",
-    "sim_result_free", "sim_check_sync_device", "sim_check_sync",
+    "sim_check_traces_device_noalloc", "sim_result_free", "sim_check_sync_device", "sim_check_sync",
     "sim_barrier_result_free", "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning",
     "sim_get_tuning", "sim_autotune", "sim_server_create", "sim_server_destroy", "sim_submit", "sim_submit_device",
     "sim_poll",
@@ -144,6 +144,9 @@ def load() -> ctypes.CDLL:
     lib.sim_check_traces.argtypes = [P, P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.POINTER(_Result))]
     lib.sim_check_traces_device.restype = ctypes.c_int
     lib.sim_check_traces_device.argtypes = [P, P, P, ctypes.c_uint32, P, P, ctypes.POINTER(ctypes.POINTER(_Result))]
+    lib.sim_check_traces_device_noalloc.restype = ctypes.c_int
+    lib.sim_check_traces_device_noalloc.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, ctypes.c_uint64,
+                                                    ctypes.POINTER(ctypes.c_uint64), P]
     lib.sim_check_sync_device.restype = ctypes.c_int
     lib.sim_check_sync_device.argtypes = [P, P, P, ctypes.c_uint32, P, P, ctypes.POINTER(ctypes.POINTER(_Result)),
                                           ctypes.POINTER(ctypes.POINTER(_BarrierResult))]
@@ -263,6 +266,35 @@ def sim_check_traces_device(ctx, d_records_ptr: int, n_records: int, offsets=Non
     if rc != SIM_OK:
         raise SimError(rc, sim_last_error(ctx))
     return _take_result(out)
+
+
+def sim_check_traces_device_noalloc(ctx, d_records_ptr: int, n_records: int, offsets=None, threads_per_block=1,
+                                    stream=None, races_cap: int = 1 << 16, races_out=None, traces_out=None):
+    """The no-allocation check (records in device memory, every device
+    buffer from the library's fixed scratch).  races_out / traces_out are
+    the caller's host arrays (RACE_DTYPE with room for races_cap entries,
+    SUMMARY_DTYPE with one per trace); made here when not given.  Returns
+    (races, summaries) as views of them."""
+    lib = load()
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, n_records)
+    if int(offsets[-1]) != n_records:
+        raise ValueError("offsets[-1] must equal the number of device records")
+    if races_out is None:
+        races_out = np.zeros(races_cap, dtype=RACE_DTYPE)
+    if traces_out is None:
+        traces_out = np.zeros(max(n_traces, 1), dtype=SUMMARY_DTYPE)
+    if races_out.dtype != RACE_DTYPE or traces_out.dtype != SUMMARY_DTYPE or len(traces_out) < n_traces:
+        raise ValueError("races_out / traces_out have the wrong type or size")
+    n = ctypes.c_uint64(0)
+    rc = lib.sim_check_traces_device_noalloc(
+        ctx, ctypes.c_void_p(d_records_ptr) if n_records else None, offsets.ctypes.data, n_traces, tpb.ctypes.data,
+        ctypes.c_void_p(stream or 0), races_out.ctypes.data if len(races_out) else None, len(races_out),
+        ctypes.byref(n), traces_out.ctypes.data)
+    if rc != SIM_OK:
+        err = SimError(rc, sim_last_error(ctx))
+        err.n_races = int(n.value)
+        raise err
+    return races_out[: n.value], traces_out[:n_traces]
 
 
 def _take_barriers(res_p):
@@ -422,6 +454,14 @@ class Context:
         """Races and barrier instances of a device tensor of records."""
         ptr, n, stream = self._device_args(tensor, stream)
         return sim_check_sync_device(self._ctx, ptr, n, offsets, threads_per_block, stream)
+
+    def check_traces_device_noalloc(self, tensor, offsets=None, threads_per_block=1, stream=None,
+                                    races_cap: int = 1 << 16, races_out=None, traces_out=None):
+        """sim_check_traces_device_noalloc on a device tensor (as in
+        check_traces_device); the result lands in host arrays."""
+        ptr, n, stream = self._device_args(tensor, stream)
+        return sim_check_traces_device_noalloc(self._ctx, ptr, n, offsets, threads_per_block, stream, races_cap,
+                                               races_out, traces_out)
 
     @staticmethod
     def _device_args(tensor, stream):

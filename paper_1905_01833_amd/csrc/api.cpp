@@ -8,6 +8,10 @@
 // a second round on the device: a trace needing more radix passes than the
 // previous call did, a tile with more racing locations than its staging
 // slice holds, or more racing locations than the output buffer holds.
+//
+// The no-allocation entry point runs the same sequence with every device
+// buffer carved out of a fixed scratch array (kernels.hip) and the tables
+// in pinned host memory the context allocated at creation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,6 +82,8 @@ struct sim_ctx {
                            // per-tile words of a staging overflow (tile counts down, references up)
   size_t h_meta_cap = 0;
   Ctrl* h_ctrl = nullptr;  // pinned
+  void* scratch = nullptr; // this device's no-allocation scratch (nullptr: its lookup failed)
+  hipError_t scratch_err = hipSuccess;
 
   hipEvent_t ev[MAX_EV] = {};
   sim_stage_time times[N_STAGE] = {};
@@ -222,7 +228,15 @@ static size_t host_bytes(uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups
   return (meta_bytes(n_traces, n_tiles, n_hgroups) + 15) / 16 * 16 + (size_t)n_tiles * 16;
 }
 
-// The fixed device regions of a call.
+// Limits of the no-allocation entry point besides the scratch itself: the
+// pinned tables every context allocates at creation hold this many traces
+// and tiles (2^23 records in the largest call the scratch can hold, plus one
+// partial tile per trace).
+constexpr uint32_t NOALLOC_MAX_TRACES = 4096;
+constexpr uint32_t NOALLOC_MAX_TILES = (1u << 23) / TILE + NOALLOC_MAX_TRACES;
+
+// The fixed device regions of a call, in one order for both ways of
+// providing them (grow-only context buffers, or the scratch).
 enum { R_KEYS0, R_KEYS1, R_META, R_STATS, R_LAYOUT, R_THIST, R_GTOT, R_GBASE, R_AGG, R_TOUT, R_CROSS, R_CFLAG,
        R_GSUM, R_CTRL, N_REGION };
 
@@ -309,9 +323,14 @@ hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t 
   return ensure(c->out, out_need, false, &c->alloc_gen);
 }
 
-// Where a call's result goes.
+// Where a call's result goes: a result the library allocates (the ordinary
+// entry points), or buffers the caller owns (the no-allocation entry point).
 struct Sink {
   sim_result** out = nullptr;
+  sim_race* races = nullptr;
+  uint64_t races_cap = 0;
+  uint64_t* n_races = nullptr;
+  sim_trace_summary* traces = nullptr;
   sim_barrier_result** barriers = nullptr;  // also the redundant-barrier check
 };
 
@@ -323,26 +342,50 @@ void barrier_result_free(sim_barrier_result* r) {
 
 // One call.  Trace i's records start at trace_recs[i] when trace_recs is
 // given (device pointers, the traces need not be adjacent), else at
-// d_records + offsets[i].
+// d_records + offsets[i].  noalloc: every device buffer comes from the
+// scratch and nothing is allocated.
 int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_recs, const uint64_t* offsets,
-        uint32_t n_traces, const uint32_t* tpb, hipStream_t s, const Sink& sink) {
+        uint32_t n_traces, const uint32_t* tpb, hipStream_t s, const Sink& sink, bool noalloc) {
   uint64_t total = 0;
   uint32_t n_tiles = 0;
-  int rc = validate(c, offsets, n_traces, tpb, sink.out, &total, &n_tiles);
+  sim_result* dummy = nullptr;
+  int rc = validate(c, offsets, n_traces, tpb, sink.out ? sink.out : &dummy, &total, &n_tiles);
   if (rc) return rc;
   if (total && !d_records && !trace_recs) return fail(c, SIM_EINVAL, "records is NULL");
   if (trace_recs)
     for (uint32_t i = 0; i < n_traces; i++)
       if (offsets[i + 1] > offsets[i] && !trace_recs[i]) return fail(c, SIM_EINVAL, "records of trace %u is NULL", i);
+  if (noalloc) {
+    if (!c->scratch)
+      return fail(c, SIM_EDEVICE, "no-allocation scratch unavailable on device %d: %s", c->device,
+                  hipGetErrorString(c->scratch_err));
+    if (n_traces > NOALLOC_MAX_TRACES)
+      return fail(c, SIM_EINVAL, "a no-allocation call holds at most %u traces", NOALLOC_MAX_TRACES);
+    if (n_tiles > NOALLOC_MAX_TILES)
+      return fail(c, SIM_EINVAL, "a no-allocation call holds at most %u tiles of 4096 records", NOALLOC_MAX_TILES);
+  }
   for (auto& t : c->times) t = sim_stage_time{0.0, 0, 0};
 
   // result delivery: summaries from the entry list, entries downloaded from
   // `dev_out` (n_races of them)
   auto deliver = [&](uint64_t n_races, const void* dev_out) -> int {
-    sim_result* r = alloc_result(n_races, n_traces);
-    if (!r) return fail(c, SIM_ENOMEM, "host allocation failed");
-    sim_trace_summary* sums = r->traces;
-    sim_race* races = r->races;
+    sim_trace_summary* sums = nullptr;
+    sim_race* races = nullptr;
+    sim_result* r = nullptr;
+    if (sink.out) {
+      r = alloc_result(n_races, n_traces);
+      if (!r) return fail(c, SIM_ENOMEM, "host allocation failed");
+      sums = r->traces;
+      races = r->races;
+    } else {
+      *sink.n_races = n_races;
+      if (n_races > sink.races_cap)
+        return fail(c, SIM_ENOSPC, "%llu racing locations, the output buffer holds %llu",
+                    (unsigned long long)n_races, (unsigned long long)sink.races_cap);
+      sums = sink.traces;
+      races = sink.races;
+      for (uint32_t i = 0; i < n_traces; i++) sums[i] = sim_trace_summary{0, 0, 0};
+    }
     hipError_t e;
     if (n_races && ((e = hipMemcpyAsync(races, dev_out, n_races * sizeof(sim_race), hipMemcpyDeviceToHost, s)) ||
                     (e = hipStreamSynchronize(s)))) {
@@ -359,7 +402,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       sums[x.trace].n_race_locs += 1;
       sums[x.trace].n_pairs += x.pairs_ww + x.pairs_rw + x.pairs_aw + x.pairs_ar;
     }
-    *sink.out = r;
+    if (sink.out) *sink.out = r;
     return SIM_OK;
   };
 
@@ -394,6 +437,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   }
   const size_t h_bytes = host_bytes(n_traces, n_tiles, n_hgroups64);
   if (c->h_meta_cap < h_bytes) {
+    if (noalloc) return fail(c, SIM_EINVAL, "the call's tables exceed the context's pinned tables");
     if (c->h_meta) (void)hipHostFree(c->h_meta);
     c->h_meta = nullptr;
     c->h_meta_cap = 0;
@@ -436,14 +480,42 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   TileOut* h_tout = (TileOut*)((char*)c->h_meta + (meta_bytes(n_traces, n_tiles, n_hgroups) + 15) / 16 * 16);
   uint64_t* h_sref = (uint64_t*)(h_tout + n_tiles);
 
-  // ---- device buffers
+  // ---- device buffers: the context's (grown as needed) or the scratch's
   const uint32_t key_bytes = wide ? 16u : 8u;
   void* reg[N_REGION];
-  if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups, key_bytes)) != hipSuccess)
-    return hip_fail(c, e, "device allocation");
-  for (int r = 0; r < N_REGION; r++) reg[r] = region_buf(c, r)->p;
-  RaceOut* out_p = (RaceOut*)c->out.p;
-  const uint64_t out_cap = c->out.cap / sizeof(RaceOut);
+  RaceOut* out_p = nullptr;
+  uint64_t out_cap = 0;
+  char* rest = nullptr;  // no-allocation calls: the scratch after the fixed regions
+  size_t rest_bytes = 0;
+  uint64_t* d_sref = nullptr;
+  if (noalloc) {
+    size_t need[N_REGION];
+    region_bytes(need, total, n_traces, n_tiles, n_hgroups, key_bytes);
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+      off = (off + 255) / 256 * 256;
+      void* p = (char*)c->scratch + off;
+      off += bytes;
+      return p;
+    };
+    for (int r = 0; r < N_REGION; r++) reg[r] = carve(need[r]);
+    d_sref = (uint64_t*)carve((size_t)n_tiles * 8);
+    off = (off + 255) / 256 * 256;
+    if (off > SCRATCH_BYTES)
+      return fail(c, SIM_EINVAL,
+                  "the call needs %llu bytes of device buffers (%u-byte keys), the no-allocation scratch holds %llu",
+                  (unsigned long long)off, key_bytes, (unsigned long long)SCRATCH_BYTES);
+    rest = (char*)c->scratch + off;
+    rest_bytes = SCRATCH_BYTES - off;
+    out_p = (RaceOut*)rest;
+    out_cap = rest_bytes / sizeof(RaceOut);
+  } else {
+    if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups, key_bytes)) != hipSuccess)
+      return hip_fail(c, e, "device allocation");
+    for (int r = 0; r < N_REGION; r++) reg[r] = region_buf(c, r)->p;
+    out_p = (RaceOut*)c->out.p;
+    out_cap = c->out.cap / sizeof(RaceOut);
+  }
   if ((e = hipMemcpyAsync(reg[R_META], c->h_meta, meta_bytes(n_traces, n_tiles, n_hgroups), hipMemcpyHostToDevice, s)))
     return hip_fail(c, e, "table upload");
 
@@ -567,8 +639,10 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   // Graph mode: the first round (every launch up to the control download)
   // is captured once per call shape and replayed while the shape, the
   // buffers and the pass count stay the same.  (Not for gathered traces,
-  // whose record addresses are not part of the shape.)
-  const bool use_graph = (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0 && !trace_recs;
+  // whose record addresses are not part of the shape, nor for calls that
+  // may not allocate: instantiating a graph does.)
+  const bool use_graph =
+      (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0 && !trace_recs && !noalloc;
   uint64_t th = 1469598103934665603ull;  // FNV-1a over the per-call tables
   if (use_graph) {
     const unsigned char* q = (const unsigned char*)offsets;
@@ -626,7 +700,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
     // a trace needs two-word keys: run the whole call again in that mode
     // (the next call starts in it while its traces keep needing it)
     c->wide_guess = true;
-    return run(c, d_records, trace_recs, offsets, n_traces, tpb, s, sink);
+    return run(c, d_records, trace_recs, offsets, n_traces, tpb, s, sink, noalloc);
   }
   const uint32_t needed = ctl.max_passes;
   if (needed > guess) {
@@ -657,11 +731,21 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
         h_sref[t] = 0;
       }
     }
-    if ((e = grow(c, c->stage, (size_t)staged * sizeof(RaceOut))) ||
-        (e = grow(c, c->stage_ref, (size_t)n_tiles * sizeof(uint64_t))))
-      return hip_fail(c, e, "device allocation");
-    RaceOut* stage = (RaceOut*)c->stage.p;
-    uint64_t* d_sref = (uint64_t*)c->stage_ref.p;
+    RaceOut* stage = nullptr;
+    if (noalloc) {  // from the end of the scratch's free part; the output keeps the rest
+      const size_t sbytes = (size_t)staged * sizeof(RaceOut);
+      if (sbytes > rest_bytes)
+        return fail(c, SIM_ENOSPC, "the call stages %llu entries, more than the no-allocation scratch holds",
+                    (unsigned long long)staged);
+      stage = (RaceOut*)(rest + (rest_bytes - sbytes) / 256 * 256);
+      b.out_cap = (size_t)((char*)stage - rest) / sizeof(RaceOut);
+    } else {
+      if ((e = grow(c, c->stage, (size_t)staged * sizeof(RaceOut))) ||
+          (e = grow(c, c->stage_ref, (size_t)n_tiles * sizeof(uint64_t))))
+        return hip_fail(c, e, "device allocation");
+      stage = (RaceOut*)c->stage.p;
+      d_sref = (uint64_t*)c->stage_ref.p;
+    }
     if ((e = hipMemcpyAsync(d_sref, h_sref, (size_t)n_tiles * sizeof(uint64_t), hipMemcpyHostToDevice, s)))
       return hip_fail(c, e, "staging table upload");
     b.stage = stage;
@@ -675,6 +759,11 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
 
   uint64_t n_races = ctl.total_entries;
   if (n_races > b.out_cap) {  // more racing locations than the output buffer holds
+    if (noalloc) {
+      if (sink.n_races) *sink.n_races = n_races;
+      return fail(c, SIM_ENOSPC, "%llu racing locations, the no-allocation scratch holds %llu",
+                  (unsigned long long)n_races, (unsigned long long)b.out_cap);
+    }
     if ((e = grow(c, c->out, n_races * sizeof(RaceOut)))) return hip_fail(c, e, "device allocation");
     b.out = (RaceOut*)c->out.p;
     b.out_cap = c->out.cap / sizeof(RaceOut);
@@ -800,7 +889,7 @@ int ctx_check_gather(sim_ctx* c, const sim_record* const* trace_recs, const uint
   DeviceGuard g(c->device);
   Sink sink;
   sink.out = out;
-  return run(c, nullptr, trace_recs, offsets, n_traces, tpb, s, sink);
+  return run(c, nullptr, trace_recs, offsets, n_traces, tpb, s, sink, false);
 }
 
 }  // namespace sc
@@ -832,6 +921,20 @@ int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg) {
       sim_destroy(c);
       return SIM_EDEVICE;
     }
+  // the no-allocation entry point: this device's scratch address (looked up
+  // once per device, with the device current), pinned tables for its
+  // largest call, and room for error texts
+  c->scratch_err = scratch_address(hip_device, &c->scratch);
+  {
+    const size_t hb = host_bytes(NOALLOC_MAX_TRACES, NOALLOC_MAX_TILES, NOALLOC_MAX_TILES);
+    if (hipHostMalloc(&c->h_meta, hb, hipHostMallocDefault) != hipSuccess) {
+      c->h_meta = nullptr;
+      sim_destroy(c);
+      return SIM_ENOMEM;
+    }
+    c->h_meta_cap = hb;
+  }
+  c->err.reserve(512);
   if (cfg && cfg->reserve_records) {  // every buffer of a call this large, allocated now
     const uint64_t n_rec = cfg->reserve_records;
     const uint32_t n_tr = cfg->reserve_traces ? cfg->reserve_traces : 1;
@@ -872,7 +975,26 @@ int sim_check_traces_device(sim_ctx* c, const sim_record* d_records, const uint6
   DeviceGuard g(c->device);
   Sink sink;
   sink.out = out;
-  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink);
+  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink, false);
+}
+
+int sim_check_traces_device_noalloc(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets,
+                                    uint32_t n_traces, const uint32_t* threads_per_block, void* stream,
+                                    sim_race* races, uint64_t races_cap, uint64_t* n_races,
+                                    sim_trace_summary* traces) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (!n_races) return fail(c, SIM_EINVAL, "n_races is NULL");
+  *n_races = 0;
+  if (n_traces && !traces) return fail(c, SIM_EINVAL, "traces is NULL");
+  if (races_cap && !races) return fail(c, SIM_EINVAL, "races is NULL with a nonzero capacity");
+  DeviceGuard g(c->device);
+  Sink sink;
+  sink.races = races;
+  sink.races_cap = races_cap;
+  sink.n_races = n_races;
+  sink.traces = traces;
+  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink, true);
 }
 
 int sim_check_traces(sim_ctx* c, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
@@ -894,7 +1016,8 @@ int sim_check_traces(sim_ctx* c, const sim_record* records, const uint64_t* offs
   }
   Sink sink;
   sink.out = out;
-  return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink);
+  return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink,
+             false);
 }
 
 int sim_check_sync_device(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
@@ -908,7 +1031,7 @@ int sim_check_sync_device(sim_ctx* c, const sim_record* d_records, const uint64_
   Sink sink;
   sink.out = races;
   sink.barriers = barriers;
-  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink);
+  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink, false);
 }
 
 int sim_check_sync(sim_ctx* c, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
@@ -932,7 +1055,8 @@ int sim_check_sync(sim_ctx* c, const sim_record* records, const uint64_t* offset
   Sink sink;
   sink.out = races;
   sink.barriers = barriers;
-  return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink);
+  return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink,
+             false);
 }
 
 void sim_barrier_result_free(sim_barrier_result* r) { barrier_result_free(r); }
@@ -1000,7 +1124,7 @@ int sim_autotune(sim_ctx* c, const sim_record* d_records, const uint64_t* offset
       const auto t0 = std::chrono::steady_clock::now();
       Sink sink;
       sink.out = &res;
-      const int rc1 = run(c, d_records, nullptr, offsets, n_traces, threads_per_block, s, sink);
+      const int rc1 = run(c, d_records, nullptr, offsets, n_traces, threads_per_block, s, sink, false);
       const auto t1 = std::chrono::steady_clock::now();
       sim_result_free(res);
       if (rc1) {

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "barrier.h"
@@ -1663,6 +1664,35 @@ hipError_t launch_barriers(const Buffers& b, const uint64_t* bar_base, BarrierCo
                      : (lp ? k_barriers<uint64_t, true> : k_barriers<uint64_t, false>);
   hipLaunchKernelGGL(kern, dim3(b.grid_scan), dim3(NT), 0, s, b, bar_base, table, copies);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------- no-allocation scratch
+//
+// Every buffer of a sim_check_traces_device_noalloc call is carved out of
+// this array.  Each GPU that loads the library holds its own copy (at its
+// own address) until the process ends.  In host code the name `scratch` is
+// only a host-side stand-in for the symbol: passing it to a kernel would
+// fault.  Host code uses the address scratch_address() returns instead.
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int MAX_SCRATCH_DEVICES = 64;
+
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[MAX_SCRATCH_DEVICES];
+  static hipError_t err[MAX_SCRATCH_DEVICES];
+  static bool looked_up[MAX_SCRATCH_DEVICES];
+  *out = nullptr;
+  if (device < 0 || device >= MAX_SCRATCH_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!looked_up[device]) {  // once per device, with that device current (the caller's guarantee)
+    void* p = nullptr;
+    err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    addr[device] = err[device] == hipSuccess ? p : nullptr;
+    looked_up[device] = true;
+  }
+  *out = addr[device];
+  return err[device];
 }
 
 }  // namespace sc

@@ -142,4 +142,11 @@ hipError_t launch_reset_errors(const Buffers& b, uint32_t mask, hipStream_t s);
 hipError_t launch_barriers(const Buffers& b, const uint64_t* bar_base, BarrierCount* table, uint64_t n_counts,
                            uint32_t copies, hipStream_t s);
 
+// Device memory of the no-allocation entry point: a file-scope array of
+// SCRATCH_BYTES in the library's device code, one copy per GPU.
+constexpr size_t SCRATCH_BYTES = (size_t)128 << 20;
+// The array's address on `device` (which must be the current device), looked
+// up once per device and remembered; the error of that lookup otherwise.
+hipError_t scratch_address(int device, void** out);
+
 }  // namespace sc
