@@ -50,6 +50,8 @@ SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pair
 KIND_BITS = {"ww": 1, "rw": 2, "aw": 4, "ar": 8, "xblock": 16}
 
 BARRIER_DTYPE = np.dtype([("trace", "<u4"), ("boundary", "<u4"), ("instances", "<u8"), ("racing", "<u8")])
+DIVERGENCE_DTYPE = np.dtype([("trace", "<u4"), ("block", "<u4"), ("min_barriers", "<u4"), ("max_barriers", "<u4"),
+                             ("early_threads", "<u8")])
 
 
 class OracleError(Exception):
@@ -98,6 +100,10 @@ def _load():
             f.restype = ctypes.c_int64
             f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64)]
+        f = lib.orc_divergence_check
+        f.restype = ctypes.c_int64
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                      ctypes.POINTER(ctypes.c_void_p)]
         lib.orc_free.restype = None
         lib.orc_free.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -229,6 +235,32 @@ def barriers_py(records, tpb):
 def barriers_to_dict(res, trace=0):
     """{boundary: (instances, racing)} of one trace from a BARRIER_DTYPE array."""
     return {int(r["boundary"]): (int(r["instances"]), int(r["racing"])) for r in res if int(r["trace"]) == trace}
+
+
+def divergence(counts, offsets, tpb):
+    """Barrier divergence (Alg. 4): counts[i] is the number of barriers
+    thread i arrived at before finishing; trace t holds threads
+    offsets[t] .. offsets[t+1], block by block (whole blocks).  One
+    DIVERGENCE_DTYPE row per block whose threads' counts differ."""
+    counts = np.ascontiguousarray(np.asarray(counts, dtype=np.uint32))
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    n_traces = len(offsets) - 1
+    tpb = np.asarray(tpb, dtype=np.uint32)
+    if tpb.ndim == 0:
+        tpb = np.full(n_traces, int(tpb), dtype=np.uint32)
+    tpb = np.ascontiguousarray(tpb)
+    lib = _load()
+    out = ctypes.c_void_p()
+    n = lib.orc_divergence_check(counts.ctypes.data if len(counts) else None, offsets.ctypes.data, n_traces,
+                                 tpb.ctypes.data, ctypes.byref(out))
+    if n < 0:
+        raise OracleError(int(n))
+    res = np.zeros(n, dtype=DIVERGENCE_DTYPE)
+    if n:
+        ctypes.memmove(res.ctypes.data, out.value, n * DIVERGENCE_DTYPE.itemsize)
+    if out.value:
+        lib.orc_free(out)
+    return res
 
 
 # ---------------------------------------------------------------------------

@@ -717,4 +717,63 @@ int64_t orc_barriers(const orc_record* recs, const uint64_t* off, uint32_t n_tra
   return (int64_t)res.n;
 }
 
+/* ===================== Barrier divergence (Alg. 4) =====================
+ *
+ * Alg. 4 reports a barrier divergence when a thread reaches the end of the
+ * kernel while other threads of its block halt at a barrier (Sec. 4.2.2):
+ * the halted thread waits at a barrier the finished one never reaches.  So,
+ * given for every thread the number of barriers it arrived at before it
+ * finished, a block diverges when those numbers are not all equal: a thread
+ * with fewer arrivals finished while a thread with more waited at a barrier
+ * it did not reach.  Per trace, threads are numbered block by block
+ * (thread t is in block t / threads_per_block), and every block of the
+ * trace is complete.  One entry per divergent block: the fewest and most
+ * arrivals, and how many of its threads arrived at fewer than the most
+ * (the threads that left early).
+ */
+typedef struct {
+  uint32_t trace;
+  uint32_t block;
+  uint32_t min_barriers;
+  uint32_t max_barriers;
+  uint64_t early_threads;
+} orc_divergence;
+
+int64_t orc_divergence_check(const uint32_t* counts, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                             orc_divergence** out) {
+  if (n_traces && (!off || !tpb)) return ORC_EINVAL;
+  if (n_traces && off[0] != 0) return ORC_EINVAL;
+  for (uint32_t t = 0; t < n_traces; t++) {
+    if (off[t + 1] < off[t] || tpb[t] == 0) return ORC_EINVAL;
+    if ((off[t + 1] - off[t]) % tpb[t] != 0) return ORC_EINVAL; /* whole blocks only */
+  }
+  if (n_traces && off[n_traces] && !counts) return ORC_EINVAL;
+  orc_divergence* v = NULL;
+  uint64_t n = 0, cap = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t n_blocks = (off[tr + 1] - off[tr]) / tpb[tr];
+    for (uint64_t b = 0; b < n_blocks; b++) {
+      const uint32_t* c = counts + off[tr] + b * tpb[tr];
+      uint32_t lo = c[0], hi = c[0];
+      for (uint32_t k = 1; k < tpb[tr]; k++) {
+        if (c[k] < lo) lo = c[k];
+        if (c[k] > hi) hi = c[k];
+      }
+      if (lo == hi) continue;
+      uint64_t early = 0;
+      for (uint32_t k = 0; k < tpb[tr]; k++) early += c[k] < hi ? 1 : 0;
+      if (n == cap) {
+        cap = cap ? 2 * cap : 64;
+        orc_divergence* nv = (orc_divergence*)realloc(v, cap * sizeof(orc_divergence));
+        if (!nv) { free(v); return ORC_ENOMEM; }
+        v = nv;
+      }
+      orc_divergence d = {tr, (uint32_t)b, lo, hi, early};
+      v[n++] = d;
+    }
+  }
+  *out = v;
+  return (int64_t)n;
+}
+
 void orc_free(void* p) { free(p); }
