@@ -50,6 +50,8 @@ SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pair
 KIND_BITS = {"ww": 1, "rw": 2, "aw": 4, "ar": 8, "xblock": 16}
 
 BARRIER_DTYPE = np.dtype([("trace", "<u4"), ("boundary", "<u4"), ("instances", "<u8"), ("racing", "<u8")])
+FITNESS_DTYPE = np.dtype([("n_records", "<u8"), ("n_locations", "<u8"), ("n_location_threads", "<u8"),
+                          ("global_range", "<u8"), ("shared_range", "<u8"), ("fitness", "<f8")])
 DIVERGENCE_DTYPE = np.dtype([("trace", "<u4"), ("block", "<u4"), ("min_barriers", "<u4"), ("max_barriers", "<u4"),
                              ("early_threads", "<u8")])
 
@@ -100,6 +102,10 @@ def _load():
             f.restype = ctypes.c_int64
             f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64)]
+        f = lib.orc_fitness_eval
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.POINTER(ctypes.c_uint64)]
         f = lib.orc_divergence_check
         f.restype = ctypes.c_int64
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
@@ -235,6 +241,21 @@ def barriers_py(records, tpb):
 def barriers_to_dict(res, trace=0):
     """{boundary: (instances, racing)} of one trace from a BARRIER_DTYPE array."""
     return {int(r["boundary"]): (int(r["instances"]), int(r["racing"])) for r in res if int(r["trace"]) == trace}
+
+
+def fitness(records, offsets=None, tpb=None):
+    """EP fitness of every trace (Eq. 1): FITNESS_DTYPE rows with the
+    locations (sum g), distinct (location, thread) pairs (sum f), the global
+    and shared unit ranges (R) and F = sum g / sum f."""
+    records, offsets, n_traces, tpb = _as_batch(records, offsets, tpb)
+    lib = _load()
+    out = np.zeros(max(n_traces, 1), dtype=FITNESS_DTYPE)
+    bad = ctypes.c_uint64(0)
+    rc = lib.orc_fitness_eval(records.ctypes.data if len(records) else None, offsets.ctypes.data, n_traces,
+                              tpb.ctypes.data, out.ctypes.data, ctypes.byref(bad))
+    if rc < 0:
+        raise OracleError(int(rc), int(bad.value) if rc == -2 else None)
+    return out[:n_traces]
 
 
 def divergence(counts, offsets, tpb):

@@ -776,4 +776,88 @@ int64_t orc_divergence_check(const uint32_t* counts, const uint64_t* off, uint32
   return (int64_t)n;
 }
 
+/* ===================== EP fitness (Eq. 1, Sec. 4.1.1) =====================
+ *
+ * For one candidate input (one trace): g(i) is 1 when memory address i is
+ * accessed at all and f(i) the number of threads that access it; the
+ * primary fitness F = sum g / sum f is 1 when no two threads share an
+ * address and smaller the more they do.  The secondary fitness is the
+ * access range R = end - start.  Addresses are the locations of the race
+ * check (a global unit, or a unit of one block's shared memory); threads
+ * are grid-wide ids.  Per trace: the number of records, sum g (locations),
+ * sum f (distinct (location, thread) pairs), the unit range of global and
+ * of shared accesses (max - min, 0 without such accesses) and F (1 for a
+ * trace without records).
+ */
+typedef struct {
+  uint64_t n_records;
+  uint64_t n_locations;
+  uint64_t n_location_threads;
+  uint64_t global_range;
+  uint64_t shared_range;
+  double fitness;
+} orc_fitness;
+
+typedef struct {
+  uint64_t unit;
+  uint32_t lblock;
+  uint32_t tid;
+  uint32_t space;
+} loc_thread;
+
+static int cmp_loc_thread(const void* pa, const void* pb) {
+  const loc_thread* a = (const loc_thread*)pa;
+  const loc_thread* b = (const loc_thread*)pb;
+  if (a->space != b->space) return a->space < b->space ? -1 : 1;
+  if (a->lblock != b->lblock) return a->lblock < b->lblock ? -1 : 1;
+  if (a->unit != b->unit) return a->unit < b->unit ? -1 : 1;
+  if (a->tid != b->tid) return a->tid < b->tid ? -1 : 1;
+  return 0;
+}
+
+int orc_fitness_eval(const orc_record* recs, const uint64_t* off, uint32_t n_traces, const uint32_t* tpb,
+                     orc_fitness* out, uint64_t* bad_index) {
+  int rc = validate(recs, off, n_traces, tpb, bad_index);
+  if (rc) return rc;
+  uint64_t maxn = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++)
+    if (off[tr + 1] - off[tr] > maxn) maxn = off[tr + 1] - off[tr];
+  loc_thread* v = maxn ? (loc_thread*)malloc(maxn * sizeof(loc_thread)) : NULL;
+  if (maxn && !v) return ORC_ENOMEM;
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t lo = off[tr], n = off[tr + 1] - off[tr];
+    uint64_t gmin = UINT64_MAX, gmax = 0, smin = UINT64_MAX, smax = 0;
+    for (uint64_t i = 0; i < n; i++) {
+      const orc_record* r = &recs[lo + i];
+      v[i].unit = r->unit;
+      v[i].tid = r->tid;
+      v[i].space = r->space;
+      v[i].lblock = r->space == 1 ? r->tid / tpb[tr] : 0xFFFFFFFFu;
+      if (r->space == 0) {
+        if (r->unit < gmin) gmin = r->unit;
+        if (r->unit > gmax) gmax = r->unit;
+      } else {
+        if (r->unit < smin) smin = r->unit;
+        if (r->unit > smax) smax = r->unit;
+      }
+    }
+    if (n) qsort(v, n, sizeof(loc_thread), cmp_loc_thread);
+    uint64_t g = 0, f = 0;
+    for (uint64_t i = 0; i < n; i++) {
+      const int new_loc = i == 0 || v[i].space != v[i - 1].space || v[i].lblock != v[i - 1].lblock ||
+                          v[i].unit != v[i - 1].unit;
+      if (new_loc) g++;
+      if (new_loc || v[i].tid != v[i - 1].tid) f++;
+    }
+    out[tr].n_records = n;
+    out[tr].n_locations = g;
+    out[tr].n_location_threads = f;
+    out[tr].global_range = gmin <= gmax ? gmax - gmin : 0;
+    out[tr].shared_range = smin <= smax ? smax - smin : 0;
+    out[tr].fitness = f ? (double)g / (double)f : 1.0;
+  }
+  free(v);
+  return ORC_OK;
+}
+
 void orc_free(void* p) { free(p); }
