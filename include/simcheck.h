@@ -248,6 +248,89 @@ int sim_check_sync(sim_ctx* ctx, const sim_record* records, const uint64_t* offs
 /* Free a barrier result.  NULL is ignored. */
 void sim_barrier_result_free(sim_barrier_result* r);
 
+/* ------------------------------------------------------------- EP fitness */
+
+/* Fitness of one candidate input of the Evolutionary Programming search
+ * (paper Sec. 4.1.1, Eq. 1), from its trace (48 bytes).  For every address
+ * i the trace touches, g(i) = 1 and f(i) is the number of threads that
+ * touch it; the primary fitness is F = sum g / sum f (1 when no address is
+ * shared between threads, smaller the more threads share addresses), the
+ * secondary score the access range R = end - start.  Addresses are the
+ * locations of the race check (a global unit, or a unit of one block's
+ * shared memory); threads are grid-wide ids; the range is taken per memory
+ * space.                                                                   */
+typedef struct sim_fitness {
+  uint64_t n_records;
+  uint64_t n_locations;        /* sum g: locations touched */
+  uint64_t n_location_threads; /* sum f: distinct (location, thread) pairs */
+  uint64_t global_range;       /* largest minus smallest global unit (0 without global records) */
+  uint64_t shared_range;       /* the same over shared units */
+  double fitness;              /* F = n_locations / n_location_threads (1.0 for an empty trace) */
+} sim_fitness;
+
+/* EP fitness of every trace of a call (one candidate per trace, e.g. a
+ * population of them in one call).  Arguments as for
+ * sim_check_traces_device; out: n_traces rows, host memory, caller-owned
+ * (row i for trace i).  The records are sorted by (location, thread) on the
+ * device -- the race check's sort with epoch and action left out of the
+ * key -- and the rows are counted from the runs.  Errors as for
+ * sim_check_traces_device; on error out is left unspecified.              */
+int sim_eval_fitness_device(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
+                            const uint32_t* threads_per_block, void* stream, sim_fitness* out);
+
+/* The same for records in host memory (copied to the device first). */
+int sim_eval_fitness(sim_ctx* ctx, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
+                     const uint32_t* threads_per_block, sim_fitness* out);
+
+/* ----------------------------------------------------- barrier divergence */
+
+/* One block whose threads arrived at different numbers of barriers before
+ * they finished (24 bytes).  Paper Sec. 4.2.2 and Alg. 4: a thread that
+ * reaches the end of the kernel while another thread of its block is
+ * halted at a barrier is a barrier divergence -- the halted thread waits at
+ * a barrier the finished one never reaches.  Given every thread's number of
+ * barrier arrivals at its end, a block diverges exactly when those numbers
+ * are not all equal.                                                       */
+typedef struct sim_divergence {
+  uint32_t trace;         /* index of the trace in the call */
+  uint32_t block;         /* block within the trace */
+  uint32_t min_barriers;  /* fewest arrivals of a thread of the block */
+  uint32_t max_barriers;  /* most arrivals */
+  uint64_t early_threads; /* threads of the block with fewer than max_barriers arrivals */
+} sim_divergence;
+
+typedef struct sim_divergence_result {
+  sim_divergence* blocks; /* n_blocks entries, host memory, ordered by trace, then block */
+  uint64_t n_blocks;
+} sim_divergence_result;
+
+/* Barrier-divergence check of n_traces traces (Alg. 4).
+ *   d_arrivals        : offsets[n_traces] counts, device memory of the
+ *                       context's GPU, caller-owned: count i is the number
+ *                       of barriers thread i of the call arrived at before
+ *                       it finished.  Trace t's threads are d_arrivals[
+ *                       offsets[t] .. offsets[t+1]), block by block: thread
+ *                       k of the trace is in block k / threads_per_block[t]
+ *   offsets           : n_traces + 1 CSR offsets over threads, host memory;
+ *                       every trace holds whole blocks (SIM_EINVAL otherwise)
+ *   threads_per_block : n_traces values >= 1, host memory
+ *   stream            : hipStream_t (NULL: the default stream); the call
+ *                       returns after the stream has finished its work
+ *   out               : receives one entry per divergent block (caller frees
+ *                       it with sim_divergence_result_free)
+ * A call holds at most 2^32 - 1 threads.  Errors and ownership as for
+ * sim_check_traces_device.                                                 */
+int sim_check_divergence_device(sim_ctx* ctx, const uint32_t* d_arrivals, const uint64_t* offsets,
+                                uint32_t n_traces, const uint32_t* threads_per_block, void* stream,
+                                sim_divergence_result** out);
+
+/* The same for arrival counts in host memory (copied to the device first). */
+int sim_check_divergence(sim_ctx* ctx, const uint32_t* arrivals, const uint64_t* offsets, uint32_t n_traces,
+                         const uint32_t* threads_per_block, sim_divergence_result** out);
+
+/* Free a divergence result.  NULL is ignored. */
+void sim_divergence_result_free(sim_divergence_result* r);
+
 /* -------------------------------------------------------------- profiling */
 
 /* Per-stage device time of the last call on a context created with

@@ -31,6 +31,10 @@ RACE_DTYPE = np.dtype(
 )
 SUMMARY_DTYPE = np.dtype([("n_records", "<u8"), ("n_race_locs", "<u8"), ("n_pairs", "<u8")])
 BARRIER_DTYPE = np.dtype([("trace", "<u4"), ("boundary", "<u4"), ("instances", "<u8"), ("racing", "<u8")])
+FITNESS_DTYPE = np.dtype([("n_records", "<u8"), ("n_locations", "<u8"), ("n_location_threads", "<u8"),
+                          ("global_range", "<u8"), ("shared_range", "<u8"), ("fitness", "<f8")])
+DIVERGENCE_DTYPE = np.dtype([("trace", "<u4"), ("block", "<u4"), ("min_barriers", "<u4"), ("max_barriers", "<u4"),
+                             ("early_threads", "<u8")])
 
 SIM_OK, SIM_EINVAL, SIM_ERECORD, SIM_ENOMEM, SIM_EDEVICE, SIM_ERANGE, SIM_ENOSPC = 0, -1, -2, -3, -4, -6, -7
 SIM_CFG_PROFILE = 1
@@ -41,7 +45,8 @@ STAGES = ["init", "stats", "layout", "keygen", "upsweep", "sort_pass", "scan_til
 EXPORTS = [
     "sim_create", "sim_destroy", "sim_last_error", "sim_check_traces", "sim_check_traces_device",
     "sim_check_traces_device_noalloc", "sim_result_free", "sim_check_sync_device", "sim_check_sync",
-    "sim_barrier_result_free", "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning",
+    "sim_barrier_result_free", "sim_eval_fitness_device", "sim_eval_fitness", "sim_check_divergence_device", "sim_check_divergence",
+    "sim_divergence_result_free", "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning",
     "sim_get_tuning", "sim_autotune", "sim_server_create", "sim_server_destroy", "sim_submit", "sim_submit_device",
     "sim_poll",
     "sim_wait", "sim_server_get_stats", "sim_server_last_error",
@@ -68,6 +73,10 @@ class _Result(ctypes.Structure):
 
 class _BarrierResult(ctypes.Structure):
     _fields_ = [("barriers", ctypes.c_void_p), ("n_barriers", ctypes.c_uint64)]
+
+
+class _DivergenceResult(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_void_p), ("n_blocks", ctypes.c_uint64)]
 
 
 class _Config(ctypes.Structure):
@@ -155,6 +164,18 @@ def load() -> ctypes.CDLL:
                                    ctypes.POINTER(ctypes.POINTER(_BarrierResult))]
     lib.sim_barrier_result_free.restype = None
     lib.sim_barrier_result_free.argtypes = [ctypes.POINTER(_BarrierResult)]
+    lib.sim_eval_fitness_device.restype = ctypes.c_int
+    lib.sim_eval_fitness_device.argtypes = [P, P, P, ctypes.c_uint32, P, P, P]
+    lib.sim_eval_fitness.restype = ctypes.c_int
+    lib.sim_eval_fitness.argtypes = [P, P, P, ctypes.c_uint32, P, P]
+    lib.sim_check_divergence_device.restype = ctypes.c_int
+    lib.sim_check_divergence_device.argtypes = [P, P, P, ctypes.c_uint32, P, P,
+                                                ctypes.POINTER(ctypes.POINTER(_DivergenceResult))]
+    lib.sim_check_divergence.restype = ctypes.c_int
+    lib.sim_check_divergence.argtypes = [P, P, P, ctypes.c_uint32, P,
+                                         ctypes.POINTER(ctypes.POINTER(_DivergenceResult))]
+    lib.sim_divergence_result_free.restype = None
+    lib.sim_divergence_result_free.argtypes = [ctypes.POINTER(_DivergenceResult)]
     lib.sim_result_free.restype = None
     lib.sim_result_free.argtypes = [ctypes.POINTER(_Result)]
     lib.sim_stage_times.restype = ctypes.c_int
@@ -342,6 +363,88 @@ def sim_check_sync(ctx, records: np.ndarray, offsets=None, threads_per_block=1):
     return races, summ, _take_barriers(bar)
 
 
+def sim_eval_fitness(ctx, records: np.ndarray, offsets=None, threads_per_block=1):
+    """EP fitness (Eq. 1) of every trace of host records: a FITNESS_DTYPE
+    row per trace."""
+    lib = load()
+    records = np.ascontiguousarray(records)
+    if records.dtype.itemsize != 16:
+        raise TypeError("records must be 16-byte sim_record entries")
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, len(records))
+    out = np.zeros(max(n_traces, 1), dtype=FITNESS_DTYPE)
+    rc = lib.sim_eval_fitness(ctx, records.ctypes.data if len(records) else None, offsets.ctypes.data, n_traces,
+                              tpb.ctypes.data, out.ctypes.data)
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return out[:n_traces]
+
+
+def sim_eval_fitness_device(ctx, d_records_ptr: int, n_records: int, offsets=None, threads_per_block=1,
+                            stream=None):
+    """sim_eval_fitness for records in device memory at d_records_ptr."""
+    lib = load()
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, n_records)
+    if int(offsets[-1]) != n_records:
+        raise ValueError("offsets[-1] must equal the number of device records")
+    out = np.zeros(max(n_traces, 1), dtype=FITNESS_DTYPE)
+    rc = lib.sim_eval_fitness_device(ctx, ctypes.c_void_p(d_records_ptr) if n_records else None, offsets.ctypes.data,
+                                     n_traces, tpb.ctypes.data, ctypes.c_void_p(stream or 0), out.ctypes.data)
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return out[:n_traces]
+
+
+def _thread_tables(offsets, tpb):
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    n_traces = len(offsets) - 1
+    tpb = np.asarray(tpb, dtype=np.uint32)
+    if tpb.ndim == 0:
+        tpb = np.full(n_traces, int(tpb), dtype=np.uint32)
+    tpb = np.ascontiguousarray(tpb)
+    if len(tpb) != n_traces:
+        raise ValueError("threads_per_block needs one value per trace")
+    return offsets, n_traces, tpb
+
+
+def _take_divergence(res_p):
+    r = res_p.contents
+    out = np.zeros(r.n_blocks, dtype=DIVERGENCE_DTYPE)
+    if r.n_blocks:
+        ctypes.memmove(out.ctypes.data, r.blocks, r.n_blocks * DIVERGENCE_DTYPE.itemsize)
+    load().sim_divergence_result_free(res_p)
+    return out
+
+
+def sim_check_divergence(ctx, arrivals: np.ndarray, offsets, threads_per_block):
+    """Barrier-divergence check (Alg. 4) of per-thread barrier arrival counts
+    in host memory (uint32, block by block; offsets: CSR over threads).
+    Returns a DIVERGENCE_DTYPE array, one row per divergent block."""
+    lib = load()
+    arrivals = np.ascontiguousarray(np.asarray(arrivals, dtype=np.uint32))
+    offsets, n_traces, tpb = _thread_tables(offsets, threads_per_block)
+    out = ctypes.POINTER(_DivergenceResult)()
+    rc = lib.sim_check_divergence(ctx, arrivals.ctypes.data if len(arrivals) else None, offsets.ctypes.data,
+                                  n_traces, tpb.ctypes.data, ctypes.byref(out))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return _take_divergence(out)
+
+
+def sim_check_divergence_device(ctx, d_arrivals_ptr: int, n_threads: int, offsets, threads_per_block, stream=None):
+    """sim_check_divergence for counts in device memory at d_arrivals_ptr."""
+    lib = load()
+    offsets, n_traces, tpb = _thread_tables(offsets, threads_per_block)
+    if int(offsets[-1]) != n_threads:
+        raise ValueError("offsets[-1] must equal the number of device counts")
+    out = ctypes.POINTER(_DivergenceResult)()
+    rc = lib.sim_check_divergence_device(ctx, ctypes.c_void_p(d_arrivals_ptr) if n_threads else None,
+                                         offsets.ctypes.data, n_traces, tpb.ctypes.data,
+                                         ctypes.c_void_p(stream or 0), ctypes.byref(out))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return _take_divergence(out)
+
+
 def sim_stage_times(ctx):
     lib = load()
     arr = (_StageTime * 16)()
@@ -454,6 +557,31 @@ class Context:
         """Races and barrier instances of a device tensor of records."""
         ptr, n, stream = self._device_args(tensor, stream)
         return sim_check_sync_device(self._ctx, ptr, n, offsets, threads_per_block, stream)
+
+    def eval_fitness(self, records, offsets=None, threads_per_block=1):
+        """EP fitness rows of host records."""
+        return sim_eval_fitness(self._ctx, records, offsets, threads_per_block)
+
+    def eval_fitness_device(self, tensor, offsets=None, threads_per_block=1, stream=None):
+        """EP fitness rows of a device tensor of records."""
+        ptr, n, stream = self._device_args(tensor, stream)
+        return sim_eval_fitness_device(self._ctx, ptr, n, offsets, threads_per_block, stream)
+
+    def check_divergence(self, arrivals, offsets, threads_per_block):
+        """Barrier divergence of host arrival counts (numpy uint32)."""
+        return sim_check_divergence(self._ctx, arrivals, offsets, threads_per_block)
+
+    def check_divergence_device(self, tensor, offsets, threads_per_block, stream=None):
+        """Barrier divergence of a contiguous device tensor of 32-bit arrival
+        counts (int32 or uint32)."""
+        if tensor.element_size() != 4 or not tensor.is_contiguous():
+            raise ValueError("arrival counts must be a contiguous tensor of 32-bit integers")
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream(tensor.device).cuda_stream
+        return sim_check_divergence_device(self._ctx, tensor.data_ptr(), tensor.numel(), offsets, threads_per_block,
+                                           stream)
 
     def check_traces_device_noalloc(self, tensor, offsets=None, threads_per_block=1, stream=None,
                                     races_cap: int = 1 << 16, races_out=None, traces_out=None):

@@ -33,6 +33,8 @@ static_assert(sizeof(sim_record) == 16, "sim_record is 16 bytes");
 static_assert(sizeof(sim_race) == 64, "sim_race is 64 bytes");
 static_assert(sizeof(RaceOut) == sizeof(sim_race), "device entry mirrors sim_race");
 static_assert(sizeof(sim_barrier) == 24, "sim_barrier is 24 bytes");
+static_assert(sizeof(sim_divergence) == sizeof(DivOut), "device divergence entry mirrors sim_divergence");
+static_assert(sizeof(sim_fitness) == sizeof(FitOut), "device fitness row mirrors sim_fitness");
 
 namespace {
 
@@ -55,6 +57,8 @@ struct sim_ctx {
   uint32_t flags = 0;
   uint32_t pass_guess = 0;  // radix passes the previous call needed
   bool wide_guess = false;  // the previous call had a trace needing two-word keys
+  uint32_t fit_pass_guess = 0;  // the same for the fitness count, whose keys are shorter
+  bool fit_wide_guess = false;
   uint64_t alloc_gen = 0;   // bumped whenever a device buffer is reallocated
 
   // one captured launch sequence, replayed while calls keep the same shape
@@ -77,6 +81,12 @@ struct sim_ctx {
 
   DevBuf records, keys0, keys1, meta, stats_part, layout, thist, gtot, gbase, agg, tout, cross, cross_flag,
       group_sum, stage, stage_ref, ctrl, out, bar, bar_base;
+  // the barrier-divergence check: arrival counts of host calls, chunk table,
+  // per-block results, per-chunk counts and offsets, divergent blocks
+  DevBuf div_in, div_chunks, div_blocks, div_cnt, div_off, div_out;
+  DevBuf fit_out;  // the fitness count's rows
+  void* h_div = nullptr;  // pinned: the chunk table, then the divergent-block count
+  size_t h_div_cap = 0;
   uint64_t dev_limit = 0;  // device bytes the buffers may hold (0: no limit; set by a server's worker)
   void* h_meta = nullptr;  // pinned: the call's tables (the layout of meta), then room for the
                            // per-tile words of a staging overflow (tile counts down, references up)
@@ -90,6 +100,14 @@ struct sim_ctx {
 };
 
 namespace {
+
+// Every device buffer of a context.
+std::vector<DevBuf*> all_bufs(sim_ctx* c) {
+  return {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist, &c->gtot,
+          &c->gbase,   &c->agg,   &c->tout,  &c->cross, &c->cross_flag, &c->group_sum, &c->stage,
+          &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base, &c->div_in, &c->div_chunks, &c->div_blocks,
+          &c->div_cnt, &c->div_off, &c->div_out, &c->fit_out};
+}
 
 int fail(sim_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -309,7 +327,9 @@ hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t 
     };
     if (after() > c->dev_limit) {
       for (int r = 0; r < N_REGION; r++) release(*region_buf(c, r));
-      for (DevBuf* b : {&c->out, &c->stage, &c->stage_ref, &c->bar, &c->bar_base}) release(*b);
+      for (DevBuf* b : {&c->out, &c->stage, &c->stage_ref, &c->bar, &c->bar_base, &c->div_in, &c->div_chunks,
+                        &c->div_blocks, &c->div_cnt, &c->div_off, &c->div_out, &c->fit_out})
+        release(*b);
       if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
       c->graph.exec = nullptr;
       c->alloc_gen++;
@@ -332,6 +352,7 @@ struct Sink {
   uint64_t* n_races = nullptr;
   sim_trace_summary* traces = nullptr;
   sim_barrier_result** barriers = nullptr;  // also the redundant-barrier check
+  sim_fitness* fitness = nullptr;           // instead of the race check: the EP fitness rows (host, n_traces)
 };
 
 void barrier_result_free(sim_barrier_result* r) {
@@ -365,6 +386,8 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       return fail(c, SIM_EINVAL, "a no-allocation call holds at most %u tiles of 4096 records", NOALLOC_MAX_TILES);
   }
   for (auto& t : c->times) t = sim_stage_time{0.0, 0, 0};
+  const bool fit = sink.fitness != nullptr;
+  if (fit && noalloc) return fail(c, SIM_EINVAL, "the fitness count has no no-allocation form");
 
   // result delivery: summaries from the entry list, entries downloaded from
   // `dev_out` (n_races of them)
@@ -406,6 +429,10 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
     return SIM_OK;
   };
 
+  if (fit && total == 0) {  // every trace empty: F = 1, no locations
+    for (uint32_t i = 0; i < n_traces; i++) sink.fitness[i] = sim_fitness{0, 0, 0, 0, 0, 1.0};
+    return SIM_OK;
+  }
   if (total == 0) {  // nothing to check: summaries only (and no barrier instances)
     sim_barrier_result* br = nullptr;
     if (sink.barriers) {
@@ -450,7 +477,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   GroupRef* hg = (GroupRef*)(ht + n_tiles);
   uint32_t* hs = (uint32_t*)(hg + n_hgroups64);
   // traces sorted whole in LDS: one tile, or up to four with one-word keys
-  const bool wide = c->wide_guess;
+  const bool wide = fit ? c->fit_wide_guess : c->wide_guess;
   const uint32_t small_max_tiles = wide ? 1u : 4u;
   uint32_t t0 = 0, g0 = 0, max_group_tiles = 1, max_trace_groups = 1, n_small1 = 0, n_small4 = 0;
   for (uint32_t i = 0; i < n_traces; i++) {
@@ -528,6 +555,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   b.keys[1] = reg[R_KEYS1];
   b.wide = wide ? 1u : 0u;
   b.key_bytes = key_bytes;
+  b.fitness = fit ? 1u : 0u;
   b.groups = (const GroupRef*)(b.tiles + n_tiles);
   b.small_traces = (const uint32_t*)(b.groups + n_hgroups);
   b.n_small1 = n_small1;
@@ -610,7 +638,13 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   };
   // counts: whether the launches are real work (a scan before missing
   // passes, or a rescan after an overflow, is left out of the stage times)
+  FitOut* fit_out = nullptr;
+  if (fit) {
+    if ((e = grow(c, c->fit_out, (size_t)n_traces * sizeof(FitOut)))) return hip_fail(c, e, "device allocation");
+    fit_out = (FitOut*)c->fit_out.p;
+  }
   auto scan = [&](uint32_t passes_done, bool counts) -> hipError_t {
+    if (fit) return timed(ST_SCAN, counts, [&] { return launch_fitness(b, passes_done, fit_out, s); });
     hipError_t e1 = timed(ST_SCAN, counts, [&] { return launch_scan_tiles(b, passes_done, s); });
     if (e1 == hipSuccess) e1 = timed(ST_CROSS, counts, [&] { return launch_scan_cross(b, passes_done, s); });
     if (e1 == hipSuccess) e1 = timed(ST_OUT, counts, [&] { return launch_scan_out(b, passes_done, s); });
@@ -618,7 +652,8 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   };
 
   // (a call of one-tile traces has all its passes done before the scan)
-  const uint32_t guess = all_small ? MAX_PASSES : (c->pass_guess < MAX_PASSES ? c->pass_guess : MAX_PASSES);
+  const uint32_t prev_guess = fit ? c->fit_pass_guess : c->pass_guess;
+  const uint32_t guess = all_small ? MAX_PASSES : (prev_guess < MAX_PASSES ? prev_guess : MAX_PASSES);
   int first_scan_ev = 0;  // events of the first round before its scan
   auto first_round = [&]() -> hipError_t {
     hipError_t e1;
@@ -642,7 +677,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   // whose record addresses are not part of the shape, nor for calls that
   // may not allocate: instantiating a graph does.)
   const bool use_graph =
-      (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0 && !trace_recs && !noalloc;
+      (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0 && !trace_recs && !noalloc && !fit;
   uint64_t th = 1469598103934665603ull;  // FNV-1a over the per-call tables
   if (use_graph) {
     const unsigned char* q = (const unsigned char*)offsets;
@@ -699,7 +734,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   if (ctl.error_flags & ERR_NEEDS_WIDE) {
     // a trace needs two-word keys: run the whole call again in that mode
     // (the next call starts in it while its traces keep needing it)
-    c->wide_guess = true;
+    (fit ? c->fit_wide_guess : c->wide_guess) = true;
     return run(c, d_records, trace_recs, offsets, n_traces, tpb, s, sink, noalloc);
   }
   const uint32_t needed = ctl.max_passes;
@@ -711,8 +746,24 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       return hip_fail(c, e, "pipeline");
     ctl = *c->h_ctrl;
   }
-  if (!all_small) c->pass_guess = needed;  // an LDS-sorted call tells nothing about global passes
-  c->wide_guess = ctl.wide_traces > 0;
+  if (!all_small) (fit ? c->fit_pass_guess : c->pass_guess) = needed;  // an LDS-sorted call tells nothing
+                                                                       // about global passes
+  (fit ? c->fit_wide_guess : c->wide_guess) = ctl.wide_traces > 0;
+  if (fit) {
+    if (ctl.error_flags) return fail(c, SIM_EDEVICE, "internal kernel check failed (flags 0x%x)", ctl.error_flags);
+    if ((e = hipMemcpyAsync(sink.fitness, fit_out, (size_t)n_traces * sizeof(FitOut), hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s)))
+      return hip_fail(c, e, "fitness download");
+    if (prof)
+      for (int k = 0; k < nev / 2; k++) {
+        if (!ev_counts[k]) continue;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
+        c->times[ev_stage[k]].ms += ms;
+        c->times[ev_stage[k]].launches += 1;
+      }
+    return SIM_OK;
+  }
   if (ctl.error_flags & ERR_STAGE_OVERFLOW) {
     // Some tile holds more racing locations than its slice of the idle key
     // buffer: give each such tile a range of a dedicated staging buffer, as
@@ -833,6 +884,125 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   *sink.barriers = br;
   return SIM_OK;
 }
+
+void divergence_result_free(sim_divergence_result* r) {
+  if (!r) return;
+  free(r->blocks);
+  free(r);
+}
+
+// The barrier-divergence check of one call (arrival counts in device
+// memory): chunk table on the host, then per-block reductions, the chunk
+// offsets and the ordered output on the device.
+// Checks the tables of a divergence call; *total threads, *n_chunks chunks.
+int div_tables(sim_ctx* c, const uint64_t* offsets, uint32_t n_traces, const uint32_t* tpb, uint64_t* total,
+               uint32_t* n_chunks) {
+  if (n_traces && (!offsets || !tpb)) return fail(c, SIM_EINVAL, "offsets or threads_per_block is NULL");
+  if (n_traces && offsets[0] != 0) return fail(c, SIM_EINVAL, "offsets[0] must be 0");
+  uint64_t n_chunks64 = 0;
+  for (uint32_t i = 0; i < n_traces; i++) {
+    if (offsets[i + 1] < offsets[i]) return fail(c, SIM_EINVAL, "offsets decrease at trace %u", i);
+    if (tpb[i] == 0) return fail(c, SIM_EINVAL, "threads_per_block[%u] is 0", i);
+    const uint64_t n = offsets[i + 1] - offsets[i];
+    if (n % tpb[i]) return fail(c, SIM_EINVAL, "trace %u holds %llu threads, not whole blocks of %u", i,
+                                (unsigned long long)n, tpb[i]);
+    const uint64_t per = std::max<uint64_t>(1, DIV_CHUNK_THREADS / tpb[i]);
+    n_chunks64 += (n / tpb[i] + per - 1) / per;
+  }
+  *total = n_traces ? offsets[n_traces] : 0;
+  if (*total >= (1ull << 32)) return fail(c, SIM_EINVAL, "a call holds at most 2^32 - 1 threads");
+  *n_chunks = (uint32_t)n_chunks64;
+  return SIM_OK;
+}
+
+int divergence(sim_ctx* c, const uint32_t* d_arr, const uint64_t* offsets, uint32_t n_traces, const uint32_t* tpb,
+               hipStream_t s, sim_divergence_result** out) {
+  if (!out) return fail(c, SIM_EINVAL, "out is NULL");
+  *out = nullptr;
+  uint64_t total = 0;
+  uint32_t n_chunks = 0;
+  const int rc = div_tables(c, offsets, n_traces, tpb, &total, &n_chunks);
+  if (rc) return rc;
+  if (total && !d_arr) return fail(c, SIM_EINVAL, "arrival counts are NULL");
+  sim_divergence_result* r = (sim_divergence_result*)calloc(1, sizeof(sim_divergence_result));
+  if (!r) return fail(c, SIM_ENOMEM, "host allocation failed");
+  if (total == 0) {
+    r->blocks = (sim_divergence*)malloc(sizeof(sim_divergence));
+    if (!r->blocks) {
+      divergence_result_free(r);
+      return fail(c, SIM_ENOMEM, "host allocation failed");
+    }
+    *out = r;
+    return SIM_OK;
+  }
+  // chunk table (pinned), the count word after it
+  const size_t tab = ((size_t)n_chunks * sizeof(DivChunk) + 15) / 16 * 16;
+  hipError_t e;
+  if (c->h_div_cap < tab + 16) {
+    if (c->h_div) (void)hipHostFree(c->h_div);
+    c->h_div = nullptr;
+    c->h_div_cap = 0;
+    if ((e = hipHostMalloc(&c->h_div, tab + 16 + tab / 8, hipHostMallocDefault)) != hipSuccess) {
+      divergence_result_free(r);
+      return hip_fail(c, e, "pinned allocation");
+    }
+    c->h_div_cap = tab + 16 + tab / 8;
+  }
+  DivChunk* hc = (DivChunk*)c->h_div;
+  uint64_t* h_total = (uint64_t*)((char*)c->h_div + tab);
+  uint32_t k = 0, block0 = 0;
+  for (uint32_t i = 0; i < n_traces; i++) {
+    const uint64_t nb = (offsets[i + 1] - offsets[i]) / tpb[i];
+    const uint64_t per = std::max<uint64_t>(1, DIV_CHUNK_THREADS / tpb[i]);
+    for (uint64_t b = 0; b < nb; b += per) {
+      const uint32_t m = (uint32_t)std::min<uint64_t>(per, nb - b);
+      hc[k++] = DivChunk{offsets[i] + b * tpb[i], i, (uint32_t)b, m, tpb[i], block0, 0};
+      block0 += m;
+    }
+  }
+  const uint64_t n_blocks = block0;
+  if ((e = grow(c, c->div_chunks, (size_t)n_chunks * sizeof(DivChunk))) ||
+      (e = grow(c, c->div_blocks, (size_t)n_blocks * sizeof(DivBlock))) ||
+      (e = grow(c, c->div_cnt, (size_t)n_chunks * 4)) || (e = grow(c, c->div_off, ((size_t)n_chunks + 1) * 8))) {
+    divergence_result_free(r);
+    return hip_fail(c, e, "device allocation");
+  }
+  DivChunk* d_chunks = (DivChunk*)c->div_chunks.p;
+  uint64_t* d_off = (uint64_t*)c->div_off.p;
+  if ((e = hipMemcpyAsync(d_chunks, hc, (size_t)n_chunks * sizeof(DivChunk), hipMemcpyHostToDevice, s)) ||
+      (e = launch_divergence(d_chunks, n_chunks, d_arr, (DivBlock*)c->div_blocks.p, (uint32_t*)c->div_cnt.p, d_off,
+                             d_off + n_chunks, s)) ||
+      (e = hipMemcpyAsync(h_total, d_off + n_chunks, 8, hipMemcpyDeviceToHost, s)) ||
+      (e = hipStreamSynchronize(s))) {
+    divergence_result_free(r);
+    return hip_fail(c, e, "divergence check");
+  }
+  const uint64_t n_div = *h_total;
+  if (n_div > n_blocks) {
+    divergence_result_free(r);
+    return fail(c, SIM_EDEVICE, "divergent block count %llu exceeds the %llu blocks", (unsigned long long)n_div,
+                (unsigned long long)n_blocks);
+  }
+  r->blocks = (sim_divergence*)malloc((n_div ? n_div : 1) * sizeof(sim_divergence));
+  if (!r->blocks) {
+    divergence_result_free(r);
+    return fail(c, SIM_ENOMEM, "host allocation failed");
+  }
+  r->n_blocks = n_div;
+  if (n_div) {
+    if ((e = grow(c, c->div_out, (size_t)n_div * sizeof(DivOut))) ||
+        (e = launch_divergence_emit(d_chunks, n_chunks, (const DivBlock*)c->div_blocks.p, d_off,
+                                    (DivOut*)c->div_out.p, s)) ||
+        (e = hipMemcpyAsync(r->blocks, c->div_out.p, (size_t)n_div * sizeof(DivOut), hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s))) {
+      divergence_result_free(r);
+      return hip_fail(c, e, "divergence output");
+    }
+  }
+  *out = r;
+  return SIM_OK;
+}
+
 }  // namespace
 
 // ---- internal hooks for the serving runtime (serve.cpp)
@@ -840,10 +1010,7 @@ namespace sc {
 
 size_t ctx_device_bytes(const sim_ctx* c) {
   size_t t = 0;
-  for (const DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist,
-                          &c->gtot, &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum,
-                          &c->stage, &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base})
-    t += b->cap;
+  for (const DevBuf* b : all_bufs(const_cast<sim_ctx*>(c))) t += b->cap;
   return t;
 }
 
@@ -851,10 +1018,7 @@ size_t ctx_device_bytes(const sim_ctx* c) {
 void ctx_trim(sim_ctx* c) {
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist, &c->gtot,
-                    &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->stage,
-                    &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base})
-    release(*b);
+  for (DevBuf* b : all_bufs(c)) release(*b);
   if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
   c->graph.exec = nullptr;
   c->alloc_gen++;
@@ -953,12 +1117,10 @@ void sim_destroy(sim_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist, &c->gtot,
-                    &c->gbase, &c->agg, &c->tout, &c->cross, &c->cross_flag, &c->group_sum, &c->stage,
-                    &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base})
-    release(*b);
+  for (DevBuf* b : all_bufs(c)) release(*b);
   if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
   if (c->h_meta) (void)hipHostFree(c->h_meta);
+  if (c->h_div) (void)hipHostFree(c->h_div);
   if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -1060,6 +1222,76 @@ int sim_check_sync(sim_ctx* c, const sim_record* records, const uint64_t* offset
 }
 
 void sim_barrier_result_free(sim_barrier_result* r) { barrier_result_free(r); }
+
+int sim_eval_fitness_device(sim_ctx* c, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
+                            const uint32_t* threads_per_block, void* stream, sim_fitness* out) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (!out && n_traces) return fail(c, SIM_EINVAL, "out is NULL");
+  DeviceGuard g(c->device);
+  Sink sink;
+  sink.fitness = out;
+  sim_fitness dummy;
+  if (!n_traces) sink.fitness = &dummy;
+  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink, false);
+}
+
+int sim_eval_fitness(sim_ctx* c, const sim_record* records, const uint64_t* offsets, uint32_t n_traces,
+                     const uint32_t* threads_per_block, sim_fitness* out) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (!out && n_traces) return fail(c, SIM_EINVAL, "out is NULL");
+  DeviceGuard g(c->device);
+  uint64_t total = 0;
+  uint32_t n_tiles = 0;
+  sim_result* dummy_r = nullptr;
+  int rc = validate(c, offsets, n_traces, threads_per_block, &dummy_r, &total, &n_tiles);
+  if (rc) return rc;
+  if (total && !records) return fail(c, SIM_EINVAL, "records is NULL");
+  if (total) {
+    hipError_t e = ensure(c->records, total * sizeof(sim_record));
+    if (e != hipSuccess) return hip_fail(c, e, "device allocation");
+    e = hipMemcpyAsync(c->records.p, records, total * sizeof(sim_record), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "record upload");
+  }
+  Sink sink;
+  sink.fitness = out;
+  sim_fitness dummy;
+  if (!n_traces) sink.fitness = &dummy;
+  return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink,
+             false);
+}
+
+int sim_check_divergence_device(sim_ctx* c, const uint32_t* d_arrivals, const uint64_t* offsets, uint32_t n_traces,
+                                const uint32_t* threads_per_block, void* stream, sim_divergence_result** out) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  DeviceGuard g(c->device);
+  return divergence(c, d_arrivals, offsets, n_traces, threads_per_block, (hipStream_t)stream, out);
+}
+
+int sim_check_divergence(sim_ctx* c, const uint32_t* arrivals, const uint64_t* offsets, uint32_t n_traces,
+                         const uint32_t* threads_per_block, sim_divergence_result** out) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (out) *out = nullptr;
+  if (!out) return fail(c, SIM_EINVAL, "out is NULL");
+  DeviceGuard g(c->device);
+  uint64_t total = 0;
+  uint32_t n_chunks = 0;
+  const int rc = div_tables(c, offsets, n_traces, threads_per_block, &total, &n_chunks);
+  if (rc) return rc;
+  if (total && !arrivals) return fail(c, SIM_EINVAL, "arrival counts are NULL");
+  if (total) {
+    hipError_t e = grow(c, c->div_in, total * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(c, e, "device allocation");
+    e = hipMemcpyAsync(c->div_in.p, arrivals, total * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "arrival upload");
+  }
+  return divergence(c, (const uint32_t*)c->div_in.p, offsets, n_traces, threads_per_block, c->stream, out);
+}
+
+void sim_divergence_result_free(sim_divergence_result* r) { divergence_result_free(r); }
 
 void sim_result_free(sim_result* r) {
   if (!r) return;

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
 template <int NTH = NT>
 __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ desc,
                                                 const TraceStats* __restrict__ part, TraceLayout* lay, Ctrl* ctrl,
-                                                uint32_t wide_call) {
+                                                uint32_t wide_call, uint32_t fitness) {
   constexpr int NW = NTH / 64;
   __shared__ uint64_t s64[5][NW];
   __shared__ uint32_t s32[2][NW];
@@ -357,6 +357,7 @@ __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ de
     S.bad_index = min(S.bad_index, s64[4][w]);
     S.max_tid = max(S.max_tid, s32[0][w]); S.max_epoch = max(S.max_epoch, s32[1][w]);
   }
+  if (fitness) S.max_epoch = 0;  // fitness keys hold no epoch (and no action)
   TraceLayout L = make_layout(S, T.tpb);
   if (T.n == 0) {
     L.error = 0;
@@ -516,6 +517,7 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
     if (L.npasses == 0) continue;
+    const uint32_t keep = b.fitness ? 0u : ~0u;  // fitness keys: epoch and action dropped
     h[tx] = 0;
     __syncthreads();
     const uint64_t start = (uint64_t)tr.local * TILE;
@@ -535,7 +537,8 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
         K k = 0;
         if (valid) {
           const Rec x = unpack_rec(vr[r]);
-          k = make_key_t<K, decltype(blk_form)::value>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb);
+          k = make_key_t<K, decltype(blk_form)::value>(L, x.unit, x.tid, x.epoch & keep, x.action & keep, x.space,
+                                                        T.tpb);
           kout[j] = k;
         }
         wave_hist_add(h, (uint32_t)(k >> 2) & (RADIX - 1), valid);
@@ -791,12 +794,14 @@ __global__ __launch_bounds__(NTH) void k_keygen_scatter(Buffers b) {
     const TraceLayout L = b.layout[tr.trace];
     if (L.npasses == 0) continue;  // uniform over the workgroup
     for (uint32_t k = tx; k < (uint32_t)(NTH / 64 * RADIX); k += NTH) (&S.wh[0][0])[k] = 0;
+    const uint32_t keep = b.fitness ? 0u : ~0u;  // fitness keys: epoch and action dropped
     K key[IT];
 #pragma unroll
     for (int i = 0; i < IT; i++) {
       const uint32_t j = wave * (IT * 64) + i * 64 + lane;
       const Rec x = unpack_rec(vr[i]);
-      key[i] = j < n_in ? make_key_t<K, BLK_POW2>(L, x.unit, x.tid, x.epoch, x.action, x.space, T.tpb) : ~(K)0;
+      key[i] = j < n_in ? make_key_t<K, BLK_POW2>(L, x.unit, x.tid, x.epoch & keep, x.action & keep, x.space, T.tpb)
+                        : ~(K)0;
     }
     __syncthreads();
     scatter_tile<K, NTH, C>(b, 0, tile, tx, tr, T, n_in, key, (K*)b.keys[1], S);
@@ -1500,6 +1505,185 @@ __global__ void k_fill_zero(unsigned long long* p, uint64_t n) {
     p[i] = 0ull;
 }
 
+// ------------------------------------------------------------ EP fitness
+//
+// Eq. 1 (Sec. 4.1.1): for one candidate input, g(i) = 1 for every address i
+// the trace touches and f(i) the number of threads touching it; the fitness
+// is F = sum g / sum f, and the secondary score the access range.  With
+// fitness keys (location, then thread; epoch and action dropped) the sorted
+// keys of a trace hold one run per location, split into one run per
+// (location, thread): sum g counts location heads and sum f counts heads at
+// any level.  k_fit_tiles counts them per tile (the first key of a trace is
+// a head of both), k_fit_traces sums a trace's tiles and writes its row.
+
+template <typename K, bool LOOP>
+__global__ __launch_bounds__(NT) void k_fit_tiles(Buffers b, uint32_t passes_done) {
+  __shared__ uint32_t s_g[NWAVE], s_f[NWAVE];
+  if (b.ctrl->error_flags) return;
+  if (b.ctrl->max_passes > passes_done) return;  // the host runs the missing passes first
+  const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    __syncthreads();  // LDS of the previous tile is free
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));
+    const TileRef tr = b.tiles[tile];
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    const K* keys = (const K*)b.keys[L.npasses & 1u] + T.off;
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
+    uint32_t g = 0, f = 0;
+    // coalesced: key j of the tile is read by thread j mod NT, with its predecessor
+#pragma unroll 4
+    for (int r = 0; r < ITEMS; r++) {
+      const uint32_t j = tx + r * NT;
+      if (j >= n_in) break;
+      const uint64_t p = start + j;
+      const uint32_t lv = p == 0 ? 0u : head_level_t<K>(L, keys[p - 1], keys[p]);
+      g += lv == 0 ? 1u : 0u;
+      f += lv < 4 ? 1u : 0u;
+    }
+    g = wave_reduce(g, 0u, [](uint32_t a, uint32_t c) { return a + c; });
+    f = wave_reduce(f, 0u, [](uint32_t a, uint32_t c) { return a + c; });
+    if ((tx & 63u) == 0) {
+      s_g[tx >> 6] = g;
+      s_f[tx >> 6] = f;
+    }
+    __syncthreads();
+    if (tx == 0) {
+      uint32_t tg = 0, tf = 0;
+#pragma unroll
+      for (int w = 0; w < NWAVE; w++) {
+        tg += s_g[w];
+        tf += s_f[w];
+      }
+      b.tout[tile] = TileOut{tg, tf};
+    }
+  }
+}
+
+// One thread per trace.
+__global__ __launch_bounds__(NT) void k_fit_traces(Buffers b, FitOut* __restrict__ out) {
+  const uint32_t t = blockIdx.x * NT + threadIdx.x;
+  if (t >= b.n_traces) return;
+  const TraceDesc T = b.desc[t];
+  const TraceLayout L = b.layout[t];
+  uint64_t g = 0, f = 0;
+  for (uint32_t k = 0; k < T.ntiles; k++) {
+    const TileOut o = b.tout[T.tile0 + k];
+    g += o.in_count;
+    f += o.owns;
+  }
+  FitOut r;
+  r.n_records = T.n;
+  r.n_locations = g;
+  r.n_location_threads = f;
+  r.global_range = T.n ? L.grange : 0;
+  r.shared_range = T.n ? L.srange : 0;
+  r.fitness = f ? (double)g / (double)f : 1.0;
+  out[t] = r;
+}
+
+// ------------------------------------------------- barrier divergence
+//
+// Alg. 4 (Sec. 4.2.2): a thread that reaches the end of the kernel while
+// another thread of its block waits at a barrier is a barrier divergence.
+// Input: for every thread the number of barriers it arrived at before it
+// finished, block by block.  A block diverges when those numbers are not
+// all equal; its entry gives the fewest and most arrivals and how many of
+// its threads arrived at fewer than the most.
+//
+// k_div_blocks: one workgroup per chunk (whole blocks of one trace, about a
+// tile of threads).  A block of up to 64 threads takes a segment of
+// pow2ceil(tpb) lanes (several blocks per wave, reduced with xor shuffles
+// inside the segment); a larger block takes a whole wave, its lanes
+// striding over the threads.  Dense per-block results and per-chunk counts
+// of divergent blocks go to global memory.  k_div_scan turns the counts
+// into offsets (one workgroup), and k_div_emit writes the divergent blocks
+// in (trace, block) order.
+
+__device__ __forceinline__ uint32_t seg_lanes(uint32_t tpb) {
+  if (tpb >= 64) return 64u;
+  uint32_t s = 1;
+  while (s < tpb) s <<= 1;
+  return s;
+}
+
+__global__ __launch_bounds__(NT) void k_div_blocks(const DivChunk* __restrict__ chunks,
+                                                   const uint32_t* __restrict__ arrivals, DivBlock* __restrict__ blocks,
+                                                   uint32_t* __restrict__ chunk_cnt) {
+  __shared__ uint32_t s_cnt;
+  const DivChunk ch = chunks[blockIdx.x];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const uint32_t S = seg_lanes(ch.tpb);  // lanes per block (uniform over the workgroup)
+  const uint32_t per_wave = 64u / S, sub = lane / S, sl = lane % S;
+  uint32_t n_div = 0;
+  for (uint32_t b0 = wave * per_wave; b0 < ch.n_blocks; b0 += NWAVE * per_wave) {
+    const uint32_t blk = b0 + sub;
+    const bool live = blk < ch.n_blocks;
+    const uint32_t* c = arrivals + ch.thread0 + (uint64_t)blk * ch.tpb;
+    uint32_t lo = ~0u, hi = 0u;
+    if (live)
+      for (uint32_t i = sl; i < ch.tpb; i += S) {
+        const uint32_t v = c[i];
+        lo = min(lo, v);
+        hi = max(hi, v);
+      }
+    for (uint32_t d = 1; d < S; d <<= 1) {
+      lo = min(lo, (uint32_t)__shfl_xor((int)lo, (int)d, 64));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, (int)d, 64));
+    }
+    uint32_t early = 0;
+    if (live && lo != hi)  // the same in every lane of the segment
+      for (uint32_t i = sl; i < ch.tpb; i += S) early += c[i] < hi ? 1u : 0u;
+    for (uint32_t d = 1; d < S; d <<= 1) early += (uint32_t)__shfl_xor((int)early, (int)d, 64);
+    if (live && sl == 0) {
+      blocks[(uint64_t)ch.block0 + blk] = DivBlock{lo, hi, early, 0u};
+      n_div += lo != hi ? 1u : 0u;
+    }
+  }
+  n_div = wave_reduce(n_div, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+  if (lane == 0 && n_div) atomicAdd(&s_cnt, n_div);
+  __syncthreads();
+  if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = s_cnt;
+}
+
+// One workgroup: exclusive offsets of the chunks' counts, and the total.
+__global__ __launch_bounds__(NT) void k_div_scan(const uint32_t* __restrict__ chunk_cnt, uint64_t* __restrict__ chunk_off,
+                                                 uint32_t n_chunks, uint64_t* __restrict__ total) {
+  __shared__ uint32_t s_sc[NWAVE];
+  uint64_t base = 0;
+  for (uint32_t i0 = 0; i0 < n_chunks; i0 += NT) {
+    const uint32_t i = i0 + threadIdx.x;
+    const uint32_t v = i < n_chunks ? chunk_cnt[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum(v, s_sc, &tot);
+    if (i < n_chunks) chunk_off[i] = base + ex;
+    base += tot;
+  }
+  if (threadIdx.x == 0) *total = base;
+}
+
+__global__ __launch_bounds__(NT) void k_div_emit(const DivChunk* __restrict__ chunks,
+                                                 const DivBlock* __restrict__ blocks,
+                                                 const uint64_t* __restrict__ chunk_off, DivOut* __restrict__ out) {
+  __shared__ uint32_t s_sc[NWAVE];
+  const DivChunk ch = chunks[blockIdx.x];
+  uint64_t base = chunk_off[blockIdx.x];
+  for (uint32_t b0 = 0; b0 < ch.n_blocks; b0 += NT) {
+    const uint32_t blk = b0 + threadIdx.x;
+    DivBlock r{0u, 0u, 0u, 0u};
+    if (blk < ch.n_blocks) r = blocks[(uint64_t)ch.block0 + blk];
+    const uint32_t flag = (blk < ch.n_blocks && r.lo != r.hi) ? 1u : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum(flag, s_sc, &tot);
+    if (flag) out[base + ex] = DivOut{ch.trace, ch.block + blk, r.lo, r.hi, (uint64_t)r.early};
+    base += tot;
+  }
+}
+
 // -------------------------------------------------------- launch wrappers
 
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -1534,9 +1718,10 @@ hipError_t launch_layout(const Buffers& b, hipStream_t s) {
   if (!b.n_traces) return hipSuccess;
   if (b.n_traces <= 64 && b.n_tiles >= 64 * b.n_traces)  // a few long traces
     hipLaunchKernelGGL(k_layout<4 * NT>, dim3(b.n_traces), dim3(4 * NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl,
-                       b.wide);
+                       b.wide, b.fitness);
   else
-    hipLaunchKernelGGL(k_layout<NT>, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl, b.wide);
+    hipLaunchKernelGGL(k_layout<NT>, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl, b.wide,
+                       b.fitness);
   return hipGetLastError();
 }
 hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
@@ -1663,6 +1848,39 @@ hipError_t launch_barriers(const Buffers& b, const uint64_t* bar_base, BarrierCo
   auto kern = b.wide ? (lp ? k_barriers<u128, true> : k_barriers<u128, false>)
                      : (lp ? k_barriers<uint64_t, true> : k_barriers<uint64_t, false>);
   hipLaunchKernelGGL(kern, dim3(b.grid_scan), dim3(NT), 0, s, b, bar_base, table, copies);
+  return hipGetLastError();
+}
+
+hipError_t launch_fitness(const Buffers& b, uint32_t passes_done, FitOut* out, hipStream_t s) {
+  if (b.n_tiles) {
+    if (!grids_ok(b)) return hipErrorInvalidConfiguration;
+    const bool lp = loops(b, b.grid_scan);
+    auto kern = b.wide ? (lp ? k_fit_tiles<u128, true> : k_fit_tiles<u128, false>)
+                       : (lp ? k_fit_tiles<uint64_t, true> : k_fit_tiles<uint64_t, false>);
+    hipLaunchKernelGGL(kern, dim3(b.grid_scan), dim3(NT), 0, s, b, passes_done);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (!b.n_traces) return hipSuccess;
+  hipLaunchKernelGGL(k_fit_traces, dim3(cdiv(b.n_traces, NT)), dim3(NT), 0, s, b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_divergence(const DivChunk* chunks, uint32_t n_chunks, const uint32_t* arrivals, DivBlock* blocks,
+                             uint32_t* chunk_cnt, uint64_t* chunk_off, uint64_t* total, hipStream_t s) {
+  if (n_chunks) {
+    hipLaunchKernelGGL(k_div_blocks, dim3(n_chunks), dim3(NT), 0, s, chunks, arrivals, blocks, chunk_cnt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_div_scan, dim3(1), dim3(NT), 0, s, chunk_cnt, chunk_off, n_chunks, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_divergence_emit(const DivChunk* chunks, uint32_t n_chunks, const DivBlock* blocks,
+                                  const uint64_t* chunk_off, DivOut* out, hipStream_t s) {
+  if (!n_chunks) return hipSuccess;
+  hipLaunchKernelGGL(k_div_emit, dim3(n_chunks), dim3(NT), 0, s, chunks, blocks, chunk_off, out);
   return hipGetLastError();
 }
 

@@ -52,6 +52,9 @@ struct TraceLayout {
   uint32_t error;      // LAYOUT_ERR_* bits
   uint32_t wide;       // 1: the key needs more than 64 bits (two-word keys)
   uint32_t max_epoch;  // largest epoch of the trace (its barrier boundaries are 0 .. max_epoch - 1)
+  uint32_t pad;
+  uint64_t grange;     // largest minus smallest global unit (0 without global records)
+  uint64_t srange;     // the same over shared units
 };
 
 // LAYOUT_ERR_* are per-trace layout errors; ERR_INTERNAL_BOUNDS is raised by
@@ -97,6 +100,9 @@ SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
   L.error = 0;
   L.wide = L.key_bits > 64 ? 1u : 0u;
   L.max_epoch = s.max_epoch;
+  L.pad = 0;
+  L.grange = has_g ? s.gmax - s.gmin : 0;
+  L.srange = has_s ? s.smax - s.smin : 0;
   if (L.key_bits > 128) L.error |= LAYOUT_ERR_WIDE;
   if (s.bad_index != ~0ull) L.error |= LAYOUT_ERR_RECORD;
   L.npasses = L.error ? 0 : (L.key_bits - 2 + RADIX_BITS - 1) / RADIX_BITS;

@@ -112,6 +112,7 @@ struct Buffers {            // device pointers of one call
   uint32_t small_from;      // first radix pass done in LDS for those traces (pass 0 is
                             // k_keygen_scatter's when fuse0)
   uint32_t key_bytes;       // 8 or 16
+  uint32_t fitness;         // 1: fitness keys (epoch and action dropped), for the EP fitness count
 };
 
 // Barrier instances (per trace and boundary) of the redundant-barrier check:
@@ -141,6 +142,43 @@ hipError_t launch_reset_errors(const Buffers& b, uint32_t mask, hipStream_t s);
 // `table` (n_counts entries) and counts every trace's barrier instances.
 hipError_t launch_barriers(const Buffers& b, const uint64_t* bar_base, BarrierCount* table, uint64_t n_counts,
                            uint32_t copies, hipStream_t s);
+
+// EP fitness of one trace (mirrors sim_fitness, 48 bytes).
+struct FitOut {
+  uint64_t n_records, n_locations, n_location_threads, global_range, shared_range;
+  double fitness;
+};
+// Over the sorted fitness keys of a finished call: every trace's row to out
+// (device memory, n_traces rows).  Does nothing while fewer than the needed
+// radix passes ran (the host runs them and launches again).
+hipError_t launch_fitness(const Buffers& b, uint32_t passes_done, FitOut* out, hipStream_t s);
+
+// Barrier divergence (Alg. 4): whole blocks of one trace per chunk.
+struct DivChunk {
+  uint64_t thread0;  // the chunk's first thread (index into the arrival counts)
+  uint32_t trace;
+  uint32_t block;    // the chunk's first block within its trace
+  uint32_t n_blocks;
+  uint32_t tpb;      // threads per block
+  uint32_t block0;   // the chunk's first block among the call's blocks (dense results)
+  uint32_t pad;
+};
+struct DivBlock {    // one block: fewest and most arrivals, threads below the most
+  uint32_t lo, hi, early, pad;
+};
+struct DivOut {      // mirrors sim_divergence (24 bytes)
+  uint32_t trace, block, lo, hi;
+  uint64_t early;
+};
+constexpr uint32_t DIV_CHUNK_THREADS = TILE;  // threads per chunk (whole blocks, at least one)
+
+// Per-block results and per-chunk counts, then the chunks' output offsets
+// and the number of divergent blocks (*total, device memory).
+hipError_t launch_divergence(const DivChunk* chunks, uint32_t n_chunks, const uint32_t* arrivals, DivBlock* blocks,
+                             uint32_t* chunk_cnt, uint64_t* chunk_off, uint64_t* total, hipStream_t s);
+// The divergent blocks, in (trace, block) order, to out.
+hipError_t launch_divergence_emit(const DivChunk* chunks, uint32_t n_chunks, const DivBlock* blocks,
+                                  const uint64_t* chunk_off, DivOut* out, hipStream_t s);
 
 // Device memory of the no-allocation entry point: a file-scope array of
 // SCRATCH_BYTES in the library's device code, one copy per GPU.

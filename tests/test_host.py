@@ -215,11 +215,20 @@ def test_abi_structs_match_binding(tmp_path):
     pairs = {
         "sim_result": pkg._Result, "sim_config": pkg._Config, "sim_stage_time": pkg._StageTime,
         "sim_tuning": pkg._Tuning, "sim_server_config": pkg._ServerConfig, "sim_server_stats": pkg._ServerStats,
+        "sim_barrier_result": pkg._BarrierResult, "sim_divergence_result": pkg._DivergenceResult,
+    }
+    dtypes = {
+        "sim_record": pkg.RECORD_DTYPE, "sim_race": pkg.RACE_DTYPE, "sim_trace_summary": pkg.SUMMARY_DTYPE,
+        "sim_barrier": pkg.BARRIER_DTYPE, "sim_fitness": pkg.FITNESS_DTYPE, "sim_divergence": pkg.DIVERGENCE_DTYPE,
     }
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "simcheck.h"', "int main(void) {"]
     for c_name, py in pairs.items():
         lines.append(f'  printf("{c_name} size %zu\\n", sizeof({c_name}));')
         for f, _ in py._fields_:
+            lines.append(f'  printf("{c_name} {f} %zu\\n", offsetof({c_name}, {f}));')
+    for c_name, dt in dtypes.items():
+        lines.append(f'  printf("{c_name} size %zu\\n", sizeof({c_name}));')
+        for f in dt.names:
             lines.append(f'  printf("{c_name} {f} %zu\\n", offsetof({c_name}, {f}));')
     lines.append("  return 0;\n}")
     src = tmp_path / "probe.c"
@@ -232,6 +241,10 @@ def test_abi_structs_match_binding(tmp_path):
         assert got[(c_name, "size")] == ctypes.sizeof(py), c_name
         for f, _ in py._fields_:
             assert got[(c_name, f)] == getattr(py, f).offset, (c_name, f)
+    for c_name, dt in dtypes.items():
+        assert got[(c_name, "size")] == dt.itemsize, c_name
+        for f in dt.names:
+            assert got[(c_name, f)] == dt.fields[f][1], (c_name, f)
 
 
 # ------------------------------------------- barrier instances (host model)

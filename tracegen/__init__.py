@@ -274,3 +274,37 @@ def random_small(rng: np.random.Generator, n: int, *, units: int = 4, blocks: in
     r["action"] = rng.integers(0, 3 if atomics else 2, n)
     r["space"] = rng.integers(0, 2, n)
     return r
+
+
+def arrivals(n_blocks: int, tpb: int, barriers: int, seed: int, diverge_rate: float = 1e-2):
+    """Per-thread barrier arrival counts of one synthetic launch, block by
+    block (uint32, n_blocks * tpb of them): every thread arrives at
+    `barriers` barriers, except in about diverge_rate of the blocks, where a
+    random subset of threads returns early after fewer (a thread-dependent
+    branch around a barrier, or an early return).  Returns (counts, list of
+    the blocks made divergent)."""
+    rng = np.random.default_rng(seed)
+    counts = np.full(n_blocks * tpb, barriers, dtype=np.uint32)
+    if barriers == 0 or n_blocks == 0 or tpb < 2:
+        return counts, []
+    picked = np.flatnonzero(rng.random(n_blocks) < diverge_rate)
+    for b in picked:
+        blk = counts[b * tpb:(b + 1) * tpb]
+        m = int(rng.integers(1, tpb))  # threads that leave early (at least one stays)
+        who = rng.choice(tpb, size=m, replace=False)
+        blk[who] = rng.integers(0, barriers, m).astype(np.uint32)
+    return counts, [int(b) for b in picked]
+
+
+def arrivals_batch(shapes, barriers: int = 4, diverge_rate: float = 1e-2, seed: int = 0x5EED0005):
+    """Arrival counts of a batch of launches, one per (n_blocks, tpb) shape:
+    (counts, CSR offsets over threads, threads per block)."""
+    parts, tpbs = [], []
+    for i, (nb, tp) in enumerate(shapes):
+        c, _ = arrivals(nb, tp, barriers, splitmix64(seed ^ i), diverge_rate)
+        parts.append(c)
+        tpbs.append(tp)
+    off = np.zeros(len(shapes) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(c) for c in parts])
+    counts = np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint32)
+    return counts, off, np.array(tpbs, dtype=np.uint32)
