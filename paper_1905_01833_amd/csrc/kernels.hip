@@ -904,6 +904,18 @@ __device__ __forceinline__ uint32_t meta_at(const uint32_t mp[3], uint32_t i) {
 
 __device__ __forceinline__ uint32_t cnt16(uint64_t packed, uint32_t q) { return (uint32_t)(packed >> (16 * q)) & 0xFFFFu; }
 
+// Three 8-bit class fields (read, write, atomic) to three 16-bit fields;
+// the top field (padding) is dropped.
+__device__ __forceinline__ uint64_t widen8(uint32_t x) {
+  return (uint64_t)(x & 0xFFu) | ((uint64_t)(x & 0xFF00u) << 8) | ((uint64_t)(x & 0xFF0000u) << 16);
+}
+
+// Bit 5 k of the result is set where item 6 w + k of a packed metadata word
+// (3-bit head level, 2-bit class per item) has head level 0.
+__device__ __forceinline__ uint32_t loc_heads(uint32_t w) {
+  return ~(w | (w >> 1) | (w >> 2)) & 0x02108421u;
+}
+
 // Pairs of one element of class c against the open-run counts run[] (the
 // counts of earlier elements of its location / block / epoch / thread runs
 // inside the tile, three 16-bit class fields per word).  The runs are
@@ -986,15 +998,12 @@ __device__ __forceinline__ RaceOut* stage_of(const Buffers& b, uint32_t tile, co
   return (RaceOut*)((char*)b.keys[(L.npasses & 1u) ^ 1u] + (T.off + start) * b.key_bytes);
 }
 
-// Occupancy of the tile scan: it is bound by VALU issue, and with no LDS
-// copy of the tile its registers alone set the waves per SIMD.  The
-// one-tile kernels ask for 6 (80 VGPRs, no spill; the block scans' totals
-// live in scalar registers) instead of the 4 that their natural count
-// gave: c1's scan took 151 us at 4 waves, 131 at 5, 129.6 at 6, 128.9 at 7
-// and 140 at 8 (spilling).  The looping variants would spill and keep
-// their natural counts.
+// Occupancy of the tile scan: with no LDS copy of the tile its registers
+// alone set the waves per SIMD.  The one-tile kernels ask for 8 waves with
+// one-word keys (64 VGPRs, no spill) and 6 with two-word keys; the looping
+// variants keep their natural counts.
 template <typename K, bool LOOP>
-constexpr int scan_min_waves() { return LOOP ? 1 : 6; }
+constexpr int scan_min_waves() { return LOOP ? 1 : (sizeof(K) == 8 ? 8 : 6); }
 
 template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(Buffers b, uint32_t passes_done) {
@@ -1003,8 +1012,8 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
   __shared__ uint32_t s_scan32[NWAVE];
   __shared__ uint8_t s_firstlv[NT];
   __shared__ uint32_t s_lead[17];  // lead counts [l][c] (12), lead pair sums (5)
-  __shared__ uint32_t s_min;
   __shared__ uint32_t s_taillast;
+  __shared__ uint32_t s_hit;  // some thread of the tile has an element with an in-tile racing partner
 
   // nothing to do on an error, or when fewer radix passes ran than some
   // trace needs (the host then runs the missing passes and scans again)
@@ -1017,7 +1026,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
     const uint32_t tid = tx, lane = tx & 63u, wave = tx >> 6;
     if (tid < 17) s_lead[tid] = 0;
-    if (tid == 0) s_min = NO_HEAD;
+    if (tid == 0) s_hit = 0;
     const TileRef tr = b.tiles[tile];
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
@@ -1045,7 +1054,6 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     // ---- element metadata: head level (3 bits) and class (2 bits)
     // head level (3 bits) and class (2 bits) of item i: bits 5 (i % 6) of mp[i / 6]
     uint32_t mp[3] = {0u, 0u, 0u};
-    uint32_t local_min = NO_HEAD;
     {
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
@@ -1055,7 +1063,6 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         if (j < n_in) {
           lv = (j == 0 && tr.local == 0) ? 0u : head_level_t<K>(L, prev, k);
           c = action_class(k);
-          local_min = min(local_min, lv);
         } else {
           lv = 4;
           c = CLS_NONE;
@@ -1065,65 +1072,62 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
       }
       s_firstlv[tid] = (uint8_t)(mp[0] & 7u);
     }
-    local_min = wave_min(local_min);
-    if (lane == 0 && local_min < NO_HEAD) atomicMin(&s_min, local_min);
 
-    // ---- pass A: segmented class counts per level
-    uint64_t aggA[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-      const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
-#pragma unroll
-      for (int l = 0; l < 4; l++)
-        if (lv <= (uint32_t)l) aggA[l] = SEGF;
-      if (c != CLS_NONE) {
-#pragma unroll
-        for (int l = 0; l < 4; l++) aggA[l] += 1ull << (16 * c);
-      }
-    }
-    uint64_t exA[4], totA[4];
-    block_seg_scan<4>(aggA, exA, totA, s_scanA);
-
-    // ---- pass B: pairs per element, summed per location run; lead data.
-    //      Locations that end in this thread are counted here when they also
-    //      start in it; the thread's first location (it may start in an
-    //      earlier thread) is settled after the scan.
-    uint64_t aggB[3] = {0, 0, 0};
-    uint32_t n_emit = 0;
-    bool pend = false;
-    uint64_t pend0 = 0, pend1 = 0;
+    // ---- pass A: segmented class counts per level.  Inside the thread the
+    //      counts are 8-bit fields of one word (a thread holds 16 elements):
+    //      the running count, and per level its value before the thread's
+    //      last head at that level or coarser.  Their difference, widened to
+    //      the 16-bit fields of the block scan, is the thread's aggregate.
+    uint64_t aggA[4];
     {
-      uint64_t run[4];
-#pragma unroll
-      for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
+      uint32_t cnt = 0, snap[4] = {0u, 0u, 0u, 0u}, mn = NO_HEAD;
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
 #pragma unroll
         for (int l = 0; l < 4; l++)
-          if (lv <= (uint32_t)l) run[l] = 0;
-        if (c == CLS_NONE) continue;
-        uint32_t v[5];
-        tile_pairs(c, run, v);
-        if (lv == 0) aggB[0] = aggB[1] = aggB[2] = SEGF;
-        aggB[0] += (uint64_t)v[K_WW] | ((uint64_t)v[K_RW] << 32);
-        aggB[1] += (uint64_t)v[K_AW] | ((uint64_t)v[K_AR] << 32);
-        aggB[2] += (uint64_t)v[K_XB];
+          if (lv <= (uint32_t)l) snap[l] = cnt;
+        cnt += 1u << (8 * c);  // padding (class 3) counts in the unused top field
+        mn = min(mn, lv);
+      }
 #pragma unroll
-        for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
-        const uint32_t j = ITEMS * tid + i;
-        bool last;
-        if (j + 1 == n_in) last = s_taillast != 0;
-        else if (i + 1 < ITEMS) last = (META(i + 1) & 7u) == 0;
-        else last = s_firstlv[tid + 1] == 0;
-        if (!last) continue;
-        if (aggB[0] & SEGF) {  // the location started in this thread
-          if (((aggB[0] | aggB[1]) & ~SEGF) != 0) n_emit++;
-        } else {
-          pend = true;
-          pend0 = aggB[0];
-          pend1 = aggB[1];
-        }
+      for (int l = 0; l < 4; l++) aggA[l] = (mn <= (uint32_t)l ? SEGF : 0ull) | widen8(cnt - snap[l]);
+    }
+    // the packed metadata is decoded again per pass, not kept decoded
+#pragma unroll
+    for (int k = 0; k < 3; k++) asm volatile("" : "+v"(mp[k]));
+    uint64_t exA[4], totA[4];
+    block_seg_scan<4>(aggA, exA, totA, s_scanA);
+
+    // ---- pass B, test: whether an element of this thread has a racing
+    //      partner among the earlier elements of its location in the tile.
+    //      The counts its pairs are drawn from are (location run - block
+    //      run) + (epoch run - thread run); both differences change only at
+    //      heads, so they are kept as d01 and d23 beside the open location
+    //      and epoch run counts r0 and r2.  Most threads find nothing and
+    //      skip the pair sums below.
+    uint32_t hit = 0;
+    {
+      uint64_t r0 = exA[0] & ~SEGF, r2 = exA[2] & ~SEGF;
+      uint64_t d01 = r0 - (exA[1] & ~SEGF), d23 = r2 - (exA[3] & ~SEGF);
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) {
+        const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
+        // selects, not branches (branches here cost registers)
+        const bool z0 = lv == 0, z1 = lv == 1, z2 = lv <= 2, z3 = lv == 3;
+        d01 = z0 ? 0ull : (z1 ? r0 : d01);
+        r0 = z0 ? 0ull : r0;
+        d23 = z2 ? 0ull : (z3 ? r2 : d23);
+        r2 = z2 ? 0ull : r2;
+        const uint64_t tot = d01 + d23;
+        // conflicting classes: a read's are writes and atomics, a write's
+        // all three, an atomic's reads and writes; padding has none
+        const uint32_t mlo = c == CLS_R ? 0xFFFF0000u : (c == CLS_NONE ? 0u : 0xFFFFFFFFu);
+        const uint32_t mhi = c <= CLS_W ? 0xFFFFu : 0u;
+        hit |= ((uint32_t)tot & mlo) | ((uint32_t)(tot >> 32) & mhi);
+        const uint64_t inc = 1ull << (16 * c);
+        r0 += inc;
+        r2 += inc;
       }
     }
     // ---- lead data: the class counts before the tile's first head at each
@@ -1171,17 +1175,80 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
       for (int k = 0; k < 5; k++)
         if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
     }
-    uint64_t exB[3], totB[3];
-    block_seg_scan<3>(aggB, exB, totB, s_scanB);  // contains a barrier: s_lead and s_min are complete after it
-    // the thread's first location: complete here only if it started in the
-    // tile (a location head in an earlier thread); otherwise it belongs to an
-    // earlier tile and is finished by k_scan_cross
-    if (pend && (exB[0] & SEGF) && ((((exB[0] + pend0) | (exB[1] + pend1)) & ~SEGF) != 0)) n_emit++;
+    if (hit) s_hit = 1u;
+    __syncthreads();  // s_hit and s_lead are complete after it
+    const bool tile_hit = s_hit != 0;
+
+    // ---- pass B, sums (tiles with a racing pair only): pairs per element,
+    //      summed per location run.  Locations that end in this thread are
+    //      counted here when they also start in it; the thread's first
+    //      location (it may start in an earlier thread) is settled after the
+    //      scan.
+    uint64_t exB[3] = {0, 0, 0}, totB[3] = {0, 0, 0};
+    uint32_t n_emit = 0;
+    if (tile_hit) {  // uniform over the workgroup
+      uint64_t aggB[3] = {0, 0, 0};
+      bool pend = false;
+      uint64_t pend0 = 0, pend1 = 0;
+      if (hit) {
+        uint64_t run[4];
+#pragma unroll
+        for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
+#pragma unroll 1
+        for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
+          const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
+#pragma unroll
+          for (int l = 0; l < 4; l++)
+            if (lv <= (uint32_t)l) run[l] = 0;
+          if (c == CLS_NONE) continue;
+          uint32_t v[5];
+          tile_pairs(c, run, v);
+          if (lv == 0) aggB[0] = aggB[1] = aggB[2] = SEGF;
+          aggB[0] += (uint64_t)v[K_WW] | ((uint64_t)v[K_RW] << 32);
+          aggB[1] += (uint64_t)v[K_AW] | ((uint64_t)v[K_AR] << 32);
+          aggB[2] += (uint64_t)v[K_XB];
+#pragma unroll
+          for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
+          const uint32_t j = ITEMS * tid + i;
+          bool last;
+          if (j + 1 == n_in) last = s_taillast != 0;
+          else if (i + 1 < (uint32_t)ITEMS) last = (meta_at(mp, i + 1) & 7u) == 0;
+          else last = s_firstlv[tid + 1] == 0;
+          if (!last) continue;
+          if (aggB[0] & SEGF) {  // the location started in this thread
+            if (((aggB[0] | aggB[1]) & ~SEGF) != 0) n_emit++;
+          } else {
+            pend = true;
+            pend0 = aggB[0];
+            pend1 = aggB[1];
+          }
+        }
+      } else if (ITEMS * tid < n_in) {
+        // every pair sum of this thread is zero: only its location heads
+        // and whether its first location ends in it matter
+        const uint32_t heads = loc_heads(mp[0]) | loc_heads(mp[1]) | (loc_heads(mp[2]) & 0x8421u);
+        if (heads) {
+          aggB[0] = aggB[1] = aggB[2] = SEGF;
+          pend = (mp[0] & 7u) != 0;  // the first location ends before the thread's first head
+        } else {
+          const uint32_t jl = min(ITEMS * tid + (uint32_t)ITEMS, n_in) - 1;  // last element of the thread
+          pend = jl + 1 == n_in ? s_taillast != 0 : s_firstlv[tid + 1] == 0;
+        }
+      }
+      block_seg_scan<3>(aggB, exB, totB, s_scanB);
+      // the thread's first location: complete here only if it started in
+      // the tile (a location head in an earlier thread); otherwise it belongs
+      // to an earlier tile and is finished by k_scan_cross
+      if (pend && (exB[0] & SEGF) && ((((exB[0] + pend0) | (exB[1] + pend1)) & ~SEGF) != 0)) n_emit++;
+    }
 
     // ---- the tile summary (lanes of wave 0 write its words)
     if (wave == 0) {
       State agg;
-      agg.m = s_min;
+      // the smallest head level of the tile: the coarsest level whose
+      // scan total carries a head flag (every tile holds an element, so
+      // the level is at most 4)
+      agg.m = (totA[0] & SEGF) ? 0u : (totA[1] & SEGF) ? 1u : (totA[2] & SEGF) ? 2u : (totA[3] & SEGF) ? 3u : 4u;
 #pragma unroll
       for (int l = 0; l < 4; l++)
 #pragma unroll
