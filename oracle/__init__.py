@@ -13,7 +13,10 @@ Two native tiers live in ``oracle.c`` (built into ``liboracle.so``):
     threads (by trace, and by location-hash bucket within a large trace).
 ``tier_a_py`` is a third, pure-Python rendering of the pairwise definition
 for tiny inputs, written separately so that the C tiers can be checked
-against it.
+against it.  ``brute_force_warp``, ``closed_form_warp`` and
+``tier_a_warp_py`` are the same three renderings of the warp-aware check
+(Theorem 1 with its warp clauses), over records plus one side word each
+(statement id, divergence bit).
 """
 from __future__ import annotations
 
@@ -102,6 +105,11 @@ def _load():
             f.restype = ctypes.c_int64
             f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64)]
+        for name in ("orc_brute_force_warp", "orc_closed_form_warp"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int64
+            f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]
         f = lib.orc_fitness_eval
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
@@ -173,6 +181,44 @@ def closed_form_par(records, offsets=None, tpb=None, threads=0, bucket_min=1 << 
     into location-hash buckets counted separately.  Same result as
     closed_form."""
     return _run("orc_closed_form_par", records, offsets, tpb, int(threads), int(bucket_min))
+
+
+SD_DIVERGED = 1 << 31  # side-word bit: the access ran while its warp was diverged
+
+
+def _run_warp(fname, records, side, offsets, tpb):
+    records, offsets, n_traces, tpb = _as_batch(records, offsets, tpb)
+    side = np.ascontiguousarray(np.asarray(side, dtype=np.uint32))
+    if len(side) != len(records):
+        raise ValueError("one side word per record")
+    lib = _load()
+    out = ctypes.c_void_p()
+    summ = np.zeros(max(n_traces, 1), dtype=SUMMARY_DTYPE)
+    bad = ctypes.c_uint64(0)
+    n = getattr(lib, fname)(records.ctypes.data if len(records) else None, side.ctypes.data if len(side) else None,
+                            offsets.ctypes.data, n_traces, tpb.ctypes.data, ctypes.byref(out), summ.ctypes.data,
+                            ctypes.byref(bad))
+    if n < 0:
+        raise OracleError(int(n), int(bad.value) if n == -2 else None)
+    races = np.zeros(n, dtype=RACE_DTYPE)
+    if n:
+        ctypes.memmove(races.ctypes.data, out.value, n * RACE_DTYPE.itemsize)
+    if out.value:
+        lib.orc_free(out)
+    return races, summ[:n_traces]
+
+
+def brute_force_warp(records, side, offsets=None, tpb=None):
+    """Warp-aware Tier A (Theorem 1 with clauses 1-3): every pair tested;
+    a same-warp pair races only when either record carries SD_DIVERGED or
+    both write by the same statement (side & ~SD_DIVERGED)."""
+    return _run_warp("orc_brute_force_warp", records, side, offsets, tpb)
+
+
+def closed_form_warp(records, side, offsets=None, tpb=None):
+    """Warp-aware Tier B: the plain group counts minus, per warp group, the
+    pairs that lockstep execution orders."""
+    return _run_warp("orc_closed_form_warp", records, side, offsets, tpb)
 
 
 def omp_threads():
@@ -312,6 +358,43 @@ def tier_a_py(records, tpb, trace=0):
                 continue
             if b1 == b2 and e1 != e2:  # a barrier of the block separates them
                 continue
+            key = (s1, b1 if s1 == 1 else None, u1)
+            d = out.setdefault(key, {"ww": 0, "rw": 0, "aw": 0, "ar": 0, "xblock": 0})
+            d[names[acts]] += 1
+            if b1 != b2:
+                d["xblock"] += 1
+    return out
+
+
+def tier_a_warp_py(records, side, tpb, trace=0):
+    """Pure-Python warp-aware rendering for one tiny trace, in the form of
+    tier_a_py.  Threads of one warp: same block, same block-local id // 32.
+    Such a pair is ordered by lockstep execution, and so does not race,
+    unless one of its accesses ran diverged or both are writes by one
+    statement."""
+    recs = [tuple(int(v) for v in r) for r in records]  # unit, tid, epoch, action, space
+    side = [int(v) for v in side]
+    out = {}
+    names = {frozenset(["W"]): "ww", frozenset(["R", "W"]): "rw",
+             frozenset(["A", "W"]): "aw", frozenset(["A", "R"]): "ar"}
+    letter = {0: "R", 1: "W", 2: "A"}
+    for i in range(len(recs)):
+        for j in range(i + 1, len(recs)):
+            u1, t1, e1, a1, s1 = recs[i]
+            u2, t2, e2, a2, s2 = recs[j]
+            b1, b2 = t1 // tpb, t2 // tpb
+            if s1 != s2 or u1 != u2 or (s1 == 1 and b1 != b2) or t1 == t2:
+                continue
+            acts = frozenset([letter[a1], letter[a2]])
+            if acts in (frozenset(["R"]), frozenset(["A"])):
+                continue
+            if b1 == b2 and e1 != e2:
+                continue
+            if b1 == b2 and (t1 % tpb) // 32 == (t2 % tpb) // 32:
+                diverged = bool((side[i] | side[j]) & SD_DIVERGED)
+                one_stmt_writes = a1 == 1 and a2 == 1 and (side[i] & ~SD_DIVERGED) == (side[j] & ~SD_DIVERGED)
+                if not diverged and not one_stmt_writes:
+                    continue
             key = (s1, b1 if s1 == 1 else None, u1)
             d = out.setdefault(key, {"ww": 0, "rw": 0, "aw": 0, "ar": 0, "xblock": 0})
             d[names[acts]] += 1

@@ -860,4 +860,263 @@ int orc_fitness_eval(const orc_record* recs, const uint64_t* off, uint32_t n_tra
   return ORC_OK;
 }
 
+/* ============ warp-aware race check (Theorem 1, clauses 1-3) ============
+ *
+ * Theorem 1, and the race loop of Alg. 5, refine the check for two threads
+ * of one warp (32 consecutive threads of a block execute in lockstep,
+ * Sec. 2): such a pair of accesses races only when the threads had
+ * undergone branch divergence (clause 3), or when both write by the same
+ * statement (clause 2); threads of different warps race as before
+ * (clause 1).  Every record comes with a side word: bits 0-30 name the
+ * statement (the static memory-access instruction) that made the access,
+ * bit 31 is set when the access ran while its warp was diverged.  A
+ * same-warp pair counts as having undergone divergence when either of its
+ * records carries the bit.  The warp of a thread is its block and its
+ * block-local id divided by 32 (CUDA's linear order within a block).
+ * Records of different blocks are in different warps, so the cross-block
+ * count equals the plain check's.
+ *
+ * Tier A (orc_brute_force_warp) adds the warp test to the pairwise
+ * definition.  Tier B (orc_closed_form_warp) takes the plain group counts
+ * and subtracts, per warp group g (the records of one location, block,
+ * epoch and warp), the pairs the lockstep rule removes: among the records
+ * of g without the divergence bit, the conflicting pairs of different
+ * threads, K_k(g0) - sum_t K_k(g0_t), except the write/write pairs of one
+ * statement, C2(w_{g0,s}) - sum_t C2(w_{g0,s,t}) summed over statements s,
+ * which stay races.  C2(m) = m(m-1)/2. */
+#define WARP_SIZE 32u
+#define SD_DIVERGED 0x80000000u
+
+static int same_warp(uint32_t t1, uint32_t t2, uint32_t T) {
+  return t1 / T == t2 / T && (t1 % T) / WARP_SIZE == (t2 % T) / WARP_SIZE;
+}
+
+int64_t orc_brute_force_warp(const orc_record* recs, const uint32_t* sd, const uint64_t* off, uint32_t n_traces,
+                             const uint32_t* tpb, orc_race** out, orc_summary* summary, uint64_t* bad_index) {
+  int rc = validate(recs, off, n_traces, tpb, bad_index);
+  if (rc) return rc;
+  if (n_traces && off[n_traces] && !sd) return ORC_EINVAL;
+  race_list hits = {0, 0, 0};
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t lo = off[tr], hi = off[tr + 1];
+    const uint32_t T = tpb[tr];
+    for (uint64_t i = lo; i < hi; i++) {
+      const orc_record* x = &recs[i];
+      const uint32_t bx = x->tid / T;
+      for (uint64_t j = i + 1; j < hi; j++) {
+        const orc_record* y = &recs[j];
+        const uint32_t by = y->tid / T;
+        if (x->space != y->space || x->unit != y->unit) continue;
+        if (x->space == 1 && bx != by) continue;
+        if (x->tid == y->tid) continue;
+        const int kind = kind_of(x->action, y->action);
+        if (kind < 0) continue;
+        if (!(bx != by || x->epoch == y->epoch)) continue;
+        /* one warp: lockstep orders the pair unless it diverged or both
+         * write by the same statement */
+        if (same_warp(x->tid, y->tid, T)) {
+          const int diverged = ((sd[i] | sd[j]) & SD_DIVERGED) != 0;
+          const int same_stmt_writes = x->action == 1 && y->action == 1 &&
+                                       (sd[i] & ~SD_DIVERGED) == (sd[j] & ~SD_DIVERGED);
+          if (!diverged && !same_stmt_writes) continue;
+        }
+        orc_race h;
+        memset(&h, 0, sizeof h);
+        h.trace = tr;
+        h.space = x->space;
+        h.block = x->space == 1 ? bx : 0xFFFFFFFFu;
+        h.unit = x->unit;
+        if (kind == KIND_WW) h.pairs_ww = 1;
+        if (kind == KIND_RW) h.pairs_rw = 1;
+        if (kind == KIND_AW) h.pairs_aw = 1;
+        if (kind == KIND_AR) h.pairs_ar = 1;
+        h.pairs_xblock = (bx != by) ? 1 : 0;
+        if (push(&hits, &h)) { free(hits.v); return ORC_ENOMEM; }
+      }
+    }
+  }
+  if (hits.n) qsort(hits.v, hits.n, sizeof(orc_race), cmp_entry);
+  race_list res = {0, 0, 0};
+  for (uint64_t i = 0; i < hits.n;) {
+    orc_race e = hits.v[i];
+    uint64_t j = i + 1;
+    while (j < hits.n && cmp_entry(&hits.v[j], &hits.v[i]) == 0) {
+      e.pairs_ww += hits.v[j].pairs_ww;
+      e.pairs_rw += hits.v[j].pairs_rw;
+      e.pairs_aw += hits.v[j].pairs_aw;
+      e.pairs_ar += hits.v[j].pairs_ar;
+      e.pairs_xblock += hits.v[j].pairs_xblock;
+      j++;
+    }
+    finish_entry(&e);
+    if (push(&res, &e)) { free(hits.v); free(res.v); return ORC_ENOMEM; }
+    i = j;
+  }
+  free(hits.v);
+  summarise(&res, off, n_traces, summary);
+  *out = res.v;
+  return (int64_t)res.n;
+}
+
+typedef struct {
+  item it;
+  uint32_t sd;
+} witem;
+
+static int cmp_witem(const void* pa, const void* pb) { return cmp_item(&((const witem*)pa)->it, &((const witem*)pb)->it); }
+
+/* (statement, thread) of a write, for the same-statement counts */
+typedef struct {
+  uint32_t stmt, tid;
+} stmt_tid;
+
+static int cmp_stmt_tid(const void* pa, const void* pb) {
+  const stmt_tid* a = (const stmt_tid*)pa;
+  const stmt_tid* b = (const stmt_tid*)pb;
+  if (a->stmt != b->stmt) return a->stmt < b->stmt ? -1 : 1;
+  if (a->tid != b->tid) return a->tid < b->tid ? -1 : 1;
+  return 0;
+}
+
+static uint64_t c2(uint64_t m) { return m ? m * (m - 1) / 2 : 0; }
+
+/* Pairs the lockstep rule removes from one warp group [i, j) (sorted by
+ * thread), by kind; st is scratch for j - i entries. */
+static void warp_group_removed(const witem* w, uint64_t i, uint64_t j, stmt_tid* st, uint64_t rem[4]) {
+  counts g0 = {0, 0, 0};
+  uint64_t sumT[4] = {0, 0, 0, 0}, tmp[4];
+  uint64_t nw = 0;
+  for (uint64_t a = i; a < j;) { /* thread groups */
+    uint64_t b = a;
+    counts t0 = {0, 0, 0};
+    while (b < j && w[b].it.tid == w[a].it.tid) {
+      if (!(w[b].sd & SD_DIVERGED)) {
+        add(&t0, w[b].it.action);
+        add(&g0, w[b].it.action);
+        if (w[b].it.action == 1) {
+          st[nw].stmt = w[b].sd & ~SD_DIVERGED;
+          st[nw].tid = w[b].it.tid;
+          nw++;
+        }
+      }
+      b++;
+    }
+    K(&t0, tmp);
+    for (int k = 0; k < 4; k++) sumT[k] += tmp[k];
+    a = b;
+  }
+  K(&g0, tmp);
+  for (int k = 0; k < 4; k++) rem[k] = tmp[k] - sumT[k];
+  /* write/write pairs of one statement from different threads stay races */
+  if (nw > 1) qsort(st, nw, sizeof(stmt_tid), cmp_stmt_tid);
+  uint64_t keep = 0;
+  for (uint64_t a = 0; a < nw;) {
+    uint64_t b = a;
+    while (b < nw && st[b].stmt == st[a].stmt) b++;
+    keep += c2(b - a);
+    for (uint64_t c = a; c < b;) {
+      uint64_t d = c;
+      while (d < b && st[d].tid == st[c].tid) d++;
+      keep -= c2(d - c);
+      c = d;
+    }
+    a = b;
+  }
+  rem[KIND_WW] -= keep;
+}
+
+static int count_sorted_warp(const witem* w, uint64_t n, uint32_t tr, uint32_t T, stmt_tid* st, race_list* res) {
+  uint64_t i = 0;
+  while (i < n) {
+    uint64_t iL = i;
+    counts cL = {0, 0, 0};
+    while (iL < n && same_loc(&w[iL].it, &w[i].it)) add(&cL, w[iL++].it.action);
+    uint64_t KL[4], SB[4] = {0, 0, 0, 0}, SE[4] = {0, 0, 0, 0}, ST[4] = {0, 0, 0, 0}, RM[4] = {0, 0, 0, 0};
+    uint64_t tmp[4];
+    K(&cL, KL);
+    for (uint64_t ib = i; ib < iL;) { /* block groups */
+      uint64_t jb = ib;
+      counts cB = {0, 0, 0};
+      while (jb < iL && w[jb].it.block == w[ib].it.block) add(&cB, w[jb++].it.action);
+      K(&cB, tmp);
+      for (int k = 0; k < 4; k++) SB[k] += tmp[k];
+      for (uint64_t ie = ib; ie < jb;) { /* epoch groups */
+        uint64_t je = ie;
+        counts cE = {0, 0, 0};
+        while (je < jb && w[je].it.epoch == w[ie].it.epoch) add(&cE, w[je++].it.action);
+        K(&cE, tmp);
+        for (int k = 0; k < 4; k++) SE[k] += tmp[k];
+        for (uint64_t itd = ie; itd < je;) { /* thread groups */
+          uint64_t jt = itd;
+          counts cT = {0, 0, 0};
+          while (jt < je && w[jt].it.tid == w[itd].it.tid) add(&cT, w[jt++].it.action);
+          K(&cT, tmp);
+          for (int k = 0; k < 4; k++) ST[k] += tmp[k];
+          itd = jt;
+        }
+        for (uint64_t iw = ie; iw < je;) { /* warp groups (threads sorted, so contiguous) */
+          uint64_t jw = iw;
+          while (jw < je && same_warp(w[jw].it.tid, w[iw].it.tid, T)) jw++;
+          warp_group_removed(w, iw, jw, st, tmp);
+          for (int k = 0; k < 4; k++) RM[k] += tmp[k];
+          iw = jw;
+        }
+        ie = je;
+      }
+      ib = jb;
+    }
+    uint64_t p[4], xb = 0;
+    for (int k = 0; k < 4; k++) {
+      p[k] = KL[k] - SB[k] + SE[k] - ST[k] - RM[k];
+      xb += KL[k] - SB[k];
+    }
+    if (p[0] + p[1] + p[2] + p[3] > 0) {
+      orc_race e;
+      memset(&e, 0, sizeof e);
+      e.trace = tr;
+      e.space = w[i].it.space;
+      e.block = w[i].it.lblock;
+      e.unit = w[i].it.unit;
+      e.pairs_ww = p[KIND_WW];
+      e.pairs_rw = p[KIND_RW];
+      e.pairs_aw = p[KIND_AW];
+      e.pairs_ar = p[KIND_AR];
+      e.pairs_xblock = xb;
+      finish_entry(&e);
+      if (push(res, &e)) return ORC_ENOMEM;
+    }
+    i = iL;
+  }
+  return ORC_OK;
+}
+
+int64_t orc_closed_form_warp(const orc_record* recs, const uint32_t* sd, const uint64_t* off, uint32_t n_traces,
+                             const uint32_t* tpb, orc_race** out, orc_summary* summary, uint64_t* bad_index) {
+  int rc = validate(recs, off, n_traces, tpb, bad_index);
+  if (rc) return rc;
+  if (n_traces && off[n_traces] && !sd) return ORC_EINVAL;
+  race_list res = {0, 0, 0};
+  uint64_t maxn = 0;
+  for (uint32_t tr = 0; tr < n_traces; tr++)
+    if (off[tr + 1] - off[tr] > maxn) maxn = off[tr + 1] - off[tr];
+  witem* w = maxn ? (witem*)malloc(maxn * sizeof(witem)) : NULL;
+  stmt_tid* st = maxn ? (stmt_tid*)malloc(maxn * sizeof(stmt_tid)) : NULL;
+  if (maxn && (!w || !st)) { free(w); free(st); return ORC_ENOMEM; }
+  for (uint32_t tr = 0; tr < n_traces; tr++) {
+    const uint64_t lo = off[tr], n = off[tr + 1] - off[tr];
+    const uint32_t T = tpb[tr];
+    for (uint64_t i = 0; i < n; i++) {
+      to_item(&recs[lo + i], T, &w[i].it);
+      w[i].sd = sd[lo + i];
+    }
+    if (n) qsort(w, n, sizeof(witem), cmp_witem);
+    if (count_sorted_warp(w, n, tr, T, st, &res)) { free(w); free(st); free(res.v); return ORC_ENOMEM; }
+  }
+  free(w);
+  free(st);
+  summarise(&res, off, n_traces, summary);
+  *out = res.v;
+  return (int64_t)res.n;
+}
+
 void orc_free(void* p) { free(p); }
