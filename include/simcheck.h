@@ -14,9 +14,10 @@
  *     or different blocks (a barrier synchronises one block only, Sec. 2);
  *   - at least one writes, and they are not both atomic (an atomic races
  *     with a plain read or write).
- * The warp clauses (1)-(3) of Theorem 1 are not applied (records carry no
- * statement or divergence data): every pair of distinct threads counts as
- * potentially concurrent.
+ * The warp clauses (1)-(3) of Theorem 1 are not applied by this check
+ * (records carry no statement or divergence data): every pair of distinct
+ * threads counts as potentially concurrent.  sim_check_traces_warp applies
+ * them to records that come with a side word of statement and divergence.
  *
  * For every racing location the library returns one entry with the exact
  * number of racing unordered record pairs by kind and the cross-block
@@ -203,6 +204,40 @@ int sim_check_traces_device_noalloc(sim_ctx* ctx, const sim_record* d_records, c
 
 /* Free a result.  NULL is ignored. */
 void sim_result_free(sim_result* r);
+
+/* ---------------------------------------------------- warp-aware check */
+
+/* Side word of a record for the warp-aware check: the statement (static
+ * memory-access instruction) that made the access in bits 0-30, and
+ * SIM_SIDE_DIVERGED when the access ran while its warp was diverged (some
+ * of the warp's threads on another control path).                         */
+#define SIM_SIDE_DIVERGED 0x80000000u
+
+/* The race check with the warp clauses of Theorem 1 (paper Sec. 4.2.3, and
+ * the race loop of Alg. 5): the 32 threads of a warp (threads of one block
+ * whose block-local ids agree after division by 32; Sec. 2) run in
+ * lockstep, so two accesses by different threads of one warp race only
+ * when the threads had diverged before them (either record carries
+ * SIM_SIDE_DIVERGED; clause 3) or both are writes by the same statement
+ * (clause 2).  Threads of different warps race as in sim_check_traces
+ * (clause 1); cross-block pairs are never in one warp.  The result has the
+ * form and order of sim_check_traces's, with the pair counts of this rule:
+ * a location whose racing pairs are all ordered by lockstep has no entry.
+ *   d_records, offsets, n_traces, threads_per_block, stream, out : as for
+ *                       sim_check_traces_device
+ *   d_side            : offsets[n_traces] side words, device memory of the
+ *                       context's GPU, caller-owned, one per record in the
+ *                       records' order
+ * Errors and ownership as for sim_check_traces_device.  The statement ids
+ * widen the sort key by 1 + log2 of the largest id bits.                  */
+int sim_check_traces_warp_device(sim_ctx* ctx, const sim_record* d_records, const uint32_t* d_side,
+                                 const uint64_t* offsets, uint32_t n_traces, const uint32_t* threads_per_block,
+                                 void* stream, sim_result** out);
+
+/* The same for records and side words in host memory (copied to the
+ * device first). */
+int sim_check_traces_warp(sim_ctx* ctx, const sim_record* records, const uint32_t* side, const uint64_t* offsets,
+                          uint32_t n_traces, const uint32_t* threads_per_block, sim_result** out);
 
 /* ------------------------------------------------------ redundant barriers */
 

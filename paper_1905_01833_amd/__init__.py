@@ -44,12 +44,12 @@ STAGES = ["init", "stats", "layout", "keygen", "upsweep", "sort_pass", "scan_til
 # Symbols declared in include/simcheck.h.
 EXPORTS = [
     "sim_create", "sim_destroy", "sim_last_error", "sim_check_traces", "sim_check_traces_device",
-    "sim_check_traces_device_noalloc", "sim_result_free", "sim_check_sync_device", "sim_check_sync",
-    "sim_barrier_result_free", "sim_eval_fitness_device", "sim_eval_fitness", "sim_check_divergence_device", "sim_check_divergence",
-    "sim_divergence_result_free", "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning",
-    "sim_get_tuning", "sim_autotune", "sim_server_create", "sim_server_destroy", "sim_submit", "sim_submit_device",
-    "sim_poll",
-    "sim_wait", "sim_server_get_stats", "sim_server_last_error",
+    "sim_check_traces_device_noalloc", "sim_result_free", "sim_check_traces_warp_device", "sim_check_traces_warp",
+    "sim_check_sync_device", "sim_check_sync", "sim_barrier_result_free", "sim_eval_fitness_device",
+    "sim_eval_fitness", "sim_check_divergence_device", "sim_check_divergence", "sim_divergence_result_free",
+    "sim_stage_times", "sim_stage_name", "sim_size_class", "sim_set_tuning", "sim_get_tuning", "sim_autotune",
+    "sim_server_create", "sim_server_destroy", "sim_submit", "sim_submit_device", "sim_poll", "sim_wait",
+    "sim_server_get_stats", "sim_server_last_error",
 ]
 SIM_EAGAIN = -5
 SIM_SIZE_CLASSES = 33
@@ -164,6 +164,11 @@ def load() -> ctypes.CDLL:
                                    ctypes.POINTER(ctypes.POINTER(_BarrierResult))]
     lib.sim_barrier_result_free.restype = None
     lib.sim_barrier_result_free.argtypes = [ctypes.POINTER(_BarrierResult)]
+    lib.sim_check_traces_warp_device.restype = ctypes.c_int
+    lib.sim_check_traces_warp_device.argtypes = [P, P, P, P, ctypes.c_uint32, P, P,
+                                                 ctypes.POINTER(ctypes.POINTER(_Result))]
+    lib.sim_check_traces_warp.restype = ctypes.c_int
+    lib.sim_check_traces_warp.argtypes = [P, P, P, P, ctypes.c_uint32, P, ctypes.POINTER(ctypes.POINTER(_Result))]
     lib.sim_eval_fitness_device.restype = ctypes.c_int
     lib.sim_eval_fitness_device.argtypes = [P, P, P, ctypes.c_uint32, P, P, P]
     lib.sim_eval_fitness.restype = ctypes.c_int
@@ -284,6 +289,46 @@ def sim_check_traces_device(ctx, d_records_ptr: int, n_records: int, offsets=Non
     out = ctypes.POINTER(_Result)()
     rc = lib.sim_check_traces_device(ctx, ctypes.c_void_p(d_records_ptr) if n_records else None, offsets.ctypes.data,
                                      n_traces, tpb.ctypes.data, ctypes.c_void_p(stream or 0), ctypes.byref(out))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return _take_result(out)
+
+
+SIM_SIDE_DIVERGED = 1 << 31  # side-word bit: the access ran while its warp was diverged
+
+
+def sim_check_traces_warp(ctx, records: np.ndarray, side: np.ndarray, offsets=None, threads_per_block=1):
+    """Warp-aware check of host records; side: one uint32 per record
+    (statement id, SIM_SIDE_DIVERGED)."""
+    lib = load()
+    records = np.ascontiguousarray(records)
+    side = np.ascontiguousarray(np.asarray(side, dtype=np.uint32))
+    if records.dtype.itemsize != 16:
+        raise TypeError("records must be 16-byte sim_record entries")
+    if len(side) != len(records):
+        raise ValueError("one side word per record")
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, len(records))
+    out = ctypes.POINTER(_Result)()
+    rc = lib.sim_check_traces_warp(ctx, records.ctypes.data if len(records) else None,
+                                   side.ctypes.data if len(side) else None, offsets.ctypes.data, n_traces,
+                                   tpb.ctypes.data, ctypes.byref(out))
+    if rc != SIM_OK:
+        raise SimError(rc, sim_last_error(ctx))
+    return _take_result(out)
+
+
+def sim_check_traces_warp_device(ctx, d_records_ptr: int, d_side_ptr: int, n_records: int, offsets=None,
+                                 threads_per_block=1, stream=None):
+    """Warp-aware check of device records, with one device side word per
+    record at d_side_ptr."""
+    lib = load()
+    offsets, n_traces, tpb = _tables(offsets, threads_per_block, n_records)
+    if int(offsets[-1]) != n_records:
+        raise ValueError("offsets[-1] must equal the number of device records")
+    out = ctypes.POINTER(_Result)()
+    rc = lib.sim_check_traces_warp_device(ctx, ctypes.c_void_p(d_records_ptr) if n_records else None,
+                                          ctypes.c_void_p(d_side_ptr) if n_records else None, offsets.ctypes.data,
+                                          n_traces, tpb.ctypes.data, ctypes.c_void_p(stream or 0), ctypes.byref(out))
     if rc != SIM_OK:
         raise SimError(rc, sim_last_error(ctx))
     return _take_result(out)
@@ -548,6 +593,19 @@ class Context:
         (16 bytes each, e.g. uint8 [n, 16] or int64 [n, 2])."""
         ptr, n, stream = self._device_args(tensor, stream)
         return sim_check_traces_device(self._ctx, ptr, n, offsets, threads_per_block, stream)
+
+    def check_traces_warp(self, records, side, offsets=None, threads_per_block=1):
+        """Warp-aware check of host records (side: uint32 per record)."""
+        return sim_check_traces_warp(self._ctx, records, side, offsets, threads_per_block)
+
+    def check_traces_warp_device(self, tensor, side_tensor, offsets=None, threads_per_block=1, stream=None):
+        """Warp-aware check of a device tensor of records, with a device
+        tensor of one uint32 side word per record."""
+        ptr, n, stream = self._device_args(tensor, stream)
+        if side_tensor.numel() * side_tensor.element_size() != 4 * n:
+            raise ValueError("one 4-byte side word per record")
+        return sim_check_traces_warp_device(self._ctx, ptr, side_tensor.data_ptr(), n, offsets, threads_per_block,
+                                            stream)
 
     def check_sync(self, records, offsets=None, threads_per_block=1):
         """Races and barrier instances of host records."""

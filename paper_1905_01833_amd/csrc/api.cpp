@@ -59,6 +59,8 @@ struct sim_ctx {
   bool wide_guess = false;  // the previous call had a trace needing two-word keys
   uint32_t fit_pass_guess = 0;  // the same for the fitness count, whose keys are shorter
   bool fit_wide_guess = false;
+  uint32_t warp_pass_guess = 0;  // ... and for the warp-aware check, whose keys are longer
+  bool warp_wide_guess = false;
   uint64_t alloc_gen = 0;   // bumped whenever a device buffer is reallocated
 
   // one captured launch sequence, replayed while calls keep the same shape
@@ -85,6 +87,9 @@ struct sim_ctx {
   // per-block results, per-chunk counts and offsets, divergent blocks
   DevBuf div_in, div_chunks, div_blocks, div_cnt, div_off, div_out;
   DevBuf fit_out;  // the fitness count's rows
+  // the warp-aware check: side words of host calls, removed pairs per entry,
+  // refined entries, their number
+  DevBuf side, warp_rm, warp_out, warp_n;
   void* h_div = nullptr;  // pinned: the chunk table, then the divergent-block count
   size_t h_div_cap = 0;
   uint64_t dev_limit = 0;  // device bytes the buffers may hold (0: no limit; set by a server's worker)
@@ -106,7 +111,7 @@ std::vector<DevBuf*> all_bufs(sim_ctx* c) {
   return {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist, &c->gtot,
           &c->gbase,   &c->agg,   &c->tout,  &c->cross, &c->cross_flag, &c->group_sum, &c->stage,
           &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base, &c->div_in, &c->div_chunks, &c->div_blocks,
-          &c->div_cnt, &c->div_off, &c->div_out, &c->fit_out};
+          &c->div_cnt, &c->div_off, &c->div_out, &c->fit_out, &c->side, &c->warp_rm, &c->warp_out, &c->warp_n};
 }
 
 int fail(sim_ctx* c, int code, const char* fmt, ...) {
@@ -353,6 +358,7 @@ struct Sink {
   sim_trace_summary* traces = nullptr;
   sim_barrier_result** barriers = nullptr;  // also the redundant-barrier check
   sim_fitness* fitness = nullptr;           // instead of the race check: the EP fitness rows (host, n_traces)
+  const uint32_t* side = nullptr;           // the warp-aware check: one side word per record (device)
 };
 
 void barrier_result_free(sim_barrier_result* r) {
@@ -388,6 +394,12 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   for (auto& t : c->times) t = sim_stage_time{0.0, 0, 0};
   const bool fit = sink.fitness != nullptr;
   if (fit && noalloc) return fail(c, SIM_EINVAL, "the fitness count has no no-allocation form");
+  const bool warp = sink.side != nullptr;
+  if (warp && (noalloc || trace_recs || fit || sink.barriers))
+    return fail(c, SIM_EINVAL, "the warp-aware check runs on its own, on adjacent device records");
+  // radix passes and key width the previous call of this kind needed
+  uint32_t& pass_guess = fit ? c->fit_pass_guess : (warp ? c->warp_pass_guess : c->pass_guess);
+  bool& wide_guess = fit ? c->fit_wide_guess : (warp ? c->warp_wide_guess : c->wide_guess);
 
   // result delivery: summaries from the entry list, entries downloaded from
   // `dev_out` (n_races of them)
@@ -477,7 +489,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   GroupRef* hg = (GroupRef*)(ht + n_tiles);
   uint32_t* hs = (uint32_t*)(hg + n_hgroups64);
   // traces sorted whole in LDS: one tile, or up to four with one-word keys
-  const bool wide = fit ? c->fit_wide_guess : c->wide_guess;
+  const bool wide = wide_guess;
   const uint32_t small_max_tiles = wide ? 1u : 4u;
   uint32_t t0 = 0, g0 = 0, max_group_tiles = 1, max_trace_groups = 1, n_small1 = 0, n_small4 = 0;
   for (uint32_t i = 0; i < n_traces; i++) {
@@ -556,6 +568,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   b.wide = wide ? 1u : 0u;
   b.key_bytes = key_bytes;
   b.fitness = fit ? 1u : 0u;
+  b.side = warp ? sink.side : nullptr;
   b.groups = (const GroupRef*)(b.tiles + n_tiles);
   b.small_traces = (const uint32_t*)(b.groups + n_hgroups);
   b.n_small1 = n_small1;
@@ -586,7 +599,8 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   // radix digit 0 is tid mod 256 when threads per block is a power of two
   // >= 256 (the local-tid field then fills key bits [2, 10)): stats build
   // its histograms and key generation does pass 0
-  b.fuse0 = 1;
+  // (not with a side field, which takes the key's lowest bits above the action)
+  b.fuse0 = warp ? 0 : 1;
   for (uint32_t i = 0; i < n_traces; i++)
     if (tpb[i] < 256 || (tpb[i] & (tpb[i] - 1)) != 0) b.fuse0 = 0;
   // a call of one-tile traces only is sorted in LDS from pass 0 on, with no
@@ -652,7 +666,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   };
 
   // (a call of one-tile traces has all its passes done before the scan)
-  const uint32_t prev_guess = fit ? c->fit_pass_guess : c->pass_guess;
+  const uint32_t prev_guess = pass_guess;
   const uint32_t guess = all_small ? MAX_PASSES : (prev_guess < MAX_PASSES ? prev_guess : MAX_PASSES);
   int first_scan_ev = 0;  // events of the first round before its scan
   auto first_round = [&]() -> hipError_t {
@@ -677,7 +691,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   // whose record addresses are not part of the shape, nor for calls that
   // may not allocate: instantiating a graph does.)
   const bool use_graph =
-      (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0 && !trace_recs && !noalloc && !fit;
+      (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0 && !trace_recs && !noalloc && !fit && !warp;
   uint64_t th = 1469598103934665603ull;  // FNV-1a over the per-call tables
   if (use_graph) {
     const unsigned char* q = (const unsigned char*)offsets;
@@ -734,7 +748,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   if (ctl.error_flags & ERR_NEEDS_WIDE) {
     // a trace needs two-word keys: run the whole call again in that mode
     // (the next call starts in it while its traces keep needing it)
-    (fit ? c->fit_wide_guess : c->wide_guess) = true;
+    wide_guess = true;
     return run(c, d_records, trace_recs, offsets, n_traces, tpb, s, sink, noalloc);
   }
   const uint32_t needed = ctl.max_passes;
@@ -746,9 +760,9 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       return hip_fail(c, e, "pipeline");
     ctl = *c->h_ctrl;
   }
-  if (!all_small) (fit ? c->fit_pass_guess : c->pass_guess) = needed;  // an LDS-sorted call tells nothing
+  if (!all_small) pass_guess = needed;  // an LDS-sorted call tells nothing
                                                                        // about global passes
-  (fit ? c->fit_wide_guess : c->wide_guess) = ctl.wide_traces > 0;
+  wide_guess = ctl.wide_traces > 0;
   if (fit) {
     if (ctl.error_flags) return fail(c, SIM_EDEVICE, "internal kernel check failed (flags 0x%x)", ctl.error_flags);
     if ((e = hipMemcpyAsync(sink.fitness, fit_out, (size_t)n_traces * sizeof(FitOut), hipMemcpyDeviceToHost, s)) ||
@@ -831,6 +845,23 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       c->times[ev_stage[k]].ms += ms;
       c->times[ev_stage[k]].launches += 1;
     }
+  }
+  if (warp) {
+    // Theorem 1's warp clauses: subtract the pairs lockstep orders, keep
+    // the entries left with a pair
+    if ((e = grow(c, c->warp_rm, (size_t)(n_races ? n_races : 1) * 4 * sizeof(uint64_t))) ||
+        (e = grow(c, c->warp_out, (size_t)(n_races ? n_races : 1) * sizeof(RaceOut))) ||
+        (e = grow(c, c->warp_n, sizeof(uint64_t))))
+      return hip_fail(c, e, "device allocation");
+    uint64_t n_ref = 0;
+    if ((e = launch_warp_refine(b, b.out, n_races, (unsigned long long*)c->warp_rm.p, (RaceOut*)c->warp_out.p,
+                                (unsigned long long*)c->warp_n.p, s)) ||
+        (e = hipMemcpyAsync(&n_ref, c->warp_n.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s)) ||
+        (e = sync_ctrl()))
+      return hip_fail(c, e, "warp refinement");
+    if (c->h_ctrl->error_flags)
+      return fail(c, SIM_EDEVICE, "internal kernel check failed (flags 0x%x)", c->h_ctrl->error_flags);
+    return deliver(n_ref, c->warp_out.p);
   }
   if (!sink.barriers) return deliver(n_races, b.out);
 
@@ -1178,6 +1209,57 @@ int sim_check_traces(sim_ctx* c, const sim_record* records, const uint64_t* offs
   }
   Sink sink;
   sink.out = out;
+  return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink,
+             false);
+}
+
+int sim_check_traces_warp_device(sim_ctx* c, const sim_record* d_records, const uint32_t* d_side,
+                                 const uint64_t* offsets, uint32_t n_traces, const uint32_t* threads_per_block,
+                                 void* stream, sim_result** out) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (out) *out = nullptr;
+  uint64_t total = 0;
+  uint32_t n_tiles = 0;
+  int rc = validate(c, offsets, n_traces, threads_per_block, out, &total, &n_tiles);
+  if (rc) return rc;
+  if (total && !d_side) return fail(c, SIM_EINVAL, "side is NULL");
+  if (!total) {  // no records: the plain check's empty result
+    Sink sink;
+    sink.out = out;
+    DeviceGuard g(c->device);
+    return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink, false);
+  }
+  DeviceGuard g(c->device);
+  Sink sink;
+  sink.out = out;
+  sink.side = d_side;
+  return run(c, d_records, nullptr, offsets, n_traces, threads_per_block, (hipStream_t)stream, sink, false);
+}
+
+int sim_check_traces_warp(sim_ctx* c, const sim_record* records, const uint32_t* side, const uint64_t* offsets,
+                          uint32_t n_traces, const uint32_t* threads_per_block, sim_result** out) {
+  if (!c) return SIM_EINVAL;
+  c->err.clear();
+  if (out) *out = nullptr;
+  DeviceGuard g(c->device);
+  uint64_t total = 0;
+  uint32_t n_tiles = 0;
+  int rc = validate(c, offsets, n_traces, threads_per_block, out, &total, &n_tiles);
+  if (rc) return rc;
+  if (total && (!records || !side)) return fail(c, SIM_EINVAL, "records or side is NULL");
+  if (total) {
+    hipError_t e = ensure(c->records, total * sizeof(sim_record));
+    if (e == hipSuccess) e = ensure(c->side, total * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(c, e, "device allocation");
+    e = hipMemcpyAsync(c->records.p, records, total * sizeof(sim_record), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->side.p, side, total * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "record upload");
+  }
+  Sink sink;
+  sink.out = out;
+  sink.side = total ? (const uint32_t*)c->side.p : nullptr;
   return run(c, (const sim_record*)c->records.p, nullptr, offsets, n_traces, threads_per_block, c->stream, sink,
              false);
 }

@@ -236,12 +236,12 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool val
 template <bool LOOP, bool HIST, int NTH = NT>
 __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles, uint32_t n_tiles,
                                                TraceStats* __restrict__ part, uint32_t* __restrict__ thist,
-                                               Ctrl* ctrl) {
+                                               Ctrl* ctrl, const uint32_t* __restrict__ side) {
   constexpr int IT = TILE / NTH, NW = NTH / 64;
   static_assert(NTH >= (int)RADIX, "one thread per histogram bin");
   __shared__ uint64_t s64[5][NW];
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl_reset(ctrl);
-  __shared__ uint32_t s32[2][NW];
+  __shared__ uint32_t s32[3][NW];
   __shared__ uint32_t h[RADIX];
   const TileWalk tw = tile_walk(n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
@@ -253,7 +253,9 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
     const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
     const ulonglong2* p = (const ulonglong2*)tr.rec;
     uint64_t gmin = ~0ull, gmax = 0, smin = ~0ull, smax = 0, bad = ~0ull;
-    uint32_t mt = 0, me = 0;
+    uint32_t mt = 0, me = 0, ms = 0;
+    if (side)  // warp-aware check: the largest statement id sizes the key's side field
+      for (uint32_t j = tx; j < n_in; j += NTH) ms = max(ms, side[tr.first + j] & ~SIDE_DIVERGED);
     if (HIST) {
       if (tx < RADIX) h[tx] = 0;
       __syncthreads();
@@ -289,11 +291,11 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
     }
     gmin = wave_min(gmin); smin = wave_min(smin); bad = wave_min(bad);
     gmax = wave_max(gmax); smax = wave_max(smax);
-    mt = wave_max(mt); me = wave_max(me);
+    mt = wave_max(mt); me = wave_max(me); ms = wave_max(ms);
     const uint32_t lane = tx & 63u, wave = tx >> 6;
     if (lane == 0) {
       s64[0][wave] = gmin; s64[1][wave] = gmax; s64[2][wave] = smin; s64[3][wave] = smax; s64[4][wave] = bad;
-      s32[0][wave] = mt; s32[1][wave] = me;
+      s32[0][wave] = mt; s32[1][wave] = me; s32[2][wave] = ms;
     }
     __syncthreads();
     if (tx == 0) {
@@ -301,11 +303,11 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
         gmin = min(gmin, s64[0][w]); gmax = max(gmax, s64[1][w]);
         smin = min(smin, s64[2][w]); smax = max(smax, s64[3][w]);
         bad = min(bad, s64[4][w]);
-        mt = max(mt, s32[0][w]); me = max(me, s32[1][w]);
+        mt = max(mt, s32[0][w]); me = max(me, s32[1][w]); ms = max(ms, s32[2][w]);
       }
       TraceStats S;
       S.gmin = gmin; S.gmax = gmax; S.smin = smin; S.smax = smax; S.bad_index = bad;
-      S.max_tid = mt; S.max_epoch = me;
+      S.max_tid = mt; S.max_epoch = me; S.max_stmt = ms; S.pad = 0;
       part[tile] = S;
     }
     if (HIST && tx < RADIX) thist[(uint64_t)tile * RADIX + tx] = h[tx];
@@ -326,10 +328,10 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
 template <int NTH = NT>
 __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ desc,
                                                 const TraceStats* __restrict__ part, TraceLayout* lay, Ctrl* ctrl,
-                                                uint32_t wide_call, uint32_t fitness) {
+                                                uint32_t wide_call, uint32_t fitness, uint32_t warp) {
   constexpr int NW = NTH / 64;
   __shared__ uint64_t s64[5][NW];
-  __shared__ uint32_t s32[2][NW];
+  __shared__ uint32_t s32[3][NW];
   const uint32_t t = blockIdx.x;
   const TraceDesc T = desc[t];
   TraceStats S;
@@ -340,14 +342,15 @@ __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ de
     S.smin = min(S.smin, P.smin); S.smax = max(S.smax, P.smax);
     S.bad_index = min(S.bad_index, P.bad_index);
     S.max_tid = max(S.max_tid, P.max_tid); S.max_epoch = max(S.max_epoch, P.max_epoch);
+    S.max_stmt = max(S.max_stmt, P.max_stmt);
   }
   S.gmin = wave_min(S.gmin); S.smin = wave_min(S.smin); S.bad_index = wave_min(S.bad_index);
   S.gmax = wave_max(S.gmax); S.smax = wave_max(S.smax);
-  S.max_tid = wave_max(S.max_tid); S.max_epoch = wave_max(S.max_epoch);
+  S.max_tid = wave_max(S.max_tid); S.max_epoch = wave_max(S.max_epoch); S.max_stmt = wave_max(S.max_stmt);
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   if (lane == 0) {
     s64[0][wave] = S.gmin; s64[1][wave] = S.gmax; s64[2][wave] = S.smin; s64[3][wave] = S.smax;
-    s64[4][wave] = S.bad_index; s32[0][wave] = S.max_tid; s32[1][wave] = S.max_epoch;
+    s64[4][wave] = S.bad_index; s32[0][wave] = S.max_tid; s32[1][wave] = S.max_epoch; s32[2][wave] = S.max_stmt;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -356,9 +359,10 @@ __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ de
     S.smin = min(S.smin, s64[2][w]); S.smax = max(S.smax, s64[3][w]);
     S.bad_index = min(S.bad_index, s64[4][w]);
     S.max_tid = max(S.max_tid, s32[0][w]); S.max_epoch = max(S.max_epoch, s32[1][w]);
+    S.max_stmt = max(S.max_stmt, s32[2][w]);
   }
   if (fitness) S.max_epoch = 0;  // fitness keys hold no epoch (and no action)
-  TraceLayout L = make_layout(S, T.tpb);
+  TraceLayout L = make_layout(S, T.tpb, warp != 0);
   if (T.n == 0) {
     L.error = 0;
     L.npasses = 0;
@@ -538,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
         if (valid) {
           const Rec x = unpack_rec(vr[r]);
           k = make_key_t<K, decltype(blk_form)::value>(L, x.unit, x.tid, x.epoch & keep, x.action & keep, x.space,
-                                                        T.tpb);
+                                                        T.tpb, b.side ? b.side[tr.first + j] : 0u);
           kout[j] = k;
         }
         wave_hist_add(h, (uint32_t)(k >> 2) & (RADIX - 1), valid);
@@ -1079,8 +1083,9 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     //      last head at that level or coarser.  Their difference, widened to
     //      the 16-bit fields of the block scan, is the thread's aggregate.
     uint64_t aggA[4];
+    uint32_t mn = NO_HEAD;  // the thread's smallest head level
     {
-      uint32_t cnt = 0, snap[4] = {0u, 0u, 0u, 0u}, mn = NO_HEAD;
+      uint32_t cnt = 0, snap[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
@@ -1130,50 +1135,29 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         r2 += inc;
       }
     }
-    // ---- lead data: the class counts before the tile's first head at each
-    //      level, and the pairs of the elements before its first location
-    //      head.  Only threads before that head hold such elements; they
-    //      walk their items again (a separate loop keeps the registers of
-    //      the main pass low).
-    if ((exA[0] & SEGF) == 0) {
-      uint64_t run[4];
-      bool seen[4];
+    // ---- lead counts: per level, the class counts of the tile's elements
+    //      before its first head at that level or coarser.  The thread that
+    //      holds that head adds the counts carried into it (exA) and those of
+    //      its own elements before the head; a level without a head in the
+    //      tile takes the tile's totals (in the summary).  The pair sums of
+    //      those elements are added by the pair pass below: only threads
+    //      with an in-tile racing partner have any.
 #pragma unroll
-      for (int l = 0; l < 4; l++) {
-        run[l] = exA[l] & ~SEGF;
-        seen[l] = (exA[l] & SEGF) != 0;
-      }
-      uint32_t leadc[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      uint32_t leads[5] = {0, 0, 0, 0, 0};
+    for (int l = 0; l < 4; l++) {
+      if ((exA[l] & SEGF) == 0 && mn <= (uint32_t)l) {
+        uint32_t cr = cnt16(exA[l], CLS_R), cw = cnt16(exA[l], CLS_W), ca = cnt16(exA[l], CLS_A);
 #pragma unroll 1
-      for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
-        const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
-#pragma unroll
-        for (int l = 0; l < 4; l++)
-          if (lv <= (uint32_t)l) {
-            run[l] = 0;
-            seen[l] = true;
-          }
-        if (seen[0]) break;  // a location head: nothing after it is lead
-        if (c == CLS_NONE) continue;
-        uint32_t v[5];
-        tile_pairs(c, run, v);
-#pragma unroll
-        for (int l = 0; l < 4; l++)
-          if (!seen[l]) leadc[l][c]++;
-#pragma unroll
-        for (int k = 0; k < 5; k++) leads[k] += v[k];
-#pragma unroll
-        for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
+        for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
+          const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
+          if (lv <= (uint32_t)l) break;
+          cr += c == CLS_R ? 1u : 0u;
+          cw += c == CLS_W ? 1u : 0u;
+          ca += c == CLS_A ? 1u : 0u;
+        }
+        s_lead[l * 3 + CLS_R] = cr;
+        s_lead[l * 3 + CLS_W] = cw;
+        s_lead[l * 3 + CLS_A] = ca;
       }
-#pragma unroll
-      for (int l = 0; l < 4; l++)
-#pragma unroll
-        for (int q = 0; q < 3; q++)
-          if (leadc[l][q]) atomicAdd(&s_lead[l * 3 + q], leadc[l][q]);
-#pragma unroll
-      for (int k = 0; k < 5; k++)
-        if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
     }
     if (hit) s_hit = 1u;
     __syncthreads();  // s_hit and s_lead are complete after it
@@ -1194,6 +1178,8 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         uint64_t run[4];
 #pragma unroll
         for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
+        bool lead = (exA[0] & SEGF) == 0;  // before the tile's first location head
+        uint32_t leads[5] = {0u, 0u, 0u, 0u, 0u};
 #pragma unroll 1
         for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
           const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
@@ -1203,6 +1189,11 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
           if (c == CLS_NONE) continue;
           uint32_t v[5];
           tile_pairs(c, run, v);
+          if (lv == 0) lead = false;
+          if (lead) {
+#pragma unroll
+            for (int k = 0; k < 5; k++) leads[k] += v[k];
+          }
           if (lv == 0) aggB[0] = aggB[1] = aggB[2] = SEGF;
           aggB[0] += (uint64_t)v[K_WW] | ((uint64_t)v[K_RW] << 32);
           aggB[1] += (uint64_t)v[K_AW] | ((uint64_t)v[K_AR] << 32);
@@ -1223,6 +1214,9 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
             pend1 = aggB[1];
           }
         }
+#pragma unroll
+        for (int k = 0; k < 5; k++)
+          if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
       } else if (ITEMS * tid < n_in) {
         // every pair sum of this thread is zero: only its location heads
         // and whether its first location ends in it matter
@@ -1253,7 +1247,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
       for (int l = 0; l < 4; l++)
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-          agg.lead[l][q] = s_lead[l * 3 + q];
+          agg.lead[l][q] = (totA[l] & SEGF) ? s_lead[l * 3 + q] : cnt16(totA[l], q);
           agg.trail[l][q] = cnt16(totA[l], q);
         }
 #pragma unroll
@@ -1751,6 +1745,128 @@ __global__ __launch_bounds__(NT) void k_div_emit(const DivChunk* __restrict__ ch
   }
 }
 
+// ------------------------------------------------- warp refinement
+//
+// Theorem 1's warp clauses (and the race loop of Alg. 5): two accesses by
+// threads of one warp (32 threads of a block, by block-local id) are
+// ordered by lockstep execution, and so do not race, unless one of them ran
+// diverged or both are writes by one statement.  The plain count over the
+// sorted keys includes such pairs.  The keys of a warp-aware call carry the
+// side field (keys.h), so the records of one (location, block, epoch, warp)
+// -- a warp group -- are adjacent, and every element without the divergence
+// bit counts, against the earlier elements of its warp group, the pairs the
+// plain count has and lockstep removes: another thread, no divergence bit, a
+// conflicting action, and not two writes of one statement.  An element with
+// such pairs finds its location's entry in the plain result (entries are in
+// key order) and subtracts them there.  Warp groups are short, a few records
+// each, except where a warp hammers one word within one barrier interval.
+
+__device__ __forceinline__ int entry_cmp(const RaceOut& e, uint32_t trace, uint32_t space, uint32_t block,
+                                         uint64_t unit) {
+  if (e.trace != trace) return e.trace < trace ? -1 : 1;
+  if (e.space != space) return e.space < space ? -1 : 1;
+  if (e.block != block) return e.block < block ? -1 : 1;
+  if (e.unit != unit) return e.unit < unit ? -1 : 1;
+  return 0;
+}
+
+// Kind of a conflicting pair of classes (K_WW .. K_AR), or 4 if they do not
+// conflict (two reads, two atomics).
+__device__ __forceinline__ uint32_t pair_kind(uint32_t c1, uint32_t c2) {
+  const uint32_t lo = min(c1, c2), hi = max(c1, c2);
+  if (lo == CLS_W) return hi == CLS_W ? (uint32_t)K_WW : (uint32_t)K_AW;
+  if (lo == CLS_R) return hi == CLS_W ? (uint32_t)K_RW : (hi == CLS_A ? (uint32_t)K_AR : 4u);
+  return 4u;
+}
+
+template <typename K, bool LOOP>
+__global__ __launch_bounds__(NT) void k_warp_removed(Buffers b, const RaceOut* __restrict__ entries,
+                                                     uint64_t n_entries, unsigned long long* __restrict__ removed) {
+  if (b.ctrl->error_flags) return;
+  const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
+  for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
+    uint32_t tx = threadIdx.x;
+    if (LOOP) asm volatile("" : "+v"(tx));  // per tile: keeps per-item offsets from being hoisted
+    const TileRef tr = b.tiles[tile];
+    const TraceDesc T = b.desc[tr.trace];
+    const TraceLayout L = b.layout[tr.trace];
+    const K* keys = (const K*)b.keys[L.npasses & 1u] + T.off;  // the trace's sorted keys
+    const uint64_t start = (uint64_t)tr.local * TILE;
+    const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
+    const uint32_t wshift = 2 + L.sb + min(L.tb, 5u);  // the bits above: location, block, epoch, warp
+#pragma unroll 1
+    for (int r = 0; r < ITEMS; r++) {
+      const uint32_t j = tx + r * NT;
+      if (j >= n_in) break;
+      const uint64_t p = start + j;
+      const K x = keys[p];
+      if (key_diverged_t<K>(L, x)) continue;
+      const uint32_t cx = action_class(x), lx = key_ltid_t<K>(L, x), sx = key_stmt_t<K>(L, x);
+      const K gx = x >> wshift;
+      uint64_t rm[4] = {0, 0, 0, 0};
+      for (uint64_t q = p; q > 0; q--) {
+        const K y = keys[q - 1];
+        if ((y >> wshift) != gx) break;  // the start of x's warp group
+        if (key_diverged_t<K>(L, y) || key_ltid_t<K>(L, y) == lx) continue;
+        const uint32_t cy = action_class(y), kd = pair_kind(cx, cy);
+        if (kd == 4u) continue;
+        if (kd == (uint32_t)K_WW && key_stmt_t<K>(L, y) == sx) continue;  // one statement's writes still race
+        rm[kd]++;
+      }
+      if ((rm[0] | rm[1] | rm[2] | rm[3]) == 0) continue;
+      uint32_t sp, blk;
+      uint64_t unit;
+      key_location_t<K>(L, x, sp, blk, unit);
+      uint64_t lo = 0, hi = n_entries;  // first entry not below x's location
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (entry_cmp(entries[mid], tr.trace, sp, blk, unit) < 0) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo == n_entries || entry_cmp(entries[lo], tr.trace, sp, blk, unit) != 0) {
+        atomicOr(&b.ctrl->error_flags, ERR_INTERNAL_BOUNDS);  // lockstep only removes pairs the plain count has
+        continue;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (rm[k]) atomicAdd(&removed[lo * 4 + k], (unsigned long long)rm[k]);
+    }
+  }
+}
+
+// One workgroup: every entry minus its removed pairs; entries left with a
+// pair are written to `out` in order, with their kinds bits; *n_out gets
+// their number.
+__global__ __launch_bounds__(4 * NT) void k_warp_finish(const RaceOut* __restrict__ in, uint64_t n,
+                                                        const unsigned long long* __restrict__ removed,
+                                                        RaceOut* __restrict__ out, unsigned long long* __restrict__ n_out,
+                                                        Ctrl* ctrl) {
+  __shared__ uint32_t s_sc[4 * NWAVE];
+  uint64_t base = 0;
+  for (uint64_t i0 = 0; i0 < n; i0 += 4 * NT) {
+    const uint64_t i = i0 + threadIdx.x;
+    RaceOut e;
+    uint32_t keep = 0;
+    if (i < n) {
+      e = in[i];
+      const unsigned long long* rm = removed + i * 4;
+      if (rm[K_WW] > e.ww || rm[K_RW] > e.rw || rm[K_AW] > e.aw || rm[K_AR] > e.ar)
+        atomicOr(&ctrl->error_flags, ERR_INTERNAL_BOUNDS);
+      e.ww -= rm[K_WW];
+      e.rw -= rm[K_RW];
+      e.aw -= rm[K_AW];
+      e.ar -= rm[K_AR];
+      keep = (e.ww | e.rw | e.aw | e.ar) != 0 ? 1u : 0u;
+      e.kinds = (uint8_t)((e.ww ? 1 : 0) | (e.rw ? 2 : 0) | (e.aw ? 4 : 0) | (e.ar ? 8 : 0) | (e.xb ? 16 : 0));
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum_n<4 * NWAVE>(keep, s_sc, &tot);
+    if (keep) out[base + ex] = e;
+    base += tot;
+  }
+  if (threadIdx.x == 0) *n_out = base;
+}
+
 // -------------------------------------------------------- launch wrappers
 
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -1778,17 +1894,17 @@ hipError_t launch_stats(const Buffers& b, hipStream_t s) {
   auto kern = b.fuse0 ? (lp ? k_stats<true, true> : k_stats<false, true>)
                       : (lp ? k_stats<true, false> : k_stats<false, false>);
   hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, b.tiles, b.n_tiles, b.stats_part, b.thist,
-                     b.ctrl);
+                     b.ctrl, b.side);
   return hipGetLastError();
 }
 hipError_t launch_layout(const Buffers& b, hipStream_t s) {
   if (!b.n_traces) return hipSuccess;
   if (b.n_traces <= 64 && b.n_tiles >= 64 * b.n_traces)  // a few long traces
     hipLaunchKernelGGL(k_layout<4 * NT>, dim3(b.n_traces), dim3(4 * NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl,
-                       b.wide, b.fitness);
+                       b.wide, b.fitness, b.side ? 1u : 0u);
   else
     hipLaunchKernelGGL(k_layout<NT>, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl, b.wide,
-                       b.fitness);
+                       b.fitness, b.side ? 1u : 0u);
   return hipGetLastError();
 }
 hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
@@ -1948,6 +2064,27 @@ hipError_t launch_divergence_emit(const DivChunk* chunks, uint32_t n_chunks, con
                                   const uint64_t* chunk_off, DivOut* out, hipStream_t s) {
   if (!n_chunks) return hipSuccess;
   hipLaunchKernelGGL(k_div_emit, dim3(n_chunks), dim3(NT), 0, s, chunks, blocks, chunk_off, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp_refine(const Buffers& b, const RaceOut* entries, uint64_t n_entries, unsigned long long* removed,
+                              RaceOut* out, unsigned long long* n_out, hipStream_t s) {
+  if (n_entries) {
+    hipLaunchKernelGGL(k_fill_zero, dim3(cdiv(4 * n_entries, NT) < 4096 ? cdiv(4 * n_entries, NT) : 4096), dim3(NT),
+                       0, s, removed, 4 * n_entries);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (b.n_tiles) {
+      if (!grids_ok(b)) return hipErrorInvalidConfiguration;
+      const bool lp = loops(b, b.grid_scan);
+      auto kern = b.wide ? (lp ? k_warp_removed<u128, true> : k_warp_removed<u128, false>)
+                         : (lp ? k_warp_removed<uint64_t, true> : k_warp_removed<uint64_t, false>);
+      hipLaunchKernelGGL(kern, dim3(b.grid_scan), dim3(NT), 0, s, b, entries, n_entries, removed);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(k_warp_finish, dim3(1), dim3(4 * NT), 0, s, entries, n_entries, removed, out, n_out, b.ctrl);
   return hipGetLastError();
 }
 

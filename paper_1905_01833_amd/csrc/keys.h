@@ -6,8 +6,13 @@
 // then by block, by epoch (visit order) and by thread, with the action in
 // the two lowest bits:
 //
-//   global : [0 | unit - gmin : ug | block : bb | epoch : eb | local tid : tb | action : 2]
-//   shared : [1 | block : bb | unit - smin : us | epoch : eb | local tid : tb | action : 2]
+//   global : [0 | unit - gmin : ug | block : bb | epoch : eb | local tid : tb | side : sb | action : 2]
+//   shared : [1 | block : bb | unit - smin : us | epoch : eb | local tid : tb | side : sb | action : 2]
+//
+// The side field is empty (sb = 0) except in the warp-aware check, where it
+// holds the record's divergence bit above its statement id (Theorem 1,
+// clauses 2 and 3): below the thread, so a thread's records stay one run and
+// the threads of one warp stay adjacent.
 //
 // The fields between the space bit and the epoch field span wl = max(ug + bb,
 // bb + us) bits in both layouts.  Field widths come from per-trace minima
@@ -36,6 +41,8 @@ struct TraceStats {
   uint64_t bad_index;   // smallest trace-relative index of an invalid record (~0: none)
   uint32_t max_tid;
   uint32_t max_epoch;
+  uint32_t max_stmt;    // largest statement id (warp-aware check; 0 otherwise)
+  uint32_t pad;
 };
 
 // Key layout of one trace.
@@ -52,7 +59,7 @@ struct TraceLayout {
   uint32_t error;      // LAYOUT_ERR_* bits
   uint32_t wide;       // 1: the key needs more than 64 bits (two-word keys)
   uint32_t max_epoch;  // largest epoch of the trace (its barrier boundaries are 0 .. max_epoch - 1)
-  uint32_t pad;
+  uint32_t sb;         // side field bits (0, or the divergence bit and the statement id's bits)
   uint64_t grange;     // largest minus smallest global unit (0 without global records)
   uint64_t srange;     // the same over shared units
 };
@@ -75,10 +82,11 @@ SC_HD uint64_t lowmask(uint32_t b) { return b >= 64 ? ~0ull : ((1ull << b) - 1);
 
 SC_HD void stats_init(TraceStats& s) {
   s.gmin = ~0ull; s.gmax = 0; s.smin = ~0ull; s.smax = 0;
-  s.bad_index = ~0ull; s.max_tid = 0; s.max_epoch = 0;
+  s.bad_index = ~0ull; s.max_tid = 0; s.max_epoch = 0; s.max_stmt = 0; s.pad = 0;
 }
 
-SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
+// warp: the key carries the side field (divergence bit and statement id).
+SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb, bool warp = false) {
   TraceLayout L;
   const bool has_g = s.gmin <= s.gmax;
   const bool has_s = s.smin <= s.smax;
@@ -91,16 +99,16 @@ SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
   L.us = has_s ? bits64(s.smax - s.smin) : 0;
   const uint32_t wg = L.ug + L.bb, ws = L.bb + L.us;
   L.wl = wg > ws ? wg : ws;
-  L.key_bits = 3 + L.tb + L.eb + L.wl;
-  L.shift_e = 2 + L.tb;
+  L.sb = warp ? 1 + bits32(s.max_stmt) : 0;
+  L.key_bits = 3 + L.sb + L.tb + L.eb + L.wl;
+  L.shift_e = 2 + L.sb + L.tb;
   L.shift_b = L.shift_e + L.eb;
   L.shift_ug = L.shift_b + L.bb;
   L.shift_bs = L.shift_b + L.us;
-  L.shift_space = 2 + L.tb + L.eb + L.wl;
+  L.shift_space = L.shift_e + L.eb + L.wl;
   L.error = 0;
   L.wide = L.key_bits > 64 ? 1u : 0u;
   L.max_epoch = s.max_epoch;
-  L.pad = 0;
   L.grange = has_g ? s.gmax - s.gmin : 0;
   L.srange = has_s ? s.smax - s.smin : 0;
   if (L.key_bits > 128) L.error |= LAYOUT_ERR_WIDE;
@@ -115,15 +123,21 @@ SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb) {
 // the third computes both on a device.
 enum : int { BLK_ANY = 0, BLK_POW2 = 1, BLK_DIV = 2 };
 
+// Divergence bit of a side word (its statement id is the other 31 bits).
+constexpr uint32_t SIDE_DIVERGED = 0x80000000u;
+
 // Key of one record (fields must be valid and within the trace's ranges);
-// K is uint64_t for keys of at most 64 bits, u128 otherwise.
+// K is uint64_t for keys of at most 64 bits, u128 otherwise.  side: the
+// record's side word when the layout has a side field (ignored otherwise).
 template <typename K, int BLK = BLK_ANY>
 SC_HD K make_key_t(const TraceLayout& L, uint64_t unit, uint32_t tid, uint32_t epoch, uint32_t action, uint32_t space,
-                   uint32_t tpb) {
+                   uint32_t tpb, uint32_t side = 0) {
   const bool pow2 = BLK == BLK_POW2 || (BLK == BLK_ANY && (tpb & (tpb - 1)) == 0);
   const uint32_t blk = pow2 ? tid >> L.tb : tid / tpb;
   const uint32_t loc = tid - blk * tpb;
-  const K low = ((K)epoch << L.shift_e) | ((K)loc << 2) | (K)(action & 3u);
+  K low = ((K)epoch << L.shift_e) | ((K)loc << (2 + L.sb)) | (K)(action & 3u);
+  if (L.sb)
+    low |= ((K)((side & SIDE_DIVERGED) ? 1u : 0u) << (1 + L.sb)) | ((K)(side & ~SIDE_DIVERGED) << 2);
   if (space == 0) return ((K)(unit - L.gmin) << L.shift_ug) | ((K)blk << L.shift_b) | low;
   return ((K)1 << L.shift_space) | ((K)blk << L.shift_bs) | ((K)(unit - L.smin) << L.shift_b) | low;
 }
@@ -144,8 +158,9 @@ SC_HD uint32_t top_bit(u128 x) {
 // 2 new epoch, 3 new thread, 4 same (location, block, epoch, thread).
 template <typename K>
 SC_HD uint32_t head_level_t(const TraceLayout& L, K p, K x) {
-  // written with selects only: it runs for every key of the tile scan
-  const K d = (x ^ p) & ~(K)3;
+  // written with selects only: it runs for every key of the tile scan; the
+  // action and side fields below the thread do not start a group
+  const K d = (x ^ p) & ~(K)lowmask(2 + L.sb);
   const uint32_t hb = d != 0 ? top_bit(d) : 0u;  // highest differing bit
   const bool shared = ((x >> L.shift_space) & 1u) != 0;
   const uint32_t inner = hb >= L.shift_e ? 2u : 3u;          // epoch or thread
@@ -162,7 +177,17 @@ SC_HD uint32_t key_epoch_t(const TraceLayout& L, K k) {
 }
 template <typename K>
 SC_HD uint32_t key_ltid_t(const TraceLayout& L, K k) {
-  return (uint32_t)((uint64_t)(k >> 2) & lowmask(L.tb));
+  return (uint32_t)((uint64_t)(k >> (2 + L.sb)) & lowmask(L.tb));
+}
+
+// Side field of a key (warp-aware check): divergence bit and statement id.
+template <typename K>
+SC_HD bool key_diverged_t(const TraceLayout& L, K k) {
+  return L.sb && ((uint64_t)(k >> (1 + L.sb)) & 1u);
+}
+template <typename K>
+SC_HD uint32_t key_stmt_t(const TraceLayout& L, K k) {
+  return L.sb ? (uint32_t)((uint64_t)(k >> 2) & lowmask(L.sb - 1)) : 0u;
 }
 
 // Location of a key: space, owning block (shared) or 0xFFFFFFFF, unit.

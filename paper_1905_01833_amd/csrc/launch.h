@@ -113,6 +113,7 @@ struct Buffers {            // device pointers of one call
                             // k_keygen_scatter's when fuse0)
   uint32_t key_bytes;       // 8 or 16
   uint32_t fitness;         // 1: fitness keys (epoch and action dropped), for the EP fitness count
+  const uint32_t* side;     // warp-aware check: one side word per record (call index), else nullptr
 };
 
 // Barrier instances (per trace and boundary) of the redundant-barrier check:
@@ -179,6 +180,14 @@ hipError_t launch_divergence(const DivChunk* chunks, uint32_t n_chunks, const ui
 // The divergent blocks, in (trace, block) order, to out.
 hipError_t launch_divergence_emit(const DivChunk* chunks, uint32_t n_chunks, const DivBlock* blocks,
                                   const uint64_t* chunk_off, DivOut* out, hipStream_t s);
+
+// Warp-aware check (Theorem 1's warp clauses) after the plain check of a
+// call whose keys carry the side field: the pairs lockstep execution
+// orders are subtracted from the plain entries (n_entries of them, device
+// memory, in key order; `removed` holds 4 counters per entry), and the
+// entries left with a pair go to `out`, their number to *n_out (device).
+hipError_t launch_warp_refine(const Buffers& b, const RaceOut* entries, uint64_t n_entries, unsigned long long* removed,
+                              RaceOut* out, unsigned long long* n_out, hipStream_t s);
 
 // Device memory of the no-allocation entry point: a file-scope array of
 // SCRATCH_BYTES in the library's device code, one copy per GPU.
