@@ -908,6 +908,24 @@ __device__ __forceinline__ uint32_t meta_at(const uint32_t mp[3], uint32_t i) {
 
 __device__ __forceinline__ uint32_t cnt16(uint64_t packed, uint32_t q) { return (uint32_t)(packed >> (16 * q)) & 0xFFFFu; }
 
+// A value uniform over the wave that the compiler may not look through
+// (moved to scalar registers).
+__device__ __forceinline__ void opaque_sgpr(uint64_t& v) {
+  v = readfirstlane(v);
+  asm volatile("" : "+s"(v));
+}
+__device__ __forceinline__ void opaque_sgpr(u128& v) {
+  uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
+  opaque_sgpr(lo);
+  opaque_sgpr(hi);
+  v = ((u128)hi << 64) | lo;
+}
+
+// Classes with a nonzero count among three 16-bit class fields, as a 3-bit set.
+__device__ __forceinline__ uint32_t class_set(uint64_t x) {
+  return ((x & 0xFFFFull) ? 1u : 0u) | ((x & 0xFFFF0000ull) ? 2u : 0u) | ((x & 0xFFFF00000000ull) ? 4u : 0u);
+}
+
 // Three 8-bit class fields (read, write, atomic) to three 16-bit fields;
 // the top field (padding) is dropped.
 __device__ __forceinline__ uint64_t widen8(uint32_t x) {
@@ -1004,10 +1022,10 @@ __device__ __forceinline__ RaceOut* stage_of(const Buffers& b, uint32_t tile, co
 
 // Occupancy of the tile scan: with no LDS copy of the tile its registers
 // alone set the waves per SIMD.  The one-tile kernels ask for 8 waves with
-// one-word keys (64 VGPRs, no spill) and 6 with two-word keys; the looping
+// one-word keys (64 VGPRs, no spill) and 5 with two-word keys; the looping
 // variants keep their natural counts.
 template <typename K, bool LOOP>
-constexpr int scan_min_waves() { return LOOP ? 1 : (sizeof(K) == 8 ? 8 : 6); }
+constexpr int scan_min_waves() { return LOOP ? 1 : (sizeof(K) == 8 ? 8 : 5); }
 
 template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(Buffers b, uint32_t passes_done) {
@@ -1042,62 +1060,75 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 
     // each thread's sixteen consecutive keys come straight from memory
     // (with the key before them), with no LDS copy of the tile: the
-    // kernel's LDS stays under 4 KiB, so registers alone bound occupancy
+    // kernel's LDS stays under 4 KiB, so registers alone bound occupancy.
+    // Indices past the tile's end are clamped to its last key (a tile holds
+    // at least one), so every load is issued without a branch; those items
+    // are padding below.
+    const uint32_t j0 = ITEMS * tid, jl = n_in - 1;
     K kk[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) kk[i] = ITEMS * tid + i < n_in ? src[ITEMS * tid + i] : (K)0;
-    const uint32_t j0 = ITEMS * tid;
-    K prev = (K)0;
-    if (j0 > 0 && j0 - 1 < n_in) prev = src[j0 - 1];
-    else if (j0 == 0 && tr.local > 0) prev = src[-1];  // the previous tile's last key
+    for (int i = 0; i < ITEMS; i++) kk[i] = src[min(j0 + (uint32_t)i, jl)];
+    // the key before the thread's first (the previous tile's last for
+    // thread 0; not read at a trace's first key)
+    const K prev0 = src[(j0 == 0 && tr.local == 0) ? 0 : (int64_t)min(j0, n_in) - 1];
+    K prev = (j0 == 0 && tr.local == 0) ? (K)0 : prev0;
     if (tid == 0) {  // whether the tile's last location ends with the tile
       const K next = trace_end ? (K)0 : src[n_in];
       s_taillast = trace_end ? 1u : (head_level_t<K>(L, src[n_in - 1], next) == 0 ? 1u : 0u);
     }
 
-    // ---- element metadata: head level (3 bits) and class (2 bits)
-    // head level (3 bits) and class (2 bits) of item i: bits 5 (i % 6) of mp[i / 6]
+    // ---- element metadata and pass A, in one loop.  Metadata: head level
+    //      (3 bits) and class (2 bits) of item i, bits 5 (i % 6) of mp[i / 6].
+    //      The head level comes from four threshold tests on the bits where
+    //      the key differs from its predecessor (keys.h: a location, block,
+    //      epoch or thread field differs; the thresholds are the fields'
+    //      lowest bits, the location's being the block's for shared keys),
+    //      and those tests, "a head at level l or coarser", also drive pass
+    //      A.  Pass A: segmented class counts per level, inside the thread as
+    //      8-bit fields of one word (a thread holds 16 elements): the running
+    //      count, and per level its value before the thread's last head at
+    //      that level or coarser.  Their difference, widened to the 16-bit
+    //      fields of the block scan, is the thread's aggregate.
     uint32_t mp[3] = {0u, 0u, 0u};
-    {
-#pragma unroll
-      for (int i = 0; i < ITEMS; i++) {
-        const uint32_t j = ITEMS * tid + i;
-        const K k = kk[i];
-        uint32_t lv, c;
-        if (j < n_in) {
-          lv = (j == 0 && tr.local == 0) ? 0u : head_level_t<K>(L, prev, k);
-          c = action_class(k);
-        } else {
-          lv = 4;
-          c = CLS_NONE;
-        }
-        mp[i / 6] |= (lv | (c << 3)) << (5 * (i % 6));
-        prev = k;
-      }
-      s_firstlv[tid] = (uint8_t)(mp[0] & 7u);
-    }
-
-    // ---- pass A: segmented class counts per level.  Inside the thread the
-    //      counts are 8-bit fields of one word (a thread holds 16 elements):
-    //      the running count, and per level its value before the thread's
-    //      last head at that level or coarser.  Their difference, widened to
-    //      the 16-bit fields of the block scan, is the thread's aggregate.
     uint64_t aggA[4];
     uint32_t mn = NO_HEAD;  // the thread's smallest head level
     {
+      const bool trace_first = j0 == 0 && tr.local == 0;  // item 0 is the trace's first key
+      // the thresholds stay opaque: compared as they are, not rewritten as
+      // shifts of the difference
+      HeadThresholds<K> hth = head_thresholds_t<K>(L);
+      opaque_sgpr(hth.low);
+      opaque_sgpr(hth.space);
+      opaque_sgpr(hth.unit_g);
+      opaque_sgpr(hth.block);
+      opaque_sgpr(hth.epoch);
       uint32_t cnt = 0, snap[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
-        const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
-#pragma unroll
-        for (int l = 0; l < 4; l++)
-          if (lv <= (uint32_t)l) snap[l] = cnt;
+        const K k = kk[i];
+        const bool valid = j0 + (uint32_t)i < n_in;
+        const bool first = i == 0 && trace_first;
+        const HeadTests<K> ht = head_tests_t<K>(hth, prev, k);
+        const bool h0 = valid && (first || ht.h[0]);
+        const bool h1 = valid && (first || ht.h[1]);
+        const bool h2 = valid && (first || ht.h[2]);
+        const bool h3 = valid && (first || ht.h[3]);
+        const uint32_t lv = h0 ? 0u : h1 ? 1u : h2 ? 2u : h3 ? 3u : 4u;
+        const uint32_t c = valid ? action_class(k) : CLS_NONE;
+        snap[0] = h0 ? cnt : snap[0];
+        snap[1] = h1 ? cnt : snap[1];
+        snap[2] = h2 ? cnt : snap[2];
+        snap[3] = h3 ? cnt : snap[3];
         cnt += 1u << (8 * c);  // padding (class 3) counts in the unused top field
         mn = min(mn, lv);
+        mp[i / 6] |= (lv | (c << 3)) << (5 * (i % 6));
+        prev = k;
       }
 #pragma unroll
       for (int l = 0; l < 4; l++) aggA[l] = (mn <= (uint32_t)l ? SEGF : 0ull) | widen8(cnt - snap[l]);
     }
+    s_firstlv[tid] = (uint8_t)(mp[0] & 7u);
+
     // the packed metadata is decoded again per pass, not kept decoded
 #pragma unroll
     for (int k = 0; k < 3; k++) asm volatile("" : "+v"(mp[k]));
@@ -1106,33 +1137,33 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 
     // ---- pass B, test: whether an element of this thread has a racing
     //      partner among the earlier elements of its location in the tile.
-    //      The counts its pairs are drawn from are (location run - block
-    //      run) + (epoch run - thread run); both differences change only at
-    //      heads, so they are kept as d01 and d23 beside the open location
-    //      and epoch run counts r0 and r2.  Most threads find nothing and
-    //      skip the pair sums below.
+    //      The counts an element's pairs are drawn from are (location run -
+    //      block run) + (epoch run - thread run); both differences change
+    //      only at heads, and only which classes they hold matters here, so
+    //      the thread keeps them as 3-bit class sets (d01, d23) beside the
+    //      class sets of the open location and epoch runs (r0, r2).  Most
+    //      threads find nothing and skip the pair sums below.
     uint32_t hit = 0;
     {
-      uint64_t r0 = exA[0] & ~SEGF, r2 = exA[2] & ~SEGF;
-      uint64_t d01 = r0 - (exA[1] & ~SEGF), d23 = r2 - (exA[3] & ~SEGF);
+      uint32_t r0 = class_set(exA[0] & ~SEGF), r2 = class_set(exA[2] & ~SEGF);
+      uint32_t d01 = class_set((exA[0] & ~SEGF) - (exA[1] & ~SEGF));
+      uint32_t d23 = class_set((exA[2] & ~SEGF) - (exA[3] & ~SEGF));
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
         // selects, not branches (branches here cost registers)
         const bool z0 = lv == 0, z1 = lv == 1, z2 = lv <= 2, z3 = lv == 3;
-        d01 = z0 ? 0ull : (z1 ? r0 : d01);
-        r0 = z0 ? 0ull : r0;
-        d23 = z2 ? 0ull : (z3 ? r2 : d23);
-        r2 = z2 ? 0ull : r2;
-        const uint64_t tot = d01 + d23;
-        // conflicting classes: a read's are writes and atomics, a write's
-        // all three, an atomic's reads and writes; padding has none
-        const uint32_t mlo = c == CLS_R ? 0xFFFF0000u : (c == CLS_NONE ? 0u : 0xFFFFFFFFu);
-        const uint32_t mhi = c <= CLS_W ? 0xFFFFu : 0u;
-        hit |= ((uint32_t)tot & mlo) | ((uint32_t)(tot >> 32) & mhi);
-        const uint64_t inc = 1ull << (16 * c);
-        r0 += inc;
-        r2 += inc;
+        d01 = z0 ? 0u : (z1 ? r0 : d01);
+        r0 = z0 ? 0u : r0;
+        d23 = z2 ? 0u : (z3 ? r2 : d23);
+        r2 = z2 ? 0u : r2;
+        // conflicting classes: a read's are writes and atomics (110b), a
+        // write's all three (111b), an atomic's reads and writes (011b);
+        // padding (class 3) has none and adds none
+        hit |= (d01 | d23) & ((0x376u >> (4 * c)) & 7u);
+        const uint32_t bit = (1u << c) & 7u;
+        r0 |= bit;
+        r2 |= bit;
       }
     }
     // ---- lead counts: per level, the class counts of the tile's elements

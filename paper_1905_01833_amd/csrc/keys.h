@@ -170,6 +170,48 @@ SC_HD uint32_t head_level_t(const TraceLayout& L, K p, K x) {
 }
 SC_HD uint32_t head_level(const TraceLayout& L, uint64_t p, uint64_t x) { return head_level_t<uint64_t>(L, p, x); }
 
+// The same levels as four tests, h[l] = "key x starts a group at level l or
+// coarser" (head_level_t(L, p, x) <= l), each one comparison of the bits
+// where the keys differ against the lowest bit of a field: the location's
+// (the unit's for global keys, the block's for shared keys, whose block is
+// part of the location), the block's, the epoch's, and any difference at
+// all.  Keys of different spaces differ in the space bit, above all of them.
+template <typename K>
+struct HeadTests {
+  bool h[4];
+};
+// The thresholds of one trace (the lowest bits of its fields), computed once.
+template <typename K>
+struct HeadThresholds {
+  K low;    // bits that do not start a group (action, side field)
+  K space;  // the space bit: a key at or above it is a shared key
+  K unit_g, block, epoch;
+};
+template <typename K>
+SC_HD HeadThresholds<K> head_thresholds_t(const TraceLayout& L) {
+  HeadThresholds<K> t;
+  t.low = ~(K)lowmask(2 + L.sb);
+  t.space = (K)1 << L.shift_space;
+  t.unit_g = (K)1 << L.shift_ug;
+  t.block = (K)1 << L.shift_b;
+  t.epoch = (K)1 << L.shift_e;
+  return t;
+}
+template <typename K>
+SC_HD HeadTests<K> head_tests_t(const HeadThresholds<K>& t, K p, K x) {
+  const K d = (x ^ p) & t.low;
+  HeadTests<K> r;
+  r.h[1] = d >= t.block;
+  r.h[0] = d >= t.unit_g || (x >= t.space && r.h[1]);  // shared: the block is part of the location
+  r.h[2] = d >= t.epoch;
+  r.h[3] = d != (K)0;
+  return r;
+}
+template <typename K>
+SC_HD HeadTests<K> head_tests_t(const TraceLayout& L, K p, K x) {
+  return head_tests_t<K>(head_thresholds_t<K>(L), p, x);
+}
+
 // Epoch and block-local thread of a key.
 template <typename K>
 SC_HD uint32_t key_epoch_t(const TraceLayout& L, K k) {

@@ -234,6 +234,68 @@ extern "C" int hs_assoc(uint64_t seed, int trials) {
   return 0;
 }
 
+// head_tests_t (the scan's four threshold tests) against head_level_t on
+// random layouts and key pairs: neighbours that differ in one chosen field,
+// and random pairs, for both key widths and with or without a side field.
+// Returns the number of disagreements.
+template <typename K>
+static int head_tests_impl(uint64_t seed, int trials) {
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 7;
+  auto rnd = [&]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
+  int bad = 0;
+  for (int t = 0; t < trials; t++) {
+    TraceStats S;
+    stats_init(S);
+    const uint32_t tpb = 1 + (uint32_t)(rnd() % 600);
+    const uint64_t gspan = rnd() >> (rnd() % 64), sspan = rnd() >> (rnd() % 64);
+    S.gmin = rnd() % 1000; S.gmax = S.gmin + gspan;
+    S.smin = rnd() % 1000; S.smax = S.smin + sspan;
+    if (rnd() % 5 == 0) { S.gmin = ~0ull; S.gmax = 0; }  // no global records
+    S.max_tid = (uint32_t)(rnd() % 100000);
+    S.max_epoch = (uint32_t)(rnd() % 70000 % 65536);
+    S.max_stmt = (uint32_t)(rnd() % 1000);
+    const bool warp = rnd() % 2;
+    const TraceLayout L = make_layout(S, tpb, warp);
+    if (L.error || (sizeof(K) == 8 && L.wide)) continue;
+    auto rec_key = [&](uint32_t space, uint64_t unit, uint32_t tid, uint32_t epoch, uint32_t action, uint32_t side) {
+      return make_key_t<K>(L, unit, tid, epoch, action, space, tpb, side);
+    };
+    for (int q = 0; q < 20; q++) {
+      const bool has_g = S.gmin <= S.gmax;
+      const uint32_t space = has_g ? (uint32_t)(rnd() % 2) : 1u;
+      const uint64_t lo = space ? S.smin : S.gmin, span = space ? sspan : gspan;
+      const uint64_t unit = lo + (span ? rnd() % (span + 1) : 0);
+      const uint32_t tid = (uint32_t)(rnd() % (S.max_tid + 1)), ep = (uint32_t)(rnd() % (S.max_epoch + 1));
+      const uint32_t act = (uint32_t)(rnd() % 3), side = (uint32_t)(rnd() % (S.max_stmt + 1)) | (rnd() % 2 ? SIDE_DIVERGED : 0u);
+      const K a = rec_key(space, unit, tid, ep, act, side);
+      // a neighbour: the same record with one field changed
+      uint32_t space2 = space, tid2 = tid, ep2 = ep, act2 = act, side2 = side;
+      uint64_t unit2 = unit;
+      switch (rnd() % 7) {
+        case 0: unit2 = lo + (span ? rnd() % (span + 1) : 0); break;
+        case 1: tid2 = (uint32_t)(rnd() % (S.max_tid + 1)); break;
+        case 2: ep2 = (uint32_t)(rnd() % (S.max_epoch + 1)); break;
+        case 3: act2 = (uint32_t)(rnd() % 3); break;
+        case 4: side2 = (uint32_t)(rnd() % (S.max_stmt + 1)); break;
+        case 5: tid2 = tid ^ 1u; if (tid2 > S.max_tid) tid2 = tid; break;
+        default:
+          if (has_g) { space2 = 1u - space; unit2 = space2 ? S.smin : S.gmin; }
+      }
+      const K b = rec_key(space2, unit2, tid2, ep2, act2, side2);
+      const K p = a < b ? a : b, y = a < b ? b : a;
+      const uint32_t lv = head_level_t<K>(L, p, y);
+      const HeadTests<K> h = head_tests_t<K>(L, p, y);
+      for (uint32_t l = 0; l < 4; l++)
+        if (h.h[l] != (lv <= l)) bad++;
+    }
+  }
+  return bad;
+}
+
+extern "C" int hs_head_tests(uint64_t seed, int trials) {
+  return head_tests_impl<uint64_t>(seed, trials) + head_tests_impl<u128>(seed + 1, trials);
+}
+
 // Tile walk of a launch as the tile kernels run it: the grid for `per_cu`
 // workgroups per CU over n_cu CUs, every workgroup's tiles counted in
 // count[n].  One-tile kernels (grid / 8 >= the tiles per XCD) visit only the

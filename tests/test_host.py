@@ -37,6 +37,8 @@ def _hostsim():
                                  ctypes.POINTER(ctypes.c_uint32)]
     lib.hs_assoc.restype = ctypes.c_int
     lib.hs_assoc.argtypes = [ctypes.c_uint64, ctypes.c_int]
+    lib.hs_head_tests.restype = ctypes.c_int
+    lib.hs_head_tests.argtypes = [ctypes.c_uint64, ctypes.c_int]
     for name in ("hs_barriers", "hs_barriers_wide"):
         f = getattr(lib, name)
         f.restype = ctypes.c_int64
@@ -92,6 +94,14 @@ def wide_trace(rng, n, tpb=64):
 
 def test_monoid_associative():
     assert _hostsim().hs_assoc(12345, 50000) == 0
+
+
+def test_head_tests_match_head_levels():
+    """The scan's four threshold tests (keys.h head_tests_t) give the same
+    head levels as head_level_t, on random layouts (with and without the
+    warp side field, one- and two-word keys) and neighbouring keys that
+    differ in one field."""
+    assert _hostsim().hs_head_tests(2024, 20000) == 0
 
 
 @pytest.mark.parametrize("seed", range(120))
