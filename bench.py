@@ -143,11 +143,24 @@ def stage_profile(pkg, dev, offsets, tpb, tuning, stream, steps):
     return ms, launches
 
 
-def roofline(stage_ms, stage_launches, steps, n, workload_name):
+# Stages whose kernels skip the traces sorted whole in one workgroup's LDS
+# (at most four tiles of 4096 records with one-word keys): their launches
+# touch only the other traces' keys.
+GLOBAL_PASS_STAGES = ("upsweep", "sort_pass")
+
+
+def globally_sorted_records(offsets):
+    """Records of the traces the global radix passes sort (more than four
+    4096-record tiles; every workload here has one-word keys)."""
+    sizes = np.diff(np.asarray(offsets, dtype=np.int64))
+    return int(sizes[-(-sizes // 4096) > 4].sum())
+
+
+def roofline(stage_ms, stage_launches, steps, n, workload_name, n_global=None):
     """Roofline of the dominant kernel from per-stage event times."""
     dom = max(BYTES_PER_RECORD, key=lambda s: stage_ms.get(s, 0.0))
     avg_ms = stage_ms[dom] / max(1, stage_launches[dom])
-    alg = BYTES_PER_RECORD[dom] * n
+    alg = BYTES_PER_RECORD[dom] * (n_global if (n_global is not None and dom in GLOBAL_PASS_STAGES) else n)
     achieved = alg / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -202,7 +215,7 @@ def check_workload(pkg, torch, name, steps, warmup, recs, offsets, tpb, desc, au
     out = {"workload": desc["workload"], "traces": desc["traces"], "records": n, "value": n / sec,
            "unit": "records/s", "ms_per_step": 1e3 * sec, "steps": steps,
            "racing_locations": int(len(races)), "tuning": tuning,
-           "roofline": roofline(ms, launches, prof_steps, n, name),
+           "roofline": roofline(ms, launches, prof_steps, n, name, globally_sorted_records(offsets)),
            "pipeline": pipeline(n / sec, name, passes, stages), "stage_ms_per_step": stages}
     return out, dev, races, summ
 
