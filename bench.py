@@ -128,11 +128,14 @@ def pmc_traffic(kernel, workload_name):
 
 def stage_profile(pkg, dev, offsets, tpb, tuning, stream, steps):
     """Per-stage device times of `steps` calls with HIP events around every
-    launch, on the stream the kernels run on."""
+    launch, on the stream the kernels run on, after one untimed call (a
+    context's first call sorts with 8-bit digits before it has seen the
+    keys' width)."""
     pctx = pkg.Context(0, profile=True)
     pctx.set_tuning(tuning["size_class"], tuning)
     ms, launches = {}, {}
     try:
+        pctx.check_traces_device(dev, offsets, tpb, stream=stream)
         for _ in range(steps):
             pctx.check_traces_device(dev, offsets, tpb, stream=stream)
             for name, (t, k) in pctx.stage_times().items():

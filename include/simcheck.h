@@ -400,7 +400,9 @@ typedef struct sim_tuning {
   uint32_t scatter_threads;   /* threads of a radix scatter workgroup: 256 (16 keys each) or 512 (8 keys
                                  each; one-word keys only, two-word calls use 256); 0: by call size,
                                  512 up to 16384 tiles, else 256 */
-  uint32_t reserved;          /* 0 */
+  uint32_t digit_bits;        /* radix digit width of the passes after the first: 8 or 9; 0: by the
+                                 key width of the context's previous call of the same kind (9 where
+                                 it saves a pass; no-allocation calls always use 8) */
   double ms;                  /* sim_autotune: fastest time of one call in the chosen shape; else 0 */
 } sim_tuning;
 

@@ -53,7 +53,8 @@ EXPORTS = [
 ]
 SIM_EAGAIN = -5
 SIM_SIZE_CLASSES = 33
-TUNING_FIELDS = ("stream_wgs_per_cu", "sort_wgs_per_cu", "scan_wgs_per_cu", "group_shift_bias", "scatter_threads")
+TUNING_FIELDS = ("stream_wgs_per_cu", "sort_wgs_per_cu", "scan_wgs_per_cu", "group_shift_bias", "scatter_threads",
+                 "digit_bits")
 
 
 class SimError(RuntimeError):
@@ -94,7 +95,7 @@ class _Tuning(ctypes.Structure):
         ("scan_wgs_per_cu", ctypes.c_uint32),
         ("group_shift_bias", ctypes.c_int32),
         ("scatter_threads", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("digit_bits", ctypes.c_uint32),
         ("ms", ctypes.c_double),
     ]
 
@@ -505,7 +506,7 @@ def sim_set_tuning(ctx, size_class: int, tuning: dict | None) -> None:
     """Set the launch shape of one size class (None: back to the default)."""
     t = None
     if tuning is not None:
-        t = _Tuning(*(int(tuning.get(f, 0)) for f in TUNING_FIELDS), 0, float(tuning.get("ms", 0.0)))
+        t = _Tuning(*(int(tuning.get(f, 0)) for f in TUNING_FIELDS), float(tuning.get("ms", 0.0)))
     rc = load().sim_set_tuning(ctx, size_class, ctypes.byref(t) if t is not None else None)
     if rc != SIM_OK:
         raise SimError(rc, sim_last_error(ctx))

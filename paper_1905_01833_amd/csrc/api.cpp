@@ -61,7 +61,12 @@ struct sim_ctx {
   bool fit_wide_guess = false;
   uint32_t warp_pass_guess = 0;  // ... and for the warp-aware check, whose keys are longer
   bool warp_wide_guess = false;
+  // per kind as above: the key bits the previous call sorted (0: none yet),
+  // and the digit width its passes (the pass guess) were counted in
+  uint32_t bits_guess = 0, fit_bits_guess = 0, warp_bits_guess = 0;
+  uint32_t db_guess = RADIX_BITS, fit_db_guess = RADIX_BITS, warp_db_guess = RADIX_BITS;
   uint64_t alloc_gen = 0;   // bumped whenever a device buffer is reallocated
+  uint64_t meta_gen = 0;    // bumped whenever a call's tables are uploaded
 
   // one captured launch sequence, replayed while calls keep the same shape
   struct {
@@ -71,7 +76,9 @@ struct sim_ctx {
     uint64_t total = 0, table_hash = 0, gen = 0;
     uint32_t n_traces = 0, n_tiles = 0, guess = 0;
     uint64_t tuning_gen = 0;
+    uint64_t meta_gen = 0;  // the table upload the captured launches read
     bool wide = false;
+    uint32_t db = 0;  // digit width of the captured passes
   } graph;
 
   // launch shapes per size class (set by hand or by sim_autotune)
@@ -263,17 +270,18 @@ constexpr uint32_t NOALLOC_MAX_TILES = (1u << 23) / TILE + NOALLOC_MAX_TRACES;
 enum { R_KEYS0, R_KEYS1, R_META, R_STATS, R_LAYOUT, R_THIST, R_GTOT, R_GBASE, R_AGG, R_TOUT, R_CROSS, R_CFLAG,
        R_GSUM, R_CTRL, N_REGION };
 
+// radix: digits of the call's widest pass (RADIX, or RADIX_MAX with 9-bit digits).
 void region_bytes(size_t need[N_REGION], uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups,
-                  uint32_t key_bytes) {
+                  uint32_t key_bytes, uint32_t radix) {
   const uint32_t n_groups = (n_tiles + GROUP - 1) / GROUP;
   need[R_KEYS0] = total * key_bytes;
   need[R_KEYS1] = total * key_bytes;
   need[R_META] = meta_bytes(n_traces, n_tiles, n_hgroups);
   need[R_STATS] = (size_t)n_tiles * sizeof(TraceStats);
   need[R_LAYOUT] = (size_t)n_traces * sizeof(TraceLayout);
-  need[R_THIST] = (size_t)n_tiles * RADIX * 4;
-  need[R_GTOT] = (size_t)n_hgroups * RADIX * 4;
-  need[R_GBASE] = (size_t)n_hgroups * RADIX * 8;
+  need[R_THIST] = (size_t)n_tiles * radix * 4;
+  need[R_GTOT] = (size_t)n_hgroups * radix * 4;
+  need[R_GBASE] = (size_t)n_hgroups * radix * 8;
   need[R_AGG] = (size_t)n_tiles * SW * 4;
   need[R_TOUT] = (size_t)n_tiles * sizeof(TileOut);
   need[R_CROSS] = (size_t)n_tiles * sizeof(RaceOut);
@@ -315,9 +323,9 @@ hipError_t grow(sim_ctx* c, DevBuf& b, size_t bytes) {
 // limit, a context whose grown buffers would exceed it first releases all of
 // them (they are idle between calls) and allocates the call's sizes afresh.
 hipError_t size_buffers(sim_ctx* c, uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups,
-                        uint32_t key_bytes) {
+                        uint32_t key_bytes, uint32_t radix) {
   size_t need[N_REGION];
-  region_bytes(need, total, n_traces, n_tiles, n_hgroups, key_bytes);
+  region_bytes(need, total, n_traces, n_tiles, n_hgroups, key_bytes, radix);
   const uint64_t cap0 = total < 65536 ? total : 65536;
   const size_t out_need = c->out.cap ? c->out.cap : cap0 * sizeof(RaceOut);
   if (c->dev_limit) {
@@ -400,6 +408,8 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   // radix passes and key width the previous call of this kind needed
   uint32_t& pass_guess = fit ? c->fit_pass_guess : (warp ? c->warp_pass_guess : c->pass_guess);
   bool& wide_guess = fit ? c->fit_wide_guess : (warp ? c->warp_wide_guess : c->wide_guess);
+  uint32_t& bits_guess = fit ? c->fit_bits_guess : (warp ? c->warp_bits_guess : c->bits_guess);
+  uint32_t& db_guess = fit ? c->fit_db_guess : (warp ? c->warp_db_guess : c->db_guess);
 
   // result delivery: summaries from the entry list, entries downloaded from
   // `dev_out` (n_races of them)
@@ -468,6 +478,14 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   // tiles keep both serial offset loops of the radix kernels short
   hipError_t e;
   const sim_tuning tune = pick_tuning(c, total);
+  // digit width of the passes after the first: the tuning's, else 9 bits
+  // where the previous call's widest key sorts in fewer passes with them
+  // (no-allocation calls: 8, the scratch's tables are sized for it)
+  uint32_t db = tune.digit_bits ? tune.digit_bits : RADIX_BITS;
+  if (!tune.digit_bits && bits_guess &&
+      radix_passes(bits_guess, RADIX_WIDE_BITS) < radix_passes(bits_guess, RADIX_BITS))
+    db = RADIX_WIDE_BITS;
+  if (noalloc) db = RADIX_BITS;
   uint64_t n_hgroups64 = 0;
   for (uint32_t i = 0; i < n_traces; i++) {
     const uint64_t nt = (offsets[i + 1] - offsets[i] + TILE - 1) / TILE;
@@ -500,13 +518,6 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
     max_group_tiles = std::max(max_group_tiles, std::min(nt, 1u << gs));
     max_trace_groups = std::max(max_trace_groups, ng);
     hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
-    const uint32_t short_flag = nt <= small_max_tiles ? TILE_SHORT : 0u;
-    const sim_record* base = trace_recs ? trace_recs[i] : d_records + offsets[i];
-    for (uint32_t k = 0; k < nt; k++) {
-      const uint64_t first = offsets[i] + (uint64_t)k * TILE;
-      const uint32_t n_in = (uint32_t)std::min<uint64_t>(TILE, offsets[i + 1] - first);
-      ht[t0 + k] = TileRef{i, k, (uint32_t)first, n_in | short_flag, base + (uint64_t)k * TILE};
-    }
     for (uint32_t k = 0; k < ng; k++) hg[g0 + k] = GroupRef{i, 0};
     if (nt == 1) hs[n_small1++] = i;
     else if (nt >= 2 && nt <= small_max_tiles) hs[n_traces - 1 - n_small4++] = i;  // from the back
@@ -515,6 +526,20 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   }
   const uint32_t n_hgroups = g0;
   if (n_small4) memmove(hs + n_small1, hs + n_traces - n_small4, (size_t)n_small4 * sizeof(uint32_t));
+  // the (trace, tile) table: filled only when the tables are uploaded (a
+  // graph replay whose upload is still on the device skips both)
+  auto fill_tiles = [&]() {
+    for (uint32_t i = 0; i < n_traces; i++) {
+      const uint32_t nt = hd[i].ntiles, tt = hd[i].tile0;
+      const uint32_t short_flag = nt <= small_max_tiles ? TILE_SHORT : 0u;
+      const sim_record* base = trace_recs ? trace_recs[i] : d_records + offsets[i];
+      for (uint32_t k = 0; k < nt; k++) {
+        const uint64_t first = offsets[i] + (uint64_t)k * TILE;
+        const uint32_t n_in = (uint32_t)std::min<uint64_t>(TILE, offsets[i + 1] - first);
+        ht[tt + k] = TileRef{i, k, (uint32_t)first, n_in | short_flag, base + (uint64_t)k * TILE};
+      }
+    }
+  };
   // host words of a staging overflow, after the tables
   TileOut* h_tout = (TileOut*)((char*)c->h_meta + (meta_bytes(n_traces, n_tiles, n_hgroups) + 15) / 16 * 16);
   uint64_t* h_sref = (uint64_t*)(h_tout + n_tiles);
@@ -529,7 +554,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   uint64_t* d_sref = nullptr;
   if (noalloc) {
     size_t need[N_REGION];
-    region_bytes(need, total, n_traces, n_tiles, n_hgroups, key_bytes);
+    region_bytes(need, total, n_traces, n_tiles, n_hgroups, key_bytes, RADIX);
     size_t off = 0;
     auto carve = [&](size_t bytes) {
       off = (off + 255) / 256 * 256;
@@ -549,14 +574,12 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
     out_p = (RaceOut*)rest;
     out_cap = rest_bytes / sizeof(RaceOut);
   } else {
-    if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups, key_bytes)) != hipSuccess)
+    if ((e = size_buffers(c, total, n_traces, n_tiles, n_hgroups, key_bytes, 1u << db)) != hipSuccess)
       return hip_fail(c, e, "device allocation");
     for (int r = 0; r < N_REGION; r++) reg[r] = region_buf(c, r)->p;
     out_p = (RaceOut*)c->out.p;
     out_cap = c->out.cap / sizeof(RaceOut);
   }
-  if ((e = hipMemcpyAsync(reg[R_META], c->h_meta, meta_bytes(n_traces, n_tiles, n_hgroups), hipMemcpyHostToDevice, s)))
-    return hip_fail(c, e, "table upload");
 
   Buffers b;
   b.desc = (const TraceDesc*)reg[R_META];
@@ -569,6 +592,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   b.key_bytes = key_bytes;
   b.fitness = fit ? 1u : 0u;
   b.side = warp ? sink.side : nullptr;
+  b.digit_bits = db;
   b.groups = (const GroupRef*)(b.tiles + n_tiles);
   b.small_traces = (const uint32_t*)(b.groups + n_hgroups);
   b.n_small1 = n_small1;
@@ -666,7 +690,8 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   };
 
   // (a call of one-tile traces has all its passes done before the scan)
-  const uint32_t prev_guess = pass_guess;
+  // (a guess counted in another width is recounted from the key bits)
+  const uint32_t prev_guess = db == db_guess || !bits_guess ? pass_guess : radix_passes(bits_guess, db);
   const uint32_t guess = all_small ? MAX_PASSES : (prev_guess < MAX_PASSES ? prev_guess : MAX_PASSES);
   int first_scan_ev = 0;  // events of the first round before its scan
   auto first_round = [&]() -> hipError_t {
@@ -687,7 +712,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   };
   // Graph mode: the first round (every launch up to the control download)
   // is captured once per call shape and replayed while the shape, the
-  // buffers and the pass count stay the same.  (Not for gathered traces,
+  // buffers, the pass count and the digit width stay the same.  (Not for gathered traces,
   // whose record addresses are not part of the shape, nor for calls that
   // may not allocate: instantiating a graph does.)
   const bool use_graph =
@@ -702,7 +727,17 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   auto& G = c->graph;
   const bool replay = use_graph && G.exec && G.records == d_records && G.stream == s && G.total == total &&
                       G.n_traces == n_traces && G.n_tiles == n_tiles && G.table_hash == th && G.gen == c->alloc_gen &&
-                      G.guess == guess && G.tuning_gen == c->tuning_gen && G.wide == wide;
+                      G.guess == guess && G.tuning_gen == c->tuning_gen && G.wide == wide && G.db == db;
+  // The tables: a replay finds them on the device when no other call
+  // uploaded tables since the captured one (same shape, same buffers, same
+  // records: the same tables); otherwise they are built and uploaded.
+  if (!(replay && G.meta_gen == c->meta_gen)) {
+    fill_tiles();
+    if ((e = hipMemcpyAsync(reg[R_META], c->h_meta, meta_bytes(n_traces, n_tiles, n_hgroups), hipMemcpyHostToDevice,
+                            s)))
+      return hip_fail(c, e, "table upload");
+    c->meta_gen++;
+  }
   if (replay) {
     e = hipGraphLaunch(G.exec, s);
   } else if (use_graph) {
@@ -727,7 +762,9 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       G.gen = c->alloc_gen;
       G.guess = guess;
       G.tuning_gen = c->tuning_gen;
+      G.meta_gen = c->meta_gen;
       G.wide = wide;
+      G.db = db;
       e = hipGraphLaunch(G.exec, s);
     } else {  // capture not possible here: run the launches directly
       (void)hipGetLastError();
@@ -760,8 +797,11 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       return hip_fail(c, e, "pipeline");
     ctl = *c->h_ctrl;
   }
-  if (!all_small) pass_guess = needed;  // an LDS-sorted call tells nothing
-                                                                       // about global passes
+  if (!all_small) {  // an LDS-sorted call tells nothing about global passes
+    pass_guess = needed;
+    db_guess = db;
+    bits_guess = ctl.max_sort_bits;
+  }
   wide_guess = ctl.wide_traces > 0;
   if (fit) {
     if (ctl.error_flags) return fail(c, SIM_EDEVICE, "internal kernel check failed (flags 0x%x)", ctl.error_flags);
@@ -1060,13 +1100,13 @@ void ctx_trim(sim_ctx* c) {
 void ctx_set_limit(sim_ctx* c, uint64_t bytes) { c->dev_limit = bytes; }
 
 // Device bytes a call of this shape holds at most in an empty context with
-// one-word (8) or two-word (16) keys: every fixed buffer with its growth
-// headroom, the output's first allocation, and a staging overflow of
-// `staged` entries with the output grown to `entries`.
+// one-word (8) or two-word (16) keys and 9-bit digits: every fixed buffer
+// with its growth headroom, the output's first allocation, and a staging
+// overflow of `staged` entries with the output grown to `entries`.
 uint64_t ctx_call_bytes(uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint32_t key_bytes, uint64_t entries,
                         uint64_t staged) {
   size_t need[N_REGION];  // histogram groups: at most one per tile
-  region_bytes(need, total, n_traces, n_tiles, n_tiles, key_bytes);
+  region_bytes(need, total, n_traces, n_tiles, n_tiles, key_bytes, RADIX_MAX);
   uint64_t t = 0;
   for (int r = 0; r < N_REGION; r++) t += grown(need[r]);
   const uint64_t cap0 = total < 65536 ? total : 65536;
@@ -1135,7 +1175,7 @@ int sim_create(sim_ctx** out, int hip_device, const sim_config* cfg) {
     const uint32_t n_tr = cfg->reserve_traces ? cfg->reserve_traces : 1;
     const uint64_t tiles = (n_rec + TILE - 1) / TILE + n_tr;
     if (n_rec >= (1ull << 32) || tiles >= (1ull << 32) || ensure(c->records, n_rec * 16) ||
-        size_buffers(c, n_rec, n_tr, (uint32_t)tiles, tiles, 8) != hipSuccess) {
+        size_buffers(c, n_rec, n_tr, (uint32_t)tiles, tiles, 8, RADIX_MAX) != hipSuccess) {
       sim_destroy(c);
       return SIM_ENOMEM;
     }
@@ -1399,9 +1439,11 @@ int sim_set_tuning(sim_ctx* c, uint32_t cls, const sim_tuning* t) {
   if (cls >= SIM_SIZE_CLASSES) return fail(c, SIM_EINVAL, "size class %u out of range", cls);
   if (t && (t->stream_wgs_per_cu > 64 || t->sort_wgs_per_cu > 64 || t->scan_wgs_per_cu > 64 ||
             t->group_shift_bias < -12 || t->group_shift_bias > 12 ||
-            (t->scatter_threads != 0 && t->scatter_threads != 256 && t->scatter_threads != 512) || t->reserved))
+            (t->scatter_threads != 0 && t->scatter_threads != 256 && t->scatter_threads != 512) ||
+            (t->digit_bits != 0 && t->digit_bits != RADIX_BITS && t->digit_bits != RADIX_WIDE_BITS)))
     return fail(c, SIM_EINVAL,
-                "tuning out of range (workgroups per CU <= 64, |bias| <= 12, scatter threads 0, 256 or 512)");
+                "tuning out of range (workgroups per CU <= 64, |bias| <= 12, scatter threads 0, 256 or 512, "
+                "digit bits 0, 8 or 9)");
   c->tuned[cls] = t != nullptr;
   c->tuning[cls] = t ? *t : sim_tuning{0, 0, 0, 0, 0, 0, 0.0};
   c->tuning_gen++;

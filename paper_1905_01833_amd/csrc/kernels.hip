@@ -205,6 +205,7 @@ __device__ __forceinline__ void ctrl_reset(Ctrl* ctrl) {
   ctrl->first_bad = ~0ull;
   ctrl->total_entries = 0;
   ctrl->wide_traces = 0;
+  ctrl->max_sort_bits = 0;
 }
 
 __global__ void k_init(Ctrl* ctrl) {
@@ -328,7 +329,8 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
 template <int NTH = NT>
 __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ desc,
                                                 const TraceStats* __restrict__ part, TraceLayout* lay, Ctrl* ctrl,
-                                                uint32_t wide_call, uint32_t fitness, uint32_t warp) {
+                                                uint32_t wide_call, uint32_t fitness, uint32_t warp,
+                                                uint32_t digit_bits) {
   constexpr int NW = NTH / 64;
   __shared__ uint64_t s64[5][NW];
   __shared__ uint32_t s32[3][NW];
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ de
     S.max_stmt = max(S.max_stmt, s32[2][w]);
   }
   if (fitness) S.max_epoch = 0;  // fitness keys hold no epoch (and no action)
-  TraceLayout L = make_layout(S, T.tpb, warp != 0);
+  TraceLayout L = make_layout(S, T.tpb, warp != 0, digit_bits);
   if (T.n == 0) {
     L.error = 0;
     L.npasses = 0;
@@ -382,6 +384,10 @@ __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ de
   }
   if (L.npasses > __hip_atomic_load(&ctrl->max_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
     atomicMax(&ctrl->max_passes, L.npasses);
+  // the host picks the next call's digit width from this
+  if (T.n && !L.error && L.key_bits - 2 > __hip_atomic_load(&ctrl->max_sort_bits, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&ctrl->max_sort_bits, L.key_bits - 2);
 }
 
 // A trace of at most b.small_max_tiles tiles is sorted whole in one
@@ -405,31 +411,31 @@ __device__ __forceinline__ bool sorted_in_lds(const Buffers& b, const TraceDesc&
 constexpr uint32_t CHUNK = 16;   // rows loaded ahead in the serial offset loops
 constexpr int MAX_PARTS = 4;     // offset kernels: up to 4 row ranges per digit (1024 threads)
 
-// Exclusive prefix over `n` rows (stride RADIX) of one digit column, split
-// over PARTS row ranges handled by the threads d, d + 256, ... .  Returns
-// the column total; rows are rewritten with `base` + prefix.
-// DIGIT_BASE: `base` is the trace's first record and every digit's column
-// starts at base + (totals of the smaller digits) -- the digit bases of a
-// radix pass -- computed here from the same reads.  s_sc holds one word per
-// wave of the workgroup and s_base one 64-bit word per digit.
-template <int PARTS, bool DIGIT_BASE, typename In, typename Out>
-__device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t base, uint64_t (*s_part)[RADIX],
+// Exclusive prefix over `n` rows (stride R, the pass's digit count) of one
+// digit column, split over PARTS row ranges handled by the threads d,
+// d + R, ... .  Returns the column total; rows are rewritten with `base` +
+// prefix.  DIGIT_BASE: `base` is the trace's first record and every digit's
+// column starts at base + (totals of the smaller digits) -- the digit bases
+// of a radix pass -- computed here from the same reads.  s_sc holds one word
+// per wave of the workgroup and s_base one 64-bit word per digit.
+template <int PARTS, bool DIGIT_BASE, uint32_t R, typename In, typename Out>
+__device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t base, uint64_t (*s_part)[R],
                                   uint32_t* s_sc = nullptr, uint64_t* s_base = nullptr) {
-  const uint32_t d = threadIdx.x % RADIX, part = threadIdx.x / RADIX;
+  const uint32_t d = threadIdx.x % R, part = threadIdx.x / R;
   const uint32_t per = (n + PARTS - 1) / PARTS;
   const uint32_t r0 = min(n, part * per), r1 = min(n, r0 + per);
   // the first chunk stays in registers for the write loop (a range of at
   // most CHUNK rows is read once)
   uint64_t first[CHUNK];
 #pragma unroll
-  for (uint32_t k = 0; k < CHUNK; k++) first[k] = (r0 + k < r1) ? (uint64_t)in[(uint64_t)(r0 + k) * RADIX + d] : 0ull;
+  for (uint32_t k = 0; k < CHUNK; k++) first[k] = (r0 + k < r1) ? (uint64_t)in[(uint64_t)(r0 + k) * R + d] : 0ull;
   uint64_t sum = 0;
 #pragma unroll
   for (uint32_t k = 0; k < CHUNK; k++) sum += first[k];
   for (uint32_t k0 = r0 + CHUNK; k0 < r1; k0 += CHUNK) {
 #pragma unroll
     for (uint32_t k = 0; k < CHUNK; k++)
-      if (k0 + k < r1) sum += in[(uint64_t)(k0 + k) * RADIX + d];
+      if (k0 + k < r1) sum += in[(uint64_t)(k0 + k) * R + d];
   }
   s_part[part][d] = sum;
   __syncthreads();
@@ -442,9 +448,9 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   }
   if (DIGIT_BASE) {
     // every thread takes part in the scan (it holds barriers); threads past
-    // the first 256 contribute 0 and come after them
+    // the first R contribute 0 and come after them
     uint32_t all;
-    const uint32_t ex = block_excl_sum_n<PARTS * RADIX / 64>(part == 0 ? (uint32_t)total : 0u, s_sc, &all);
+    const uint32_t ex = block_excl_sum_n<PARTS * R / 64>(part == 0 ? (uint32_t)total : 0u, s_sc, &all);
     if (part == 0) s_base[d] = base + ex;
     __syncthreads();
     base = s_base[d];
@@ -453,17 +459,17 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
 #pragma unroll
   for (uint32_t k = 0; k < CHUNK; k++)
     if (r0 + k < r1) {
-      out[(uint64_t)(r0 + k) * RADIX + d] = (Out)run;
+      out[(uint64_t)(r0 + k) * R + d] = (Out)run;
       run += first[k];
     }
   for (uint32_t k0 = r0 + CHUNK; k0 < r1; k0 += CHUNK) {
     uint64_t c[CHUNK];
 #pragma unroll
-    for (uint32_t k = 0; k < CHUNK; k++) c[k] = (k0 + k < r1) ? (uint64_t)in[(uint64_t)(k0 + k) * RADIX + d] : 0ull;
+    for (uint32_t k = 0; k < CHUNK; k++) c[k] = (k0 + k < r1) ? (uint64_t)in[(uint64_t)(k0 + k) * R + d] : 0ull;
 #pragma unroll
     for (uint32_t k = 0; k < CHUNK; k++)
       if (k0 + k < r1) {
-        out[(uint64_t)(k0 + k) * RADIX + d] = (Out)run;
+        out[(uint64_t)(k0 + k) * R + d] = (Out)run;
         run += c[k];
       }
   }
@@ -472,37 +478,39 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
 }
 
 // Row ranges per digit for a column of n rows: one range per CHUNK rows, at
-// most MAX_PARTS (short columns need no more than one 256-thread workgroup).
-SC_HD uint32_t offset_parts(uint32_t max_rows) {
-  return max_rows <= CHUNK ? 1u : (max_rows <= 2 * CHUNK ? 2u : 4u);
+// most MAX_PARTS (short columns need no more than one 256-thread workgroup),
+// and at most 1024 threads with R digits.
+SC_HD uint32_t offset_parts(uint32_t max_rows, uint32_t R) {
+  const uint32_t p = max_rows <= CHUNK ? 1u : (max_rows <= 2 * CHUNK ? 2u : 4u);
+  return p * R <= 1024u ? p : 1024u / R;
 }
 
-template <int PARTS>
-__global__ __launch_bounds__(RADIX * PARTS) void k_group_offsets(Buffers b, uint32_t pass) {
-  __shared__ uint64_t s_part[PARTS][RADIX];
+template <int PARTS, uint32_t R>
+__global__ __launch_bounds__(R * PARTS) void k_group_offsets(Buffers b, uint32_t pass) {
+  __shared__ uint64_t s_part[PARTS][R];
   const uint32_t g = blockIdx.x;
   const GroupRef gr = b.groups[g];
   const TraceDesc T = b.desc[gr.trace];
   if (pass >= b.layout[gr.trace].npasses || sorted_in_lds(b, T, pass)) return;
   const uint32_t g_first = (g - T.group0) << T.gshift;
   const uint32_t g_n = min(1u << T.gshift, T.ntiles - g_first);
-  uint32_t* rows = b.thist + (uint64_t)(T.tile0 + g_first) * RADIX;
-  const uint64_t total = column_prefix<PARTS, false>(rows, rows, g_n, 0, s_part);
-  if (threadIdx.x < RADIX) b.gtot[(uint64_t)g * RADIX + threadIdx.x] = (uint32_t)total;
+  uint32_t* rows = b.thist + (uint64_t)(T.tile0 + g_first) * R;
+  const uint64_t total = column_prefix<PARTS, false, R>(rows, rows, g_n, 0, s_part);
+  if (threadIdx.x < R) b.gtot[(uint64_t)g * R + threadIdx.x] = (uint32_t)total;
 }
 
-template <int PARTS>
-__global__ __launch_bounds__(RADIX * PARTS) void k_trace_offsets(Buffers b, uint32_t pass) {
-  __shared__ uint64_t s_part[PARTS][RADIX];
-  __shared__ uint64_t s_base[RADIX];
-  __shared__ uint32_t s_sc[PARTS * RADIX / 64];
+template <int PARTS, uint32_t R>
+__global__ __launch_bounds__(R * PARTS) void k_trace_offsets(Buffers b, uint32_t pass) {
+  __shared__ uint64_t s_part[PARTS][R];
+  __shared__ uint64_t s_base[R];
+  __shared__ uint32_t s_sc[PARTS * R / 64];
   const uint32_t t = blockIdx.x;
   const TraceDesc T = b.desc[t];
   if (pass >= b.layout[t].npasses || sorted_in_lds(b, T, pass)) return;  // uniform over the workgroup
   // group rows of the trace -> digit bases (from the column totals) and the
   // absolute base of every group (digit base + earlier groups)
-  (void)column_prefix<PARTS, true>(b.gtot + (uint64_t)T.group0 * RADIX, b.gbase + (uint64_t)T.group0 * RADIX,
-                                    T.ngroups, T.off, s_part, s_sc, s_base);
+  (void)column_prefix<PARTS, true, R>(b.gtot + (uint64_t)T.group0 * R, b.gbase + (uint64_t)T.group0 * R, T.ngroups,
+                                       T.off, s_part, s_sc, s_base);
 }
 
 
@@ -558,15 +566,18 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
 // ------------------------------------------------------------ k_upsweep
 constexpr int HIST_SPREAD = 8;
 
-// Tile histogram of radix digit `pass` (keys in the buffer that pass reads).
+// Tile histogram of radix digit `pass` (keys in the buffer that pass reads),
+// a digit of DB bits (the call's width; passes after the first).
 
-template <typename K, bool LOOP>
+template <typename K, bool LOOP, uint32_t DB>
 __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
   // HIST_SPREAD copies of every bin, one per group of lanes (lane mod
   // HIST_SPREAD): the lanes of one atomic instruction that share a digit
   // mostly hit different copies.  High digits often take a handful of
   // values, and with one copy their atomics serialised up to 64 deep.
-  __shared__ uint32_t h[RADIX * HIST_SPREAD];
+  constexpr uint32_t R = 1u << DB, DPT = R / NT;  // digits per thread
+  static_assert(R % NT == 0, "whole digits per thread");
+  __shared__ uint32_t h[R * HIST_SPREAD];
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -586,51 +597,63 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
     const uint32_t npasses = b.layout[tr.trace].npasses;
     if (pass >= npasses || ((tr.n_flags & TILE_SHORT) && pass >= b.small_from)) continue;
 #pragma unroll
-    for (int q = 0; q < HIST_SPREAD; q++) h[q * NT + tx] = 0;
+    for (uint32_t q = 0; q < HIST_SPREAD * DPT; q++) h[q * NT + tx] = 0;
     __syncthreads();
-    const uint32_t shift = 2 + RADIX_BITS * pass;
+    const uint32_t shift = pass_shift(pass, DB);
     const uint32_t copy = tx & (HIST_SPREAD - 1);
 #pragma unroll
     for (int r = 0; r < ITEMS; r++)
-      if (tx + r * NT < n_in) atomicAdd(&h[((uint32_t)(k[r] >> shift) & (RADIX - 1)) * HIST_SPREAD + copy], 1u);
+      if (tx + r * NT < n_in) atomicAdd(&h[((uint32_t)(k[r] >> shift) & (R - 1)) * HIST_SPREAD + copy], 1u);
     __syncthreads();
-    uint32_t sum = 0;
 #pragma unroll
-    for (int q = 0; q < HIST_SPREAD; q++) sum += h[tx * HIST_SPREAD + q];
-    b.thist[(uint64_t)tile * RADIX + tx] = sum;
+    for (uint32_t e = 0; e < DPT; e++) {
+      const uint32_t d = e * NT + tx;
+      uint32_t sum = 0;
+#pragma unroll
+      for (int q = 0; q < HIST_SPREAD; q++) sum += h[d * HIST_SPREAD + q];
+      b.thist[(uint64_t)tile * R + d] = sum;
+    }
   }
 }
 
 // ------------------------------------------------------------ k_scatter
 //
-// One stable LSD pass on the 8-bit digit at bits [2 + 8 pass, 10 + 8 pass).
-// Keys are loaded wave-striped (key index = wave * 64 * items + item * 64 +
-// lane) so that lane order within an item is key order.  Each item's digit is
-// matched across the wave with eight ballots; the lowest matching lane
-// advances the wave's per-digit counter, which gives every key a stable
-// rank within its wave.  Per-digit wave offsets, the tile's digit starts and
-// the offsets left by the upsweep give each key its destination; keys are
-// staged in LDS in destination order and written out in runs per digit.
+// One stable LSD pass on the digit of DB bits at bits [shift, shift + DB)
+// (pass_shift).  Keys are loaded wave-striped (key index = wave * 64 * items
+// + item * 64 + lane) so that lane order within an item is key order.  Each
+// item's digit is matched across the wave with one ballot per digit bit;
+// the lowest matching lane advances the wave's per-digit counter, which
+// gives every key a stable rank within its wave.  Per-digit wave offsets,
+// the tile's digit starts and the offsets left by the upsweep give each key
+// its destination; keys are staged in LDS in destination order and written
+// out in runs per digit.
 
-// LDS of one scatter workgroup of NTH threads; per-wave digit counters of
-// type C (16 bits suffice: a tile holds 4096 keys).
-template <typename K, int NTH = NT, typename C = uint32_t>
+// LDS of one scatter workgroup of NTH threads over 2^DB digits; per-wave
+// digit counters of type C (16 bits suffice: a tile holds 4096 keys).
+// Destinations are call indices, below 2^32: 32-bit digit bases.
+template <typename K, int NTH, typename C, uint32_t DB>
 struct ScatterLds {
   K keys[TILE];
-  C wh[NTH / 64][RADIX];
-  uint64_t gbase[RADIX];
+  C wh[NTH / 64][1u << DB];
+  uint32_t gbase[1u << DB];
   uint32_t scan[NTH / 64];
   uint32_t bad;  // some digit's destination range leaves the trace
 };
+
+// Counter type of a scatter workgroup: 32 bits for 256 threads over 8-bit
+// digits, else 16 (the LDS of four workgroups per CU).
+template <int NTH, uint32_t DB>
+using ScatterCount = typename std::conditional<NTH == NT && DB == RADIX_BITS, uint32_t, uint16_t>::type;
 
 // Lanes of the wave whose digit equals this lane's: one ballot per digit
 // bit; a lane keeps the ballot where its own bit is set and the complement
 // where it is clear.  The bit is taken as 0 or all ones (a signed one-bit
 // field), so keeping is an XNOR with the ballot's halves.
+template <uint32_t DB>
 __device__ __forceinline__ uint64_t peer_mask(uint32_t dg) {
   uint32_t lo = ~0u, hi = ~0u;
 #pragma unroll
-  for (int bt = 0; bt < (int)RADIX_BITS; bt++) {
+  for (int bt = 0; bt < (int)DB; bt++) {
     const uint32_t all = (uint32_t)__builtin_amdgcn_sbfe((int)dg, bt, 1);  // 0 or ~0
     const uint64_t bal = __builtin_amdgcn_uicmp(all, 0u, 33);  // lanes whose bit is set (33: not equal)
     lo &= ~((uint32_t)bal ^ all);
@@ -640,19 +663,19 @@ __device__ __forceinline__ uint64_t peer_mask(uint32_t dg) {
 }
 
 // Stable rank of every key of the wave among the wave's keys of its digit
-// (the digit at `shift`), items in order: the lowest lane of each group of
+// (the DB bits at `shift`), items in order: the lowest lane of each group of
 // equal digits advances the wave's counter wh[wave][digit] (zero on entry)
 // by the group's size.  On return wh[wave][d] counts the wave's keys of
 // digit d.
-template <typename K, int IT, typename C>
-__device__ __forceinline__ void wave_rank(const K (&key)[IT], uint32_t shift, uint32_t tx, C (*wh)[RADIX],
+template <uint32_t DB, typename K, int IT, typename C>
+__device__ __forceinline__ void wave_rank(const K (&key)[IT], uint32_t shift, uint32_t tx, C (*wh)[1u << DB],
                                           uint32_t (&rank)[IT]) {
   const uint32_t lane = tx & 63u, wave = tx >> 6;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
   for (int i = 0; i < IT; i++) {
-    const uint32_t dg = (uint32_t)(key[i] >> shift) & (RADIX - 1);
-    const uint64_t m = peer_mask(dg);
+    const uint32_t dg = (uint32_t)(key[i] >> shift) & ((1u << DB) - 1);
+    const uint64_t m = peer_mask<DB>(dg);
     const uint32_t before = (uint32_t)__popcll(m & lt_mask);
     const uint32_t old = wh[wave][dg];
     if (before == 0) wh[wave][dg] = (C)(old + (uint32_t)__popcll(m));
@@ -662,55 +685,73 @@ __device__ __forceinline__ void wave_rank(const K (&key)[IT], uint32_t shift, ui
 
 // One stable pass over one tile: key[] holds the tile's keys wave-striped
 // (key index = wave * 64 * items + item * 64 + lane; ~0 past the end, which
-// sorts last); they go to their places in `kout`.
-template <typename K, int NTH = NT, typename C = uint32_t>
+// sorts last); they go to their places in `kout`.  The per-digit steps give
+// each thread DPT consecutive digits (threads past the last digit idle).
+template <typename K, int NTH, typename C, uint32_t DB>
 __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, uint32_t tile, uint32_t tx,
                                              const TileRef& tr, const TraceDesc& T, uint32_t n_in,
-                                             K (&key)[TILE / NTH], K* kout, ScatterLds<K, NTH, C>& S) {
+                                             K (&key)[TILE / NTH], K* kout, ScatterLds<K, NTH, C, DB>& S) {
   constexpr int IT = TILE / NTH, NW = NTH / 64;
+  constexpr uint32_t R = 1u << DB, DPT = R >= (uint32_t)NTH ? R / NTH : 1u;
   const uint32_t wave = tx >> 6;
-  const uint32_t d = tx;  // digit of the per-digit steps (threads below RADIX)
-  const bool dig = tx < RADIX;
-  const uint32_t shift = 2 + RADIX_BITS * pass;
+  const uint32_t d0 = tx * DPT;  // first digit of the per-digit steps
+  const bool dig = d0 < R;
+  const uint32_t shift = pass_shift(pass, DB);
   uint32_t rank[IT];
-  wave_rank(key, shift, tx, S.wh, rank);
+  wave_rank<DB>(key, shift, tx, S.wh, rank);
   // destination base of each digit: group base + offset within the group
-  uint64_t gb = 0;
-  if (dig)
-    gb = b.gbase[(uint64_t)(T.group0 + (tr.local >> T.gshift)) * RADIX + d] + b.thist[(uint64_t)tile * RADIX + d];
+  uint64_t gb[DPT];
+  if (dig) {
+    const uint64_t* grow = b.gbase + (uint64_t)(T.group0 + (tr.local >> T.gshift)) * R;
+    const uint32_t* trow = b.thist + (uint64_t)tile * R;
+#pragma unroll
+    for (uint32_t e = 0; e < DPT; e++) gb[e] = grow[d0 + e] + trow[d0 + e];
+  }
   __syncthreads();
 
   // per digit: tile count, tile-local start, and each wave's first slot
-  // (the digit's start + the counts of the earlier waves); only thread d
-  // touches column d of S.wh, which holds the earlier waves' count in between
-  uint32_t cnt = 0;
+  // (the digit's start + the counts of the earlier waves); only the thread
+  // of digit d touches column d of S.wh, which holds the earlier waves'
+  // count in between
+  uint32_t cnt[DPT], csum = 0;
   if (dig) {
 #pragma unroll
-    for (int w = 0; w < NW; w++) {
-      const uint32_t c = S.wh[w][d];
-      S.wh[w][d] = (C)cnt;
-      cnt += c;
+    for (uint32_t e = 0; e < DPT; e++) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int w = 0; w < NW; w++) {
+        const uint32_t x = S.wh[w][d0 + e];
+        S.wh[w][d0 + e] = (C)c;
+        c += x;
+      }
+      cnt[e] = c;
+      csum += c;
     }
   }
   if (tx == 0) S.bad = 0;
   uint32_t tot;
-  const uint32_t dstart = block_excl_sum_n<NW>(cnt, S.scan, &tot);
+  uint32_t dstart = block_excl_sum_n<NW>(csum, S.scan, &tot);
   if (dig) {
-#pragma unroll
-    for (int w = 0; w < NW; w++) S.wh[w][d] = (C)(S.wh[w][d] + dstart);
-    S.gbase[d] = gb - dstart;
-    // bounds, once per digit: the tile's keys of digit d go to [gb, gb + real)
     // (padding past the trace's end ranks last, in the digit of an all-ones
-    // key: 255, or fewer ones in the top pass of a 64- or 128-bit key)
-    const uint32_t pad_digit = (uint32_t)(~(K)0 >> shift) & (RADIX - 1);
-    const uint32_t real = d == pad_digit ? cnt - (uint32_t)(TILE - n_in) : cnt;
-    if (real && (gb < T.off || gb + real > T.off + T.n)) S.bad = 1;
+    // key: all ones, or fewer in the top pass of a 64- or 128-bit key)
+    const uint32_t pad_digit = (uint32_t)(~(K)0 >> shift) & (R - 1);
+#pragma unroll
+    for (uint32_t e = 0; e < DPT; e++) {
+      const uint32_t d = d0 + e;
+#pragma unroll
+      for (int w = 0; w < NW; w++) S.wh[w][d] = (C)(S.wh[w][d] + dstart);
+      S.gbase[d] = (uint32_t)(gb[e] - dstart);
+      // bounds, once per digit: the tile's keys of digit d go to [gb, gb + real)
+      const uint32_t real = d == pad_digit ? cnt[e] - (uint32_t)(TILE - n_in) : cnt[e];
+      if (real && (gb[e] < T.off || gb[e] + real > T.off + T.n)) S.bad = 1;
+      dstart += cnt[e];
+    }
   }
   __syncthreads();
 
 #pragma unroll
   for (int i = 0; i < IT; i++) {
-    const uint32_t dd = (uint32_t)(key[i] >> shift) & (RADIX - 1);
+    const uint32_t dd = (uint32_t)(key[i] >> shift) & (R - 1);
     S.keys[S.wh[wave][dd] + rank[i]] = key[i];
   }
   __syncthreads();
@@ -723,19 +764,19 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
     const uint32_t j = tx + r * NTH;
     if (j < n_in) {
       const K k = S.keys[j];
-      kout[S.gbase[(uint32_t)(k >> shift) & (RADIX - 1)] + j] = k;
+      kout[(uint32_t)(S.gbase[(uint32_t)(k >> shift) & (R - 1)] + j)] = k;  // a call index (< 2^32)
     }
   }
 }
 
-// NTH threads of TILE / NTH keys each: 256 x 16, or 512 x 8 with 16-bit
-// wave counters (more waves per CU for the same LDS; one-word keys, chosen
-// by the launch shape).
-template <typename K, bool LOOP, int NTH = NT>
+// NTH threads of TILE / NTH keys each: 256 x 16, or 512 x 8 (more waves per
+// CU for the same LDS; one-word keys, chosen by the launch shape); digits of
+// DB bits (8 in pass 0, the call's width after it).
+template <typename K, bool LOOP, int NTH, uint32_t DB>
 __global__ __launch_bounds__(NTH) void k_scatter(Buffers b, uint32_t pass) {
   constexpr int IT = TILE / NTH;
-  using C = typename std::conditional<NTH == NT, uint32_t, uint16_t>::type;
-  __shared__ ScatterLds<K, NTH, C> S;
+  using C = ScatterCount<NTH, DB>;
+  __shared__ ScatterLds<K, NTH, C, DB> S;
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -756,9 +797,9 @@ __global__ __launch_bounds__(NTH) void k_scatter(Buffers b, uint32_t pass) {
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
     if (pass >= L.npasses || sorted_in_lds(b, T, pass)) continue;  // uniform over the workgroup
-    for (uint32_t k = tx; k < (uint32_t)(NTH / 64 * RADIX); k += NTH) (&S.wh[0][0])[k] = 0;
+    for (uint32_t k = tx; k < ((uint32_t)(NTH / 64) << DB); k += NTH) (&S.wh[0][0])[k] = 0;
     __syncthreads();
-    scatter_tile<K, NTH, C>(b, pass, tile, tx, tr, T, n_in, key, (K*)b.keys[(pass + 1) & 1], S);
+    scatter_tile<K, NTH, C, DB>(b, pass, tile, tx, tr, T, n_in, key, (K*)b.keys[(pass + 1) & 1], S);
   }
 }
 
@@ -775,8 +816,8 @@ __global__ __launch_bounds__(NTH) void k_scatter(Buffers b, uint32_t pass) {
 template <typename K, bool LOOP, int NTH = NT>
 __global__ __launch_bounds__(NTH) void k_keygen_scatter(Buffers b) {
   constexpr int IT = TILE / NTH;
-  using C = typename std::conditional<NTH == NT, uint32_t, uint16_t>::type;
-  __shared__ ScatterLds<K, NTH, C> S;
+  using C = ScatterCount<NTH, RADIX_BITS>;
+  __shared__ ScatterLds<K, NTH, C, RADIX_BITS> S;
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -808,17 +849,18 @@ __global__ __launch_bounds__(NTH) void k_keygen_scatter(Buffers b) {
                         : ~(K)0;
     }
     __syncthreads();
-    scatter_tile<K, NTH, C>(b, 0, tile, tx, tr, T, n_in, key, (K*)b.keys[1], S);
+    scatter_tile<K, NTH, C, RADIX_BITS>(b, 0, tile, tx, tr, T, n_in, key, (K*)b.keys[1], S);
   }
 }
 
 // ------------------------------------------------------- k_sort_small
-// A short trace (one tile, or up to four with one-word keys): radix passes
-// small_from .. npasses - 1 all in LDS, one workgroup of NTH threads (16
-// keys each) per trace, with the same stable wave ranking as k_scatter (so
-// the order equals that of the global passes); the sorted keys go to the
-// buffer the scan reads.  Padding past the trace's end holds all-ones keys,
-// which rank after every real key in every pass.
+// A short trace (one tile, or up to four with one-word keys): the key bits
+// from pass small_from's digit on, sorted all in LDS with 8-bit digits, one
+// workgroup of NTH threads (16 keys each) per trace, with the same stable
+// wave ranking as k_scatter (a stable LSD sort of the same bits gives the
+// order of the global passes, whatever their digit width); the sorted keys
+// go to the buffer the scan reads.  Padding past the trace's end holds
+// all-ones keys, which rank after every real key in every pass.
 
 template <typename K, int NTH>
 struct SortLds {
@@ -844,12 +886,15 @@ __global__ __launch_bounds__(NTH) void k_sort_small(Buffers b, const uint32_t* _
     const uint32_t j = wave * (ITEMS * 64) + i * 64 + lane;
     key[i] = (j < n_in) ? src[j] : ~(K)0;
   }
-  for (uint32_t pass = b.small_from; pass < L.npasses; pass++) {
-    const uint32_t shift = 2 + RADIX_BITS * pass;
+  // pass small_from's first bit is 2 + 8 small_from whatever the call's
+  // width (small_from is 0 or 1)
+  const uint32_t n8 = radix_passes(L.key_bits - 2, RADIX_BITS);
+  for (uint32_t pass = b.small_from; pass < n8; pass++) {
+    const uint32_t shift = pass_shift(pass, RADIX_BITS);
     for (uint32_t k = tx; k < (uint32_t)(NW * RADIX); k += NTH) (&S.wh[0][0])[k] = 0;
     __syncthreads();
     uint32_t rank[ITEMS];
-    wave_rank(key, shift, tx, S.wh, rank);
+    wave_rank<RADIX_BITS>(key, shift, tx, S.wh, rank);
     __syncthreads();
     // thread d < 256: digit d's count, then each wave's first slot (the
     // digit's start + the counts of the earlier waves); only thread d
@@ -1932,10 +1977,10 @@ hipError_t launch_layout(const Buffers& b, hipStream_t s) {
   if (!b.n_traces) return hipSuccess;
   if (b.n_traces <= 64 && b.n_tiles >= 64 * b.n_traces)  // a few long traces
     hipLaunchKernelGGL(k_layout<4 * NT>, dim3(b.n_traces), dim3(4 * NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl,
-                       b.wide, b.fitness, b.side ? 1u : 0u);
+                       b.wide, b.fitness, b.side ? 1u : 0u, b.digit_bits);
   else
     hipLaunchKernelGGL(k_layout<NT>, dim3(b.n_traces), dim3(NT), 0, s, b.desc, b.stats_part, b.layout, b.ctrl, b.wide,
-                       b.fitness, b.side ? 1u : 0u);
+                       b.fitness, b.side ? 1u : 0u, b.digit_bits);
   return hipGetLastError();
 }
 hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
@@ -1958,46 +2003,66 @@ hipError_t launch_keygen(const Buffers& b, hipStream_t s) {
   }
   return hipGetLastError();
 }
+template <uint32_t R>
+static hipError_t launch_offsets(const Buffers& b, uint32_t pass, hipStream_t s) {
+  switch (offset_parts(b.max_group_tiles, R)) {
+    case 1: hipLaunchKernelGGL((k_group_offsets<1, R>), dim3(b.n_groups), dim3(R), 0, s, b, pass); break;
+    case 2: hipLaunchKernelGGL((k_group_offsets<2, R>), dim3(b.n_groups), dim3(2 * R), 0, s, b, pass); break;
+    default: hipLaunchKernelGGL((k_group_offsets<4, R>), dim3(b.n_groups), dim3(4 * R), 0, s, b, pass); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (offset_parts(b.max_trace_groups, R)) {
+    case 1: hipLaunchKernelGGL((k_trace_offsets<1, R>), dim3(b.n_traces), dim3(R), 0, s, b, pass); break;
+    case 2: hipLaunchKernelGGL((k_trace_offsets<2, R>), dim3(b.n_traces), dim3(2 * R), 0, s, b, pass); break;
+    default: hipLaunchKernelGGL((k_trace_offsets<4, R>), dim3(b.n_traces), dim3(4 * R), 0, s, b, pass); break;
+  }
+  return hipGetLastError();
+}
+
+// A pass's digit width: 8 bits in pass 0, the call's after it.
+static bool wide_digit(const Buffers& b, uint32_t pass) { return pass > 0 && b.digit_bits == RADIX_WIDE_BITS; }
+
 hipError_t launch_upsweep(const Buffers& b, uint32_t pass, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
+  if (b.digit_bits != RADIX_BITS && b.digit_bits != RADIX_WIDE_BITS) return hipErrorInvalidValue;
+  const bool w9 = wide_digit(b, pass);
   if (pass > 0) {  // digit 0's histograms come from k_keygen
     const bool lp = loops(b, b.grid_stream);
-    auto kern = b.wide ? (lp ? k_upsweep<u128, true> : k_upsweep<u128, false>)
-                       : (lp ? k_upsweep<uint64_t, true> : k_upsweep<uint64_t, false>);
+    auto kern = w9 ? (b.wide ? (lp ? k_upsweep<u128, true, RADIX_WIDE_BITS> : k_upsweep<u128, false, RADIX_WIDE_BITS>)
+                             : (lp ? k_upsweep<uint64_t, true, RADIX_WIDE_BITS>
+                                   : k_upsweep<uint64_t, false, RADIX_WIDE_BITS>))
+                   : (b.wide ? (lp ? k_upsweep<u128, true, RADIX_BITS> : k_upsweep<u128, false, RADIX_BITS>)
+                             : (lp ? k_upsweep<uint64_t, true, RADIX_BITS> : k_upsweep<uint64_t, false, RADIX_BITS>));
     hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, b, pass);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  switch (offset_parts(b.max_group_tiles)) {
-    case 1: hipLaunchKernelGGL(k_group_offsets<1>, dim3(b.n_groups), dim3(RADIX), 0, s, b, pass); break;
-    case 2: hipLaunchKernelGGL(k_group_offsets<2>, dim3(b.n_groups), dim3(2 * RADIX), 0, s, b, pass); break;
-    default: hipLaunchKernelGGL(k_group_offsets<4>, dim3(b.n_groups), dim3(4 * RADIX), 0, s, b, pass); break;
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  switch (offset_parts(b.max_trace_groups)) {
-    case 1: hipLaunchKernelGGL(k_trace_offsets<1>, dim3(b.n_traces), dim3(RADIX), 0, s, b, pass); break;
-    case 2: hipLaunchKernelGGL(k_trace_offsets<2>, dim3(b.n_traces), dim3(2 * RADIX), 0, s, b, pass); break;
-    default: hipLaunchKernelGGL(k_trace_offsets<4>, dim3(b.n_traces), dim3(4 * RADIX), 0, s, b, pass); break;
+  return w9 ? launch_offsets<RADIX_MAX>(b, pass, s) : launch_offsets<RADIX>(b, pass, s);
+}
+
+template <uint32_t DB>
+static hipError_t launch_scatter_db(const Buffers& b, uint32_t pass, hipStream_t s) {
+  const bool lp = loops(b, b.grid_sort);
+  if (b.wide) {
+    auto kern = lp ? k_scatter<u128, true, NT, DB> : k_scatter<u128, false, NT, DB>;
+    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
+  } else if (b.scatter_nt == 2 * NT) {
+    auto kern = lp ? k_scatter<uint64_t, true, 2 * NT, DB> : k_scatter<uint64_t, false, 2 * NT, DB>;
+    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(2 * NT), 0, s, b, pass);
+  } else {
+    auto kern = lp ? k_scatter<uint64_t, true, NT, DB> : k_scatter<uint64_t, false, NT, DB>;
+    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
   }
   return hipGetLastError();
 }
+
 hipError_t launch_scatter(const Buffers& b, uint32_t pass, hipStream_t s) {
   if (!b.n_tiles) return hipSuccess;
   if (!grids_ok(b)) return hipErrorInvalidConfiguration;
-  const bool lp = loops(b, b.grid_sort);
-  if (b.wide) {
-    auto kern = lp ? k_scatter<u128, true> : k_scatter<u128, false>;
-    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
-  } else if (b.scatter_nt == 2 * NT) {
-    auto kern = lp ? k_scatter<uint64_t, true, 2 * NT> : k_scatter<uint64_t, false, 2 * NT>;
-    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(2 * NT), 0, s, b, pass);
-  } else {
-    auto kern = lp ? k_scatter<uint64_t, true> : k_scatter<uint64_t, false>;
-    hipLaunchKernelGGL(kern, dim3(b.grid_sort), dim3(NT), 0, s, b, pass);
-  }
-  return hipGetLastError();
+  if (b.digit_bits != RADIX_BITS && b.digit_bits != RADIX_WIDE_BITS) return hipErrorInvalidValue;
+  return wide_digit(b, pass) ? launch_scatter_db<RADIX_WIDE_BITS>(b, pass, s) : launch_scatter_db<RADIX_BITS>(b, pass, s);
 }
 hipError_t launch_sort_small(const Buffers& b, hipStream_t s) {
   if (b.n_small1) {

@@ -50,7 +50,7 @@ struct TraceLayout {
   uint64_t gmin, smin;
   uint32_t tb, eb, bb, ug, us, wl;
   uint32_t key_bits;   // total bits including the action bits
-  uint32_t npasses;    // 8-bit radix passes over bits [2, key_bits)
+  uint32_t npasses;    // radix passes over bits [2, key_bits) (pass_shift gives each pass's digit)
   uint32_t shift_e;    // epoch field
   uint32_t shift_b;    // block field of global keys; unit field of shared keys
   uint32_t shift_ug;   // unit field of global keys
@@ -69,9 +69,22 @@ struct TraceLayout {
 // and reported as a device error.
 enum : uint32_t { LAYOUT_ERR_WIDE = 1, LAYOUT_ERR_RECORD = 2, ERR_INTERNAL_BOUNDS = 4 };
 
+// Radix digits: pass 0 sorts the 8 bits [2, 10); every later pass of a call
+// sorts `db` bits (the call's digit width, RADIX_BITS or RADIX_WIDE_BITS),
+// so pass p >= 1 sorts bits [10 + db (p - 1), 10 + db p).
 constexpr uint32_t RADIX_BITS = 8;
 constexpr uint32_t RADIX = 1u << RADIX_BITS;
+constexpr uint32_t RADIX_WIDE_BITS = 9;
+constexpr uint32_t RADIX_MAX = 1u << RADIX_WIDE_BITS;
 constexpr uint32_t MAX_PASSES = 16;  // ceil(126 / 8)
+
+SC_HD uint32_t pass_shift(uint32_t pass, uint32_t db) { return pass == 0 ? 2u : 2u + RADIX_BITS + db * (pass - 1); }
+
+// Passes that sort `sorted` (>= 1) key bits with digits of width db after
+// the first.
+SC_HD uint32_t radix_passes(uint32_t sorted, uint32_t db) {
+  return sorted <= RADIX_BITS ? 1u : 1u + (sorted - RADIX_BITS + db - 1) / db;
+}
 
 // A key of a trace wider than 64 bits: two words, one 128-bit integer.
 typedef unsigned __int128 u128;
@@ -86,7 +99,7 @@ SC_HD void stats_init(TraceStats& s) {
 }
 
 // warp: the key carries the side field (divergence bit and statement id).
-SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb, bool warp = false) {
+SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb, bool warp = false, uint32_t db = RADIX_BITS) {
   TraceLayout L;
   const bool has_g = s.gmin <= s.gmax;
   const bool has_s = s.smin <= s.smax;
@@ -113,7 +126,7 @@ SC_HD TraceLayout make_layout(const TraceStats& s, uint32_t tpb, bool warp = fal
   L.srange = has_s ? s.smax - s.smin : 0;
   if (L.key_bits > 128) L.error |= LAYOUT_ERR_WIDE;
   if (s.bad_index != ~0ull) L.error |= LAYOUT_ERR_RECORD;
-  L.npasses = L.error ? 0 : (L.key_bits - 2 + RADIX_BITS - 1) / RADIX_BITS;
+  L.npasses = L.error ? 0 : radix_passes(L.key_bits - 2, db);
   return L;
 }
 

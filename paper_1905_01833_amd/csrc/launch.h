@@ -62,7 +62,7 @@ struct Ctrl {               // per-call control block (device)
   uint64_t first_bad;       // smallest global index of an invalid record
   uint64_t total_entries;   // racing locations of the call
   uint32_t wide_traces;     // traces whose key needs two words
-  uint32_t pad;
+  uint32_t max_sort_bits;   // most key bits a trace of the call sorts (key_bits - 2)
 };
 
 struct RaceOut {            // mirrors sim_race (64 bytes)
@@ -80,9 +80,10 @@ struct Buffers {            // device pointers of one call
   TraceLayout* layout;      // [trace]
   void* keys[2];             // uint64_t[] (one-word keys) or u128[] (two-word keys, `wide`)
   const GroupRef* groups;   // [group]
-  uint32_t* thist;          // [tile][RADIX] digit counts of the current pass -> offsets within the group
-  uint32_t* gtot;           // [group][RADIX] group totals
-  uint64_t* gbase;          // [group][RADIX] absolute digit bases of the group
+  uint32_t* thist;          // [tile][radix] digit counts of the current pass -> offsets within the group
+  uint32_t* gtot;           // [group][radix] group totals
+  uint64_t* gbase;          // [group][radix] absolute digit bases of the group
+                            // (radix: 2^8 in pass 0, 2^digit_bits after it; rows of RADIX_MAX words at most)
   uint32_t* agg;            // [tile][SW]
   TileOut* tout;            // [tile]
   RaceOut* cross;           // [tile]
@@ -114,6 +115,7 @@ struct Buffers {            // device pointers of one call
   uint32_t key_bytes;       // 8 or 16
   uint32_t fitness;         // 1: fitness keys (epoch and action dropped), for the EP fitness count
   const uint32_t* side;     // warp-aware check: one side word per record (call index), else nullptr
+  uint32_t digit_bits;      // digit width of the radix passes after pass 0: RADIX_BITS or RADIX_WIDE_BITS
 };
 
 // Barrier instances (per trace and boundary) of the redundant-barrier check:

@@ -316,3 +316,64 @@ extern "C" uint32_t hs_tile_walk(uint32_t n, uint32_t per_cu, uint32_t n_cu, uin
   }
   return grid;
 }
+
+// The radix digit plan (pass_shift, radix_passes): for every sorted width
+// and digit width, the passes' digits tile the bits [2, 2 + sorted) exactly,
+// and a stable LSD sort with that plan (counting sort per digit, the
+// all-ones padding of a partial tile included) equals a full sort of the
+// keys.  Returns the number of failures.
+template <typename K>
+static int plan_sort_impl(uint64_t seed, int trials, uint32_t db) {
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 7;
+  auto rnd = [&]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
+  int bad = 0;
+  const uint32_t maxbits = sizeof(K) == 8 ? 64 : 128;
+  for (int t = 0; t < trials; t++) {
+    const uint32_t key_bits = 3 + (uint32_t)(rnd() % (maxbits - 2));
+    const uint32_t n = 1 + (uint32_t)(rnd() % 300);
+    std::vector<K> k(n), pad(n + 5);
+    for (uint32_t i = 0; i < n; i++) {
+      K v = ((K)rnd() << 64 % (8 * sizeof(K))) ^ (K)rnd();
+      if (key_bits < 8 * sizeof(K)) v &= (((K)1) << key_bits) - 1;
+      if (rnd() % 4 == 0 && i) v = k[rnd() % i];  // repeats
+      k[i] = v;
+    }
+    // the sort proper ignores the two action bits: bits >= 2 compared, ties
+    // in input order (what a stable sort of bits [2, key_bits) gives)
+    std::vector<K> want = k;
+    std::stable_sort(want.begin(), want.end(), [](K a, K b) { return (a >> 2) < (b >> 2); });
+    std::vector<K> cur = k;
+    for (uint32_t i = 0; i < 5; i++) cur.push_back(~(K)0);  // padding ranks last in every pass
+    const uint32_t np = radix_passes(key_bits - 2, db);
+    for (uint32_t p = 0; p < np; p++) {
+      const uint32_t sh = pass_shift(p, db), w = p == 0 ? RADIX_BITS : db;
+      std::vector<std::vector<K>> bucket(1u << w);
+      for (const K& v : cur) bucket[(uint32_t)(v >> sh) & ((1u << w) - 1)].push_back(v);
+      cur.clear();
+      for (auto& bk : bucket) cur.insert(cur.end(), bk.begin(), bk.end());
+    }
+    cur.resize(n);
+    if (cur != want) bad++;
+  }
+  return bad;
+}
+
+extern "C" int hs_digit_plan(uint64_t seed, int trials) {
+  int bad = 0;
+  for (uint32_t db : {RADIX_BITS, RADIX_WIDE_BITS})
+    for (uint32_t sorted = 1; sorted <= 126; sorted++) {
+      const uint32_t np = radix_passes(sorted, db);
+      if (pass_shift(0, db) != 2) bad++;
+      for (uint32_t p = 0; p + 1 < np + 1; p++) {
+        const uint32_t w = p == 0 ? RADIX_BITS : db;
+        if (pass_shift(p + 1, db) != pass_shift(p, db) + w) bad++;
+      }
+      // the last pass starts inside the sorted bits and the passes reach their end
+      if (!(pass_shift(np - 1, db) < 2 + sorted && pass_shift(np, db) >= 2 + sorted)) bad++;
+      if (db == RADIX_BITS && np != (sorted + 7) / 8) bad++;
+      if (np > MAX_PASSES) bad++;
+    }
+  for (uint32_t db : {RADIX_BITS, RADIX_WIDE_BITS})
+    bad += plan_sort_impl<uint64_t>(seed + db, trials, db) + plan_sort_impl<u128>(seed + 2 * db, trials, db);
+  return bad;
+}

@@ -329,14 +329,19 @@ SHAPES = [
     {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 0, "scan_wgs_per_cu": 0, "group_shift_bias": 0},
     {"stream_wgs_per_cu": 1, "sort_wgs_per_cu": 1, "scan_wgs_per_cu": 1, "group_shift_bias": -1},
     {"stream_wgs_per_cu": 2, "sort_wgs_per_cu": 1, "scan_wgs_per_cu": 1, "group_shift_bias": 1,
-     "scatter_threads": 512},
-    {"stream_wgs_per_cu": 8, "sort_wgs_per_cu": 4, "scan_wgs_per_cu": 2, "group_shift_bias": -12},
+     "scatter_threads": 512, "digit_bits": 9},
+    {"stream_wgs_per_cu": 8, "sort_wgs_per_cu": 4, "scan_wgs_per_cu": 2, "group_shift_bias": -12,
+     "digit_bits": 9},
     {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 2, "scan_wgs_per_cu": 0, "group_shift_bias": 12,
      "scatter_threads": 512},
     {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 0, "scan_wgs_per_cu": 0, "group_shift_bias": 0,
      "scatter_threads": 512},
     {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 1, "scan_wgs_per_cu": 0, "group_shift_bias": 0,
      "scatter_threads": 256},
+    {"stream_wgs_per_cu": 0, "sort_wgs_per_cu": 0, "scan_wgs_per_cu": 0, "group_shift_bias": 12,
+     "scatter_threads": 256, "digit_bits": 9},
+    {"stream_wgs_per_cu": 1, "sort_wgs_per_cu": 2, "scan_wgs_per_cu": 1, "group_shift_bias": 0,
+     "digit_bits": 8},
 ]
 
 

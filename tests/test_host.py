@@ -104,6 +104,31 @@ def test_head_tests_match_head_levels():
     assert _hostsim().hs_head_tests(2024, 20000) == 0
 
 
+def test_radix_digit_plan():
+    """The radix passes (keys.h pass_shift / radix_passes) with 8-bit digits,
+    and with 9-bit digits after the first pass: their digits tile the sorted
+    key bits exactly, 8-bit plans take ceil(bits / 8) passes, and a stable
+    LSD sort under either plan (all-ones padding included) equals a full
+    sort of random one- and two-word keys."""
+    assert _hostsim().hs_digit_plan(77, 400) == 0
+
+
+def test_nine_bit_digits_save_a_pass_where_expected():
+    """9-bit digits after the 8-bit first pass save a pass exactly where
+    1 + ceil((b - 8) / 9) < ceil(b / 8): for the sorted widths of the
+    batched workload's largest traces (41..44 bits) but not for 45..48."""
+    import math
+
+    def p8(b):
+        return math.ceil(b / 8)
+
+    def p9(b):
+        return 1 if b <= 8 else 1 + math.ceil((b - 8) / 9)
+
+    assert [b for b in range(40, 49) if p9(b) < p8(b)] == [41, 42, 43, 44]
+    assert p8(42) == 6 and p9(42) == 5
+
+
 @pytest.mark.parametrize("seed", range(120))
 def test_host_model_matches_oracle_small(seed):
     rng = np.random.default_rng(seed)
