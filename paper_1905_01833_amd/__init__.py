@@ -252,17 +252,35 @@ def _tables(offsets, tpb, n_records):
     return offsets, n_traces, tpb
 
 
+class _ResultMemory:
+    """A library result (sim_result): freed with sim_result_free once the
+    last array that views its entries or summaries is gone."""
+
+    def __init__(self, res_p):
+        self._p = res_p
+        self._free = load().sim_result_free  # bound now: usable during shutdown
+
+    def __del__(self):
+        p, self._p = self._p, None
+        if p is not None:
+            self._free(p)
+
+
+def _view(ptr, n, dtype, owner):
+    """Array of n `dtype` items at host address ptr, owned by `owner`."""
+    if n == 0:
+        return np.zeros(0, dtype=dtype)
+    buf = (ctypes.c_char * (n * dtype.itemsize)).from_address(ptr)
+    buf._owner = owner  # the buffer, and so every array on it, keeps the result alive
+    return np.frombuffer(buf, dtype=dtype)
+
+
 def _take_result(res_p):
-    lib = load()
+    """The entries and summaries of a result as arrays on the library's own
+    memory (no copy)."""
     r = res_p.contents
-    races = np.zeros(r.n_races, dtype=RACE_DTYPE)
-    if r.n_races:
-        ctypes.memmove(races.ctypes.data, r.races, r.n_races * RACE_DTYPE.itemsize)
-    summ = np.zeros(r.n_traces, dtype=SUMMARY_DTYPE)
-    if r.n_traces:
-        ctypes.memmove(summ.ctypes.data, r.traces, r.n_traces * SUMMARY_DTYPE.itemsize)
-    lib.sim_result_free(res_p)
-    return races, summ
+    owner = _ResultMemory(res_p)
+    return _view(r.races, r.n_races, RACE_DTYPE, owner), _view(r.traces, r.n_traces, SUMMARY_DTYPE, owner)
 
 
 def sim_check_traces(ctx, records: np.ndarray, offsets=None, threads_per_block=1):
@@ -578,8 +596,10 @@ class Context:
             sim_destroy(self._ctx)
             self._ctx = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be cleared when
+        # a destructor runs during interpreter shutdown)
+        if not getattr(self, "_ctx", None) or _finalizing():  # (also after a failed __init__)
             return
         try:
             self.close()
@@ -747,8 +767,10 @@ class Server:
             self._srv = None
             self._keep.clear()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be cleared when
+        # a destructor runs during interpreter shutdown)
+        if not getattr(self, "_srv", None) or _finalizing():  # (also after a failed __init__)
             return
         try:
             self.close()

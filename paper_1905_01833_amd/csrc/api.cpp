@@ -73,7 +73,9 @@ struct sim_ctx {
     hipGraphExec_t exec = nullptr;
     const void* records = nullptr;
     hipStream_t stream = nullptr;
-    uint64_t total = 0, table_hash = 0, gen = 0;
+    uint64_t total = 0, gen = 0;
+    std::vector<uint64_t> offsets;  // the captured call's tables (compared in full)
+    std::vector<uint32_t> tpb;
     uint32_t n_traces = 0, n_tiles = 0, guess = 0;
     uint64_t tuning_gen = 0;
     uint64_t meta_gen = 0;  // the table upload the captured launches read
@@ -717,17 +719,12 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   // may not allocate: instantiating a graph does.)
   const bool use_graph =
       (c->flags & SIM_CFG_GRAPHS) && !prof && s != nullptr && guess > 0 && !trace_recs && !noalloc && !fit && !warp;
-  uint64_t th = 1469598103934665603ull;  // FNV-1a over the per-call tables
-  if (use_graph) {
-    const unsigned char* q = (const unsigned char*)offsets;
-    for (size_t k = 0; k < (size_t)(n_traces + 1) * sizeof(uint64_t); k++) th = (th ^ q[k]) * 1099511628211ull;
-    q = (const unsigned char*)tpb;
-    for (size_t k = 0; k < (size_t)n_traces * sizeof(uint32_t); k++) th = (th ^ q[k]) * 1099511628211ull;
-  }
   auto& G = c->graph;
   const bool replay = use_graph && G.exec && G.records == d_records && G.stream == s && G.total == total &&
-                      G.n_traces == n_traces && G.n_tiles == n_tiles && G.table_hash == th && G.gen == c->alloc_gen &&
-                      G.guess == guess && G.tuning_gen == c->tuning_gen && G.wide == wide && G.db == db;
+                      G.n_traces == n_traces && G.n_tiles == n_tiles && G.gen == c->alloc_gen && G.guess == guess &&
+                      G.tuning_gen == c->tuning_gen && G.wide == wide && G.db == db &&
+                      std::memcmp(G.offsets.data(), offsets, (size_t)(n_traces + 1) * sizeof(uint64_t)) == 0 &&
+                      std::memcmp(G.tpb.data(), tpb, (size_t)n_traces * sizeof(uint32_t)) == 0;
   // The tables: a replay finds them on the device when no other call
   // uploaded tables since the captured one (same shape, same buffers, same
   // records: the same tables); otherwise they are built and uploaded.
@@ -758,7 +755,8 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       G.total = total;
       G.n_traces = n_traces;
       G.n_tiles = n_tiles;
-      G.table_hash = th;
+      G.offsets.assign(offsets, offsets + n_traces + 1);
+      G.tpb.assign(tpb, tpb + n_traces);
       G.gen = c->alloc_gen;
       G.guess = guess;
       G.tuning_gen = c->tuning_gen;
