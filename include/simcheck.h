@@ -451,10 +451,10 @@ int sim_autotune(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offs
  * Admission by device-memory footprint.  A request's footprint is what its
  * check may hold on the device: its records when they come from host
  * memory (16 bytes each), two key buffers of 16 bytes per record (two-word
- * keys are possible until the device has seen the request), about 4.3 KiB
- * per 4096-record tile and 136 bytes per trace of tables, and the output's
- * first allocation (up to 64 Ki entries of 64 bytes), each with 1/8 growth
- * headroom.  Every worker is charged the device bytes it may hold: an idle
+ * keys are possible until the device has seen the request), about 8.3 KiB
+ * per 4096-record tile (tables for 9-bit radix digits) and 136 bytes per
+ * trace of tables, and the output's first allocation (up to 64 Ki entries
+ * of 64 bytes), each with 1/8 growth headroom.  Every worker is charged the device bytes it may hold: an idle
  * worker what it holds, a worker checking a batch the larger of that and
  * the batch's footprint, and its buffers never grow past its charge (a
  * worker whose buffers would grow past it releases them and allocates the
