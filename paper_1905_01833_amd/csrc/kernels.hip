@@ -944,6 +944,9 @@ __global__ __launch_bounds__(NTH) void k_sort_small(Buffers b, const uint32_t* _
 // k_scan_cross, which finishes the locations that cross tile boundaries.
 // Counts inside a tile fit 16 bits and pair sums 32 bits.
 
+// Two one-word keys, 8-byte aligned (a trace's keys start at any record).
+typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+
 #define META(i) ((mp[(i) / 6] >> (5 * ((i) % 6))) & 31u)
 // the same for a loop index that is not unrolled (no dynamic register indexing)
 __device__ __forceinline__ uint32_t meta_at(const uint32_t mp[3], uint32_t i) {
@@ -1111,8 +1114,21 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     // are padding below.
     const uint32_t j0 = ITEMS * tid, jl = n_in - 1;
     K kk[ITEMS];
+    if (sizeof(K) == 8 && n_in == (uint32_t)TILE) {
+      // a whole tile of one-word keys: two keys per load (a lane's sixteen
+      // keys are one 128-byte line, so each load instruction touches 64
+      // lines whatever its width; half the instructions, half the touches)
+      const u64x2_a8* p2 = (const u64x2_a8*)(src + j0);
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) kk[i] = src[min(j0 + (uint32_t)i, jl)];
+      for (int i = 0; i < ITEMS / 2; i++) {
+        const u64x2_a8 v = p2[i];
+        kk[2 * i] = (K)v.x;
+        kk[2 * i + 1] = (K)v.y;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) kk[i] = src[min(j0 + (uint32_t)i, jl)];
+    }
     // the key before the thread's first (the previous tile's last for
     // thread 0; not read at a trace's first key)
     const K prev0 = src[(j0 == 0 && tr.local == 0) ? 0 : (int64_t)min(j0, n_in) - 1];
