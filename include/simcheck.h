@@ -424,12 +424,14 @@ int sim_get_tuning(const sim_ctx* ctx, uint32_t size_class, sim_tuning* t);
  * sim_check_traces_device) under candidate shapes -- coordinate descent over
  * the workgroups per CU of the scatter (0, 1, 2, 4, 8), of the tile scan,
  * of the streaming kernels, then the histogram-group bias (-2 .. +2), then
- * the scatter's other thread count (256 or 512).  A
- * candidate's time is the fastest of `reps` calls (0: 3; at least 5 when a
- * call takes under 10 ms), and it replaces the current shape only when it
- * is at least 1.5 % faster.  The chosen shape is stored for the input's
- * size class and written to *best.  Results of the trial calls are
- * discarded; on error the class keeps its old shape.                      */
+ * the scatter's other thread count (256 or 512).  Each candidate runs
+ * `reps` calls (0: 3; at least 5 when a call takes under 10 ms) taking turns
+ * with as many calls of the current shape, so that a drift of the GPU's
+ * speed during tuning reaches both; it replaces the current shape only when
+ * its fastest call is at least 0.5 % faster than the current shape's.  The
+ * chosen shape is stored for the input's size class and written to *best.
+ * Results of the trial calls are discarded; on error the class keeps its
+ * old shape.                                                               */
 int sim_autotune(sim_ctx* ctx, const sim_record* d_records, const uint64_t* offsets, uint32_t n_traces,
                  const uint32_t* threads_per_block, void* stream, uint32_t reps, sim_tuning* best);
 

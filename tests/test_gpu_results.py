@@ -1,0 +1,64 @@
+"""Result memory: entry lists of 1 MiB and more come from a small pool of
+pinned host blocks that sim_result_free recycles (at most eight blocks;
+beyond that, plain host memory).  Results held at the same time, freed in
+any order and then reused must each stay the oracle's, byte for byte.
+
+Every case prints its name before it touches the GPU.  Inputs are seeded
+and synthetic; expected values come from oracle/ only."""
+import gc
+
+import numpy as np
+import pytest
+
+import oracle
+import tracegen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[gpu-results] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1905_01833_amd as pkg
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def test_large_results_held_freed_and_reused(ctx):
+    recs, _ = tracegen.c1(n_blocks=64, inject_rate=5e-2, seed=71)
+    want, wsum = oracle.closed_form(recs, None, 256)
+    assert len(want) * 64 >= 1 << 20, len(want)  # large enough for a pinned block
+    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    for rnd in range(2):
+        held = []
+        for k in range(10):  # more results alive than pinned blocks
+            say(f"round {rnd}, call {k}: {len(want)} entries")
+            got, gsum = ctx.check_traces_device(dev, None, 256)
+            torch.cuda.synchronize()
+            held.append((got, gsum))
+        for got, gsum in held:
+            assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes()
+        # free in a mixed order; each remaining result is untouched
+        for k in (3, 0, 7, 9, 1):
+            held[k] = None
+        gc.collect()
+        for item in held:
+            if item is not None:
+                assert item[0].tobytes() == want.tobytes()
+        held.clear()
+        gc.collect()
+    # a small result after the large ones (plain host memory)
+    say("small result")
+    small = recs[:5000]
+    got, _ = ctx.check_traces_device(dev[:5000], None, 256)
+    torch.cuda.synchronize()
+    assert got.tobytes() == oracle.closed_form(small, None, 256)[0].tobytes()
