@@ -202,13 +202,17 @@ def check_workload(pkg, torch, name, steps, warmup, recs, offsets, tpb, desc, au
     n = int(len(recs))
     dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream().cuda_stream
+    # a stream of its own (default priority): the library captures and
+    # replays HIP graphs on a non-null stream only
+    side = torch.cuda.Stream()
+    stream = side.cuda_stream
     ctx = pkg.Context(0, graphs=True)
     try:
-        log(f"{name}: autotune")
-        tuning = ctx.autotune(dev, offsets, tpb, stream=stream, reps=autotune_reps)
-        log(f"{name}: {steps} timed steps")
-        sec, races, summ = timed_calls(ctx, dev, offsets, tpb, stream, steps, warmup)
+        with torch.cuda.stream(side):
+            log(f"{name}: autotune")
+            tuning = ctx.autotune(dev, offsets, tpb, stream=stream, reps=autotune_reps)
+            log(f"{name}: {steps} timed steps")
+            sec, races, summ = timed_calls(ctx, dev, offsets, tpb, stream, steps, warmup)
     finally:
         ctx.close()
     prof_steps = max(2, min(steps, 5))

@@ -69,6 +69,19 @@ struct sim_ctx {
   uint32_t db_guess = RADIX_BITS, fit_db_guess = RADIX_BITS, warp_db_guess = RADIX_BITS;
   uint64_t alloc_gen = 0;   // bumped whenever a device buffer is reallocated
   uint64_t meta_gen = 0;    // bumped whenever a call's tables are uploaded
+  uint64_t host_gen = 0;    // bumped whenever the host copy's trace and group tables are rebuilt
+  // the trace and group tables in the host copy, and what they were built
+  // from: a call of the same offsets, threads per block, group bias and
+  // LDS-sort limit reuses them while host_gen is unchanged
+  struct {
+    std::vector<uint64_t> offsets;
+    std::vector<uint32_t> tpb;
+    int32_t bias = 0;
+    uint32_t small_max_tiles = 0;
+    uint64_t host_gen = 0;
+    bool valid = false;
+    uint32_t n_hgroups = 0, max_group_tiles = 1, max_trace_groups = 1, n_small1 = 0, n_small4 = 0;
+  } plan;
 
   // one captured launch sequence, replayed while calls keep the same shape
   struct {
@@ -548,18 +561,28 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
       radix_passes(bits_guess, RADIX_WIDE_BITS) < radix_passes(bits_guess, RADIX_BITS))
     db = RADIX_WIDE_BITS;
   if (noalloc) db = RADIX_BITS;
-  uint64_t n_hgroups64 = 0;
-  for (uint32_t i = 0; i < n_traces; i++) {
-    const uint64_t nt = (offsets[i + 1] - offsets[i] + TILE - 1) / TILE;
-    const int gs = group_shift(nt, tune.group_shift_bias);
-    n_hgroups64 += (nt + (1ull << gs) - 1) >> gs;
-  }
+  // traces sorted whole in LDS: one tile, or up to four with one-word keys
+  const bool wide = wide_guess;
+  const uint32_t small_max_tiles = wide ? 1u : 4u;
+  auto& P = c->plan;
+  const bool plan_hit = P.valid && P.host_gen == c->host_gen && P.bias == tune.group_shift_bias &&
+                        P.small_max_tiles == small_max_tiles && P.offsets.size() == (size_t)n_traces + 1 &&
+                        std::memcmp(P.offsets.data(), offsets, ((size_t)n_traces + 1) * sizeof(uint64_t)) == 0 &&
+                        std::memcmp(P.tpb.data(), tpb, (size_t)n_traces * sizeof(uint32_t)) == 0;
+  uint64_t n_hgroups64 = plan_hit ? P.n_hgroups : 0;
+  if (!plan_hit)
+    for (uint32_t i = 0; i < n_traces; i++) {
+      const uint64_t nt = (offsets[i + 1] - offsets[i] + TILE - 1) / TILE;
+      const int gs = group_shift(nt, tune.group_shift_bias);
+      n_hgroups64 += (nt + (1ull << gs) - 1) >> gs;
+    }
   const size_t h_bytes = host_bytes(n_traces, n_tiles, n_hgroups64);
   if (c->h_meta_cap < h_bytes) {
     if (noalloc) return fail(c, SIM_EINVAL, "the call's tables exceed the context's pinned tables");
     if (c->h_meta) (void)hipHostFree(c->h_meta);
     c->h_meta = nullptr;
     c->h_meta_cap = 0;
+    c->host_gen++;  // (a plan hit never gets here: its tables fitted before)
     e = hipHostMalloc(&c->h_meta, h_bytes + h_bytes / 8, hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(c, e, "pinned allocation");
     c->h_meta_cap = h_bytes + h_bytes / 8;
@@ -568,11 +591,15 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   TileRef* ht = (TileRef*)(hd + n_traces);
   GroupRef* hg = (GroupRef*)(ht + n_tiles);
   uint32_t* hs = (uint32_t*)(hg + n_hgroups64);
-  // traces sorted whole in LDS: one tile, or up to four with one-word keys
-  const bool wide = wide_guess;
-  const uint32_t small_max_tiles = wide ? 1u : 4u;
   uint32_t t0 = 0, g0 = 0, max_group_tiles = 1, max_trace_groups = 1, n_small1 = 0, n_small4 = 0;
-  for (uint32_t i = 0; i < n_traces; i++) {
+  if (plan_hit) {  // the host copy holds this call's trace and group tables
+    g0 = P.n_hgroups;
+    max_group_tiles = P.max_group_tiles;
+    max_trace_groups = P.max_trace_groups;
+    n_small1 = P.n_small1;
+    n_small4 = P.n_small4;
+  }
+  for (uint32_t i = 0; i < (plan_hit ? 0u : n_traces); i++) {
     const uint64_t n = offsets[i + 1] - offsets[i];
     const uint32_t nt = (uint32_t)((n + TILE - 1) / TILE);
     const uint32_t gs = (uint32_t)group_shift(nt, tune.group_shift_bias);
@@ -587,7 +614,21 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
     g0 += ng;
   }
   const uint32_t n_hgroups = g0;
-  if (n_small4) memmove(hs + n_small1, hs + n_traces - n_small4, (size_t)n_small4 * sizeof(uint32_t));
+  if (!plan_hit) {
+    if (n_small4) memmove(hs + n_small1, hs + n_traces - n_small4, (size_t)n_small4 * sizeof(uint32_t));
+    c->host_gen++;
+    P.offsets.assign(offsets, offsets + n_traces + 1);
+    P.tpb.assign(tpb, tpb + n_traces);
+    P.bias = tune.group_shift_bias;
+    P.small_max_tiles = small_max_tiles;
+    P.host_gen = c->host_gen;
+    P.valid = true;
+    P.n_hgroups = n_hgroups;
+    P.max_group_tiles = max_group_tiles;
+    P.max_trace_groups = max_trace_groups;
+    P.n_small1 = n_small1;
+    P.n_small4 = n_small4;
+  }
   // the (trace, tile) table: filled only when the tables are uploaded (a
   // graph replay whose upload is still on the device skips both)
   auto fill_tiles = [&]() {
