@@ -1469,59 +1469,70 @@ __global__ __launch_bounds__(NT) void k_scan_cross(Buffers b, uint32_t passes_do
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   const uint32_t j = blockIdx.x * NWAVE + wave;
   if (j >= b.n_tiles) return;
-  if (!b.tout[j].owns) {
+  // one round of loads: the ownership flag, and for the common span (the
+  // location ends in the next tile) that tile's head level and both
+  // summaries; a tile that owns a crossing location is not its trace's last
+  const bool has_next = j + 1 < b.n_tiles;
+  const uint32_t owns = b.tout[j].owns;
+  const uint32_t next_m = has_next ? b.agg[(uint64_t)(j + 1) * SW] : 1u;
+  State S = load_state(b.agg + (uint64_t)j * SW);
+  const State S1 = has_next ? load_state(b.agg + (uint64_t)(j + 1) * SW) : identity();
+  if (!owns) {
     if (lane == 0) b.cross_flag[j] = 0;
     return;
   }
-  const TileRef tr = b.tiles[j];
-  const TraceDesc T = b.desc[tr.trace];
-  const TraceLayout L = b.layout[tr.trace];
-  const uint32_t last = T.tile0 + T.ntiles - 1;  // last tile of the trace
-
-  // end of the span: the first later tile of the trace with a location head
-  uint32_t k = j + 1;  // candidate
-  bool to_end = false;
-  while (true) {
-    const uint32_t c = k + lane;
-    const bool head = c <= last && b.agg[(uint64_t)c * SW] == 0;
-    const uint64_t bal = __ballot(head);
-    if (bal) {
-      k += (uint32_t)__ffsll((unsigned long long)bal) - 1;
-      break;
-    }
-    if (k + 64 > last) {
-      to_end = true;
-      break;
-    }
-    k += 64;
-  }
-  // combine summaries of tiles j .. end-1 (end = k, or last + 1 when the
-  // location runs to the end of the trace)
-  const uint32_t end = to_end ? last + 1 : k;
-  State S = identity();
-  if (end == j + 1) S = load_state(b.agg + (uint64_t)j * SW);  // the common span: no tree needed
-  else for (uint32_t c0 = j; c0 < end; c0 += 64) {
-    const uint32_t c = c0 + lane;
-    State s = c < end ? load_state(b.agg + (uint64_t)c * SW) : identity();
-#pragma unroll
-    for (uint32_t dlt = 1; dlt < 64; dlt <<= 1) {
-      const State o = shfl_down_state(s, dlt);
-      if ((lane & (2 * dlt - 1)) == 0) s = combine(s, o);
-    }
-    S = combine(S, readlane_state(s, 0));
-  }
   uint64_t fin[5];
-  if (to_end) {
-    const uint64_t* t = tail_sums(S);
-#pragma unroll
-    for (int q = 0; q < 5; q++) fin[q] = t[q];
+  if (next_m == 0) {  // tile j + 1 holds a location head: the span is tile j
+    open_sums(S, S1, fin);
   } else {
-    open_sums(S, load_state(b.agg + (uint64_t)k * SW), fin);
+    const TraceDesc T = b.desc[b.tiles[j].trace];
+    const uint32_t last = T.tile0 + T.ntiles - 1;  // last tile of the trace
+    // end of the span: the first later tile of the trace with a location
+    // head (tile j + 1 has none)
+    uint32_t k = j + 2;  // candidate
+    bool to_end = false;
+    while (true) {
+      if (k > last) {
+        to_end = true;
+        break;
+      }
+      const uint32_t c = k + lane;
+      const bool head = c <= last && b.agg[(uint64_t)c * SW] == 0;
+      const uint64_t bal = __ballot(head);
+      if (bal) {
+        k += (uint32_t)__ffsll((unsigned long long)bal) - 1;
+        break;
+      }
+      k += 64;
+    }
+    // combine summaries of tiles j + 1 .. end - 1 into S (end = k, or last +
+    // 1 when the location runs to the end of the trace)
+    const uint32_t end = to_end ? last + 1 : k;
+    for (uint32_t c0 = j + 1; c0 < end; c0 += 64) {
+      const uint32_t c = c0 + lane;
+      State s = c < end ? load_state(b.agg + (uint64_t)c * SW) : identity();
+#pragma unroll
+      for (uint32_t dlt = 1; dlt < 64; dlt <<= 1) {
+        const State o = shfl_down_state(s, dlt);
+        if ((lane & (2 * dlt - 1)) == 0) s = combine(s, o);
+      }
+      S = combine(S, readlane_state(s, 0));
+    }
+    if (to_end) {
+      const uint64_t* t = tail_sums(S);
+#pragma unroll
+      for (int q = 0; q < 5; q++) fin[q] = t[q];
+    } else {
+      open_sums(S, load_state(b.agg + (uint64_t)k * SW), fin);
+    }
   }
   const bool racing = fin[K_WW] + fin[K_RW] + fin[K_AW] + fin[K_AR] > 0;
   if (lane == 0) {
     b.cross_flag[j] = racing ? 1u : 0u;
     if (racing) {
+      const TileRef tr = b.tiles[j];
+      const TraceDesc T = b.desc[tr.trace];
+      const TraceLayout L = b.layout[tr.trace];
       const uint64_t start = (uint64_t)tr.local * TILE;
       const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
       const K key = ((const K*)b.keys[L.npasses & 1u])[T.off + start + n_in - 1];
