@@ -887,7 +887,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
     wide_guess = true;
     return run(c, d_records, trace_recs, offsets, n_traces, tpb, s, sink, noalloc);
   }
-  const uint32_t needed = ctl.max_passes;
+  const uint32_t needed = ctrl_passes(ctl.pass_bits);
   if (needed > guess) {
     // too few passes ran: the scan kernels above returned at once
     for (int k = first_scan_ev; k < nev / 2; k++) ev_counts[k] = false;
@@ -899,7 +899,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   if (!all_small) {  // an LDS-sorted call tells nothing about global passes
     pass_guess = needed;
     db_guess = db;
-    bits_guess = ctl.max_sort_bits;
+    bits_guess = ctl.pass_bits & 0xFFFFu;
   }
   wide_guess = ctl.wide_traces > 0;
   if (fit) {

@@ -200,12 +200,11 @@ __device__ void block_seg_scan(const uint64_t (&v)[K], uint64_t (&ex)[K], uint64
 // workgroup (no kernel before k_layout reads them); k_init serves calls
 // without tiles.
 __device__ __forceinline__ void ctrl_reset(Ctrl* ctrl) {
-  ctrl->max_passes = 0;
+  ctrl->pass_bits = 0;
   ctrl->error_flags = 0;
   ctrl->first_bad = ~0ull;
   ctrl->total_entries = 0;
   ctrl->wide_traces = 0;
-  ctrl->max_sort_bits = 0;
 }
 
 __global__ void k_init(Ctrl* ctrl) {
@@ -382,12 +381,15 @@ __global__ __launch_bounds__(NTH) void k_layout(const TraceDesc* __restrict__ de
     if (L.error & LAYOUT_ERR_RECORD)
       atomicMin((unsigned long long*)&ctrl->first_bad, (unsigned long long)(T.off + S.bad_index));
   }
-  if (L.npasses > __hip_atomic_load(&ctrl->max_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    atomicMax(&ctrl->max_passes, L.npasses);
-  // the host picks the next call's digit width from this
-  if (T.n && !L.error && L.key_bits - 2 > __hip_atomic_load(&ctrl->max_sort_bits, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT))
-    atomicMax(&ctrl->max_sort_bits, L.key_bits - 2);
+  // one atomic for the call's pass count and widest key (the host picks the
+  // next call's digit width from it): with one digit width per call a
+  // trace's passes grow with its sorted bits, so the largest packed word
+  // holds the largest of each; traces without passes add nothing.  (The
+  // workgroups of all traces run at once and mostly read zero here, so
+  // each atomic on this one word costs the whole launch time.)
+  const uint32_t pb = L.npasses ? (L.npasses << 16) | (L.key_bits - 2) : 0u;
+  if (pb > __hip_atomic_load(&ctrl->pass_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&ctrl->pass_bits, pb);
 }
 
 // A trace of at most b.small_max_tiles tiles is sorted whole in one
@@ -1088,7 +1090,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
   // nothing to do on an error, or when fewer radix passes ran than some
   // trace needs (the host then runs the missing passes and scans again)
   if (b.ctrl->error_flags) return;
-  if (b.ctrl->max_passes > passes_done) return;
+  if (ctrl_passes(b.ctrl->pass_bits) > passes_done) return;
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free
@@ -1465,7 +1467,7 @@ __device__ __forceinline__ State readlane_state(const State& s, int src) {
 template <typename K>
 __global__ __launch_bounds__(NT) void k_scan_cross(Buffers b, uint32_t passes_done) {
   if (b.ctrl->error_flags) return;
-  if (b.ctrl->max_passes > passes_done) return;
+  if (ctrl_passes(b.ctrl->pass_bits) > passes_done) return;
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   const uint32_t j = blockIdx.x * NWAVE + wave;
   if (j >= b.n_tiles) return;
@@ -1547,7 +1549,7 @@ __global__ __launch_bounds__(NT) void k_scan_cross(Buffers b, uint32_t passes_do
 
 __global__ __launch_bounds__(NT) void k_group_sums(Buffers b, uint32_t passes_done) {
   __shared__ uint32_t sc[NWAVE];
-  if (b.ctrl->error_flags || b.ctrl->max_passes > passes_done) return;
+  if (b.ctrl->error_flags || ctrl_passes(b.ctrl->pass_bits) > passes_done) return;
   const uint32_t t = blockIdx.x * GROUP + threadIdx.x;
   const uint32_t c = t < b.n_tiles ? b.tout[t].in_count + b.cross_flag[t] : 0u;
   uint32_t tot;
@@ -1563,7 +1565,7 @@ constexpr uint32_t DIRECT_GROUPS = 32;
 template <bool DIRECT>
 __global__ __launch_bounds__(NT) void k_scan_out(Buffers b, uint32_t passes_done) {
   __shared__ uint32_t sc[NWAVE];
-  if (b.ctrl->error_flags || b.ctrl->max_passes > passes_done) return;
+  if (b.ctrl->error_flags || ctrl_passes(b.ctrl->pass_bits) > passes_done) return;
   // entries of the earlier groups
   uint64_t before = 0;
   if (DIRECT) {
@@ -1684,7 +1686,7 @@ template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT) void k_fit_tiles(Buffers b, uint32_t passes_done) {
   __shared__ uint32_t s_g[NWAVE], s_f[NWAVE];
   if (b.ctrl->error_flags) return;
-  if (b.ctrl->max_passes > passes_done) return;  // the host runs the missing passes first
+  if (ctrl_passes(b.ctrl->pass_bits) > passes_done) return;  // the host runs the missing passes first
   const TileWalk tw = tile_walk(b.n_tiles, gridDim.x, blockIdx.x);
   for (uint32_t tile = tw.first; tile < tw.end; tile = LOOP ? tile + tw.step : tw.end) {
     __syncthreads();  // LDS of the previous tile is free

@@ -57,13 +57,15 @@ struct TileOut {     // per tile, from the tile scan
 };
 
 struct Ctrl {               // per-call control block (device)
-  uint32_t max_passes;      // max radix passes over the call's traces
+  uint32_t pass_bits;       // (most radix passes of a trace << 16) | the key bits that trace sorts
   uint32_t error_flags;     // LAYOUT_ERR_* / ERR_* of any trace or kernel
   uint64_t first_bad;       // smallest global index of an invalid record
   uint64_t total_entries;   // racing locations of the call
   uint32_t wide_traces;     // traces whose key needs two words
-  uint32_t max_sort_bits;   // most key bits a trace of the call sorts (key_bits - 2)
+  uint32_t pad;
 };
+// Radix passes the call's traces need (all of them done: the scan may run).
+SC_HD uint32_t ctrl_passes(uint32_t pass_bits) { return pass_bits >> 16; }
 
 struct RaceOut {            // mirrors sim_race (64 bytes)
   uint32_t trace;
