@@ -607,7 +607,9 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
     max_group_tiles = std::max(max_group_tiles, std::min(nt, 1u << gs));
     max_trace_groups = std::max(max_trace_groups, ng);
     hd[i] = TraceDesc{offsets[i], n, tpb[i], t0, nt, g0, ng, gs, {0, 0, 0}};
-    for (uint32_t k = 0; k < ng; k++) hg[g0 + k] = GroupRef{i, 0};
+    for (uint32_t k = 0; k < ng; k++)
+      hg[g0 + k] = GroupRef{i, t0 + (k << gs), std::min(nt - (k << gs), 1u << gs) | (nt <= small_max_tiles ? TILE_SHORT : 0u),
+                            0u};
     if (nt == 1) hs[n_small1++] = i;
     else if (nt >= 2 && nt <= small_max_tiles) hs[n_traces - 1 - n_small4++] = i;  // from the back
     t0 += nt;

@@ -422,7 +422,7 @@ constexpr int MAX_PARTS = 4;     // offset kernels: up to 4 row ranges per digit
 // per wave of the workgroup and s_base one 64-bit word per digit.
 template <int PARTS, bool DIGIT_BASE, uint32_t R, typename In, typename Out>
 __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t base, uint64_t (*s_part)[R],
-                                  uint32_t* s_sc = nullptr, uint64_t* s_base = nullptr) {
+                                  uint32_t* s_sc = nullptr, uint64_t* s_base = nullptr, bool skip = false) {
   const uint32_t d = threadIdx.x % R, part = threadIdx.x / R;
   const uint32_t per = (n + PARTS - 1) / PARTS;
   const uint32_t r0 = min(n, part * per), r1 = min(n, r0 + per);
@@ -431,6 +431,9 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   uint64_t first[CHUNK];
 #pragma unroll
   for (uint32_t k = 0; k < CHUNK; k++) first[k] = (r0 + k < r1) ? (uint64_t)in[(uint64_t)(r0 + k) * R + d] : 0ull;
+  // skip (uniform over the workgroup): the column needs no offsets in this
+  // pass; decided by the caller from loads that went out with these
+  if (skip) return 0;
   uint64_t sum = 0;
 #pragma unroll
   for (uint32_t k = 0; k < CHUNK; k++) sum += first[k];
@@ -491,13 +494,15 @@ template <int PARTS, uint32_t R>
 __global__ __launch_bounds__(R * PARTS) void k_group_offsets(Buffers b, uint32_t pass) {
   __shared__ uint64_t s_part[PARTS][R];
   const uint32_t g = blockIdx.x;
+  // the group's rows are read together with the trace's pass count (one
+  // round trip after the group reference); a group that needs no offsets in
+  // this pass writes nothing
   const GroupRef gr = b.groups[g];
-  const TraceDesc T = b.desc[gr.trace];
-  if (pass >= b.layout[gr.trace].npasses || sorted_in_lds(b, T, pass)) return;
-  const uint32_t g_first = (g - T.group0) << T.gshift;
-  const uint32_t g_n = min(1u << T.gshift, T.ntiles - g_first);
-  uint32_t* rows = b.thist + (uint64_t)(T.tile0 + g_first) * R;
-  const uint64_t total = column_prefix<PARTS, false, R>(rows, rows, g_n, 0, s_part);
+  const bool skip = pass >= b.layout[gr.trace].npasses || ((gr.n_flags & TILE_SHORT) && pass >= b.small_from);
+  uint32_t* rows = b.thist + (uint64_t)gr.first * R;
+  const uint64_t total =
+      column_prefix<PARTS, false, R>(rows, rows, gr.n_flags & ~TILE_SHORT, 0, s_part, nullptr, nullptr, skip);
+  if (skip) return;
   if (threadIdx.x < R) b.gtot[(uint64_t)g * R + threadIdx.x] = (uint32_t)total;
 }
 

@@ -46,8 +46,10 @@ constexpr uint32_t TILE_SHORT = 1u << 31;
 constexpr uint32_t STAGE_CAP_BITS = 16;
 constexpr uint64_t STAGE_CAP_MASK = (1ull << STAGE_CAP_BITS) - 1;
 
-struct GroupRef {    // histogram group -> trace
+struct GroupRef {    // histogram group -> trace, and its tiles
   uint32_t trace;
+  uint32_t first;    // call index of the group's first tile
+  uint32_t n_flags;  // tiles in the group (bits 0..30); bit 31 (TILE_SHORT): the trace is sorted whole in LDS
   uint32_t pad;
 };
 
