@@ -1165,7 +1165,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
       // the thresholds stay opaque: compared as they are, not rewritten as
       // shifts of the difference
       HeadThresholds<K> hth = head_thresholds_t<K>(L);
-      opaque_sgpr(hth.low);
+      opaque_sgpr(hth.thread);
       opaque_sgpr(hth.space);
       opaque_sgpr(hth.unit_g);
       opaque_sgpr(hth.block);

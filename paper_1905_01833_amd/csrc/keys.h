@@ -194,16 +194,20 @@ struct HeadTests {
   bool h[4];
 };
 // The thresholds of one trace (the lowest bits of its fields), computed once.
+// Every threshold is a power of two at or above the thread field's lowest
+// bit 2^(2 + sb), so the bits below it (action, side field), which start no
+// group, need no masking: for such a threshold T, d >= T exactly when the
+// masked difference is, and a difference above those bits is d >= 2^(2 + sb).
 template <typename K>
 struct HeadThresholds {
-  K low;    // bits that do not start a group (action, side field)
-  K space;  // the space bit: a key at or above it is a shared key
+  K thread;  // the thread field's lowest bit
+  K space;   // the space bit: a key at or above it is a shared key
   K unit_g, block, epoch;
 };
 template <typename K>
 SC_HD HeadThresholds<K> head_thresholds_t(const TraceLayout& L) {
   HeadThresholds<K> t;
-  t.low = ~(K)lowmask(2 + L.sb);
+  t.thread = (K)1 << (2 + L.sb);
   t.space = (K)1 << L.shift_space;
   t.unit_g = (K)1 << L.shift_ug;
   t.block = (K)1 << L.shift_b;
@@ -212,12 +216,12 @@ SC_HD HeadThresholds<K> head_thresholds_t(const TraceLayout& L) {
 }
 template <typename K>
 SC_HD HeadTests<K> head_tests_t(const HeadThresholds<K>& t, K p, K x) {
-  const K d = (x ^ p) & t.low;
+  const K d = x ^ p;
   HeadTests<K> r;
   r.h[1] = d >= t.block;
   r.h[0] = d >= t.unit_g || (x >= t.space && r.h[1]);  // shared: the block is part of the location
   r.h[2] = d >= t.epoch;
-  r.h[3] = d != (K)0;
+  r.h[3] = d >= t.thread;
   return r;
 }
 template <typename K>
