@@ -1133,8 +1133,14 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         kk[2 * i + 1] = (K)v.y;
       }
     } else {
+      // a partial tile: items past its end repeat its last key with the
+      // action bits set to the padding class; they differ from the key before
+      // them below the thread field only, so they start no run
 #pragma unroll
-      for (int i = 0; i < ITEMS; i++) kk[i] = src[min(j0 + (uint32_t)i, jl)];
+      for (int i = 0; i < ITEMS; i++) {
+        const K v = src[min(j0 + (uint32_t)i, jl)];
+        kk[i] = j0 + (uint32_t)i < n_in ? v : (v | (K)CLS_NONE);
+      }
     }
     // the key before the thread's first (the previous tile's last for
     // thread 0; not read at a trace's first key)
@@ -1174,15 +1180,14 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
         const K k = kk[i];
-        const bool valid = j0 + (uint32_t)i < n_in;
         const bool first = i == 0 && trace_first;
         const HeadTests<K> ht = head_tests_t<K>(hth, prev, k);
-        const bool h0 = valid && (first || ht.h[0]);
-        const bool h1 = valid && (first || ht.h[1]);
-        const bool h2 = valid && (first || ht.h[2]);
-        const bool h3 = valid && (first || ht.h[3]);
+        const bool h0 = first || ht.h[0];
+        const bool h1 = first || ht.h[1];
+        const bool h2 = first || ht.h[2];
+        const bool h3 = first || ht.h[3];
         const uint32_t lv = h0 ? 0u : h1 ? 1u : h2 ? 2u : h3 ? 3u : 4u;
-        const uint32_t c = valid ? action_class(k) : CLS_NONE;
+        const uint32_t c = action_class(k);  // padding: CLS_NONE
         snap[0] = h0 ? cnt : snap[0];
         snap[1] = h1 ? cnt : snap[1];
         snap[2] = h2 ? cnt : snap[2];
