@@ -105,7 +105,7 @@ struct sim_ctx {
   const sim_tuning* force = nullptr;  // sim_autotune's candidate
   std::string err;
 
-  DevBuf records, keys0, keys1, meta, stats_part, layout, thist, gtot, gbase, agg, tout, cross, cross_flag,
+  DevBuf records, keys0, keys1, meta, stats_part, layout, thist, tcnt, gtot, gbase, agg, tout, cross, cross_flag,
       group_sum, stage, stage_ref, ctrl, out, bar, bar_base;
   // the barrier-divergence check: arrival counts of host calls, chunk table,
   // per-block results, per-chunk counts and offsets, divergent blocks
@@ -132,7 +132,7 @@ namespace {
 
 // Every device buffer of a context.
 std::vector<DevBuf*> all_bufs(sim_ctx* c) {
-  return {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist, &c->gtot,
+  return {&c->records, &c->keys0, &c->keys1, &c->meta, &c->stats_part, &c->layout, &c->thist, &c->tcnt, &c->gtot,
           &c->gbase,   &c->agg,   &c->tout,  &c->cross, &c->cross_flag, &c->group_sum, &c->stage,
           &c->stage_ref, &c->ctrl, &c->out, &c->bar, &c->bar_base, &c->div_in, &c->div_chunks, &c->div_blocks,
           &c->div_cnt, &c->div_off, &c->div_out, &c->fit_out, &c->side, &c->warp_rm, &c->warp_out, &c->warp_n};
@@ -342,8 +342,8 @@ constexpr uint32_t NOALLOC_MAX_TILES = (1u << 23) / TILE + NOALLOC_MAX_TRACES;
 
 // The fixed device regions of a call, in one order for both ways of
 // providing them (grow-only context buffers, or the scratch).
-enum { R_KEYS0, R_KEYS1, R_META, R_STATS, R_LAYOUT, R_THIST, R_GTOT, R_GBASE, R_AGG, R_TOUT, R_CROSS, R_CFLAG,
-       R_GSUM, R_CTRL, N_REGION };
+enum { R_KEYS0, R_KEYS1, R_META, R_STATS, R_LAYOUT, R_THIST, R_TCNT, R_GTOT, R_GBASE, R_AGG, R_TOUT, R_CROSS,
+       R_CFLAG, R_GSUM, R_CTRL, N_REGION };
 
 // radix: digits of the call's widest pass (RADIX, or RADIX_MAX with 9-bit digits).
 void region_bytes(size_t need[N_REGION], uint64_t total, uint32_t n_traces, uint32_t n_tiles, uint64_t n_hgroups,
@@ -355,6 +355,7 @@ void region_bytes(size_t need[N_REGION], uint64_t total, uint32_t n_traces, uint
   need[R_STATS] = (size_t)n_tiles * sizeof(TraceStats);
   need[R_LAYOUT] = (size_t)n_traces * sizeof(TraceLayout);
   need[R_THIST] = (size_t)n_tiles * radix * 4;
+  need[R_TCNT] = (size_t)n_tiles * radix * 2;
   need[R_GTOT] = (size_t)n_hgroups * radix * 4;
   need[R_GBASE] = (size_t)n_hgroups * radix * 8;
   need[R_AGG] = (size_t)n_tiles * SW * 4;
@@ -367,8 +368,8 @@ void region_bytes(size_t need[N_REGION], uint64_t total, uint32_t n_traces, uint
 
 DevBuf* region_buf(sim_ctx* c, int r) {
   DevBuf* const bufs[N_REGION] = {&c->keys0, &c->keys1, &c->meta,  &c->stats_part, &c->layout,
-                                  &c->thist, &c->gtot,  &c->gbase, &c->agg,        &c->tout,
-                                  &c->cross, &c->cross_flag, &c->group_sum, &c->ctrl};
+                                  &c->thist, &c->tcnt,  &c->gtot,  &c->gbase,      &c->agg,
+                                  &c->tout,  &c->cross, &c->cross_flag, &c->group_sum, &c->ctrl};
   return bufs[r];
 }
 
@@ -704,6 +705,7 @@ int run(sim_ctx* c, const sim_record* d_records, const sim_record* const* trace_
   b.n_small4 = n_small4;
   b.small_max_tiles = small_max_tiles;
   b.thist = (uint32_t*)reg[R_THIST];
+  b.tcnt = (uint16_t*)reg[R_TCNT];
   b.gtot = (uint32_t*)reg[R_GTOT];
   b.gbase = (uint64_t*)reg[R_GBASE];
   b.agg = (uint32_t*)reg[R_AGG];

@@ -235,7 +235,7 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool val
 // NTH threads of TILE / NTH records each.
 template <bool LOOP, bool HIST, int NTH = NT>
 __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles, uint32_t n_tiles,
-                                               TraceStats* __restrict__ part, uint32_t* __restrict__ thist,
+                                               TraceStats* __restrict__ part, uint16_t* __restrict__ tcnt,
                                                Ctrl* ctrl, const uint32_t* __restrict__ side) {
   constexpr int IT = TILE / NTH, NW = NTH / 64;
   static_assert(NTH >= (int)RADIX, "one thread per histogram bin");
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
       S.max_tid = mt; S.max_epoch = me; S.max_stmt = ms; S.pad = 0;
       part[tile] = S;
     }
-    if (HIST && tx < RADIX) thist[(uint64_t)tile * RADIX + tx] = h[tx];
+    if (HIST && tx < RADIX) tcnt[(uint64_t)tile * RADIX + tx] = (uint16_t)h[tx];
   }
 }
 
@@ -401,10 +401,11 @@ __device__ __forceinline__ bool sorted_in_lds(const Buffers& b, const TraceDesc&
 
 // ----------------------------------------------------- radix offsets
 //
-// Each tile stores the digit histogram of the current pass in thist[tile].
+// Each tile stores the digit histogram of the current pass in tcnt[tile]
+// (16-bit counts: half the bytes of the offsets they become).
 // k_group_offsets turns the rows of each histogram group (2^gshift
 // consecutive tiles of one trace, about sqrt(ntiles) of them) into
-// exclusive offsets within the group and stores the group totals;
+// exclusive offsets within the group, in thist, and stores the group totals;
 // k_trace_offsets turns a trace's group totals into absolute bases (trace
 // offset + digit base + earlier groups).  Separate launches make the
 // previous kernel's stores visible to plain, cached loads; no workgroup
@@ -499,9 +500,10 @@ __global__ __launch_bounds__(R * PARTS) void k_group_offsets(Buffers b, uint32_t
   // this pass writes nothing
   const GroupRef gr = b.groups[g];
   const bool skip = pass >= b.layout[gr.trace].npasses || ((gr.n_flags & TILE_SHORT) && pass >= b.small_from);
-  uint32_t* rows = b.thist + (uint64_t)gr.first * R;
-  const uint64_t total =
-      column_prefix<PARTS, false, R>(rows, rows, gr.n_flags & ~TILE_SHORT, 0, s_part, nullptr, nullptr, skip);
+  const uint16_t* counts = b.tcnt + (uint64_t)gr.first * R;
+  uint32_t* offsets = b.thist + (uint64_t)gr.first * R;
+  const uint64_t total = column_prefix<PARTS, false, R>(counts, offsets, gr.n_flags & ~TILE_SHORT, 0, s_part, nullptr,
+                                                        nullptr, skip);
   if (skip) return;
   if (threadIdx.x < R) b.gtot[(uint64_t)g * R + threadIdx.x] = (uint32_t)total;
 }
@@ -566,7 +568,7 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
     if ((T.tpb & (T.tpb - 1)) == 0) keys_of(std::integral_constant<int, BLK_POW2>{});
     else keys_of(std::integral_constant<int, BLK_DIV>{});
     __syncthreads();
-    b.thist[(uint64_t)tile * RADIX + tx] = h[tx];
+    b.tcnt[(uint64_t)tile * RADIX + tx] = (uint16_t)h[tx];
   }
 }
 
@@ -618,7 +620,7 @@ __global__ __launch_bounds__(NT) void k_upsweep(Buffers b, uint32_t pass) {
       uint32_t sum = 0;
 #pragma unroll
       for (int q = 0; q < HIST_SPREAD; q++) sum += h[d * HIST_SPREAD + q];
-      b.thist[(uint64_t)tile * R + d] = sum;
+      b.tcnt[(uint64_t)tile * R + d] = (uint16_t)sum;
     }
   }
 }
@@ -2008,7 +2010,7 @@ hipError_t launch_stats(const Buffers& b, hipStream_t s) {
   const bool lp = loops(b, b.grid_stream);
   auto kern = b.fuse0 ? (lp ? k_stats<true, true> : k_stats<false, true>)
                       : (lp ? k_stats<true, false> : k_stats<false, false>);
-  hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, b.tiles, b.n_tiles, b.stats_part, b.thist,
+  hipLaunchKernelGGL(kern, dim3(b.grid_stream), dim3(NT), 0, s, b.tiles, b.n_tiles, b.stats_part, b.tcnt,
                      b.ctrl, b.side);
   return hipGetLastError();
 }
