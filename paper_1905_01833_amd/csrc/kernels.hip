@@ -428,10 +428,16 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   const uint32_t per = (n + PARTS - 1) / PARTS;
   const uint32_t r0 = min(n, part * per), r1 = min(n, r0 + per);
   // the first chunk stays in registers for the write loop (a range of at
-  // most CHUNK rows is read once)
+  // most CHUNK rows is read once).  Row indices are clamped to the column's
+  // last row (a column has at least one), so every load is issued without a
+  // branch; rows past the range count zero.
+  const uint32_t last = n ? n - 1 : 0;
   uint64_t first[CHUNK];
 #pragma unroll
-  for (uint32_t k = 0; k < CHUNK; k++) first[k] = (r0 + k < r1) ? (uint64_t)in[(uint64_t)(r0 + k) * R + d] : 0ull;
+  for (uint32_t k = 0; k < CHUNK; k++) {
+    const uint64_t v = in[(uint64_t)min(r0 + k, last) * R + d];
+    first[k] = (r0 + k < r1) ? v : 0ull;
+  }
   // skip (uniform over the workgroup): the column needs no offsets in this
   // pass; decided by the caller from loads that went out with these
   if (skip) return 0;
@@ -440,8 +446,10 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   for (uint32_t k = 0; k < CHUNK; k++) sum += first[k];
   for (uint32_t k0 = r0 + CHUNK; k0 < r1; k0 += CHUNK) {
 #pragma unroll
-    for (uint32_t k = 0; k < CHUNK; k++)
-      if (k0 + k < r1) sum += in[(uint64_t)(k0 + k) * R + d];
+    for (uint32_t k = 0; k < CHUNK; k++) {
+      const uint64_t v = in[(uint64_t)min(k0 + k, last) * R + d];
+      sum += (k0 + k < r1) ? v : 0ull;
+    }
   }
   s_part[part][d] = sum;
   __syncthreads();
@@ -471,7 +479,10 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
   for (uint32_t k0 = r0 + CHUNK; k0 < r1; k0 += CHUNK) {
     uint64_t c[CHUNK];
 #pragma unroll
-    for (uint32_t k = 0; k < CHUNK; k++) c[k] = (k0 + k < r1) ? (uint64_t)in[(uint64_t)(k0 + k) * R + d] : 0ull;
+    for (uint32_t k = 0; k < CHUNK; k++) {
+      const uint64_t v = in[(uint64_t)min(k0 + k, last) * R + d];
+      c[k] = (k0 + k < r1) ? v : 0ull;
+    }
 #pragma unroll
     for (uint32_t k = 0; k < CHUNK; k++)
       if (k0 + k < r1) {
