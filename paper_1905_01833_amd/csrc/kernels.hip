@@ -228,6 +228,19 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t dg, bool val
 }
 
 // -------------------------------------------------------------- k_stats
+// A tile's records, read through the pointer its table entry holds.  To the
+// compiler that pointer is generic, so it would load through flat
+// instructions, and a flat load also holds up every wait for an LDS
+// operation.  Records are always in memory the GPU addresses as global, so
+// they are read as global memory.
+typedef uint64_t rec_words __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) rec_words* GRecords;
+__device__ __forceinline__ GRecords global_records(const void* p) { return (GRecords)p; }
+__device__ __forceinline__ ulonglong2 load_record(GRecords p, uint32_t j) {
+  const rec_words v = p[j];
+  return ulonglong2{v.x, v.y};
+}
+
 // Per-tile partial statistics; k_layout reduces them per trace.
 
 // HIST: also the tile histogram of radix digit 0 for calls whose digit 0 is
@@ -251,7 +264,7 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
     const TileRef tr = tiles[tile];
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
-    const ulonglong2* p = (const ulonglong2*)tr.rec;
+    const GRecords p = global_records(tr.rec);
     uint64_t gmin = ~0ull, gmax = 0, smin = ~0ull, smax = 0, bad = ~0ull;
     uint32_t mt = 0, me = 0, ms = 0;
     if (side)  // warp-aware check: the largest statement id sizes the key's side field
@@ -263,7 +276,7 @@ __global__ __launch_bounds__(NTH) void k_stats(const TileRef* __restrict__ tiles
     // all loads first: every record of the thread in flight
     ulonglong2 vr[IT];
 #pragma unroll
-    for (int r = 0; r < IT; r++) vr[r] = tx + r * NTH < n_in ? p[tx + r * NTH] : ulonglong2{0ull, 0ull};
+    for (int r = 0; r < IT; r++) vr[r] = tx + r * NTH < n_in ? load_record(p, tx + r * NTH) : ulonglong2{0ull, 0ull};
 #pragma unroll
     for (int r = 0; r < IT; r++) {
       const uint32_t j = tx + r * NTH;
@@ -554,11 +567,11 @@ __global__ __launch_bounds__(NT) void k_keygen(Buffers b) {
     __syncthreads();
     const uint64_t start = (uint64_t)tr.local * TILE;
     const uint32_t n_in = (uint32_t)min<uint64_t>((uint64_t)TILE, T.n - start);
-    const ulonglong2* p = (const ulonglong2*)tr.rec;
+    const GRecords p = global_records(tr.rec);
     K* kout = (K*)b.keys[0] + T.off + start;
     ulonglong2 vr[ITEMS];  // all loads first
 #pragma unroll
-    for (int r = 0; r < ITEMS; r++) vr[r] = tx + r * NT < n_in ? p[tx + r * NT] : ulonglong2{0ull, 0ull};
+    for (int r = 0; r < ITEMS; r++) vr[r] = tx + r * NT < n_in ? load_record(p, tx + r * NT) : ulonglong2{0ull, 0ull};
     // the block size's form is uniform over the tile: one branch, and each
     // side computes the block index one way
     auto keys_of = [&](auto blk_form) {
@@ -848,12 +861,12 @@ __global__ __launch_bounds__(NTH) void k_keygen_scatter(Buffers b) {
     const TileRef tr = b.tiles[tile];
     const uint32_t lane = tx & 63u, wave = tx >> 6;
     const uint32_t n_in = tr.n_flags & ~TILE_SHORT;
-    const ulonglong2* p = (const ulonglong2*)tr.rec;
+    const GRecords p = global_records(tr.rec);
     ulonglong2 vr[IT];  // all loads first: every record of the thread in flight
 #pragma unroll
     for (int i = 0; i < IT; i++) {
       const uint32_t j = wave * (IT * 64) + i * 64 + lane;
-      vr[i] = j < n_in ? p[j] : ulonglong2{0ull, 0ull};
+      vr[i] = j < n_in ? load_record(p, j) : ulonglong2{0ull, 0ull};
     }
     const TraceDesc T = b.desc[tr.trace];
     const TraceLayout L = b.layout[tr.trace];
