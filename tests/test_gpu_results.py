@@ -62,3 +62,37 @@ def test_large_results_held_freed_and_reused(ctx):
     got, _ = ctx.check_traces_device(dev[:5000], None, 256)
     torch.cuda.synchronize()
     assert got.tobytes() == oracle.closed_form(small, None, 256)[0].tobytes()
+
+
+def test_call_tables_follow_every_change_of_shape():
+    """Calls whose trace tables differ in the split of the same records, or
+    only in threads per block, alternate on one context (with and without
+    graph replay): every call uses its own tables, never the previous
+    call's, and equals the oracle."""
+    import paper_1905_01833_amd as pkg
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    recs, _ = tracegen.c1(n_blocks=16, inject_rate=2e-3, seed=81)
+    n = len(recs)
+    shapes = [
+        (np.array([0, n // 3, n], dtype=np.uint64), np.array([256, 256], dtype=np.uint32)),
+        (np.array([0, n // 2, n], dtype=np.uint64), np.array([256, 256], dtype=np.uint32)),
+        (np.array([0, n // 2, n], dtype=np.uint64), np.array([256, 512], dtype=np.uint32)),
+    ]
+    wants = [oracle.closed_form(recs, off, tpb) for off, tpb in shapes]
+    dev = torch.from_numpy(recs.view(np.uint8).reshape(-1, 16)).to("cuda:0")
+    for graphs in (False, True):
+        c = pkg.Context(0, graphs=graphs)
+        try:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                for rep in range(3):
+                    for k, (off, tpb) in enumerate(shapes):
+                        say(f"graphs={graphs}, round {rep}, shape {k}")
+                        got, gsum = c.check_traces_device(dev, off, tpb, stream=stream.cuda_stream)
+                        torch.cuda.synchronize()
+                        want, wsum = wants[k]
+                        assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes(), (graphs, rep, k)
+        finally:
+            c.close()
