@@ -194,6 +194,78 @@ __device__ void block_seg_scan(const uint64_t (&v)[K], uint64_t (&ex)[K], uint64
   __syncthreads();
 }
 
+// Per 16-bit field maximum of two words of four fields.
+__device__ __forceinline__ uint32_t max_u16x2(uint32_t a, uint32_t b) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t,
+                            __builtin_elementwise_max(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint64_t max_u16x4(uint64_t a, uint64_t b) {
+  return ((uint64_t)max_u16x2((uint32_t)(a >> 32), (uint32_t)(b >> 32)) << 32) | max_u16x2((uint32_t)a, (uint32_t)b);
+}
+
+// LDS of block_nested_scan: each thread's prefix before its last head per
+// level, and the waves' totals.
+struct NestedLds {
+  uint64_t P[NT][4];
+  uint64_t C[NWAVE];
+  uint64_t H[NWAVE];
+};
+
+// The nested segmented scan of the tile scan's class counts, over the NT
+// threads of a workgroup, in the value a segmented scan (block_seg_scan) of
+// the per-level aggregates (SEGF if the thread holds a head at level l or
+// coarser) | (its counts after the last such head) gives.  The levels nest
+// (a head at level l is one at every finer level too), so the segment of
+// level l before thread t starts after the last head at level l or coarser
+// of h, the last earlier thread that holds one: its counts are C(t) - P_l(h),
+// with C the plain exclusive prefix of the counts and P_l(h) = C(h) + the
+// counts of h's elements before that head (P_l(h) <= C(t) field by field:
+// no borrows).  One plain add scan, one max scan of (thread + 1) per level
+// in 16-bit fields, and one LDS look-up per level replace four segmented
+// 64-bit scans.
+// cnt: the thread's class counts (16-bit fields); snap[l]: its counts before
+// its last head at level l or coarser; mn: its smallest head level.  ex: the
+// exclusive value per level (SEGF: some earlier thread holds a head at that
+// level or coarser); tot: the workgroup's inclusive value per level.
+__device__ void block_nested_scan(uint64_t cnt, const uint64_t (&snap)[4], uint32_t mn, uint64_t (&ex)[4],
+                                  uint64_t (&tot)[4], NestedLds& S) {
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6, tid = threadIdx.x;
+  const uint64_t cinc = wave_incl_scan(cnt, [](uint64_t a, uint64_t b) { return a + b; });
+  uint64_t hv = 0;
+#pragma unroll
+  for (int l = 0; l < 4; l++) hv |= mn <= (uint32_t)l ? (uint64_t)(tid + 1) << (16 * l) : 0ull;
+  const uint64_t hinc = wave_incl_scan(hv, max_u16x4);
+  if (lane == 63) {
+    S.C[wave] = cinc;
+    S.H[wave] = hinc;
+  }
+  uint64_t c = dpp<DPP_WAVE_SHR1>(cinc), h = dpp<DPP_WAVE_SHR1>(hinc);
+  __syncthreads();
+  uint64_t call = 0, hall = 0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; w++) {
+    const uint64_t xc = S.C[w], xh = S.H[w];
+    if (w < (int)wave) {
+      c += xc;
+      h = max_u16x4(h, xh);
+    }
+    call += xc;
+    hall = max_u16x4(hall, xh);
+  }
+#pragma unroll
+  for (int l = 0; l < 4; l++) S.P[tid][l] = c + snap[l];
+  __syncthreads();
+#pragma unroll
+  for (int l = 0; l < 4; l++) {
+    const uint32_t hl = (uint32_t)(h >> (16 * l)) & 0xFFFFu;
+    ex[l] = hl ? ((c - S.P[hl - 1][l]) | SEGF) : c;
+    const uint32_t tl = (uint32_t)readfirstlane((uint32_t)(hall >> (16 * l)) & 0xFFFFu);
+    tot[l] = readfirstlane(tl ? ((call - S.P[tl - 1][l]) | SEGF) : call);  // uniform
+  }
+  __syncthreads();
+}
+
 // --------------------------------------------------------------- k_init
 
 // The call's control words start clear.  k_stats does this in its first
@@ -1002,9 +1074,11 @@ __device__ __forceinline__ void opaque_sgpr(u128& v) {
   v = ((u128)hi << 64) | lo;
 }
 
-// Classes with a nonzero count among three 16-bit class fields, as a 3-bit set.
+// Classes with a nonzero count among three 16-bit class fields (bits 0..47;
+// nothing else set), as a 3-bit set; tested on the 32-bit halves.
 __device__ __forceinline__ uint32_t class_set(uint64_t x) {
-  return ((x & 0xFFFFull) ? 1u : 0u) | ((x & 0xFFFF0000ull) ? 2u : 0u) | ((x & 0xFFFF00000000ull) ? 4u : 0u);
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  return ((lo & 0xFFFFu) ? 1u : 0u) | (lo > 0xFFFFu ? 2u : 0u) | (hi ? 4u : 0u);
 }
 
 // Three 8-bit class fields (read, write, atomic) to three 16-bit fields;
@@ -1110,7 +1184,7 @@ constexpr int scan_min_waves() { return LOOP ? 1 : (sizeof(K) == 8 ? 8 : 5); }
 
 template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(Buffers b, uint32_t passes_done) {
-  __shared__ uint64_t s_scanA[NWAVE][4];
+  __shared__ NestedLds s_nest;
   __shared__ uint64_t s_scanB[NWAVE][3];
   __shared__ uint32_t s_scan32[NWAVE];
   __shared__ uint8_t s_firstlv[NT];
@@ -1187,10 +1261,10 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     //      A.  Pass A: segmented class counts per level, inside the thread as
     //      8-bit fields of one word (a thread holds 16 elements): the running
     //      count, and per level its value before the thread's last head at
-    //      that level or coarser.  Their difference, widened to the 16-bit
-    //      fields of the block scan, is the thread's aggregate.
+    //      that level or coarser, both widened to the 16-bit fields of the
+    //      block scan (their difference is the thread's aggregate).
     uint32_t mp[3] = {0u, 0u, 0u};
-    uint64_t aggA[4];
+    uint64_t cntA, snapA[4];  // the thread's class counts, and before its last head per level (16-bit fields)
     uint32_t mn = NO_HEAD;  // the thread's smallest head level
     {
       const bool trace_first = j0 == 0 && tr.local == 0;  // item 0 is the trace's first key
@@ -1223,8 +1297,13 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         mp[i / 6] |= (lv | (c << 3)) << (5 * (i % 6));
         prev = k;
       }
+      // the snapshots are formed here, not kept as per-item conditions
+      // across the block scan
 #pragma unroll
-      for (int l = 0; l < 4; l++) aggA[l] = (mn <= (uint32_t)l ? SEGF : 0ull) | widen8(cnt - snap[l]);
+      for (int l = 0; l < 4; l++) asm volatile("" : "+v"(snap[l]));
+      cntA = widen8(cnt);
+#pragma unroll
+      for (int l = 0; l < 4; l++) snapA[l] = widen8(snap[l]);
     }
     s_firstlv[tid] = (uint8_t)(mp[0] & 7u);
 
@@ -1232,7 +1311,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 #pragma unroll
     for (int k = 0; k < 3; k++) asm volatile("" : "+v"(mp[k]));
     uint64_t exA[4], totA[4];
-    block_seg_scan<4>(aggA, exA, totA, s_scanA);
+    block_nested_scan(cntA, snapA, mn, exA, totA, s_nest);
 
     // ---- pass B, test: whether an element of this thread has a racing
     //      partner among the earlier elements of its location in the tile.
@@ -1258,9 +1337,10 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         r2 = z2 ? 0u : r2;
         // conflicting classes: a read's are writes and atomics (110b), a
         // write's all three (111b), an atomic's reads and writes (011b);
-        // padding (class 3) has none and adds none
-        hit |= (d01 | d23) & ((0x376u >> (4 * c)) & 7u);
-        const uint32_t bit = (1u << c) & 7u;
+        // padding (class 3) has none and adds none (both from 4-bit tables)
+        const uint32_t c4 = 4 * c;
+        hit |= (d01 | d23) & ((0x376u >> c4) & 7u);
+        const uint32_t bit = (0x0421u >> c4) & 7u;
         r0 |= bit;
         r2 |= bit;
       }
