@@ -1053,9 +1053,11 @@ __global__ __launch_bounds__(NTH) void k_sort_small(Buffers b, const uint32_t* _
 typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
 
 #define META(i) ((mp[(i) / 6] >> (5 * ((i) % 6))) & 31u)
-// the same for a loop index that is not unrolled (no dynamic register indexing)
-__device__ __forceinline__ uint32_t meta_at(const uint32_t mp[3], uint32_t i) {
-  const uint32_t w = i < 6 ? mp[0] : (i < 12 ? mp[1] : mp[2]);
+// the same for a loop index that is not unrolled.  The words come as
+// values: an index into the array would make the compiler move the array to
+// LDS and read it there, one LDS round trip per item in the rolled loops.
+__device__ __forceinline__ uint32_t meta_at(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t i) {
+  const uint32_t w = i < 6 ? m0 : (i < 12 ? m1 : m2);
   return (w >> (5 * (i % 6))) & 31u;
 }
 
@@ -1215,7 +1217,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 
     // each thread's sixteen consecutive keys come straight from memory
     // (with the key before them), with no LDS copy of the tile: the
-    // kernel's LDS stays under 4 KiB, so registers alone bound occupancy.
+    // kernel's LDS stays under 9 KiB, so registers alone bound occupancy.
     // Indices past the tile's end are clamped to its last key (a tile holds
     // at least one), so every load is issued without a branch; those items
     // are padding below.
@@ -1358,7 +1360,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         uint32_t cr = cnt16(exA[l], CLS_R), cw = cnt16(exA[l], CLS_W), ca = cnt16(exA[l], CLS_A);
 #pragma unroll 1
         for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
-          const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
+          const uint32_t m = meta_at(mp[0], mp[1], mp[2], i), lv = m & 7u, c = m >> 3;
           if (lv <= (uint32_t)l) break;
           cr += c == CLS_R ? 1u : 0u;
           cw += c == CLS_W ? 1u : 0u;
@@ -1392,7 +1394,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         uint32_t leads[5] = {0u, 0u, 0u, 0u, 0u};
 #pragma unroll 1
         for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
-          const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
+          const uint32_t m = meta_at(mp[0], mp[1], mp[2], i), lv = m & 7u, c = m >> 3;
 #pragma unroll
           for (int l = 0; l < 4; l++)
             if (lv <= (uint32_t)l) run[l] = 0;
@@ -1413,7 +1415,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
           const uint32_t j = ITEMS * tid + i;
           bool last;
           if (j + 1 == n_in) last = s_taillast != 0;
-          else if (i + 1 < (uint32_t)ITEMS) last = (meta_at(mp, i + 1) & 7u) == 0;
+          else if (i + 1 < (uint32_t)ITEMS) last = (meta_at(mp[0], mp[1], mp[2], i + 1) & 7u) == 0;
           else last = s_firstlv[tid + 1] == 0;
           if (!last) continue;
           if (aggB[0] & SEGF) {  // the location started in this thread
@@ -1491,7 +1493,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
       bool seen0 = (exB[0] & SEGF) != 0;
 #pragma unroll 1
       for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
-        const uint32_t m = meta_at(mp, i), lv = m & 7u, c = m >> 3;
+        const uint32_t m = meta_at(mp[0], mp[1], mp[2], i), lv = m & 7u, c = m >> 3;
 #pragma unroll
         for (int l = 0; l < 4; l++)
           if (lv <= (uint32_t)l) run[l] = 0;
@@ -1511,7 +1513,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         const uint32_t j = ITEMS * tid + i;
         bool last;
         if (j + 1 == n_in) last = s_taillast != 0;
-        else if (i + 1 < (uint32_t)ITEMS) last = (meta_at(mp, i + 1) & 7u) == 0;
+        else if (i + 1 < (uint32_t)ITEMS) last = (meta_at(mp[0], mp[1], mp[2], i + 1) & 7u) == 0;
         else last = s_firstlv[tid + 1] == 0;
         if (!last) continue;
         uint64_t S[5];
