@@ -1052,14 +1052,13 @@ __global__ __launch_bounds__(NTH) void k_sort_small(Buffers b, const uint32_t* _
 // Two one-word keys, 8-byte aligned (a trace's keys start at any record).
 typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
 
-#define META(i) ((mp[(i) / 6] >> (5 * ((i) % 6))) & 31u)
-// the same for a loop index that is not unrolled.  The words come as
-// values: an index into the array would make the compiler move the array to
-// LDS and read it there, one LDS round trip per item in the rolled loops.
-__device__ __forceinline__ uint32_t meta_at(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t i) {
-  const uint32_t w = i < 6 ? m0 : (i < 12 ? m1 : m2);
-  return (w >> (5 * (i % 6))) & 31u;
-}
+// Per-item metadata of a thread's sixteen elements, packed: the head level
+// (0..4) of item i in bits 3 i of a 64-bit word (levels), its class (0..3)
+// in bits 2 i of a 32-bit word (classes).  The rolled loops walk them by
+// shifting, one item per step; bits 48..50 of the levels word can carry
+// the level of the element after the thread's last (see next_levels).
+__device__ __forceinline__ uint32_t lv_of(uint64_t lvs, int i) { return (uint32_t)(lvs >> (3 * i)) & 7u; }
+__device__ __forceinline__ uint32_t cls_of(uint32_t cls, int i) { return (cls >> (2 * i)) & 3u; }
 
 __device__ __forceinline__ uint32_t cnt16(uint64_t packed, uint32_t q) { return (uint32_t)(packed >> (16 * q)) & 0xFFFFu; }
 
@@ -1089,10 +1088,10 @@ __device__ __forceinline__ uint64_t widen8(uint32_t x) {
   return (uint64_t)(x & 0xFFu) | ((uint64_t)(x & 0xFF00u) << 8) | ((uint64_t)(x & 0xFF0000u) << 16);
 }
 
-// Bit 5 k of the result is set where item 6 w + k of a packed metadata word
-// (3-bit head level, 2-bit class per item) has head level 0.
-__device__ __forceinline__ uint32_t loc_heads(uint32_t w) {
-  return ~(w | (w >> 1) | (w >> 2)) & 0x02108421u;
+// Whether some item of a levels word has head level 0 (a location head):
+// bit 3 i of the result is set where item i's level is 0.
+__device__ __forceinline__ uint64_t loc_heads(uint64_t lvs) {
+  return ~(lvs | (lvs >> 1) | (lvs >> 2)) & 0x249249249249ull;
 }
 
 // Pairs of one element of class c against the open-run counts run[] (the
@@ -1254,7 +1253,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     }
 
     // ---- element metadata and pass A, in one loop.  Metadata: head level
-    //      (3 bits) and class (2 bits) of item i, bits 5 (i % 6) of mp[i / 6].
+    //      (3 bits) and class (2 bits) of item i, in the words lvs and cls.
     //      The head level comes from four threshold tests on the bits where
     //      the key differs from its predecessor (keys.h: a location, block,
     //      epoch or thread field differs; the thresholds are the fields'
@@ -1265,7 +1264,8 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     //      count, and per level its value before the thread's last head at
     //      that level or coarser, both widened to the 16-bit fields of the
     //      block scan (their difference is the thread's aggregate).
-    uint32_t mp[3] = {0u, 0u, 0u};
+    uint64_t lvs = 0;
+    uint32_t cls = 0;
     uint64_t cntA, snapA[4];  // the thread's class counts, and before its last head per level (16-bit fields)
     uint32_t mn = NO_HEAD;  // the thread's smallest head level
     {
@@ -1296,7 +1296,8 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
         snap[3] = h3 ? cnt : snap[3];
         cnt += 1u << (8 * c);  // padding (class 3) counts in the unused top field
         mn = min(mn, lv);
-        mp[i / 6] |= (lv | (c << 3)) << (5 * (i % 6));
+        lvs |= (uint64_t)lv << (3 * i);
+        cls |= c << (2 * i);
         prev = k;
       }
       // the snapshots are formed here, not kept as per-item conditions
@@ -1307,11 +1308,11 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 #pragma unroll
       for (int l = 0; l < 4; l++) snapA[l] = widen8(snap[l]);
     }
-    s_firstlv[tid] = (uint8_t)(mp[0] & 7u);
+    s_firstlv[tid] = (uint8_t)(lvs & 7u);
 
     // the packed metadata is decoded again per pass, not kept decoded
-#pragma unroll
-    for (int k = 0; k < 3; k++) asm volatile("" : "+v"(mp[k]));
+    asm volatile("" : "+v"(lvs));
+    asm volatile("" : "+v"(cls));
     uint64_t exA[4], totA[4];
     block_nested_scan(cntA, snapA, mn, exA, totA, s_nest);
 
@@ -1330,7 +1331,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
       uint32_t d23 = class_set((exA[2] & ~SEGF) - (exA[3] & ~SEGF));
 #pragma unroll
       for (int i = 0; i < ITEMS; i++) {
-        const uint32_t lv = META(i) & 7u, c = META(i) >> 3;
+        const uint32_t lv = lv_of(lvs, i), c = cls_of(cls, i);
         // selects, not branches (branches here cost registers)
         const bool z0 = lv == 0, z1 = lv == 1, z2 = lv <= 2, z3 = lv == 3;
         d01 = z0 ? 0u : (z1 ? r0 : d01);
@@ -1358,9 +1359,11 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     for (int l = 0; l < 4; l++) {
       if ((exA[l] & SEGF) == 0 && mn <= (uint32_t)l) {
         uint32_t cr = cnt16(exA[l], CLS_R), cw = cnt16(exA[l], CLS_W), ca = cnt16(exA[l], CLS_A);
+        uint64_t lw = lvs;
+        uint32_t cw_ = cls;
 #pragma unroll 1
-        for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
-          const uint32_t m = meta_at(mp[0], mp[1], mp[2], i), lv = m & 7u, c = m >> 3;
+        for (uint32_t i = 0; i < (uint32_t)ITEMS; i++, lw >>= 3, cw_ >>= 2) {
+          const uint32_t lv = (uint32_t)lw & 7u, c = cw_ & 3u;
           if (lv <= (uint32_t)l) break;
           cr += c == CLS_R ? 1u : 0u;
           cw += c == CLS_W ? 1u : 0u;
@@ -1382,19 +1385,37 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     //      scan.
     uint64_t exB[3] = {0, 0, 0}, totB[3] = {0, 0, 0};
     uint32_t n_emit = 0;
+    // the levels word with the level of the element after the thread's last
+    // in bits 48..50 (the next thread's first), and where the tile ends in
+    // this thread, 0 or 4 after its last element by whether the location
+    // ends with the tile: an element ends its location where the next
+    // level is 0
+    auto next_levels = [&]() {
+      uint64_t x = lvs | ((uint64_t)(tid + 1 < (uint32_t)NT ? s_firstlv[tid + 1] : 4u) << 48);
+      const uint32_t tail_i = n_in - 1 - ITEMS * tid;  // the tile's last element, when it is this thread's
+      if (tail_i < (uint32_t)ITEMS) {
+        const uint32_t sh = 3 * (tail_i + 1);
+        x = (x & ~(7ull << sh)) | ((uint64_t)(s_taillast ? 0u : 4u) << sh);
+      }
+      return x;
+    };
     if (tile_hit) {  // uniform over the workgroup
       uint64_t aggB[3] = {0, 0, 0};
       bool pend = false;
       uint64_t pend0 = 0, pend1 = 0;
+      uint32_t leads[5] = {0u, 0u, 0u, 0u, 0u};
       if (hit) {
         uint64_t run[4];
 #pragma unroll
         for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
         bool lead = (exA[0] & SEGF) == 0;  // before the tile's first location head
-        uint32_t leads[5] = {0u, 0u, 0u, 0u, 0u};
+        uint64_t lw = next_levels();
+        uint32_t cw_ = cls;
 #pragma unroll 1
         for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
-          const uint32_t m = meta_at(mp[0], mp[1], mp[2], i), lv = m & 7u, c = m >> 3;
+          const uint32_t lv = (uint32_t)lw & 7u, c = cw_ & 3u;
+          lw >>= 3;
+          cw_ >>= 2;
 #pragma unroll
           for (int l = 0; l < 4; l++)
             if (lv <= (uint32_t)l) run[l] = 0;
@@ -1412,12 +1433,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
           aggB[2] += (uint64_t)v[K_XB];
 #pragma unroll
           for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
-          const uint32_t j = ITEMS * tid + i;
-          bool last;
-          if (j + 1 == n_in) last = s_taillast != 0;
-          else if (i + 1 < (uint32_t)ITEMS) last = (meta_at(mp[0], mp[1], mp[2], i + 1) & 7u) == 0;
-          else last = s_firstlv[tid + 1] == 0;
-          if (!last) continue;
+          if (((uint32_t)lw & 7u) != 0) continue;  // the location does not end here
           if (aggB[0] & SEGF) {  // the location started in this thread
             if (((aggB[0] | aggB[1]) & ~SEGF) != 0) n_emit++;
           } else {
@@ -1426,19 +1442,24 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
             pend1 = aggB[1];
           }
         }
-#pragma unroll
-        for (int k = 0; k < 5; k++)
-          if (leads[k]) atomicAdd(&s_lead[12 + k], leads[k]);
       } else if (ITEMS * tid < n_in) {
         // every pair sum of this thread is zero: only its location heads
         // and whether its first location ends in it matter
-        const uint32_t heads = loc_heads(mp[0]) | loc_heads(mp[1]) | (loc_heads(mp[2]) & 0x8421u);
-        if (heads) {
+        if (loc_heads(lvs)) {
           aggB[0] = aggB[1] = aggB[2] = SEGF;
-          pend = (mp[0] & 7u) != 0;  // the first location ends before the thread's first head
+          pend = (lvs & 7u) != 0;  // the first location ends before the thread's first head
         } else {
           const uint32_t jl = min(ITEMS * tid + (uint32_t)ITEMS, n_in) - 1;  // last element of the thread
           pend = jl + 1 == n_in ? s_taillast != 0 : s_firstlv[tid + 1] == 0;
+        }
+      }
+      // the lead pair sums: one sum per wave, added by one lane (a lane
+      // per thread would make the atomics a loop over the wave's lanes)
+      if (__builtin_amdgcn_ballot_w64((leads[0] | leads[1] | leads[2] | leads[3] | leads[4]) != 0)) {
+#pragma unroll
+        for (int k = 0; k < 5; k++) {
+          const uint32_t t = wave_reduce(leads[k], 0u, [](uint32_t a, uint32_t b) { return a + b; });
+          if (lane == 0 && t) atomicAdd(&s_lead[12 + k], t);
         }
       }
       block_seg_scan<3>(aggB, exB, totB, s_scanB);
@@ -1491,9 +1512,13 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
       for (int l = 0; l < 4; l++) run[l] = exA[l] & ~SEGF;
       uint64_t s0 = exB[0] & ~SEGF, s1 = exB[1] & ~SEGF, s2 = exB[2] & ~SEGF;
       bool seen0 = (exB[0] & SEGF) != 0;
+      uint64_t lw = next_levels();
+      uint32_t cw_ = cls;
 #pragma unroll 1
       for (uint32_t i = 0; i < (uint32_t)ITEMS; i++) {
-        const uint32_t m = meta_at(mp[0], mp[1], mp[2], i), lv = m & 7u, c = m >> 3;
+        const uint32_t lv = (uint32_t)lw & 7u, c = cw_ & 3u;
+        lw >>= 3;
+        cw_ >>= 2;
 #pragma unroll
         for (int l = 0; l < 4; l++)
           if (lv <= (uint32_t)l) run[l] = 0;
@@ -1510,12 +1535,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 #pragma unroll
         for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
         if (!seen0) continue;  // the location entering the tile belongs to an earlier tile
-        const uint32_t j = ITEMS * tid + i;
-        bool last;
-        if (j + 1 == n_in) last = s_taillast != 0;
-        else if (i + 1 < (uint32_t)ITEMS) last = (meta_at(mp[0], mp[1], mp[2], i + 1) & 7u) == 0;
-        else last = s_firstlv[tid + 1] == 0;
-        if (!last) continue;
+        if (((uint32_t)lw & 7u) != 0) continue;  // the location does not end here
         uint64_t S[5];
         S[K_WW] = (uint32_t)s0; S[K_RW] = (uint32_t)(s0 >> 32);
         S[K_AW] = (uint32_t)s1; S[K_AR] = (uint32_t)(s1 >> 32);
