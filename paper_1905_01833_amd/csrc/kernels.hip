@@ -1192,6 +1192,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
   __shared__ uint32_t s_lead[17];  // lead counts [l][c] (12), lead pair sums (5)
   __shared__ uint32_t s_taillast;
   __shared__ uint32_t s_hit;  // some thread of the tile has an element with an in-tile racing partner
+  __shared__ uint64_t s_pend[NT][3];  // sums of the location a thread's first element belongs to, when it is emitted there
 
   // nothing to do on an error, or when fewer radix passes ran than some
   // trace needs (the host then runs the missing passes and scans again)
@@ -1216,7 +1217,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
 
     // each thread's sixteen consecutive keys come straight from memory
     // (with the key before them), with no LDS copy of the tile: the
-    // kernel's LDS stays under 9 KiB, so registers alone bound occupancy.
+    // kernel's LDS stays under 15 KiB, so registers alone bound occupancy.
     // Indices past the tile's end are clamped to its last key (a tile holds
     // at least one), so every load is issued without a branch; those items
     // are padding below.
@@ -1384,7 +1385,8 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     //      location (it may start in an earlier thread) is settled after the
     //      scan.
     uint64_t exB[3] = {0, 0, 0}, totB[3] = {0, 0, 0};
-    uint32_t n_emit = 0;
+    uint32_t n_emit = 0;      // complete locations emitted by this thread
+    bool pend_emit = false;   // one of them is its first location (sums in s_pend)
     // the levels word with the level of the element after the thread's last
     // in bits 48..50 (the next thread's first), and where the tile ends in
     // this thread, 0 or 4 after its last element by whether the location
@@ -1402,7 +1404,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     if (tile_hit) {  // uniform over the workgroup
       uint64_t aggB[3] = {0, 0, 0};
       bool pend = false;
-      uint64_t pend0 = 0, pend1 = 0;
+      uint64_t pend0 = 0, pend1 = 0, pend2 = 0;
       uint32_t leads[5] = {0u, 0u, 0u, 0u, 0u};
       if (hit) {
         uint64_t run[4];
@@ -1435,11 +1437,21 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
           for (int l = 0; l < 4; l++) run[l] += 1ull << (16 * c);
           if (((uint32_t)lw & 7u) != 0) continue;  // the location does not end here
           if (aggB[0] & SEGF) {  // the location started in this thread
-            if (((aggB[0] | aggB[1]) & ~SEGF) != 0) n_emit++;
+            if (((aggB[0] | aggB[1]) & ~SEGF) != 0) {
+              // the first such location's sums and last element wait in
+              // LDS (the nested scan's table is free by now) for the output
+              if (n_emit == 0) {
+                s_nest.P[tid][0] = aggB[0] & ~SEGF;
+                s_nest.P[tid][1] = aggB[1] & ~SEGF;
+                s_nest.P[tid][2] = (aggB[2] & ~SEGF) | ((uint64_t)i << 48);
+              }
+              n_emit++;
+            }
           } else {
             pend = true;
             pend0 = aggB[0];
             pend1 = aggB[1];
+            pend2 = aggB[2];
           }
         }
       } else if (ITEMS * tid < n_in) {
@@ -1466,7 +1478,16 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
       // the thread's first location: complete here only if it started in
       // the tile (a location head in an earlier thread); otherwise it belongs
       // to an earlier tile and is finished by k_scan_cross
-      if (pend && (exB[0] & SEGF) && ((((exB[0] + pend0) | (exB[1] + pend1)) & ~SEGF) != 0)) n_emit++;
+      if (pend && (exB[0] & SEGF)) {
+        const uint64_t f0 = (exB[0] & ~SEGF) + pend0, f1 = (exB[1] & ~SEGF) + pend1;
+        if ((f0 | f1) != 0) {
+          s_pend[tid][0] = f0;
+          s_pend[tid][1] = f1;
+          s_pend[tid][2] = (exB[2] & ~SEGF) + pend2;
+          pend_emit = true;
+          n_emit++;
+        }
+      }
     }
 
     // ---- the tile summary (lanes of wave 0 write its words)
@@ -1549,7 +1570,26 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     const uint32_t my_off = block_excl_sum(n_emit, s_scan32, &tile_emit);
     uint32_t cap;
     RaceOut* stage = stage_of(b, tile, T, L, start, n_in, &cap);
-    if (n_emit) walk_emit(stage, cap, my_off);
+    // a thread with at most one complete location besides its first writes
+    // them from the sums kept above; one with more walks its elements again
+    if (n_emit) {
+      const uint32_t own = n_emit - (pend_emit ? 1u : 0u);
+      if (own <= 1) {
+        uint32_t pos = my_off;
+        auto put = [&](uint64_t s0, uint64_t s1, uint64_t s2, uint32_t i) {
+          uint64_t S[5];
+          S[K_WW] = (uint32_t)s0; S[K_RW] = (uint32_t)(s0 >> 32);
+          S[K_AW] = (uint32_t)s1; S[K_AR] = (uint32_t)(s1 >> 32);
+          S[K_XB] = (uint32_t)s2;
+          if (pos < cap) write_entry<K>(stage + pos, tr.trace, L, src[ITEMS * tid + i], S);
+          pos++;
+        };
+        if (pend_emit) put(s_pend[tid][0], s_pend[tid][1], s_pend[tid][2], 0);
+        if (own) put(s_nest.P[tid][0], s_nest.P[tid][1], s_nest.P[tid][2], (uint32_t)(s_nest.P[tid][2] >> 48));
+      } else {
+        walk_emit(stage, cap, my_off);
+      }
+    }
     if (tid == 0) {
       b.tout[tile].in_count = tile_emit;
       if (tile_emit > cap) atomicOr(&b.ctrl->error_flags, ERR_STAGE_OVERFLOW);
