@@ -158,38 +158,59 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* lds /* 
   return block_excl_sum_n<NWAVE>(v, lds, total);
 }
 
-// Segmented scan operator on packed values: a head flag in bit 63 restarts
-// the sum.
-__device__ __forceinline__ uint64_t seg_op(uint64_t a, uint64_t b) { return (b & SEGF) ? b : a + b; }
-
-// Exclusive segmented scan of K packed words over the workgroup; tot[]
-// receives the inclusive value at the last thread.
-template <int K>
-__device__ void block_seg_scan(const uint64_t (&v)[K], uint64_t (&ex)[K], uint64_t (&tot)[K],
-                               uint64_t (*lds)[K] /* [NWAVE][K] */) {
-  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
-  uint64_t inc[K];
+// Segmented exclusive scan over the workgroup of three packed words that
+// share one head flag (SEGF in bit 63 of the first: the thread holds a
+// head; the words then hold its sums after its last head).  The value a
+// segmented scan gives thread t is flagged when some earlier thread h holds
+// a head, and then sums the words of h .. t - 1, which is C(t) - C(h) for
+// the plain exclusive prefix C of the words; otherwise it is C(t).  So one
+// add scan per word, one max scan of (thread + 1) over the head holders and
+// one look-up of C(h) in a table of the thread prefixes give it.
+// v: the thread's words; ex: its exclusive values; tot: the workgroup's
+// inclusive values (uniform); P: an [NT][3] table of LDS free for the call;
+// C, H: the waves' totals.
+struct HeadScanLds {
+  uint64_t C[NWAVE][3];
+  uint32_t H[NWAVE];
+};
+__device__ void block_head_scan3(const uint64_t (&v)[3], uint64_t (&ex)[3], uint64_t (&tot)[3], uint64_t (*P)[3],
+                                 HeadScanLds& S) {
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6, tid = threadIdx.x;
+  uint64_t c[3];
 #pragma unroll
-  for (int k = 0; k < K; k++) {
-    inc[k] = wave_incl_scan(v[k], seg_op);
-    ex[k] = dpp<DPP_WAVE_SHR1>(inc[k]);
-  }
+  for (int q = 0; q < 3; q++) c[q] = wave_incl_scan(v[q] & ~SEGF, [](uint64_t a, uint64_t b) { return a + b; });
+  const uint32_t hinc = wave_incl_scan((v[0] & SEGF) ? tid + 1u : 0u, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
   if (lane == 63) {
 #pragma unroll
-    for (int k = 0; k < K; k++) lds[wave][k] = inc[k];
+    for (int q = 0; q < 3; q++) S.C[wave][q] = c[q];
+    S.H[wave] = hinc;
   }
+#pragma unroll
+  for (int q = 0; q < 3; q++) c[q] = dpp<DPP_WAVE_SHR1>(c[q]);
+  uint32_t h = dpp<DPP_WAVE_SHR1>(hinc);
   __syncthreads();
+  uint64_t call[3] = {0, 0, 0};
+  uint32_t hall = 0;
 #pragma unroll
-  for (int k = 0; k < K; k++) {
-    uint64_t pre = 0, all = 0;
+  for (int w = 0; w < NWAVE; w++) {
 #pragma unroll
-    for (int w = 0; w < NWAVE; w++) {
-      const uint64_t x = lds[w][k];
-      if (w < (int)wave) pre = seg_op(pre, x);
-      all = seg_op(all, x);
+    for (int q = 0; q < 3; q++) {
+      const uint64_t x = S.C[w][q];
+      if (w < (int)wave) c[q] += x;
+      call[q] += x;
     }
-    ex[k] = seg_op(pre, ex[k]);
-    tot[k] = readfirstlane(all);  // uniform: scalar registers hold it
+    const uint32_t xh = S.H[w];
+    if (w < (int)wave) h = max(h, xh);
+    hall = max(hall, xh);
+  }
+#pragma unroll
+  for (int q = 0; q < 3; q++) P[tid][q] = c[q];
+  __syncthreads();
+  hall = (uint32_t)__builtin_amdgcn_readfirstlane((int)hall);
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    ex[q] = h ? ((c[q] - P[h - 1][q]) | SEGF) : c[q];
+    tot[q] = readfirstlane(hall ? ((call[q] - P[hall - 1][q]) | SEGF) : call[q]);  // uniform
   }
   __syncthreads();
 }
@@ -213,8 +234,8 @@ struct NestedLds {
 };
 
 // The nested segmented scan of the tile scan's class counts, over the NT
-// threads of a workgroup, in the value a segmented scan (block_seg_scan) of
-// the per-level aggregates (SEGF if the thread holds a head at level l or
+// threads of a workgroup, in the value a segmented scan of the per-level
+// aggregates (SEGF if the thread holds a head at level l or
 // coarser) | (its counts after the last such head) gives.  The levels nest
 // (a head at level l is one at every finer level too), so the segment of
 // level l before thread t starts after the last head at level l or coarser
@@ -1186,7 +1207,7 @@ constexpr int scan_min_waves() { return LOOP ? 1 : (sizeof(K) == 8 ? 8 : 5); }
 template <typename K, bool LOOP>
 __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(Buffers b, uint32_t passes_done) {
   __shared__ NestedLds s_nest;
-  __shared__ uint64_t s_scanB[NWAVE][3];
+  __shared__ HeadScanLds s_scanB;
   __shared__ uint32_t s_scan32[NWAVE];
   __shared__ uint8_t s_firstlv[NT];
   __shared__ uint32_t s_lead[17];  // lead counts [l][c] (12), lead pair sums (5)
@@ -1474,7 +1495,7 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
           if (lane == 0 && t) atomicAdd(&s_lead[12 + k], t);
         }
       }
-      block_seg_scan<3>(aggB, exB, totB, s_scanB);
+      block_head_scan3(aggB, exB, totB, s_pend, s_scanB);  // s_pend is free until after it
       // the thread's first location: complete here only if it started in
       // the tile (a location head in an earlier thread); otherwise it belongs
       // to an earlier tile and is finished by k_scan_cross
