@@ -518,6 +518,14 @@ __device__ __forceinline__ bool sorted_in_lds(const Buffers& b, const TraceDesc&
 // waits on another.
 
 constexpr uint32_t CHUNK = 16;   // rows loaded ahead in the serial offset loops
+
+// In-group offsets are 16-bit when no group of the call has more than 16
+// tiles (an offset then sums at most 15 tiles of 4096 keys): half the bytes
+// of the rows k_group_offsets writes and k_scatter reads.
+constexpr uint32_t THIST16_TILES = 65536u / TILE;
+template <uint32_t R>
+__device__ __forceinline__ uint32_t d_of() { return threadIdx.x % R; }  // the digit column of a thread
+__device__ __forceinline__ bool thist16(const Buffers& b) { return b.max_group_tiles <= THIST16_TILES; }
 constexpr int MAX_PARTS = 4;     // offset kernels: up to 4 row ranges per digit (1024 threads)
 
 // Exclusive prefix over `n` rows (stride R, the pass's digit count) of one
@@ -526,10 +534,16 @@ constexpr int MAX_PARTS = 4;     // offset kernels: up to 4 row ranges per digit
 // prefix.  DIGIT_BASE: `base` is the trace's first record and every digit's
 // column starts at base + (totals of the smaller digits) -- the digit bases
 // of a radix pass -- computed here from the same reads.  s_sc holds one word
-// per wave of the workgroup and s_base one 64-bit word per digit.
+// per wave of the workgroup and s_base one 64-bit word per digit.  narrow
+// (uniform): `out` holds 16-bit words instead (32-bit Out only).
 template <int PARTS, bool DIGIT_BASE, uint32_t R, typename In, typename Out>
 __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t base, uint64_t (*s_part)[R],
-                                  uint32_t* s_sc = nullptr, uint64_t* s_base = nullptr, bool skip = false) {
+                                  uint32_t* s_sc = nullptr, uint64_t* s_base = nullptr, bool skip = false,
+                                  bool narrow = false) {
+  auto put = [&](uint32_t row, uint64_t v) {
+    if (sizeof(Out) == 4 && narrow) ((uint16_t*)out)[(uint64_t)row * R + d_of<R>()] = (uint16_t)v;
+    else out[(uint64_t)row * R + d_of<R>()] = (Out)v;
+  };
   const uint32_t d = threadIdx.x % R, part = threadIdx.x / R;
   const uint32_t per = (n + PARTS - 1) / PARTS;
   const uint32_t r0 = min(n, part * per), r1 = min(n, r0 + per);
@@ -579,7 +593,7 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
 #pragma unroll
   for (uint32_t k = 0; k < CHUNK; k++)
     if (r0 + k < r1) {
-      out[(uint64_t)(r0 + k) * R + d] = (Out)run;
+      put(r0 + k, run);
       run += first[k];
     }
   for (uint32_t k0 = r0 + CHUNK; k0 < r1; k0 += CHUNK) {
@@ -592,7 +606,7 @@ __device__ uint64_t column_prefix(const In* in, Out* out, uint32_t n, uint64_t b
 #pragma unroll
     for (uint32_t k = 0; k < CHUNK; k++)
       if (k0 + k < r1) {
-        out[(uint64_t)(k0 + k) * R + d] = (Out)run;
+        put(k0 + k, run);
         run += c[k];
       }
   }
@@ -618,9 +632,11 @@ __global__ __launch_bounds__(R * PARTS) void k_group_offsets(Buffers b, uint32_t
   const GroupRef gr = b.groups[g];
   const bool skip = pass >= b.layout[gr.trace].npasses || ((gr.n_flags & TILE_SHORT) && pass >= b.small_from);
   const uint16_t* counts = b.tcnt + (uint64_t)gr.first * R;
-  uint32_t* offsets = b.thist + (uint64_t)gr.first * R;
-  const uint64_t total = column_prefix<PARTS, false, R>(counts, offsets, gr.n_flags & ~TILE_SHORT, 0, s_part, nullptr,
-                                                        nullptr, skip);
+  const uint32_t rows = gr.n_flags & ~TILE_SHORT;
+  uint32_t* offsets = b.thist + (uint64_t)gr.first * R;  // 32-bit rows, or 16-bit ones from the same start
+  if (thist16(b)) offsets = (uint32_t*)((uint16_t*)b.thist + (uint64_t)gr.first * R);
+  const uint64_t total = column_prefix<PARTS, false, R>(counts, offsets, rows, 0, s_part, nullptr, nullptr, skip,
+                                                        thist16(b));
   if (skip) return;
   if (threadIdx.x < R) b.gtot[(uint64_t)g * R + threadIdx.x] = (uint32_t)total;
 }
@@ -829,9 +845,16 @@ __device__ __forceinline__ void scatter_tile(const Buffers& b, uint32_t pass, ui
   uint64_t gb[DPT];
   if (dig) {
     const uint64_t* grow = b.gbase + (uint64_t)(T.group0 + (tr.local >> T.gshift)) * R;
-    const uint32_t* trow = b.thist + (uint64_t)tile * R;
+    const uint64_t row = (uint64_t)tile * R + d0;
+    if (thist16(b)) {
+      const uint16_t* trow = (const uint16_t*)b.thist + row;
 #pragma unroll
-    for (uint32_t e = 0; e < DPT; e++) gb[e] = grow[d0 + e] + trow[d0 + e];
+      for (uint32_t e = 0; e < DPT; e++) gb[e] = grow[d0 + e] + trow[e];
+    } else {
+      const uint32_t* trow = b.thist + row;
+#pragma unroll
+      for (uint32_t e = 0; e < DPT; e++) gb[e] = grow[d0 + e] + trow[e];
+    }
   }
   __syncthreads();
 

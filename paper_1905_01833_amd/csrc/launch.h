@@ -85,6 +85,7 @@ struct Buffers {            // device pointers of one call
   void* keys[2];             // uint64_t[] (one-word keys) or u128[] (two-word keys, `wide`)
   const GroupRef* groups;   // [group]
   uint32_t* thist;          // [tile][radix] the current pass's digit offsets within the tile's group
+                            // (uint16_t when no group has more than 16 tiles, see kernels.hip)
   uint16_t* tcnt;           // [tile][radix] the current pass's digit counts (a tile holds 4096 keys)
   uint32_t* gtot;           // [group][radix] group totals
   uint64_t* gbase;          // [group][radix] absolute digit bases of the group
