@@ -1399,24 +1399,27 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     //      its own elements before the head; a level without a head in the
     //      tile takes the tile's totals (in the summary).  The pair sums of
     //      those elements are added by the pair pass below: only threads
-    //      with an in-tile racing partner have any.
+    //      with an in-tile racing partner have any.  The thread's own
+    //      counts come from masks, not a walk: per class a mask of its
+    //      items (bit 2 i), per level a mask of the items with a head at
+    //      that level or coarser (bit 3 i, from the level's bits: 0, at most
+    //      1, at most 2, at most 3 of 0..4), and bit counts below the first
+    //      such head.
+    {
+      const uint32_t cx = cls, cy = cls >> 1;  // padding (class 3) is in no mask
+      const uint32_t mR = ~(cx | cy) & 0x55555555u, mW = cx & ~cy & 0x55555555u, mA = ~cx & cy & 0x55555555u;
+      const uint64_t M = 0x249249249249ull;
+      const uint64_t f0 = lvs & M, f1 = (lvs >> 1) & M, f2 = (lvs >> 2) & M;
+      const uint64_t le[4] = {~(f0 | f1 | f2) & M, ~(f1 | f2) & M, ~f2 & ~(f1 & f0) & M, ~f2 & M};
 #pragma unroll
-    for (int l = 0; l < 4; l++) {
-      if ((exA[l] & SEGF) == 0 && mn <= (uint32_t)l) {
-        uint32_t cr = cnt16(exA[l], CLS_R), cw = cnt16(exA[l], CLS_W), ca = cnt16(exA[l], CLS_A);
-        uint64_t lw = lvs;
-        uint32_t cw_ = cls;
-#pragma unroll 1
-        for (uint32_t i = 0; i < (uint32_t)ITEMS; i++, lw >>= 3, cw_ >>= 2) {
-          const uint32_t lv = (uint32_t)lw & 7u, c = cw_ & 3u;
-          if (lv <= (uint32_t)l) break;
-          cr += c == CLS_R ? 1u : 0u;
-          cw += c == CLS_W ? 1u : 0u;
-          ca += c == CLS_A ? 1u : 0u;
+      for (int l = 0; l < 4; l++) {
+        if ((exA[l] & SEGF) == 0 && mn <= (uint32_t)l) {  // mn <= l: le[l] has a bit
+          const uint32_t p = (uint32_t)__builtin_ctzll(le[l]) / 3;  // the first such head
+          const uint32_t below = (1u << (2 * p)) - 1u;
+          s_lead[l * 3 + CLS_R] = cnt16(exA[l], CLS_R) + __builtin_popcount(mR & below);
+          s_lead[l * 3 + CLS_W] = cnt16(exA[l], CLS_W) + __builtin_popcount(mW & below);
+          s_lead[l * 3 + CLS_A] = cnt16(exA[l], CLS_A) + __builtin_popcount(mA & below);
         }
-        s_lead[l * 3 + CLS_R] = cr;
-        s_lead[l * 3 + CLS_W] = cw;
-        s_lead[l * 3 + CLS_A] = ca;
       }
     }
     if (hit) s_hit = 1u;
