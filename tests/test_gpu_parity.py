@@ -160,6 +160,28 @@ def test_many_racing_locations_grow_output(ctx):
     assert len(got) == n
 
 
+def test_location_lengths_across_threads(ctx):
+    """Locations of 1 to 40 records in a repeating cycle, so that a thread's
+    16 elements hold no, one or several complete locations and its first
+    element belongs to a location that started in an earlier thread, a
+    location that ends in it or one that runs on: every way the tile scan
+    writes an entry (from the sums its pair pass kept, or by walking the
+    thread's elements again) and locations that cross threads and tiles.
+    Two threads per block, three barrier intervals, all three actions."""
+    rng = np.random.default_rng(17)
+    lens = np.tile(np.arange(1, 41), 600)
+    n = int(lens.sum())
+    r = np.zeros(n, dtype=RECORD_DTYPE)
+    r["unit"] = np.repeat(np.arange(len(lens), dtype=np.uint64) * 5, lens)
+    r["tid"] = rng.integers(0, 8, n)
+    r["epoch"] = rng.integers(0, 3, n)
+    r["action"] = rng.choice(np.array([0, 1, 2], dtype=np.uint8), n, p=[0.6, 0.3, 0.1])
+    got = assert_parity(ctx, r, tpb=2, name="locations of 1..40 records")
+    assert len(got) > 10000
+    r["space"] = 1
+    assert_parity(ctx, r, tpb=2, name="shared locations of 1..40 records")
+
+
 def test_batched_mixed_sizes(ctx):
     shapes = tracegen.c3_shapes(48, log2_max=16)
     recs, off, tpb, inj = tracegen.batch(shapes, inject_rate=5e-4)
