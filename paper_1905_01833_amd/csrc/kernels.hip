@@ -1572,8 +1572,11 @@ __global__ __launch_bounds__(NT, (scan_min_waves<K, LOOP>())) void k_scan_tiles(
     }
 
     // ---- complete locations: started after the tile's first location head
-    //      and ended inside the tile.  Written (rarely: only threads that
-    //      counted one) at their last element.
+    //      and ended inside the tile, written by the thread holding their
+    //      last element.  This walk recomputes a thread's sums element by
+    //      element; it serves only the rare thread with more than one
+    //      complete location of its own (the others write from the sums the
+    //      pair pass kept, below).
     auto walk_emit = [&](RaceOut* dst, uint32_t cap, uint32_t pos) {
       uint64_t run[4];
 #pragma unroll
