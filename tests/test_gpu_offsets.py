@@ -101,3 +101,34 @@ def test_batch_widths_alternate(pkg):
                 assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes(), (name, rep)
     finally:
         c.close()
+
+
+def wide_hot_trace(n_tiles, seed):
+    """As hot_trace, with two-word keys: units spread over 2^62 and thread
+    ids up to 2^20 outside the hot part."""
+    r = hot_trace(n_tiles, seed)
+    rng = np.random.default_rng(seed + 1000)
+    cold = r["unit"] != 0
+    pool = rng.integers(0, 1 << 62, 16, dtype=np.uint64)
+    r["unit"][cold] = pool[rng.integers(0, len(pool), int(cold.sum()))]
+    r["tid"][cold] = rng.integers(0, 1 << 20, int(cold.sum()))
+    r["unit"][-1] = (1 << 62) - 1
+    return r
+
+
+@pytest.mark.parametrize("n_tiles", [256, 300])
+def test_two_word_keys_both_widths(pkg, n_tiles):
+    """Two-word keys with 16-bit offset rows (256 tiles: groups of 16) and
+    32-bit ones (300 tiles: groups of 32)."""
+    recs = wide_hot_trace(n_tiles, seed=11)
+    want, wsum = oracle.closed_form(recs, None, 256)
+    dev = to_dev(recs)
+    c = pkg.Context(0)
+    try:
+        for rep in range(2):
+            say(f"two-word keys, {n_tiles} tiles, call {rep}")
+            got, gsum = c.check_traces_device(dev, None, 256)
+            torch.cuda.synchronize()
+            assert got.tobytes() == want.tobytes() and gsum.tobytes() == wsum.tobytes(), (n_tiles, rep)
+    finally:
+        c.close()
